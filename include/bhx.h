@@ -1,0 +1,197 @@
+/*
+ * bhx.h - biharmonic field extension on AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the extension problem of Sec. 2 of Moroney, Lusmore,
+ * McCue and McElwain, "Extending fields in a level set method by solving a
+ * biharmonic equation":
+ *
+ *   - a field F is known at the grid nodes where the level-set function
+ *     phi < 0 (the known set K; the region definitions of Sec. 3 use a strict
+ *     inequality, so phi == 0 and NaN are unknown);
+ *   - at every other node (the unknown set U) the 13-point discrete
+ *     biharmonic equation, eq. (12), must hold; near the edges of the grid
+ *     the stencil uses two ghost layers whose values follow the boundary rule
+ *     of each axis (Algorithm 1 pads the array for Dirichlet conditions;
+ *     Sec. 3.1 and 3.2 describe the Neumann and periodic variants);
+ *   - the unknowns solve the symmetric positive definite system
+ *     A_UU u = -A_UK F_K (Sec. 2.2) by matrix-free preconditioned conjugate
+ *     gradients, the preconditioner being the fast Poisson solver on the whole
+ *     rectangle: embed the residual (zero at K), transform, divide by the
+ *     squared eigenvalues of the discrete Laplacian, transform back, restrict
+ *     (Algorithm 1; cosine transforms for Neumann axes, Fourier (Hartley)
+ *     transforms for periodic axes, sine transforms for Dirichlet axes).
+ *
+ * Conventions for every entry point:
+ *   - Arrays are float64, contiguous, row-major with x fastest:
+ *     a[j*nx + i], 0 <= i < nx, 0 <= j < ny.  phi and F are DEVICE pointers
+ *     owned by the caller (for instance torch tensors on the same device).
+ *   - F is in/out.  Values at known nodes are read and never written
+ *     (bit-exact).  Values at unknown nodes on input are ignored (the solve
+ *     starts from zero, as Algorithm 1 does) and on return hold the
+ *     extension.
+ *   - The stencil is the paper's unscaled integer stencil; the grid spacing h
+ *     cancels from the system and from the relative residual, so h is only
+ *     validated (finite, > 0).
+ *   - The stopping test is ||b - A_UU x||_2 <= tol * ||b||_2 on the recursive
+ *     residual, followed by one check of the true residual computed with
+ *     compensated (double-double) arithmetic; if that check fails the solve
+ *     restarts from the true residual (up to the iteration limit).
+ *   - Return values: 0 = BHX_OK; > 0 = warning, F holds the last iterate;
+ *     < 0 = error, F untouched.  Nothing is thrown across this interface.
+ *   - Entry points that take a stream enqueue their GPU work on it; they
+ *     synchronise with it before returning (stats are valid on return).
+ *     A handle is not thread-safe: use one handle per host thread.
+ */
+#ifndef BHX_H
+#define BHX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Boundary rule of one axis. */
+enum {
+  BHX_NEUMANN = 0,    /* half-sample even reflection: g[-1]=f[0], g[-2]=f[1]; DCT-II */
+  BHX_PERIODIC = 1,   /* wrap-around: g[-1]=f[n-1], g[-2]=f[n-2]; Hartley (DFT) */
+  BHX_DIRICHLET = 2   /* Algorithm 1: g[-1]=0, g[-2]=-f[0]; DST-I */
+};
+/* Both axes packed into one int: low nibble x axis, next nibble y axis. */
+#define BHX_BC(bx, by) ((bx) | ((by) << 4))
+
+/* Status codes. */
+enum {
+  BHX_OK = 0,
+  BHX_NOT_CONVERGED = 1,   /* iteration limit reached; F holds the last iterate   */
+  BHX_ERR_ARG = -1,        /* invalid argument (sizes < 4, bad bc, tol not in (0,1),
+                              h not finite or <= 0, null pointer, count < 1)        */
+  BHX_ERR_SINGULAR = -2,   /* no known node and no Dirichlet axis: the system is
+                              singular (constants are in the null space)           */
+  BHX_ERR_NONFINITE = -3,  /* a known value inside the stencil reach of an unknown
+                              node is NaN or infinite (the right-hand side is not
+                              finite)                                              */
+  BHX_ERR_NOMEM = -4,      /* device or pinned host allocation failed              */
+  BHX_ERR_HIP = -5,        /* a HIP runtime call failed                            */
+  BHX_BUSY = -6,           /* engine: the request does not fit right now           */
+  BHX_ERR_BREAKDOWN = -7   /* the iteration produced a non-finite or non-positive
+                              curvature (should not happen for valid input); F holds
+                              the last finite iterate                              */
+};
+
+/* Precision of the preconditioner (transforms and spectral scaling). */
+enum {
+  BHX_PREC_FP64 = 0,       /* everything float64, standard PCG                     */
+  BHX_PREC_FP32 = 1        /* transforms and scaling in float32, stencil, dots and
+                              recurrences in float64; flexible (Polak-Ribiere) PCG */
+};
+
+typedef struct {
+  int precision;    /* BHX_PREC_FP64 or BHX_PREC_FP32                              */
+  int maxit;        /* iteration limit; 0 -> 50 * max(nx, ny)                       */
+  int precond;      /* 1 = spectral fast Poisson preconditioner, 0 = none (plain CG) */
+  int accurate;     /* 1 = outer defect correction: inner solves to tol_inner
+                         relative to a compensated true residual until the true
+                         residual meets tol                                         */
+  double tol_inner; /* inner tolerance for accurate mode; 0 -> 1e-8                 */
+  int flexible;     /* -1 = default (flexible iff precision is FP32), 0 = standard
+                         beta = r.z / r_old.z_old, 1 = Polak-Ribiere beta           */
+  int chunk;        /* iterations per captured graph between convergence checks;
+                         0 -> 32                                                     */
+} bhx_opts;
+
+typedef struct {
+  int status;              /* per-instance status code (see above)                 */
+  int iterations;          /* conjugate-gradient iterations (matrix-vector products) */
+  int restarts;            /* number of true-residual restarts                       */
+  int n_unknown;           /* |U|                                                    */
+  double rel_residual;     /* recursive ||r|| / ||b|| at exit                         */
+  double true_rel_residual;/* compensated ||b - A_UU x|| / ||b|| at exit             */
+  double seconds;          /* host wall time of the call that produced this record   */
+} bhx_stats;
+
+typedef struct bhx_handle bhx_handle;
+typedef struct bhx_engine bhx_engine;
+
+/* Fill *o with defaults (FP64, spectral, maxit 0, chunk 0, flexible -1). */
+void bhx_default_opts(bhx_opts* o);
+
+/* Create / destroy a handle bound to HIP device `device`.  The handle owns
+ * transform tables, a growable device workspace and captured graphs.
+ * Returns BHX_OK, BHX_ERR_ARG (null out / bad device) or BHX_ERR_HIP. */
+int bhx_create(bhx_handle** out, int device);
+void bhx_destroy(bhx_handle* h);
+
+/* Single extension with the library's default handle on device 0, the null
+ * stream and default options (FP64 PCG).  Blocks until done.  `bc` is
+ * BHX_BC(bx, by).  Returns a status code. */
+int bhx_extend(const double* phi, double* F, int nx, int ny, double h, int bc, double tol);
+
+/* Single extension with explicit handle, options (NULL -> defaults), stream
+ * (a hipStream_t passed as void*, NULL -> null stream) and stats (may be
+ * NULL). */
+int bhx_extend_ex(bhx_handle* hd, const double* phi, double* F, int nx, int ny, double h,
+                  int bc, double tol, const bhx_opts* o, void* stream, bhx_stats* out);
+
+/* `count` independent extensions of mixed sizes and boundary rules solved
+ * together: each pass of every iteration is one launch over the tiles of all
+ * unfinished instances; instances retire independently.  phi, F are host
+ * arrays of `count` device pointers; nx, ny, h, bc, tol are host arrays of
+ * `count` values; out (may be NULL) receives `count` records.  Returns
+ * BHX_OK if every instance converged, the first negative per-instance code
+ * if any instance failed, else BHX_NOT_CONVERGED.  Argument errors in any
+ * instance reject the whole call before any GPU work. */
+int bhx_extend_batched(bhx_handle* hd, int count, const double* const* phi, double* const* F,
+                       const int* nx, const int* ny, const double* h, const int* bc,
+                       const double* tol, const bhx_opts* o, void* stream, bhx_stats* out);
+
+/* Device bytes the library needs for one instance (workspace vectors, mask,
+ * partial sums, control block), excluding phi and F.  Host-only; 0 for
+ * invalid arguments. */
+size_t bhx_workspace_bytes(int nx, int ny, int bc, const bhx_opts* o);
+
+/* ---- Serving engine: continuous batching of requests --------------------
+ * The engine owns a worker thread and a stream on `device`.  Requests are
+ * admitted while their workspace fits in `hbm_budget` bytes and a slot is
+ * free (at most `max_slots` in flight); admitted requests join the running
+ * batch at the next iteration-chunk boundary, so their work overlaps with
+ * requests already on the device.  phi and F stay owned by the caller and
+ * must stay valid until the request completes. */
+int bhx_engine_create(bhx_engine** e, int device, size_t hbm_budget, int max_slots,
+                      const bhx_opts* o);
+/* Non-blocking.  Returns BHX_OK and the request id, BHX_BUSY if the request
+ * cannot be admitted now (budget or slots; retry later), BHX_ERR_ARG for
+ * invalid arguments or a request that could never fit the budget. */
+int bhx_engine_submit(bhx_engine* e, const double* phi, double* F, int nx, int ny, double h,
+                      int bc, double tol, uint64_t* id);
+/* Collect up to `max` finished requests: ids[i], st[i]; *n_done receives the
+ * count.  Non-blocking. */
+int bhx_engine_poll(bhx_engine* e, uint64_t* ids, bhx_stats* st, int max, int* n_done);
+/* Number of requests admitted and not yet collected by poll. */
+int bhx_engine_inflight(bhx_engine* e);
+/* Stops the worker after in-flight requests finish and frees everything. */
+void bhx_engine_destroy(bhx_engine* e);
+
+/* Diagnostic: apply one operator of the iteration to a device vector `in`
+ * (float64, nx*ny) with the known set taken from phi (phi < 0):
+ *   op 0: out = R A R^T in - the masked 13-point operator of eq. (12):
+ *         values of `in` at known nodes are treated as 0, and out is 0 there;
+ *   op 1: out = the fast Poisson preconditioner of Algorithm 1 applied to
+ *         `in` restricted to the unknown nodes (embed with zeros at K,
+ *         transform, divide by (lambda_x + lambda_y)^2 with 0 for a zero
+ *         eigenvalue, transform back, restrict), in the given precision.
+ * Synchronises with the stream.  Returns a status code. */
+int bhx_debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, double* out,
+                    int nx, int ny, int bc, int precision, void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* bhx_status_string(int status);
+
+/* Library version string (static storage). */
+const char* bhx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BHX_H */

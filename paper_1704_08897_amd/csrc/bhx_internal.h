@@ -1,0 +1,136 @@
+// Internal layout shared by the HIP kernels and the host driver.
+//
+// Every solve is a batch of instances.  Each instance has a descriptor in
+// device memory (Inst) and a control block (Ctl).  Each pass of the
+// conjugate-gradient iteration is one launch over a flat list of work items
+// (instance, local item) covering all instances of the batch; a persistent
+// grid loops over the list, and items of finished instances return at once.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bhx {
+
+constexpr int kThreads = 256;          // threads per workgroup, every kernel
+constexpr int kTileX = 64;             // stencil tile (nodes)
+constexpr int kTileY = 16;
+constexpr int kLdsBytes = 64 * 1024;   // dynamic LDS of each transform kernel
+constexpr int kMaxPairs = 12;          // (k, n-k) pairs held in registers per thread
+
+enum Bc { kNeumann = 0, kPeriodic = 1, kDirichlet = 2 };
+enum Pass { kPassS = 0, kPassR = 1, kPassC = 2, kNumPass = 3 };
+
+// Stencil kernel modes.
+enum SMode {
+  kModeRhs = 0,     // r = -(A f_K) at U, f_K = F at K and 0 at U; partial ||r||^2
+  kModeIter = 1,    // p = z + beta p; q = A p at U; partial p.q; convergence test
+  kModeResid = 2,   // r = -(A F) at U in double-double (true residual); partial ||r||^2
+  kModeApply = 3,   // q = A (z at U, 0 at K) at U (diagnostic operator application)
+};
+
+// Done codes in Ctl::done.
+enum Done { kRunning = 0, kConverged = 1, kMaxIt = 2, kBreakdown = 3, kSkip = 4 };
+
+// One 1-D transform: length n, boundary rule, FFT core of length m.
+struct AxisPlan {
+  int n;
+  int bc;          // Bc
+  int m;           // power-of-two core length (== n, or >= 2n-1 for Bluestein)
+  int logm;
+  int bluestein;   // 0: direct radix-4/2 core; 1: chirp-z through length m
+  int off_tw;      // W_m^k = exp(-2 pi i k / m), k < m/2        (complex table)
+  int off_chirp;   // exp(-i pi k^2 / n), k < n                  (complex table)
+  int off_bhat;    // FFT_m(conj chirp, wrapped) / m, length m   (complex table)
+  int off_post;    // DCT: exp(-i pi k / (2n)), k < n; Dirichlet: unused
+  int off_lam;     // eigenvalues lambda_k of T, k < n           (real table)
+};
+
+struct Ctl {
+  int iter;           // completed iterations (matrix-vector products)
+  int done;           // Done
+  int restart_iter;   // iteration at which beta restarts from 0
+  int restarts;
+  double bb;          // ||b||^2 (of the current restart's right-hand side)
+  double bb0;         // ||b||^2 of the original system
+  double rr;          // last recursive ||r||^2 (written when done)
+  double true_rr;     // compensated true ||r||^2 (finalize)
+  double thresh;      // stop when the recursive ||r||^2 <= thresh
+  double accept;      // accept when the true ||r||^2 <= accept (= tol^2 bb0)
+  double tol_inner2;  // accurate mode: thresh = tol_inner^2 * (restart ||r||^2)
+  double tol2;        // tol^2
+  double n_unknown;
+  int accurate;
+  int max_restarts;
+  double pad[2];
+};
+
+struct Inst {
+  int nx, ny;
+  int bcx, bcy;
+  int planx, plany;     // AxisPlan indices
+  int G;                // rows per item in the row passes (even)
+  int Gc;               // columns per item in the column pass (even)
+  int tiles_x, tiles_y; // stencil tiles
+  int n_items[kNumPass];
+  int maxit;
+  int flexible;
+  int pad0;
+  const double* phi;
+  double* F;
+  uint8_t* mask;        // 1 = unknown, 0 = known
+  double* r;
+  double* p[2];         // search direction, double-buffered by iteration parity
+  double* q;
+  double* z;
+  void* t;              // transform buffer, [nx][ny] (y fastest), double or float
+  double* part;         // partial sums, see PartLayout
+  Ctl* ctl;
+};
+
+// Offsets (in doubles) of the partial-sum arrays inside Inst::part.
+struct PartLayout {
+  int nS, nR;
+  __host__ __device__ PartLayout(int s, int r) : nS(s), nR(r) {}
+  __host__ __device__ int pq() const { return 0; }                  // [nS]
+  __host__ __device__ int aux() const { return nS; }                // [nS]  counts U / ||r||^2
+  __host__ __device__ int aux2() const { return 2 * nS; }           // [nS]  counts K
+  __host__ __device__ int rr() const { return 3 * nS; }             // [nR]
+  __host__ __device__ int rz(int par) const { return 3 * nS + nR + par * nR; }    // 2 x [nR]
+  __host__ __device__ int rzo(int par) const { return 3 * nS + 3 * nR + par * nR; } // 2 x [nR]
+  __host__ __device__ int total() const { return 3 * nS + 5 * nR; }
+};
+
+// Flat work list of one pass: items[i] = (instance << 20) | local item.
+constexpr int kItemShift = 20;
+constexpr int kItemMask = (1 << kItemShift) - 1;
+
+// Batch header, resident in device memory; kernels read it at run time so a
+// captured graph stays valid while the batch's contents change.
+struct Batch {
+  int count;                 // instances
+  int n_items[kNumPass];     // total items per pass
+  const Inst* inst;          // [count]
+  const int* items[kNumPass];
+  const AxisPlan* plans;
+  const void* ctab[2];       // complex tables: [0] double2, [1] float2 (same layout)
+  const void* rtab[2];       // real tables (eigenvalues): [0] double, [1] float
+};
+
+}  // namespace bhx
+
+// Launch wrappers (defined with the kernels).
+namespace bhx {
+enum FinModeHost { kFinSetupH = 0, kFinResidH = 1 };
+hipError_t launch_setup(const Batch* B, int grid, hipStream_t st);
+hipError_t launch_stencil(const Batch* B, int mode, int grid, hipStream_t st);
+hipError_t launch_resid(const Batch* B, int grid, hipStream_t st);
+hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, hipStream_t st);
+hipError_t launch_col(const Batch* B, int prec, int count_iter, int grid, hipStream_t st);
+hipError_t launch_rowinv(const Batch* B, int prec, int grid, hipStream_t st);
+hipError_t launch_identity(const Batch* B, int grid, hipStream_t st);
+hipError_t launch_finalize(const Batch* B, int count, int mode, hipStream_t st);
+hipError_t launch_restart(const Batch* B, int count, hipStream_t st);
+hipError_t launch_bump(const Batch* B, int count, hipStream_t st);
+hipError_t launch_zero_unknown(const Batch* B, const int* flag, int grid, hipStream_t st);
+hipError_t set_kernel_attributes();
+}  // namespace bhx

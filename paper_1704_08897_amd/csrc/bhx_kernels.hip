@@ -1,0 +1,1101 @@
+// HIP kernels of the biharmonic-extension PCG (gfx950).
+//
+// One PCG iteration is four launches, each over the work items of every
+// unfinished instance of a batch:
+//   S  (k_stencil, mode iter): p = z + beta p; q = A p at unknown nodes; p.q
+//   R  (k_rowfwd, update):     alpha = r.z / p.q; x += alpha p; r -= alpha q;
+//                              ||r||^2; forward transform of r along x,
+//                              written transposed ([nx][ny], y fastest)
+//   C  (k_col):                forward transform along y, divide by
+//                              (lambda_x + lambda_y)^2, inverse along y
+//   RI (k_rowinv):             inverse transform along x, restrict to the
+//                              unknown nodes -> z; r.z (and r.z_old)
+// The method is Sec. 2.2 and Algorithm 1 of the paper: the 13-point stencil
+// of eq. (12) evaluated on demand as the 5-point Laplacian applied twice over
+// two ghost layers, and the fast Poisson preconditioner (embed, transform,
+// scale by the inverse squared eigenvalues, transform back, restrict).
+//
+// Transforms: Neumann axes use the orthonormal DCT-II (inverse DCT-III)
+// through a complex FFT of the same length (Makhoul's even/odd reordering);
+// periodic axes use the orthonormal discrete Hartley transform, a real
+// eigenbasis of the symmetric circulant second difference.  Two real rows are
+// packed into one complex row.  The complex FFT runs in LDS: radix-4/2
+// decimation in time on bit-reversed input for power-of-two lengths, and
+// Bluestein's chirp-z (through a power-of-two length m >= 2n-1) otherwise.
+//
+// Scalars never cross blocks inside a kernel: a producer writes one partial
+// sum per work item; every consumer item reduces the partial array itself in
+// a fixed order, so each block computes bit-identical alpha/beta and the
+// result does not depend on scheduling or on the batch composition.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bhx_internal.h"
+
+namespace bhx {
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+
+template <typename R> struct V2;
+template <> struct V2<double> { using T = double2; };
+template <> struct V2<float> { using T = float2; };
+
+template <typename C> __device__ __forceinline__ C mk(decltype(C::x) a, decltype(C::x) b) {
+  C c; c.x = a; c.y = b; return c;
+}
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename C> __device__ __forceinline__ C cconj(C a) { return mk<C>(a.x, -a.y); }
+// a * (-i)
+template <typename C> __device__ __forceinline__ C cmul_mi(C a) { return mk<C>(a.y, -a.x); }
+// a * (+i)
+template <typename C> __device__ __forceinline__ C cmul_pi(C a) { return mk<C>(-a.y, a.x); }
+
+__device__ __forceinline__ int bitrev(int k, int logm) {
+  return (int)(__brev((unsigned)k) >> (32 - logm));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of a[0..n) by the whole block in a fixed order; every thread gets it.
+__device__ double block_sum_array(const double* __restrict__ a, int n, double* red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) s += a[i];
+  s = wave_sum(s);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = s;
+  __syncthreads();
+  double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
+// Block reduction of one value per thread; result valid in every thread.
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
+// Ghost-node rule of one axis: global index g in [-2, n+1] -> stored index,
+// with sign s (Dirichlet odd reflection of Algorithm 1: g[-1] = 0,
+// g[-2] = -f[0]); Neumann half-sample even reflection; periodic wrap.
+__device__ __forceinline__ int map_axis(int g, int n, int bc, double& s) {
+  s = 1.0;
+  if (g >= 0 && g < n) return g;
+  if (bc == kNeumann) return g < 0 ? -g - 1 : 2 * n - 1 - g;
+  if (bc == kPeriodic) return g < 0 ? g + n : g - n;
+  if (g == -1 || g == n) { s = 0.0; return 0; }
+  s = -1.0;
+  return g < 0 ? 0 : n - 1;
+}
+
+// Persistent-grid item loop with an XCD-aware block order: consecutive
+// logical blocks (neighbouring tiles / row groups) land on the same XCD,
+// whose L2 then serves their shared halo rows.
+__device__ __forceinline__ int logical_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  if (nb % 8 != 0) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// Transform plan access
+// ---------------------------------------------------------------------------
+
+template <typename R>
+struct XPlan {
+  using C = typename V2<R>::T;
+  int n, m, logm, blue, bc;
+  const C* tw;
+  const C* chirp;
+  const C* bhat;
+  const C* post;
+  const R* lam;
+  __device__ XPlan(const Batch& B, int idx) {
+    const AxisPlan& P = B.plans[idx];
+    n = P.n; m = P.m; logm = P.logm; blue = P.bluestein; bc = P.bc;
+    const int pi = sizeof(R) == 8 ? 0 : 1;
+    const C* ct = (const C*)B.ctab[pi];
+    tw = ct + P.off_tw;
+    chirp = ct + P.off_chirp;
+    bhat = ct + P.off_bhat;
+    post = ct + P.off_post;
+    lam = (const R*)B.rtab[pi] + P.off_lam;
+  }
+  // LDS position of logical FFT input k
+  __device__ __forceinline__ int pos(int k) const { return bitrev(k, logm); }
+  // logical FFT output k of a row (after core())
+  __device__ __forceinline__ C out(const C* row, int k) const {
+    if (!blue) return row[k];
+    return cmul(chirp[k], row[bitrev(k, logm)]);
+  }
+};
+
+// In-place radix-4/2 DIT FFT of `rows` rows (stride `st`) of length m held in
+// LDS in bit-reversed order; natural-order output; sign -1.
+template <typename R>
+__device__ void fft_dit(typename V2<R>::T* buf, int rows, int st, int m, int logm,
+                        const typename V2<R>::T* __restrict__ tw) {
+  using C = typename V2<R>::T;
+  const int tid = threadIdx.x;
+  int h = 1, lh = 0;
+  if (logm & 1) {
+    const int half = m >> 1;
+    for (int idx = tid; idx < rows * half; idx += kThreads) {
+      const int r = idx >> (logm - 1), b = (idx & (half - 1)) << 1;
+      C* a = buf + r * st + b;
+      C u = a[0], v = a[1];
+      a[0] = cadd(u, v);
+      a[1] = csub(u, v);
+    }
+    __syncthreads();
+    h = 2; lh = 1;
+  }
+  const int lq = logm - 2;
+  for (; h < m; h <<= 2, lh += 2) {
+    const int quarter = m >> 2;
+    const int ls1 = logm - 1 - lh, ls2 = logm - 2 - lh;   // table strides m/(2h), m/(4h)
+    for (int idx = tid; idx < rows * quarter; idx += kThreads) {
+      const int r = idx >> lq, rem = idx & (quarter - 1);
+      const int k = rem & (h - 1);
+      const int b = (rem - k) << 2;
+      C* a = buf + r * st + b + k;
+      const C w1 = tw[k << ls1];
+      const C w2 = tw[k << ls2];
+      C a0 = a[0], a1 = a[h], a2 = a[2 * h], a3 = a[3 * h];
+      C t = cmul(w1, a1);
+      C t0 = cadd(a0, t), t1 = csub(a0, t);
+      t = cmul(w1, a3);
+      C t2 = cadd(a2, t), t3 = csub(a2, t);
+      t = cmul(w2, t2);
+      a[0] = cadd(t0, t);
+      a[2 * h] = csub(t0, t);
+      t = cmul_mi(cmul(w2, t3));          // W_4h^(k+h) = W_4h^k * (-i)
+      a[h] = cadd(t1, t);
+      a[3 * h] = csub(t1, t);
+    }
+    __syncthreads();
+  }
+}
+
+// In-place radix-4/2 DIF FFT, natural-order input, bit-reversed output,
+// sign +1, unnormalised (inverse of fft_dit up to the factor m).
+template <typename R>
+__device__ void fft_dif_inv(typename V2<R>::T* buf, int rows, int st, int m, int logm,
+                            const typename V2<R>::T* __restrict__ tw) {
+  using C = typename V2<R>::T;
+  const int tid = threadIdx.x;
+  const int lq = logm - 2;
+  int lh = logm - 2;
+  for (int h = m >> 2; h >= 1; h >>= 2, lh -= 2) {
+    const int quarter = m >> 2;
+    const int ls1 = logm - 1 - lh, ls2 = logm - 2 - lh;
+    for (int idx = tid; idx < rows * quarter; idx += kThreads) {
+      const int r = idx >> lq, rem = idx & (quarter - 1);
+      const int k = rem & (h - 1);
+      const int b = (rem - k) << 2;
+      C* a = buf + r * st + b + k;
+      const C w1 = cconj(tw[k << ls1]);
+      const C w2 = cconj(tw[k << ls2]);
+      C a0 = a[0], a1 = a[h], a2 = a[2 * h], a3 = a[3 * h];
+      C t0 = cadd(a0, a2), t2 = cmul(csub(a0, a2), w2);
+      C t1 = cadd(a1, a3), t3 = cmul_pi(cmul(csub(a1, a3), w2));   // conj(W_4h^(k+h))
+      a[0] = cadd(t0, t1);
+      a[h] = cmul(csub(t0, t1), w1);
+      a[2 * h] = cadd(t2, t3);
+      a[3 * h] = cmul(csub(t2, t3), w1);
+    }
+    __syncthreads();
+    if (h == 1) break;
+  }
+  if (logm & 1) {
+    const int half = m >> 1;
+    for (int idx = tid; idx < rows * half; idx += kThreads) {
+      const int r = idx >> (logm - 1), b = (idx & (half - 1)) << 1;
+      C* a = buf + r * st + b;
+      C u = a[0], v = a[1];
+      a[0] = cadd(u, v);
+      a[1] = csub(u, v);
+    }
+    __syncthreads();
+  }
+}
+
+// After inputs are placed at pos(k) (k < n): Bluestein multiplies by the
+// chirp and zero-fills k in [n, m); then the core forward DFT of length n.
+template <typename R>
+__device__ void dft_core(const XPlan<R>& X, typename V2<R>::T* buf, int rows) {
+  using C = typename V2<R>::T;
+  const int st = X.m;
+  if (X.blue) {
+    for (int idx = threadIdx.x; idx < rows * X.m; idx += kThreads) {
+      const int r = idx >> X.logm, k = idx & (X.m - 1);
+      C* row = buf + r * st;
+      const int p = bitrev(k, X.logm);
+      if (k < X.n) row[p] = cmul(row[p], X.chirp[k]);
+      else row[p] = mk<C>(0, 0);
+    }
+    __syncthreads();
+  }
+  fft_dit<R>(buf, rows, st, X.m, X.logm, X.tw);
+  if (X.blue) {
+    for (int idx = threadIdx.x; idx < rows * X.m; idx += kThreads) {
+      const int r = idx >> X.logm, k = idx & (X.m - 1);
+      buf[r * st + k] = cmul(buf[r * st + k], X.bhat[k]);
+    }
+    __syncthreads();
+    fft_dif_inv<R>(buf, rows, st, X.m, X.logm, X.tw);
+  }
+}
+
+// Logical FFT input index of spatial sample i for the forward transform:
+// DCT-II reorders evens ascending then odds descending (Makhoul); the
+// Hartley transform takes the samples in order.
+__device__ __forceinline__ int fwd_index(int i, int n, int bc) {
+  if (bc != kNeumann) return i;
+  return (i & 1) ? n - 1 - (i >> 1) : (i >> 1);
+}
+// Position in the inverse DCT's FFT output holding spatial sample j.
+__device__ __forceinline__ int inv_index(int j, int n) {
+  return (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
+}
+
+// Forward real spectra of the two rows packed in one complex FFT output, at
+// the pair (k, kk = (n - k) mod n).  C = out(k), D = out(kk).
+//   DCT-II (orthonormal): V_a = (C + conj D)/2, V_b = (C - conj D)/(2i),
+//     X[k] = s_k Re(exp(-i pi k/2n) V[k]), s_0 = sqrt(1/n), s_k = sqrt(2/n).
+//   Hartley (orthonormal): H_a = (Cr + Dr - Ci + Di) / (2 sqrt n),
+//                          H_b = (Ci + Di + Cr - Dr) / (2 sqrt n).
+template <typename R>
+__device__ __forceinline__ void fwd_post_pair(const XPlan<R>& X, typename V2<R>::T Ck,
+                                              typename V2<R>::T Dk, int k, int kk, R& xa_k,
+                                              R& xb_k, R& xa_kk, R& xb_kk) {
+  using C = typename V2<R>::T;
+  const R n = (R)X.n;
+  if (X.bc == kNeumann) {
+    const C va = mk<C>((Ck.x + Dk.x) * (R)0.5, (Ck.y - Dk.y) * (R)0.5);
+    // (C - conj D)/(2i) = ((Ci + Di) - i (Cr - Dr)) / 2
+    const C vb = mk<C>((Ck.y + Dk.y) * (R)0.5, -(Ck.x - Dk.x) * (R)0.5);
+    const R s0 = sqrt((R)1 / n), s1 = sqrt((R)2 / n);
+    const C tk = X.post[k];
+    xa_k = (k == 0 ? s0 : s1) * (tk.x * va.x - tk.y * va.y);
+    xb_k = (k == 0 ? s0 : s1) * (tk.x * vb.x - tk.y * vb.y);
+    // V[kk] = conj(V[k])
+    const C tkk = X.post[kk];
+    xa_kk = (kk == 0 ? s0 : s1) * (tkk.x * va.x + tkk.y * va.y);
+    xb_kk = (kk == 0 ? s0 : s1) * (tkk.x * vb.x + tkk.y * vb.y);
+  } else {
+    const R sc = (R)0.5 / sqrt(n);
+    xa_k = (Ck.x + Dk.x - Ck.y + Dk.y) * sc;
+    xb_k = (Ck.y + Dk.y + Ck.x - Dk.x) * sc;
+    xa_kk = (Dk.x + Ck.x - Dk.y + Ck.y) * sc;
+    xb_kk = (Dk.y + Ck.y + Dk.x - Ck.x) * sc;
+  }
+}
+
+// Inverse-transform FFT inputs for the pair (k, kk) from the two rows' real
+// spectra.  DCT: W[k] = exp(i pi k/2n) (P[k] - i P[n-k]) with
+// P = g (Y_a + i Y_b), g_0 = 1/sqrt n, g_k = 1/sqrt(2n), P[n] = 0; the
+// unnormalised inverse DFT is taken as conj(DFT(conj W)), so conj(W) is
+// returned.  Hartley: the forward transform again, inputs Y_a + i Y_b.
+template <typename R>
+__device__ __forceinline__ void inv_pre_pair(const XPlan<R>& X, R ya_k, R yb_k, R ya_kk,
+                                             R yb_kk, int k, int kk, typename V2<R>::T& in_k,
+                                             typename V2<R>::T& in_kk) {
+  using C = typename V2<R>::T;
+  if (X.bc == kNeumann) {
+    const R n = (R)X.n;
+    const R g0 = (R)1 / sqrt(n), g1 = (R)1 / sqrt((R)2 * n);
+    const R gk = k == 0 ? g0 : g1, gkk = kk == 0 ? g0 : g1;
+    C Pk = mk<C>(gk * ya_k, gk * yb_k);
+    C Pkk = mk<C>(gkk * ya_kk, gkk * yb_kk);
+    if (k == 0) {
+      in_k = cconj(Pk);                    // W[0] = P[0]
+      in_kk = in_k;
+      return;
+    }
+    const C tk = cconj(X.post[k]);         // exp(+i pi k / 2n)
+    const C tkk = cconj(X.post[kk]);
+    const C Wk = cmul(tk, csub(Pk, cmul_pi(Pkk)));    // P[k] - i P[n-k]
+    const C Wkk = cmul(tkk, csub(Pkk, cmul_pi(Pk)));
+    in_k = cconj(Wk);
+    in_kk = cconj(Wkk);
+  } else {
+    in_k = mk<C>(ya_k, yb_k);
+    in_kk = mk<C>(ya_kk, yb_kk);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Setup: mask from the sign of phi; zero the workspace vectors; count |U|.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kThreads) k_setup(const Batch* __restrict__ Bp) {
+  const Batch& B = *Bp;
+  __shared__ double red[4];
+  for (int it = logical_block(); it < B.n_items[kPassS]; it += gridDim.x) {
+    const int code = B.items[kPassS][it];
+    const Inst& I = B.inst[code >> kItemShift];
+    const int tile = code & kItemMask;
+    if (I.ctl->done) continue;
+    const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
+    const int i0 = tx * kTileX, j0 = ty * kTileY;
+    double cnt = 0;
+    for (int e = threadIdx.x; e < kTileX * kTileY; e += kThreads) {
+      const int i = i0 + (e & (kTileX - 1)), j = j0 + e / kTileX;
+      if (i < I.nx && j < I.ny) {
+        const size_t o = (size_t)j * I.nx + i;
+        const uint8_t u = !(I.phi[o] < 0.0);
+        I.mask[o] = u;
+        cnt += u;
+        I.r[o] = 0.0;
+        I.p[0][o] = 0.0;
+        I.p[1][o] = 0.0;
+        I.q[o] = 0.0;
+        I.z[o] = 0.0;
+      }
+    }
+    cnt = block_sum(cnt, red);
+    if (threadIdx.x == 0) {
+      PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
+      I.part[PL.aux2() + tile] = cnt;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stencil pass: 13-point operator as L(L f) on an LDS tile with a two-node
+// halo whose ghost values follow each axis' rule.
+// ---------------------------------------------------------------------------
+
+constexpr int kPW = kTileX + 4, kPH = kTileY + 4;   // f tile with 2-node halo
+constexpr int kLW = kTileX + 2, kLH = kTileY + 2;   // L f with 1-node halo
+
+__global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ Bp, int mode) {
+  const Batch& B = *Bp;
+  __shared__ double P[kPH][kPW + 1];
+  __shared__ double L[kLH][kLW + 1];
+  __shared__ double red[4];
+  for (int it = logical_block(); it < B.n_items[kPassS]; it += gridDim.x) {
+    const int code = B.items[kPassS][it];
+    const Inst& I = B.inst[code >> kItemShift];
+    const int tile = code & kItemMask;
+    Ctl* ctl = I.ctl;
+    if (ctl->done) continue;
+    const int nx = I.nx, ny = I.ny;
+    const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
+    double beta = 0.0;
+    const double* pold = nullptr;
+    double* pnew = nullptr;
+    if (mode == kModeIter) {
+      const int k = ctl->iter;
+      const int par = k & 1;
+      const double rz = block_sum_array(I.part + PL.rz(par), PL.nR, red);
+      const bool first = (k == ctl->restart_iter);
+      if (!first) {
+        const double rr = block_sum_array(I.part + PL.rr(), PL.nR, red);
+        int d = kRunning;
+        if (!(rr <= ctl->thresh)) {
+          if (k >= I.maxit) d = kMaxIt;
+          else if (!(rr == rr) || rr > 1e300) d = kBreakdown;
+        } else {
+          d = kConverged;
+        }
+        if (d != kRunning) {
+          if (tile == 0 && threadIdx.x == 0) {
+            ctl->rr = rr;
+            ctl->done = d;
+          }
+          continue;
+        }
+        const double rzold = block_sum_array(I.part + PL.rz(par ^ 1), PL.nR, red);
+        if (I.flexible) {
+          const double rzo = block_sum_array(I.part + PL.rzo(par), PL.nR, red);
+          beta = (rz - rzo) / rzold;
+        } else {
+          beta = rz / rzold;
+        }
+      }
+      if (!(rz > 0.0) || !(beta == beta)) {
+        if (tile == 0 && threadIdx.x == 0) ctl->done = kBreakdown;
+        continue;
+      }
+      pold = first ? nullptr : I.p[k & 1];
+      pnew = I.p[(k + 1) & 1];
+    }
+    const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
+    const int i0 = tx * kTileX, j0 = ty * kTileY;
+    for (int e = threadIdx.x; e < kPH * kPW; e += kThreads) {
+      const int jj = e / kPW, ii = e - jj * kPW;
+      const int gi = i0 + ii - 2, gj = j0 + jj - 2;
+      double v = 0.0;
+      if (gi >= -2 && gi <= nx + 1 && gj >= -2 && gj <= ny + 1) {
+        double sx, sy;
+        const int mi = map_axis(gi, nx, I.bcx, sx);
+        const int mj = map_axis(gj, ny, I.bcy, sy);
+        const double s = sx * sy;
+        if (s != 0.0) {
+          const size_t o = (size_t)mj * nx + mi;
+          if (mode == kModeIter) {
+            v = I.z[o];
+            if (pold) v += beta * pold[o];
+          } else if (mode == kModeRhs) {
+            v = I.mask[o] ? 0.0 : I.F[o];
+          } else if (mode == kModeApply) {
+            v = I.mask[o] ? I.z[o] : 0.0;
+          } else {
+            v = I.F[o];
+          }
+          v *= s;
+        }
+      }
+      P[jj][ii] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kLH * kLW; e += kThreads) {
+      const int jj = e / kLW, ii = e - jj * kLW;
+      L[jj][ii] = 4.0 * P[jj + 1][ii + 1] - P[jj][ii + 1] - P[jj + 2][ii + 1] - P[jj + 1][ii] -
+                  P[jj + 1][ii + 2];
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < kTileX * kTileY; e += kThreads) {
+      const int jj = e / kTileX, ii = e - jj * kTileX;
+      const int gi = i0 + ii, gj = j0 + jj;
+      if (gi < nx && gj < ny) {
+        const size_t o = (size_t)gj * nx + gi;
+        if (I.mask[o]) {
+          const double qv = 4.0 * L[jj + 1][ii + 1] - L[jj][ii + 1] - L[jj + 2][ii + 1] -
+                            L[jj + 1][ii] - L[jj + 1][ii + 2];
+          if (mode == kModeIter) {
+            const double pv = P[jj + 2][ii + 2];
+            pnew[o] = pv;
+            I.q[o] = qv;
+            acc += pv * qv;
+          } else if (mode == kModeApply) {
+            I.q[o] = qv;
+          } else {
+            I.r[o] = -qv;
+            acc += qv * qv;
+          }
+        }
+      }
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) I.part[(mode == kModeIter ? PL.pq() : PL.aux()) + tile] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// True residual r = -(A F) at U with F = known values at K and the current
+// iterate at U, in double-double arithmetic (error-free transformations).
+// ---------------------------------------------------------------------------
+
+struct dd { double hi, lo; };
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ dd fast_two_sum(double a, double b) {
+  const double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ dd dd_x4(dd a) { return {4.0 * a.hi, 4.0 * a.lo}; }
+
+__device__ __forceinline__ dd five_point_dd(dd c, dd n, dd s, dd w, dd e) {
+  dd t = dd_add(dd_neg(n), dd_neg(s));
+  t = dd_add(t, dd_add(dd_neg(w), dd_neg(e)));
+  return dd_add(dd_x4(c), t);
+}
+
+__global__ void __launch_bounds__(kThreads) k_resid(const Batch* __restrict__ Bp) {
+  const Batch& B = *Bp;
+  __shared__ double P[kPH][kPW + 1];
+  __shared__ double Lh[kLH][kLW + 1];
+  __shared__ double Ll[kLH][kLW + 1];
+  __shared__ double red[4];
+  for (int it = logical_block(); it < B.n_items[kPassS]; it += gridDim.x) {
+    const int code = B.items[kPassS][it];
+    const Inst& I = B.inst[code >> kItemShift];
+    const int tile = code & kItemMask;
+    const int dn = I.ctl->done;
+    if (dn != kConverged && dn != kMaxIt) continue;
+    const int nx = I.nx, ny = I.ny;
+    const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
+    const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
+    const int i0 = tx * kTileX, j0 = ty * kTileY;
+    for (int e = threadIdx.x; e < kPH * kPW; e += kThreads) {
+      const int jj = e / kPW, ii = e - jj * kPW;
+      const int gi = i0 + ii - 2, gj = j0 + jj - 2;
+      double v = 0.0;
+      if (gi >= -2 && gi <= nx + 1 && gj >= -2 && gj <= ny + 1) {
+        double sx, sy;
+        const int mi = map_axis(gi, nx, I.bcx, sx);
+        const int mj = map_axis(gj, ny, I.bcy, sy);
+        const double s = sx * sy;
+        if (s != 0.0) v = s * I.F[(size_t)mj * nx + mi];
+      }
+      P[jj][ii] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kLH * kLW; e += kThreads) {
+      const int jj = e / kLW, ii = e - jj * kLW;
+      const dd l = five_point_dd({P[jj + 1][ii + 1], 0.0}, {P[jj][ii + 1], 0.0},
+                                 {P[jj + 2][ii + 1], 0.0}, {P[jj + 1][ii], 0.0},
+                                 {P[jj + 1][ii + 2], 0.0});
+      Lh[jj][ii] = l.hi;
+      Ll[jj][ii] = l.lo;
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < kTileX * kTileY; e += kThreads) {
+      const int jj = e / kTileX, ii = e - jj * kTileX;
+      const int gi = i0 + ii, gj = j0 + jj;
+      if (gi < nx && gj < ny) {
+        const size_t o = (size_t)gj * nx + gi;
+        if (I.mask[o]) {
+          const dd q = five_point_dd({Lh[jj + 1][ii + 1], Ll[jj + 1][ii + 1]},
+                                     {Lh[jj][ii + 1], Ll[jj][ii + 1]},
+                                     {Lh[jj + 2][ii + 1], Ll[jj + 2][ii + 1]},
+                                     {Lh[jj + 1][ii], Ll[jj + 1][ii]},
+                                     {Lh[jj + 1][ii + 2], Ll[jj + 1][ii + 2]});
+          const double rv = -(q.hi + q.lo);
+          I.r[o] = rv;
+          acc += rv * rv;
+        }
+      }
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) I.part[PL.aux() + tile] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row pass, forward: optional CG update, then forward transform of r along x
+// for G rows, written transposed to t[k * ny + j].
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ Bp, int update) {
+  using C = typename V2<R>::T;
+  const Batch& B = *Bp;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* buf = (C*)smem;
+  R* stg = (R*)smem;
+  __shared__ double red[4];
+  for (int itm = logical_block(); itm < B.n_items[kPassR]; itm += gridDim.x) {
+    const int code = B.items[kPassR][itm];
+    const Inst& I = B.inst[code >> kItemShift];
+    const int g = code & kItemMask;
+    Ctl* ctl = I.ctl;
+    if (ctl->done) continue;
+    const int nx = I.nx, ny = I.ny, G = I.G, j0 = g * G;
+    const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
+    const int k_it = ctl->iter;
+    double alpha = 0.0;
+    const double* pcur = nullptr;
+    if (update) {
+      const double rz = block_sum_array(I.part + PL.rz(k_it & 1), PL.nR, red);
+      const double pq = block_sum_array(I.part + PL.pq(), PL.nS, red);
+      alpha = rz / pq;
+      pcur = I.p[(k_it + 1) & 1];
+    }
+    const XPlan<R> X(B, I.planx);
+    const int rows = G >> 1;
+    const int st = X.m;
+    double acc = 0.0;
+    // 1. update and place r into the packed rows
+    for (int e = threadIdx.x; e < G * nx; e += kThreads) {
+      const int jr = e / nx, i = e - jr * nx;
+      const int j = j0 + jr;
+      double rv = 0.0;
+      if (j < ny) {
+        const size_t o = (size_t)j * nx + i;
+        if (I.mask[o]) {
+          rv = I.r[o];
+          if (update) {
+            const double pv = pcur[o];
+            const double xv = (k_it == 0 ? 0.0 : I.F[o]) + alpha * pv;
+            I.F[o] = xv;
+            rv -= alpha * I.q[o];
+            I.r[o] = rv;
+            acc += rv * rv;
+          }
+        }
+      }
+      R* cell = (R*)(buf + (jr >> 1) * st + X.pos(fwd_index(i, nx, X.bc)));
+      cell[jr & 1] = (R)rv;
+    }
+    __syncthreads();
+    if (update) {
+      acc = block_sum(acc, red);
+      if (threadIdx.x == 0) I.part[PL.rr() + g] = acc;
+      if (update == 2) continue;       // plain CG: update only
+    }
+    // 2. FFT
+    dft_core<R>(X, buf, rows);
+    // 3. real spectra of the pairs (k, n-k) into registers
+    const int np = (nx >> 1) + 1;
+    R va[kMaxPairs][4];
+#pragma unroll
+    for (int s = 0; s < kMaxPairs; ++s) {
+      const int pidx = threadIdx.x + s * kThreads;
+      if (pidx < rows * np) {
+        const int rr = pidx / np, k = pidx - rr * np;
+        const int kk = k == 0 ? 0 : nx - k;
+        const C* row = buf + rr * st;
+        fwd_post_pair<R>(X, X.out(row, k), X.out(row, kk), k, kk, va[s][0], va[s][1],
+                         va[s][2], va[s][3]);
+      }
+    }
+    __syncthreads();
+    // 4. stage transposed in LDS: stg[k * G + jr]
+#pragma unroll
+    for (int s = 0; s < kMaxPairs; ++s) {
+      const int pidx = threadIdx.x + s * kThreads;
+      if (pidx < rows * np) {
+        const int rr = pidx / np, k = pidx - rr * np;
+        const int kk = k == 0 ? 0 : nx - k;
+        stg[k * G + 2 * rr] = va[s][0];
+        stg[k * G + 2 * rr + 1] = va[s][1];
+        if (kk != k) {
+          stg[kk * G + 2 * rr] = va[s][2];
+          stg[kk * G + 2 * rr + 1] = va[s][3];
+        }
+      }
+    }
+    __syncthreads();
+    // 5. coalesced transposed store
+    R* t = (R*)I.t;
+    for (int e = threadIdx.x; e < nx * G; e += kThreads) {
+      const int k = e / G, jr = e - k * G;
+      const int j = j0 + jr;
+      if (j < ny) t[(size_t)k * ny + j] = stg[e];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass: forward transform along y, scale, inverse transform along y,
+// in place on rows kx of t (length ny).
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, int count_iter) {
+  using C = typename V2<R>::T;
+  const Batch& B = *Bp;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* buf = (C*)smem;
+  for (int itm = logical_block(); itm < B.n_items[kPassC]; itm += gridDim.x) {
+    const int code = B.items[kPassC][itm];
+    const Inst& I = B.inst[code >> kItemShift];
+    const int c = code & kItemMask;
+    Ctl* ctl = I.ctl;
+    if (ctl->done) continue;
+    const int nx = I.nx, ny = I.ny, Gc = I.Gc, kx0 = c * Gc;
+    const XPlan<R> X(B, I.plany);
+    const XPlan<R> Xx(B, I.planx);
+    const int rows = Gc >> 1;
+    const int st = X.m;
+    R* t = (R*)I.t;
+    // 1. load and place
+    for (int e = threadIdx.x; e < Gc * ny; e += kThreads) {
+      const int cr = e / ny, j = e - cr * ny;
+      const int kx = kx0 + cr;
+      const R v = kx < nx ? t[(size_t)kx * ny + j] : (R)0;
+      R* cell = (R*)(buf + (cr >> 1) * st + X.pos(fwd_index(j, ny, X.bc)));
+      cell[cr & 1] = v;
+    }
+    __syncthreads();
+    dft_core<R>(X, buf, rows);
+    // 2. spectra, scale by 1/(lambda_x + lambda_y)^2, inverse inputs
+    const int np = (ny >> 1) + 1;
+    C vin[kMaxPairs][2];
+#pragma unroll
+    for (int s = 0; s < kMaxPairs; ++s) {
+      const int pidx = threadIdx.x + s * kThreads;
+      if (pidx < rows * np) {
+        const int rr = pidx / np, k = pidx - rr * np;
+        const int kk = k == 0 ? 0 : ny - k;
+        const C* row = buf + rr * st;
+        R xa, xb, xak, xbk;
+        fwd_post_pair<R>(X, X.out(row, k), X.out(row, kk), k, kk, xa, xb, xak, xbk);
+        const int kxa = kx0 + 2 * rr, kxb = kxa + 1;
+        const R la = kxa < nx ? Xx.lam[kxa] : (R)0;
+        const R lb = kxb < nx ? Xx.lam[kxb] : (R)0;
+        R s1 = la + X.lam[k], s2 = lb + X.lam[k], s3 = la + X.lam[kk], s4 = lb + X.lam[kk];
+        xa = s1 > (R)0 ? xa / (s1 * s1) : (R)0;
+        xb = s2 > (R)0 ? xb / (s2 * s2) : (R)0;
+        xak = s3 > (R)0 ? xak / (s3 * s3) : (R)0;
+        xbk = s4 > (R)0 ? xbk / (s4 * s4) : (R)0;
+        inv_pre_pair<R>(X, xa, xb, xak, xbk, k, kk, vin[s][0], vin[s][1]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kMaxPairs; ++s) {
+      const int pidx = threadIdx.x + s * kThreads;
+      if (pidx < rows * np) {
+        const int rr = pidx / np, k = pidx - rr * np;
+        const int kk = k == 0 ? 0 : ny - k;
+        C* row = buf + rr * st;
+        row[X.pos(k)] = vin[s][0];
+        if (kk != k) row[X.pos(kk)] = vin[s][1];
+      }
+    }
+    __syncthreads();
+    dft_core<R>(X, buf, rows);
+    // 3. inverse outputs back into t
+    if (X.bc == kNeumann) {
+      for (int e = threadIdx.x; e < Gc * ny; e += kThreads) {
+        const int cr = e / ny, j = e - cr * ny;
+        const int kx = kx0 + cr;
+        if (kx < nx) {
+          const C v = X.out(buf + (cr >> 1) * st, inv_index(j, ny));
+          t[(size_t)kx * ny + j] = (cr & 1) ? -v.y : v.x;
+        }
+      }
+    } else {
+      R vo[kMaxPairs][4];
+#pragma unroll
+      for (int s = 0; s < kMaxPairs; ++s) {
+        const int pidx = threadIdx.x + s * kThreads;
+        if (pidx < rows * np) {
+          const int rr = pidx / np, k = pidx - rr * np;
+          const int kk = k == 0 ? 0 : ny - k;
+          const C* row = buf + rr * st;
+          fwd_post_pair<R>(X, X.out(row, k), X.out(row, kk), k, kk, vo[s][0], vo[s][1],
+                           vo[s][2], vo[s][3]);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < kMaxPairs; ++s) {
+        const int pidx = threadIdx.x + s * kThreads;
+        if (pidx < rows * np) {
+          const int rr = pidx / np, k = pidx - rr * np;
+          const int kk = k == 0 ? 0 : ny - k;
+          const int kxa = kx0 + 2 * rr, kxb = kxa + 1;
+          if (kxa < nx) {
+            t[(size_t)kxa * ny + k] = vo[s][0];
+            if (kk != k) t[(size_t)kxa * ny + kk] = vo[s][2];
+          }
+          if (kxb < nx) {
+            t[(size_t)kxb * ny + k] = vo[s][1];
+            if (kk != k) t[(size_t)kxb * ny + kk] = vo[s][3];
+          }
+        }
+      }
+    }
+    if (count_iter && c == 0 && threadIdx.x == 0) ctl->iter = ctl->iter + 1;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row pass, inverse: read G rows of spectra transposed from t, inverse
+// transform along x, restrict to U -> z; partial r.z and r.z_old.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ Bp) {
+  using C = typename V2<R>::T;
+  const Batch& B = *Bp;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* buf = (C*)smem;
+  R* stg = (R*)smem;
+  __shared__ double red[4];
+  for (int itm = logical_block(); itm < B.n_items[kPassR]; itm += gridDim.x) {
+    const int code = B.items[kPassR][itm];
+    const Inst& I = B.inst[code >> kItemShift];
+    const int g = code & kItemMask;
+    Ctl* ctl = I.ctl;
+    if (ctl->done) continue;
+    const int nx = I.nx, ny = I.ny, G = I.G, j0 = g * G;
+    const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
+    const int par = ctl->iter & 1;
+    const XPlan<R> X(B, I.planx);
+    const int rows = G >> 1;
+    const int st = X.m;
+    const R* t = (const R*)I.t;
+    // 1. coalesced transposed load: stg[k * G + jr] = t[k * ny + j0 + jr]
+    for (int e = threadIdx.x; e < nx * G; e += kThreads) {
+      const int k = e / G, jr = e - k * G;
+      const int j = j0 + jr;
+      stg[e] = j < ny ? t[(size_t)k * ny + j] : (R)0;
+    }
+    __syncthreads();
+    // 2. inverse inputs of the pairs, through registers
+    const int np = (nx >> 1) + 1;
+    C vin[kMaxPairs][2];
+#pragma unroll
+    for (int s = 0; s < kMaxPairs; ++s) {
+      const int pidx = threadIdx.x + s * kThreads;
+      if (pidx < rows * np) {
+        const int rr = pidx / np, k = pidx - rr * np;
+        const int kk = k == 0 ? 0 : nx - k;
+        inv_pre_pair<R>(X, stg[k * G + 2 * rr], stg[k * G + 2 * rr + 1], stg[kk * G + 2 * rr],
+                        stg[kk * G + 2 * rr + 1], k, kk, vin[s][0], vin[s][1]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kMaxPairs; ++s) {
+      const int pidx = threadIdx.x + s * kThreads;
+      if (pidx < rows * np) {
+        const int rr = pidx / np, k = pidx - rr * np;
+        const int kk = k == 0 ? 0 : nx - k;
+        C* row = buf + rr * st;
+        row[X.pos(k)] = vin[s][0];
+        if (kk != k) row[X.pos(kk)] = vin[s][1];
+      }
+    }
+    __syncthreads();
+    dft_core<R>(X, buf, rows);
+    // 3. outputs: restrict, store z, dots
+    double acc = 0.0, acco = 0.0;
+    const bool flex = I.flexible != 0;
+    for (int e = threadIdx.x; e < G * nx; e += kThreads) {
+      const int jr = e / nx, i = e - jr * nx;
+      const int j = j0 + jr;
+      if (j >= ny) continue;
+      const size_t o = (size_t)j * nx + i;
+      if (!I.mask[o]) continue;
+      const C* row = buf + (jr >> 1) * st;
+      R v;
+      if (X.bc == kNeumann) {
+        const C c = X.out(row, inv_index(i, nx));
+        v = (jr & 1) ? -c.y : c.x;
+      } else {
+        const int ii = i == 0 ? 0 : nx - i;
+        R xa, xb, xak, xbk;
+        fwd_post_pair<R>(X, X.out(row, i), X.out(row, ii), i, ii, xa, xb, xak, xbk);
+        v = (jr & 1) ? xb : xa;
+      }
+      const double zv = (double)v;
+      const double rv = I.r[o];
+      if (flex) acco += rv * I.z[o];
+      I.z[o] = zv;
+      acc += rv * zv;
+    }
+    acc = block_sum(acc, red);
+    if (flex) acco = block_sum(acco, red);
+    if (threadIdx.x == 0) {
+      I.part[PL.rz(par) + g] = acc;
+      if (flex) I.part[PL.rzo(par) + g] = acco;
+    }
+  }
+}
+
+// Plain CG (no preconditioner): z = r at U; partial r.z (and r.z_old).
+__global__ void __launch_bounds__(kThreads) k_identity(const Batch* __restrict__ Bp) {
+  const Batch& B = *Bp;
+  __shared__ double red[4];
+  for (int itm = logical_block(); itm < B.n_items[kPassR]; itm += gridDim.x) {
+    const int code = B.items[kPassR][itm];
+    const Inst& I = B.inst[code >> kItemShift];
+    const int g = code & kItemMask;
+    Ctl* ctl = I.ctl;
+    if (ctl->done) continue;
+    const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
+    const int par = ctl->iter & 1;
+    const int nx = I.nx, ny = I.ny, j0 = g * I.G;
+    const int jn = min(I.G, ny - j0);
+    const bool flex = I.flexible != 0;
+    double acc = 0.0, acco = 0.0;
+    for (int e = threadIdx.x; e < jn * nx; e += kThreads) {
+      const size_t o = (size_t)j0 * nx + e;
+      if (!I.mask[o]) continue;
+      const double rv = I.r[o];
+      if (flex) acco += rv * I.z[o];
+      I.z[o] = rv;
+      acc += rv * rv;
+    }
+    acc = block_sum(acc, red);
+    if (flex) acco = block_sum(acco, red);
+    if (threadIdx.x == 0) {
+      I.part[PL.rz(par) + g] = acc;
+      if (flex) I.part[PL.rzo(par) + g] = acco;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-instance finalisation (one block per instance) and helpers.
+// ---------------------------------------------------------------------------
+
+enum FinMode { kFinSetup = 0, kFinResid = 1 };
+
+__global__ void __launch_bounds__(kThreads) k_finalize(const Batch* __restrict__ Bp, int mode) {
+  const Batch& B = *Bp;
+  __shared__ double red[4];
+  const int inst = blockIdx.x;
+  if (inst >= B.count) return;
+  const Inst& I = B.inst[inst];
+  Ctl* ctl = I.ctl;
+  const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
+  if (mode == kFinSetup) {
+    if (ctl->done) return;
+    const double nu = block_sum_array(I.part + PL.aux2(), PL.nS, red);
+    const double bb = block_sum_array(I.part + PL.aux(), PL.nS, red);
+    if (threadIdx.x == 0) {
+      ctl->n_unknown = nu;
+      ctl->bb = bb;
+      ctl->bb0 = bb;
+      ctl->accept = ctl->tol2 * bb;
+      ctl->thresh = (ctl->accurate ? ctl->tol_inner2 : ctl->tol2) * bb;
+    }
+  } else {
+    if (ctl->done != kConverged && ctl->done != kMaxIt) return;
+    const double rr = block_sum_array(I.part + PL.aux(), PL.nS, red);
+    if (threadIdx.x == 0) ctl->true_rr = rr;
+  }
+}
+
+// Plain CG counts its iterations here (the preconditioned path counts in k_col).
+__global__ void k_bump(const Batch* __restrict__ Bp) {
+  const Batch& B = *Bp;
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst >= B.count) return;
+  Ctl* ctl = B.inst[inst].ctl;
+  if (ctl->done) return;
+  ctl->iter = ctl->iter + 1;
+}
+
+// Instances whose true residual misses the target restart from it.
+__global__ void k_restart(const Batch* __restrict__ Bp) {
+  const Batch& B = *Bp;
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst >= B.count) return;
+  Ctl* ctl = B.inst[inst].ctl;
+  if (ctl->done != kConverged) return;
+  if (ctl->true_rr <= ctl->accept) return;
+  if (ctl->restarts >= ctl->max_restarts || ctl->iter >= B.inst[inst].maxit) return;
+  ctl->restarts = ctl->restarts + 1;
+  ctl->restart_iter = ctl->iter;
+  ctl->bb = ctl->true_rr;
+  if (ctl->accurate) ctl->thresh = ctl->tol_inner2 * ctl->true_rr;
+  ctl->done = kRunning;
+}
+
+// F = 0 at the unknown nodes of instances flagged by `flag` (zero right-hand side).
+__global__ void __launch_bounds__(kThreads) k_zero_unknown(const Batch* __restrict__ Bp,
+                                                           const int* __restrict__ flag) {
+  const Batch& B = *Bp;
+  for (int it = logical_block(); it < B.n_items[kPassS]; it += gridDim.x) {
+    const int code = B.items[kPassS][it];
+    const int ins = code >> kItemShift;
+    if (!flag[ins]) continue;
+    const Inst& I = B.inst[ins];
+    const int tile = code & kItemMask;
+    const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
+    for (int e = threadIdx.x; e < kTileX * kTileY; e += kThreads) {
+      const int i = tx * kTileX + (e & (kTileX - 1)), j = ty * kTileY + e / kTileX;
+      if (i < I.nx && j < I.ny) {
+        const size_t o = (size_t)j * I.nx + i;
+        if (I.mask[o]) I.F[o] = 0.0;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (host side)
+// ---------------------------------------------------------------------------
+
+hipError_t launch_setup(const Batch* B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_setup, dim3(grid), dim3(kThreads), 0, st, B);
+  return hipGetLastError();
+}
+hipError_t launch_stencil(const Batch* B, int mode, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_stencil, dim3(grid), dim3(kThreads), 0, st, B, mode);
+  return hipGetLastError();
+}
+hipError_t launch_resid(const Batch* B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_resid, dim3(grid), dim3(kThreads), 0, st, B);
+  return hipGetLastError();
+}
+hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, hipStream_t st) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_rowfwd<double>, dim3(grid), dim3(kThreads), kLdsBytes, st, B, update);
+  else
+    hipLaunchKernelGGL(k_rowfwd<float>, dim3(grid), dim3(kThreads), kLdsBytes, st, B, update);
+  return hipGetLastError();
+}
+hipError_t launch_col(const Batch* B, int prec, int count_iter, int grid, hipStream_t st) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_col<double>, dim3(grid), dim3(kThreads), kLdsBytes, st, B, count_iter);
+  else
+    hipLaunchKernelGGL(k_col<float>, dim3(grid), dim3(kThreads), kLdsBytes, st, B, count_iter);
+  return hipGetLastError();
+}
+hipError_t launch_rowinv(const Batch* B, int prec, int grid, hipStream_t st) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_rowinv<double>, dim3(grid), dim3(kThreads), kLdsBytes, st, B);
+  else
+    hipLaunchKernelGGL(k_rowinv<float>, dim3(grid), dim3(kThreads), kLdsBytes, st, B);
+  return hipGetLastError();
+}
+hipError_t launch_identity(const Batch* B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_identity, dim3(grid), dim3(kThreads), 0, st, B);
+  return hipGetLastError();
+}
+hipError_t launch_finalize(const Batch* B, int count, int mode, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(count), dim3(kThreads), 0, st, B, mode);
+  return hipGetLastError();
+}
+hipError_t launch_restart(const Batch* B, int count, hipStream_t st) {
+  hipLaunchKernelGGL(k_restart, dim3((count + 255) / 256), dim3(256), 0, st, B);
+  return hipGetLastError();
+}
+hipError_t launch_bump(const Batch* B, int count, hipStream_t st) {
+  hipLaunchKernelGGL(k_bump, dim3((count + 255) / 256), dim3(256), 0, st, B);
+  return hipGetLastError();
+}
+hipError_t launch_zero_unknown(const Batch* B, const int* flag, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_unknown, dim3(grid), dim3(kThreads), 0, st, B, flag);
+  return hipGetLastError();
+}
+
+hipError_t set_kernel_attributes() {
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* f) {
+    hipError_t x = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    if (x != hipSuccess) e = x;
+  };
+  set((const void*)k_rowfwd<double>);
+  set((const void*)k_rowfwd<float>);
+  set((const void*)k_col<double>);
+  set((const void*)k_col<float>);
+  set((const void*)k_rowinv<double>);
+  set((const void*)k_rowinv<float>);
+  return e;
+}
+
+}  // namespace bhx

@@ -1,0 +1,639 @@
+// Host runtime: transform plans, workspace layout, batch construction and the
+// driver loop of the preconditioned conjugate-gradient solve.
+#include "bhx_runtime.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+namespace bhx {
+
+namespace {
+
+constexpr long double kPi = 3.141592653589793238462643383279502884L;
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+int ilog2(int m) {
+  int l = 0;
+  while ((1 << l) < m) ++l;
+  return l;
+}
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Iterative radix-2 FFT in long double (host), sign -1, in place.
+void host_fft(std::vector<std::complex<long double>>& a) {
+  const int m = (int)a.size();
+  const int lg = ilog2(m);
+  for (int i = 0; i < m; ++i) {
+    int r = 0;
+    for (int b = 0; b < lg; ++b) r |= ((i >> b) & 1) << (lg - 1 - b);
+    if (r > i) std::swap(a[i], a[r]);
+  }
+  for (int len = 2; len <= m; len <<= 1) {
+    for (int i = 0; i < m; i += len) {
+      for (int k = 0; k < len / 2; ++k) {
+        const long double ang = -2 * kPi * k / len;
+        const std::complex<long double> w(cosl(ang), sinl(ang));
+        const auto u = a[i + k], v = a[i + k + len / 2] * w;
+        a[i + k] = u + v;
+        a[i + k + len / 2] = u - v;
+      }
+    }
+  }
+}
+
+template <typename T>
+hipError_t grow(T** p, size_t* cap, size_t need) {
+  if (need <= *cap && *p) return hipSuccess;
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    if (e != hipSuccess) return e;
+    *p = nullptr;
+  }
+  size_t c = std::max(need, *cap * 2);
+  hipError_t e = hipMalloc((void**)p, c * sizeof(T));
+  if (e != hipSuccess) {
+    *cap = 0;
+    return e;
+  }
+  *cap = c;
+  return hipSuccess;
+}
+
+}  // namespace
+
+int core_length(int n) {
+  if (is_pow2(n)) return n;
+  int m = 1;
+  while (m < 2 * n - 1) m <<= 1;
+  return m;
+}
+
+bool length_supported(int n, int prec) {
+  if (n < 4) return false;
+  const int csize = prec == 0 ? 16 : 8;
+  const int m = core_length(n);
+  if ((long)m * csize > kLdsBytes) return false;             // one packed row must fit
+  if ((n / 2 + 1) > kThreads * kMaxPairs) return false;
+  return true;
+}
+
+bool make_layout(int nx, int ny, int prec, int mx, int my, Layout* L) {
+  const int csize = prec == 0 ? 16 : 8;
+  const int rows_cap = prec == 0 ? 4 : 8;
+  auto rows_for = [&](int n, int m) {
+    int r = std::min(rows_cap, kLdsBytes / (m * csize));
+    r = std::min(r, (kThreads * kMaxPairs) / (n / 2 + 1));
+    return r;
+  };
+  const int rx = rows_for(nx, mx), ry = rows_for(ny, my);
+  if (rx < 1 || ry < 1) return false;
+  L->G = 2 * rx;
+  L->Gc = 2 * ry;
+  L->tiles_x = (nx + kTileX - 1) / kTileX;
+  L->tiles_y = (ny + kTileY - 1) / kTileY;
+  L->n_items[kPassS] = L->tiles_x * L->tiles_y;
+  L->n_items[kPassR] = (ny + L->G - 1) / L->G;
+  L->n_items[kPassC] = (nx + L->Gc - 1) / L->Gc;
+  const size_t N = (size_t)nx * ny;
+  const PartLayout PL(L->n_items[kPassS], L->n_items[kPassR]);
+  size_t o = 0;
+  L->off_mask = o; o = align_up(o + N);
+  L->off_vec = o;  o = align_up(o + 5 * N * sizeof(double));
+  L->off_t = o;    o = align_up(o + N * (prec == 0 ? sizeof(double) : sizeof(float)));
+  L->off_part = o; o = align_up(o + (size_t)PL.total() * sizeof(double));
+  L->off_ctl = o;  o = align_up(o + sizeof(Ctl));
+  L->bytes = o;
+  return true;
+}
+
+size_t instance_bytes(int nx, int ny, int prec) {
+  Layout L;
+  if (!length_supported(nx, prec) || !length_supported(ny, prec)) return 0;
+  if (!make_layout(nx, ny, prec, core_length(nx), core_length(ny), &L)) return 0;
+  return L.bytes;
+}
+
+Resolved resolve_opts(const bhx_opts* o) {
+  bhx_opts d;
+  bhx_default_opts(&d);
+  if (!o) o = &d;
+  Resolved R;
+  R.precision = o->precision;
+  R.maxit_user = o->maxit;
+  R.precond = o->precond;
+  R.accurate = o->accurate;
+  R.tol_inner = o->tol_inner > 0 ? o->tol_inner : 1e-8;
+  R.flexible = o->flexible < 0 ? (o->precision == BHX_PREC_FP32 ? 1 : 0) : o->flexible;
+  R.chunk = o->chunk > 0 ? o->chunk : 32;
+  return R;
+}
+
+// ---------------------------------------------------------------------------
+// PlanCache
+// ---------------------------------------------------------------------------
+
+PlanCache::~PlanCache() { release(); }
+
+void PlanCache::release() {
+  if (plans_d_) (void)hipFree(plans_d_);
+  if (ctab_d_) (void)hipFree(ctab_d_);
+  if (ctab_f_) (void)hipFree(ctab_f_);
+  if (rtab_d_) (void)hipFree(rtab_d_);
+  if (rtab_f_) (void)hipFree(rtab_f_);
+  plans_d_ = nullptr; ctab_d_ = nullptr; ctab_f_ = nullptr; rtab_d_ = nullptr; rtab_f_ = nullptr;
+  cap_plans_ = cap_c_ = cap_r_ = 0;
+  dirty_ = !plans_.empty();
+}
+
+int PlanCache::get(int n, int bc) {
+  auto key = std::make_pair(n, bc);
+  auto it = index_.find(key);
+  if (it != index_.end()) return it->second;
+  AxisPlan P;
+  std::memset(&P, 0, sizeof(P));
+  P.n = n;
+  P.bc = bc;
+  P.m = core_length(n);
+  P.logm = ilog2(P.m);
+  P.bluestein = P.m != n;
+  using cl = std::complex<long double>;
+  auto expi = [](long double a) { return cl(cosl(a), sinl(a)); };
+  P.off_tw = (int)ctab_.size();
+  for (int k = 0; k < P.m / 2; ++k) ctab_.push_back(expi(-2 * kPi * k / P.m));
+  P.off_chirp = (int)ctab_.size();
+  P.off_bhat = P.off_chirp;
+  if (P.bluestein) {
+    std::vector<cl> w(n);
+    for (int k = 0; k < n; ++k) {
+      const long long kk = ((long long)k * k) % (2LL * n);   // exact argument reduction
+      w[k] = expi(-kPi * (long double)kk / n);
+    }
+    for (int k = 0; k < n; ++k) ctab_.push_back(w[k]);
+    std::vector<cl> b(P.m, cl(0, 0));
+    for (int l = 0; l < n; ++l) b[l] = std::conj(w[l]);
+    for (int l = 1; l < n; ++l) b[P.m - l] = std::conj(w[l]);
+    host_fft(b);
+    P.off_bhat = (int)ctab_.size();
+    for (int k = 0; k < P.m; ++k) ctab_.push_back(b[k] / (long double)P.m);
+  }
+  P.off_post = (int)ctab_.size();
+  for (int k = 0; k < n; ++k) ctab_.push_back(expi(-kPi * k / (2.0L * n)));
+  P.off_lam = (int)rtab_.size();
+  for (int k = 0; k < n; ++k) {
+    // eigenvalues of the 1-D second difference, 4 sin^2(theta/2)
+    const long double th = bc == kNeumann ? kPi * k / n : 2 * kPi * k / n;
+    const long double s = sinl(th / 2);
+    rtab_.push_back(4 * s * s);
+  }
+  const int idx = (int)plans_.size();
+  plans_.push_back(P);
+  index_[key] = idx;
+  dirty_ = true;
+  return idx;
+}
+
+hipError_t PlanCache::sync_device() {
+  if (!dirty_) return hipSuccess;
+  hipError_t e;
+  if ((e = grow(&plans_d_, &cap_plans_, plans_.size())) != hipSuccess) return e;
+  size_t cc = cap_c_;
+  if ((e = grow(&ctab_d_, &cap_c_, ctab_.size())) != hipSuccess) return e;
+  cap_c_ = cc;
+  if ((e = grow(&ctab_f_, &cap_c_, ctab_.size())) != hipSuccess) return e;
+  size_t rc = cap_r_;
+  if ((e = grow(&rtab_d_, &cap_r_, rtab_.size())) != hipSuccess) return e;
+  cap_r_ = rc;
+  if ((e = grow(&rtab_f_, &cap_r_, rtab_.size())) != hipSuccess) return e;
+  std::vector<double2> cd(ctab_.size());
+  std::vector<float2> cf(ctab_.size());
+  for (size_t i = 0; i < ctab_.size(); ++i) {
+    cd[i] = make_double2((double)ctab_[i].real(), (double)ctab_[i].imag());
+    cf[i] = make_float2((float)ctab_[i].real(), (float)ctab_[i].imag());
+  }
+  std::vector<double> rd(rtab_.size());
+  std::vector<float> rf(rtab_.size());
+  for (size_t i = 0; i < rtab_.size(); ++i) {
+    rd[i] = (double)rtab_[i];
+    rf[i] = (float)rtab_[i];
+  }
+  if ((e = hipMemcpy(plans_d_, plans_.data(), plans_.size() * sizeof(AxisPlan),
+                     hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemcpy(ctab_d_, cd.data(), cd.size() * sizeof(double2), hipMemcpyHostToDevice)) !=
+      hipSuccess) return e;
+  if ((e = hipMemcpy(ctab_f_, cf.data(), cf.size() * sizeof(float2), hipMemcpyHostToDevice)) !=
+      hipSuccess) return e;
+  if ((e = hipMemcpy(rtab_d_, rd.data(), rd.size() * sizeof(double), hipMemcpyHostToDevice)) !=
+      hipSuccess) return e;
+  if ((e = hipMemcpy(rtab_f_, rf.data(), rf.size() * sizeof(float), hipMemcpyHostToDevice)) !=
+      hipSuccess) return e;
+  dirty_ = false;
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
+
+int validate(const double* phi, const double* F, int nx, int ny, double h, int bc, double tol,
+             const Resolved& R) {
+  if (!phi || !F) return BHX_ERR_ARG;
+  if (nx < 4 || ny < 4) return BHX_ERR_ARG;
+  if (!std::isfinite(h) || !(h > 0)) return BHX_ERR_ARG;
+  if (!std::isfinite(tol) || !(tol > 0) || !(tol < 1)) return BHX_ERR_ARG;
+  if (bc < 0 || (bc >> 8) != 0) return BHX_ERR_ARG;
+  const int bx = bc & 15, by = (bc >> 4) & 15;
+  if ((bx != BHX_NEUMANN && bx != BHX_PERIODIC) || (by != BHX_NEUMANN && by != BHX_PERIODIC))
+    return BHX_ERR_ARG;
+  if (R.precision != BHX_PREC_FP64 && R.precision != BHX_PREC_FP32) return BHX_ERR_ARG;
+  if (R.precond != 0 && R.precond != 1) return BHX_ERR_ARG;
+  if (R.accurate != 0 && R.accurate != 1) return BHX_ERR_ARG;
+  if (R.maxit_user < 0 || R.chunk > 100000) return BHX_ERR_ARG;
+  if (!(R.tol_inner > 0 && R.tol_inner < 1)) return BHX_ERR_ARG;
+  if (R.flexible != 0 && R.flexible != 1) return BHX_ERR_ARG;
+  if (!length_supported(nx, R.precision) || !length_supported(ny, R.precision)) return BHX_ERR_ARG;
+  if ((long long)nx * ny > (1LL << 31)) return BHX_ERR_ARG;
+  return BHX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+
+int init_handle(bhx_handle* hd, int device) {
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return BHX_ERR_ARG;
+  hd->device = device;
+  if (hipSetDevice(device) != hipSuccess) return BHX_ERR_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return BHX_ERR_HIP;
+  hd->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  if (set_kernel_attributes() != hipSuccess) return BHX_ERR_HIP;
+  if (hipMalloc((void**)&hd->batch_d, sizeof(Batch)) != hipSuccess) return BHX_ERR_NOMEM;
+  if (hipStreamCreate(&hd->own_stream) != hipSuccess) return BHX_ERR_HIP;
+  return BHX_OK;
+}
+
+void free_handle(bhx_handle* hd) {
+  if (!hd) return;
+  (void)hipSetDevice(hd->device);
+  if (hd->own_stream) (void)hipStreamSynchronize(hd->own_stream);
+  for (auto& g : hd->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  hd->graphs.clear();
+  hd->plans.release();
+  if (hd->ws) (void)hipFree(hd->ws);
+  if (hd->batch_d) (void)hipFree(hd->batch_d);
+  if (hd->inst_d) (void)hipFree(hd->inst_d);
+  for (int p = 0; p < kNumPass; ++p)
+    if (hd->items_d[p]) (void)hipFree(hd->items_d[p]);
+  if (hd->flag_d) (void)hipFree(hd->flag_d);
+  if (hd->ctl_h) (void)hipHostFree(hd->ctl_h);
+  if (hd->own_stream) (void)hipStreamDestroy(hd->own_stream);
+}
+
+// ---------------------------------------------------------------------------
+// Solve
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Grids {
+  int s, r, c;
+};
+
+int hd_count(bhx_handle* hd) { return hd->batch_count; }
+
+hipError_t launch_precond(bhx_handle* hd, const Resolved& R, const Grids& g, hipStream_t st) {
+  hipError_t e;
+  if (!R.precond) return launch_identity(hd->batch_d, g.r, st);
+  if ((e = launch_rowfwd(hd->batch_d, R.precision, 0, g.r, st)) != hipSuccess) return e;
+  if ((e = launch_col(hd->batch_d, R.precision, 0, g.c, st)) != hipSuccess) return e;
+  return launch_rowinv(hd->batch_d, R.precision, g.r, st);
+}
+
+hipError_t launch_iterations(bhx_handle* hd, const Resolved& R, const Grids& g, int count,
+                             hipStream_t st) {
+  hipError_t e;
+  for (int c = 0; c < count; ++c) {
+    if ((e = launch_stencil(hd->batch_d, kModeIter, g.s, st)) != hipSuccess) return e;
+    if (R.precond) {
+      if ((e = launch_rowfwd(hd->batch_d, R.precision, 1, g.r, st)) != hipSuccess) return e;
+      if ((e = launch_col(hd->batch_d, R.precision, 1, g.c, st)) != hipSuccess) return e;
+      if ((e = launch_rowinv(hd->batch_d, R.precision, g.r, st)) != hipSuccess) return e;
+    } else {
+      // plain CG: update-only row pass, iteration count, z = r
+      if ((e = launch_rowfwd(hd->batch_d, R.precision, 2, g.r, st)) != hipSuccess) return e;
+      if ((e = launch_bump(hd->batch_d, hd_count(hd), st)) != hipSuccess) return e;
+      if ((e = launch_identity(hd->batch_d, g.r, st)) != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+bool use_graphs() {
+  const char* v = getenv("BHX_NO_GRAPH");
+  return !(v && v[0] == '1');
+}
+
+hipError_t run_chunk(bhx_handle* hd, const Resolved& R, const Grids& g, hipStream_t st) {
+  if (!use_graphs()) return launch_iterations(hd, R, g, R.chunk, st);
+  for (auto& gr : hd->graphs) {
+    if (gr.stream == st && gr.prec == R.precision && gr.chunk == R.chunk &&
+        gr.precond == R.precond && gr.gs == g.s && gr.gr == g.r && gr.gc == g.c)
+      return hipGraphLaunch(gr.exec, st);
+  }
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t el = launch_iterations(hd, R, g, R.chunk, st);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(st, &graph);
+  if (el != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return el;
+  }
+  if (e != hipSuccess) return e;
+  Graph G;
+  e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return e;
+  G.stream = st; G.prec = R.precision; G.chunk = R.chunk; G.precond = R.precond;
+  G.gs = g.s; G.gr = g.r; G.gc = g.c;
+  if (hd->graphs.size() >= 16) {
+    (void)hipGraphExecDestroy(hd->graphs.front().exec);
+    hd->graphs.erase(hd->graphs.begin());
+  }
+  hd->graphs.push_back(G);
+  return hipGraphLaunch(G.exec, st);
+}
+
+}  // namespace
+
+#define BHX_CHECK(x)                                \
+  do {                                              \
+    hipError_t _e = (x);                            \
+    if (_e != hipSuccess) {                         \
+      return _e == hipErrorOutOfMemory ? BHX_ERR_NOMEM : BHX_ERR_HIP; \
+    }                                               \
+  } while (0)
+
+int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
+                  hipStream_t st, Grids* gout) {
+  BHX_CHECK(hipSetDevice(hd->device));
+  // plans and layouts
+  std::vector<int> px(n), py(n);
+  std::vector<Layout> lay(n);
+  for (int i = 0; i < n; ++i) {
+    px[i] = hd->plans.get(specs[i].nx, specs[i].bcx);
+    py[i] = hd->plans.get(specs[i].ny, specs[i].bcy);
+    if (!make_layout(specs[i].nx, specs[i].ny, R.precision, hd->plans.plan(px[i]).m,
+                     hd->plans.plan(py[i]).m, &lay[i]))
+      return BHX_ERR_ARG;
+  }
+  BHX_CHECK(hd->plans.sync_device());
+  const size_t ctl_bytes = align_up((size_t)n * sizeof(Ctl));
+  size_t total = ctl_bytes;
+  std::vector<size_t> base(n);
+  for (int i = 0; i < n; ++i) {
+    base[i] = total;
+    total += lay[i].bytes;
+  }
+  if (total > hd->ws_cap) {
+    BHX_CHECK(hipStreamSynchronize(st));
+    if (hd->ws) BHX_CHECK(hipFree(hd->ws));
+    hd->ws = nullptr;
+    hd->ws_cap = 0;
+    BHX_CHECK(hipMalloc(&hd->ws, total));
+    hd->ws_cap = total;
+  }
+  char* ws = (char*)hd->ws;
+  Ctl* ctl_d = (Ctl*)ws;
+  // host descriptors
+  std::vector<Inst> inst(n);
+  std::vector<int> items[kNumPass];
+  std::vector<Ctl> ctl(n);
+  for (int i = 0; i < n; ++i) {
+    const InstSpec& S = specs[i];
+    const Layout& L = lay[i];
+    Inst& I = inst[i];
+    std::memset(&I, 0, sizeof(I));
+    I.nx = S.nx; I.ny = S.ny; I.bcx = S.bcx; I.bcy = S.bcy;
+    I.planx = px[i]; I.plany = py[i];
+    I.G = L.G; I.Gc = L.Gc; I.tiles_x = L.tiles_x; I.tiles_y = L.tiles_y;
+    for (int p = 0; p < kNumPass; ++p) I.n_items[p] = L.n_items[p];
+    I.maxit = R.maxit_user > 0 ? R.maxit_user : 50 * std::max(S.nx, S.ny);
+    I.flexible = R.flexible;
+    I.phi = S.phi;
+    I.F = S.F;
+    const size_t N = (size_t)S.nx * S.ny;
+    char* b = ws + base[i];
+    I.mask = (uint8_t*)(b + L.off_mask);
+    double* v = (double*)(b + L.off_vec);
+    I.r = v; I.p[0] = v + N; I.p[1] = v + 2 * N; I.q = v + 3 * N; I.z = v + 4 * N;
+    I.t = b + L.off_t;
+    I.part = (double*)(b + L.off_part);
+    I.ctl = ctl_d + i;
+    for (int p = 0; p < kNumPass; ++p)
+      for (int k = 0; k < L.n_items[p]; ++k) items[p].push_back((i << kItemShift) | k);
+    Ctl& C = ctl[i];
+    std::memset(&C, 0, sizeof(C));
+    C.tol2 = S.tol * S.tol;
+    C.tol_inner2 = R.tol_inner * R.tol_inner;
+    C.accurate = R.accurate;
+    C.max_restarts = R.accurate ? 12 : 4;
+  }
+  // device descriptors
+  if (n > hd->inst_cap) {
+    if (hd->inst_d) BHX_CHECK(hipFree(hd->inst_d));
+    hd->inst_d = nullptr;
+    BHX_CHECK(hipMalloc((void**)&hd->inst_d, std::max(n, 2 * hd->inst_cap) * sizeof(Inst)));
+    hd->inst_cap = std::max(n, 2 * hd->inst_cap);
+  }
+  for (int p = 0; p < kNumPass; ++p) {
+    const int need = std::max<int>(1, (int)items[p].size());
+    if (need > hd->items_cap[p]) {
+      if (hd->items_d[p]) BHX_CHECK(hipFree(hd->items_d[p]));
+      hd->items_d[p] = nullptr;
+      const int cap = std::max(need, 2 * hd->items_cap[p]);
+      BHX_CHECK(hipMalloc((void**)&hd->items_d[p], cap * sizeof(int)));
+      hd->items_cap[p] = cap;
+    }
+  }
+  if (n > hd->flag_cap) {
+    if (hd->flag_d) BHX_CHECK(hipFree(hd->flag_d));
+    hd->flag_d = nullptr;
+    BHX_CHECK(hipMalloc((void**)&hd->flag_d, std::max(n, 2 * hd->flag_cap) * sizeof(int)));
+    hd->flag_cap = std::max(n, 2 * hd->flag_cap);
+  }
+  if (n > hd->ctl_h_cap) {
+    if (hd->ctl_h) BHX_CHECK(hipHostFree(hd->ctl_h));
+    hd->ctl_h = nullptr;
+    BHX_CHECK(hipHostMalloc((void**)&hd->ctl_h, std::max(n, 2 * hd->ctl_h_cap) * sizeof(Ctl)));
+    hd->ctl_h_cap = std::max(n, 2 * hd->ctl_h_cap);
+  }
+  Batch Bh;
+  std::memset(&Bh, 0, sizeof(Bh));
+  Bh.count = n;
+  hd->batch_count = n;
+  for (int p = 0; p < kNumPass; ++p) {
+    Bh.n_items[p] = (int)items[p].size();
+    Bh.items[p] = hd->items_d[p];
+  }
+  Bh.inst = hd->inst_d;
+  Bh.plans = hd->plans.plans_d();
+  for (int p = 0; p < 2; ++p) {
+    Bh.ctab[p] = hd->plans.ctab(p);
+    Bh.rtab[p] = hd->plans.rtab(p);
+  }
+  BHX_CHECK(hipStreamSynchronize(st));
+  BHX_CHECK(hipMemcpy(hd->inst_d, inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
+  for (int p = 0; p < kNumPass; ++p)
+    BHX_CHECK(hipMemcpy(hd->items_d[p], items[p].data(), items[p].size() * sizeof(int),
+                        hipMemcpyHostToDevice));
+  BHX_CHECK(hipMemcpy(ctl_d, ctl.data(), n * sizeof(Ctl), hipMemcpyHostToDevice));
+  BHX_CHECK(hipMemcpy(hd->batch_d, &Bh, sizeof(Batch), hipMemcpyHostToDevice));
+
+  Grids g;
+  g.s = std::max(1, std::min(Bh.n_items[kPassS], hd->num_cu * 8));
+  g.r = std::max(1, std::min(Bh.n_items[kPassR], hd->num_cu * 2));
+  g.c = std::max(1, std::min(Bh.n_items[kPassC], hd->num_cu * 2));
+  *gout = g;
+  return BHX_OK;
+}
+
+int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
+                hipStream_t stream, bhx_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = stream ? stream : hd->own_stream;
+  Grids g;
+  {
+    const int s = prepare_batch(hd, n, specs, R, st, &g);
+    if (s != BHX_OK) return s;
+  }
+  Ctl* ctl_d = (Ctl*)hd->ws;
+  // setup: mask, right-hand side, counts
+  BHX_CHECK(launch_setup(hd->batch_d, g.s, st));
+  BHX_CHECK(launch_stencil(hd->batch_d, kModeRhs, g.s, st));
+  BHX_CHECK(launch_finalize(hd->batch_d, n, kFinSetupH, st));
+  Ctl* ch = hd->ctl_h;
+  BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  BHX_CHECK(hipStreamSynchronize(st));
+  std::vector<int> status(n, BHX_OK), preset(n, 0), zero_flag(n, 0);
+  int active = 0, any_zero = 0;
+  for (int i = 0; i < n; ++i) {
+    const double N = (double)specs[i].nx * specs[i].ny;
+    const double nu = ch[i].n_unknown;
+    if (nu == 0) {
+      preset[i] = 1;
+    } else if (nu == N) {
+      preset[i] = 1;
+      status[i] = BHX_ERR_SINGULAR;
+    } else if (!std::isfinite(ch[i].bb)) {
+      preset[i] = 1;
+      status[i] = BHX_ERR_NONFINITE;
+    } else if (ch[i].bb == 0.0) {
+      preset[i] = 1;
+      zero_flag[i] = 1;
+      any_zero = 1;
+    }
+    if (preset[i]) ch[i].done = kSkip;
+    else ++active;
+  }
+  if (active < n) {
+    BHX_CHECK(hipMemcpyAsync(ctl_d, ch, n * sizeof(Ctl), hipMemcpyHostToDevice, st));
+    if (any_zero) {
+      BHX_CHECK(hipMemcpyAsync(hd->flag_d, zero_flag.data(), n * sizeof(int),
+                               hipMemcpyHostToDevice, st));
+      BHX_CHECK(launch_zero_unknown(hd->batch_d, hd->flag_d, g.s, st));
+    }
+    BHX_CHECK(hipStreamSynchronize(st));
+  }
+  if (active > 0) {
+    BHX_CHECK(launch_precond(hd, R, g, st));
+    for (;;) {
+      BHX_CHECK(run_chunk(hd, R, g, st));
+      BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
+      BHX_CHECK(hipStreamSynchronize(st));
+      bool all_done = true;
+      for (int i = 0; i < n; ++i)
+        if (ch[i].done == kRunning) all_done = false;
+      if (!all_done) continue;
+      // true residual of finished instances; restart those that miss the target
+      BHX_CHECK(launch_resid(hd->batch_d, g.s, st));
+      BHX_CHECK(launch_finalize(hd->batch_d, n, kFinResidH, st));
+      BHX_CHECK(launch_restart(hd->batch_d, n, st));
+      BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
+      BHX_CHECK(hipStreamSynchronize(st));
+      bool restarted = false;
+      for (int i = 0; i < n; ++i)
+        if (ch[i].done == kRunning) restarted = true;
+      if (!restarted) break;
+      BHX_CHECK(launch_precond(hd, R, g, st));
+    }
+  }
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int ret = BHX_OK;
+  for (int i = 0; i < n; ++i) {
+    int s = status[i];
+    if (!preset[i]) {
+      switch (ch[i].done) {
+        case kConverged:
+          s = ch[i].true_rr <= ch[i].accept ? BHX_OK : BHX_NOT_CONVERGED;
+          break;
+        case kMaxIt: s = BHX_NOT_CONVERGED; break;
+        default: s = BHX_ERR_BREAKDOWN; break;
+      }
+    }
+    if (s < 0 && ret >= 0) ret = s;
+    else if (s > 0 && ret == BHX_OK) ret = s;
+    if (stats) {
+      bhx_stats& o = stats[i];
+      o.status = s;
+      o.iterations = preset[i] ? 0 : ch[i].iter;
+      o.restarts = preset[i] ? 0 : ch[i].restarts;
+      o.n_unknown = (int)ch[i].n_unknown;
+      const double bb0 = ch[i].bb0;
+      o.rel_residual = (preset[i] || !(bb0 > 0)) ? 0.0 : std::sqrt(ch[i].rr / bb0);
+      o.true_rel_residual = (preset[i] || !(bb0 > 0)) ? 0.0 : std::sqrt(ch[i].true_rr / bb0);
+      o.seconds = secs;
+    }
+  }
+  return ret;
+}
+
+int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, double* out, int nx,
+                int ny, int bcx, int bcy, int precision, hipStream_t stream) {
+  bhx_opts o;
+  bhx_default_opts(&o);
+  o.precision = precision;
+  const Resolved R = resolve_opts(&o);
+  hipStream_t st = stream ? stream : hd->own_stream;
+  InstSpec s{phi, out, nx, ny, bcx, bcy, 0.5};
+  Grids g;
+  int rc = prepare_batch(hd, 1, &s, R, st, &g);
+  if (rc != BHX_OK) return rc;
+  Layout L;
+  make_layout(nx, ny, precision, core_length(nx), core_length(ny), &L);
+  const size_t N = (size_t)nx * ny;
+  double* v = (double*)((char*)hd->ws + align_up(sizeof(Ctl)) + L.off_vec);
+  double* r = v;
+  double* q = v + 3 * N;
+  double* z = v + 4 * N;
+  BHX_CHECK(launch_setup(hd->batch_d, g.s, st));
+  if (op == 0) {
+    BHX_CHECK(hipMemcpyAsync(z, in, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    BHX_CHECK(launch_stencil(hd->batch_d, kModeApply, g.s, st));
+    BHX_CHECK(hipMemcpyAsync(out, q, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  } else {
+    BHX_CHECK(hipMemcpyAsync(r, in, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    BHX_CHECK(launch_precond(hd, R, g, st));
+    BHX_CHECK(hipMemcpyAsync(out, z, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  BHX_CHECK(hipStreamSynchronize(st));
+  return BHX_OK;
+}
+
+}  // namespace bhx

@@ -1,0 +1,113 @@
+// Host runtime of the biharmonic-extension library: transform plans, device
+// workspace, batch construction and the PCG driver loop.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bhx.h"
+#include "bhx_internal.h"
+
+namespace bhx {
+
+// Transform tables for every (n, bc) seen by a handle.  Host master copies
+// are long double; device copies are double and float with one layout.
+class PlanCache {
+ public:
+  ~PlanCache();
+  int get(int n, int bc);                // plan index, created on first use
+  hipError_t sync_device();              // upload if new plans were added
+  const AxisPlan& plan(int i) const { return plans_[i]; }
+  const AxisPlan* plans_d() const { return plans_d_; }
+  const void* ctab(int p) const { return p == 0 ? (const void*)ctab_d_ : (const void*)ctab_f_; }
+  const void* rtab(int p) const { return p == 0 ? (const void*)rtab_d_ : (const void*)rtab_f_; }
+  void release();
+
+ private:
+  std::vector<AxisPlan> plans_;
+  std::vector<std::complex<long double>> ctab_;
+  std::vector<long double> rtab_;
+  std::map<std::pair<int, int>, int> index_;
+  bool dirty_ = false;
+  AxisPlan* plans_d_ = nullptr;
+  double2* ctab_d_ = nullptr;
+  float2* ctab_f_ = nullptr;
+  double* rtab_d_ = nullptr;
+  float* rtab_f_ = nullptr;
+  size_t cap_plans_ = 0, cap_c_ = 0, cap_r_ = 0;
+};
+
+// Static description of one instance before device pointers are assigned.
+struct InstSpec {
+  const double* phi;
+  double* F;
+  int nx, ny, bcx, bcy;
+  double tol;
+};
+
+// Per-instance layout decisions.
+struct Layout {
+  int G, Gc, tiles_x, tiles_y;
+  int n_items[kNumPass];
+  size_t off_mask, off_vec, off_t, off_part, off_ctl, bytes;
+};
+
+// Choose row-group sizes and item counts; false if the size is unsupported.
+bool make_layout(int nx, int ny, int prec, int mx, int my, Layout* L);
+// Core FFT length of a transform of length n (power of two, or Bluestein).
+int core_length(int n);
+// Largest supported transform length for a precision (0 fp64, 1 fp32).
+bool length_supported(int n, int prec);
+
+struct Resolved {           // options after defaults
+  int precision, maxit_user, precond, accurate, flexible, chunk;
+  double tol_inner;
+};
+Resolved resolve_opts(const bhx_opts* o);
+
+struct Graph {
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;
+  int prec = -1, chunk = 0, precond = -1, gs = 0, gr = 0, gc = 0;
+};
+
+}  // namespace bhx
+
+struct bhx_handle {
+  int device = 0;
+  int num_cu = 256;
+  bhx::PlanCache plans;
+  void* ws = nullptr;          // device workspace (grow-only)
+  size_t ws_cap = 0;
+  bhx::Batch* batch_d = nullptr;   // device batch header
+  bhx::Inst* inst_d = nullptr;
+  int inst_cap = 0;
+  int* items_d[bhx::kNumPass] = {nullptr, nullptr, nullptr};
+  int items_cap[bhx::kNumPass] = {0, 0, 0};
+  int batch_count = 0;         // instances of the current batch
+  int* flag_d = nullptr;
+  int flag_cap = 0;
+  bhx::Ctl* ctl_h = nullptr;   // pinned copy of the control blocks
+  int ctl_h_cap = 0;
+  hipStream_t own_stream = nullptr;
+  std::vector<bhx::Graph> graphs;
+  std::mutex mu;
+};
+
+namespace bhx {
+// Validate one instance's arguments (host only).  Returns BHX_OK or BHX_ERR_ARG.
+int validate(const double* phi, const double* F, int nx, int ny, double h, int bc, double tol,
+             const Resolved& R);
+// Solve `n` instances on `hd`; stats[n] filled (may be null).
+int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
+                hipStream_t stream, bhx_stats* stats);
+size_t instance_bytes(int nx, int ny, int prec);
+int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, double* out, int nx,
+                int ny, int bcx, int bcy, int precision, hipStream_t stream);
+int init_handle(bhx_handle* hd, int device);
+void free_handle(bhx_handle* hd);
+}  // namespace bhx

@@ -1,0 +1,83 @@
+"""Host-side checks of the C interface: the library loads, exports every
+function include/bhx.h declares, and rejects bad arguments before touching a
+GPU.  No compute call is made here."""
+import ctypes
+
+import pytest
+
+from paper_1704_08897_amd import bhx
+
+
+def test_exports_every_declared_symbol():
+    names = bhx.header_functions()
+    assert "bhx_extend" in names and "bhx_extend_batched" in names
+    assert "bhx_engine_submit" in names and "bhx_workspace_bytes" in names
+    missing = [n for n in names if not bhx.exported(n)]
+    assert not missing, missing
+
+
+def test_default_opts_and_strings():
+    o = bhx.default_opts()
+    assert (o.precision, o.maxit, o.precond, o.accurate, o.flexible, o.chunk) == (0, 0, 1, 0, -1, 0)
+    assert bhx.status_string(bhx.OK) == "ok"
+    assert "singular" in bhx.status_string(bhx.ERR_SINGULAR)
+    assert bhx.status_string(12345) == "unknown status"
+    assert "gfx950" in bhx.version()
+
+
+FAKE = 0x1000  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("nx,ny,h,bc,tol", [
+    (3, 8, 1.0, 0, 1e-8),            # too small
+    (8, 2, 1.0, 0, 1e-8),
+    (8, 8, 0.0, 0, 1e-8),            # h <= 0
+    (8, 8, float("nan"), 0, 1e-8),
+    (8, 8, 1.0, 0, 0.0),             # tol outside (0, 1)
+    (8, 8, 1.0, 0, 1.0),
+    (8, 8, 1.0, 0, float("inf")),
+    (8, 8, 1.0, 3, 1e-8),            # bad bc nibble
+    (8, 8, 1.0, 0x300, 1e-8),
+    (8, 8, 1.0, -1, 1e-8),
+    (5000, 8, 1.0, 0, 1e-8),         # transform length not supported
+])
+def test_extend_rejects_bad_arguments(nx, ny, h, bc, tol):
+    assert bhx._lib.bhx_extend(FAKE, FAKE, nx, ny, h, bc, tol) == bhx.ERR_ARG
+
+
+def test_null_pointers_and_handles():
+    assert bhx._lib.bhx_extend(None, FAKE, 8, 8, 1.0, 0, 1e-8) == bhx.ERR_ARG
+    assert bhx._lib.bhx_extend(FAKE, None, 8, 8, 1.0, 0, 1e-8) == bhx.ERR_ARG
+    s, _ = bhx.extend_ex(None, FAKE, FAKE, 8, 8, 1.0, 0, 1e-8)
+    assert s == bhx.ERR_ARG
+    assert bhx._lib.bhx_create(None, 0) == bhx.ERR_ARG
+    st = (bhx.Stats * 1)()
+    assert bhx._lib.bhx_extend_batched(None, 1, None, None, None, None, None, None, None, None,
+                                       None, st) == bhx.ERR_ARG
+
+
+def test_bad_options_rejected():
+    for kw in ({"precision": 2}, {"precond": 3}, {"maxit": -1}, {"flexible": 2},
+               {"tol_inner": 2.0}, {"accurate": 5}):
+        o = bhx.default_opts(**kw)
+        s, _ = bhx.extend_ex(FAKE, FAKE, FAKE, 8, 8, 1.0, 0, 1e-8, opts=o)
+        assert s == bhx.ERR_ARG, kw
+    assert bhx.workspace_bytes(64, 64, 0, bhx.default_opts(precision=7)) == 0
+
+
+def test_workspace_bytes():
+    w64 = bhx.workspace_bytes(1024, 1024, 0)
+    w32 = bhx.workspace_bytes(1024, 1024, 0, bhx.default_opts(precision=1))
+    N = 1024 * 1024
+    # mask + five float64 vectors + transform buffer (+ small tails)
+    assert 49 * N <= w64 < 49 * N + 2 * 1024 * 1024
+    assert 45 * N <= w32 < 45 * N + 2 * 1024 * 1024
+    assert bhx.workspace_bytes(3, 64, 0) == 0
+    assert bhx.workspace_bytes(100, 77, bhx.BC(1, 0)) > 0
+    # Dirichlet axes are solved by the oracle only
+    assert bhx.workspace_bytes(64, 64, bhx.BC(2, 0)) == 0
+
+
+def test_engine_rejects_without_device():
+    e = ctypes.c_void_p()
+    assert bhx._lib.bhx_engine_create(ctypes.byref(e), -1, 1 << 30, 4, None) == bhx.ERR_ARG
