@@ -40,7 +40,10 @@
  *     < 0 = error, F untouched.  Nothing is thrown across this interface.
  *   - Entry points that take a stream enqueue their GPU work on it; they
  *     synchronise with it before returning (stats are valid on return).
- *     A handle is not thread-safe: use one handle per host thread.
+ *     Calls on one handle are serialised by a lock inside the handle.
+ *   - Boundary rules: Neumann and periodic axes are solved on the GPU;
+ *     BHX_DIRICHLET is part of the interface but rejected with BHX_ERR_ARG by
+ *     this version of the GPU library.
  */
 #ifndef BHX_H
 #define BHX_H
@@ -99,6 +102,10 @@ typedef struct {
                          beta = r.z / r_old.z_old, 1 = Polak-Ribiere beta           */
   int chunk;        /* iterations per captured graph between convergence checks;
                          0 -> 32                                                     */
+  int profile;      /* bit mask of iteration passes to time with HIP events recorded
+                         on the solve's stream around each launch (captured into the
+                         graph): bit 0 stencil, 1 row-forward, 2 column, 3 row-inverse;
+                         results in bhx_stats.pass_ms / pass_launches; 0 = off       */
 } bhx_opts;
 
 typedef struct {
@@ -109,6 +116,8 @@ typedef struct {
   double rel_residual;     /* recursive ||r|| / ||b|| at exit                         */
   double true_rel_residual;/* compensated ||b - A_UU x|| / ||b|| at exit             */
   double seconds;          /* host wall time of the call that produced this record   */
+  double pass_ms[4];       /* summed event-timed duration of each profiled pass       */
+  int pass_launches[4];    /* launches counted in pass_ms (iterations that did work)  */
 } bhx_stats;
 
 typedef struct bhx_handle bhx_handle;
@@ -187,6 +196,10 @@ int bhx_debug_apply(bhx_handle* hd, int op, const double* phi, const double* in,
 
 /* Human-readable name of a status code (static storage). */
 const char* bhx_status_string(int status);
+
+/* Description of the last HIP failure on the calling thread (the runtime
+ * call, its source location and HIP's message); "" if none. */
+const char* bhx_last_error(void);
 
 /* Library version string (static storage). */
 const char* bhx_version(void);

@@ -38,17 +38,21 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("precond", ctypes.c_int), ("accurate", ctypes.c_int),
                 ("tol_inner", ctypes.c_double), ("flexible", ctypes.c_int),
-                ("chunk", ctypes.c_int)]
+                ("chunk", ctypes.c_int), ("profile", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("n_unknown", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("true_rel_residual", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("pass_ms", ctypes.c_double * 4),
+                ("pass_launches", ctypes.c_int * 4)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["pass_ms"] = list(self.pass_ms)
+        d["pass_launches"] = list(self.pass_launches)
+        return d
 
 
 _vp, _ci, _cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
@@ -74,6 +78,7 @@ _sig = {
     "bhx_engine_destroy": (None, [_vp]),
     "bhx_status_string": (ctypes.c_char_p, [_ci]),
     "bhx_version": (ctypes.c_char_p, []),
+    "bhx_last_error": (ctypes.c_char_p, []),
     "bhx_debug_apply": (_ci, [_vp, _ci, _vp, _vp, _vp, _ci, _ci, _ci, _ci, _vp]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -147,9 +152,14 @@ def version() -> str:
     return _lib.bhx_version().decode()
 
 
+def last_error() -> str:
+    return _lib.bhx_last_error().decode()
+
+
 class BhxError(RuntimeError):
     def __init__(self, status):
-        super().__init__(f"bhx status {status}: {status_string(status)}")
+        extra = f" ({last_error()})" if status == ERR_HIP else ""
+        super().__init__(f"bhx status {status}: {status_string(status)}{extra}")
         self.status = status
 
 

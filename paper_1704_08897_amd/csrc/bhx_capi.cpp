@@ -25,6 +25,8 @@ void bhx_default_opts(bhx_opts* o) {
 
 const char* bhx_version(void) { return "bhx 0.1 (gfx950)"; }
 
+const char* bhx_last_error(void) { return bhx::last_error(); }
+
 const char* bhx_status_string(int s) {
   switch (s) {
     case BHX_OK: return "ok";

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 
 namespace bhx {
@@ -60,6 +61,14 @@ hipError_t grow(T** p, size_t* cap, size_t need) {
   }
   *cap = c;
   return hipSuccess;
+}
+
+void free_graph(Graph& G) {
+  if (G.exec) (void)hipGraphExecDestroy(G.exec);
+  for (auto& x : G.ev)
+    if (x) (void)hipEventDestroy(x);
+  G.exec = nullptr;
+  G.ev.clear();
 }
 
 }  // namespace
@@ -128,6 +137,7 @@ Resolved resolve_opts(const bhx_opts* o) {
   R.tol_inner = o->tol_inner > 0 ? o->tol_inner : 1e-8;
   R.flexible = o->flexible < 0 ? (o->precision == BHX_PREC_FP32 ? 1 : 0) : o->flexible;
   R.chunk = o->chunk > 0 ? o->chunk : 32;
+  R.profile = o->profile;
   return R;
 }
 
@@ -253,6 +263,7 @@ int validate(const double* phi, const double* F, int nx, int ny, double h, int b
   if (R.maxit_user < 0 || R.chunk > 100000) return BHX_ERR_ARG;
   if (!(R.tol_inner > 0 && R.tol_inner < 1)) return BHX_ERR_ARG;
   if (R.flexible != 0 && R.flexible != 1) return BHX_ERR_ARG;
+  if (R.profile < 0 || R.profile > 15) return BHX_ERR_ARG;
   if (!length_supported(nx, R.precision) || !length_supported(ny, R.precision)) return BHX_ERR_ARG;
   if ((long long)nx * ny > (1LL << 31)) return BHX_ERR_ARG;
   return BHX_OK;
@@ -280,8 +291,7 @@ void free_handle(bhx_handle* hd) {
   if (!hd) return;
   (void)hipSetDevice(hd->device);
   if (hd->own_stream) (void)hipStreamSynchronize(hd->own_stream);
-  for (auto& g : hd->graphs)
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  for (auto& g : hd->graphs) free_graph(g);
   hd->graphs.clear();
   hd->plans.release();
   if (hd->ws) (void)hipFree(hd->ws);
@@ -314,22 +324,45 @@ hipError_t launch_precond(bhx_handle* hd, const Resolved& R, const Grids& g, hip
   return launch_rowinv(hd->batch_d, R.precision, g.r, st);
 }
 
+// Event of pass p, iteration c, edge e (0 start, 1 end) in a Graph's array.
+inline hipEvent_t ev_at(const std::vector<hipEvent_t>* ev, int chunk, int p, int c, int e) {
+  return (*ev)[((size_t)p * chunk + c) * 2 + e];
+}
+
 hipError_t launch_iterations(bhx_handle* hd, const Resolved& R, const Grids& g, int count,
-                             hipStream_t st) {
+                             hipStream_t st, const std::vector<hipEvent_t>* ev) {
   hipError_t e;
+  auto rec = [&](int p, int c, int edge) -> hipError_t {
+    if (!ev || !(R.profile & (1 << p))) return hipSuccess;
+    return hipEventRecord(ev_at(ev, count, p, c, edge), st);
+  };
+#define BHX_TRY(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
   for (int c = 0; c < count; ++c) {
-    if ((e = launch_stencil(hd->batch_d, kModeIter, g.s, st)) != hipSuccess) return e;
+    BHX_TRY(rec(0, c, 0));
+    BHX_TRY(launch_stencil(hd->batch_d, kModeIter, g.s, st));
+    BHX_TRY(rec(0, c, 1));
     if (R.precond) {
-      if ((e = launch_rowfwd(hd->batch_d, R.precision, 1, g.r, st)) != hipSuccess) return e;
-      if ((e = launch_col(hd->batch_d, R.precision, 1, g.c, st)) != hipSuccess) return e;
-      if ((e = launch_rowinv(hd->batch_d, R.precision, g.r, st)) != hipSuccess) return e;
+      BHX_TRY(rec(1, c, 0));
+      BHX_TRY(launch_rowfwd(hd->batch_d, R.precision, 1, g.r, st));
+      BHX_TRY(rec(1, c, 1));
+      BHX_TRY(rec(2, c, 0));
+      BHX_TRY(launch_col(hd->batch_d, R.precision, 1, g.c, st));
+      BHX_TRY(rec(2, c, 1));
+      BHX_TRY(rec(3, c, 0));
+      BHX_TRY(launch_rowinv(hd->batch_d, R.precision, g.r, st));
+      BHX_TRY(rec(3, c, 1));
     } else {
       // plain CG: update-only row pass, iteration count, z = r
-      if ((e = launch_rowfwd(hd->batch_d, R.precision, 2, g.r, st)) != hipSuccess) return e;
-      if ((e = launch_bump(hd->batch_d, hd_count(hd), st)) != hipSuccess) return e;
-      if ((e = launch_identity(hd->batch_d, g.r, st)) != hipSuccess) return e;
+      BHX_TRY(rec(1, c, 0));
+      BHX_TRY(launch_rowfwd(hd->batch_d, R.precision, 2, g.r, st));
+      BHX_TRY(rec(1, c, 1));
+      BHX_TRY(launch_bump(hd->batch_d, hd_count(hd), st));
+      BHX_TRY(rec(3, c, 0));
+      BHX_TRY(launch_identity(hd->batch_d, g.r, st));
+      BHX_TRY(rec(3, c, 1));
     }
   }
+#undef BHX_TRY
   return hipSuccess;
 }
 
@@ -338,45 +371,83 @@ bool use_graphs() {
   return !(v && v[0] == '1');
 }
 
-hipError_t run_chunk(bhx_handle* hd, const Resolved& R, const Grids& g, hipStream_t st) {
-  if (!use_graphs()) return launch_iterations(hd, R, g, R.chunk, st);
+hipError_t make_events(std::vector<hipEvent_t>* ev, int chunk) {
+  ev->assign((size_t)4 * chunk * 2, nullptr);
+  for (auto& x : *ev) {
+    hipError_t e = hipEventCreate(&x);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Launch one chunk of iterations; returns the Graph used (for its events).
+hipError_t run_chunk(bhx_handle* hd, const Resolved& R, const Grids& g, hipStream_t st,
+                     Graph** used) {
+  *used = nullptr;
+  // HIP cannot time events recorded as graph nodes, so a profiled chunk is
+  // launched directly with events around the selected passes.
+  const bool graph = use_graphs() && R.profile == 0;
   for (auto& gr : hd->graphs) {
     if (gr.stream == st && gr.prec == R.precision && gr.chunk == R.chunk &&
-        gr.precond == R.precond && gr.gs == g.s && gr.gr == g.r && gr.gc == g.c)
-      return hipGraphLaunch(gr.exec, st);
+        gr.precond == R.precond && gr.gs == g.s && gr.gr == g.r && gr.gc == g.c &&
+        gr.profile == R.profile && (gr.exec != nullptr) == graph) {
+      *used = &gr;
+      if (gr.exec) return hipGraphLaunch(gr.exec, st);
+      return launch_iterations(hd, R, g, R.chunk, st, &gr.ev);
+    }
   }
-  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return e;
-  hipError_t el = launch_iterations(hd, R, g, R.chunk, st);
-  hipGraph_t graph = nullptr;
-  e = hipStreamEndCapture(st, &graph);
-  if (el != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return el;
-  }
-  if (e != hipSuccess) return e;
   Graph G;
-  e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) return e;
   G.stream = st; G.prec = R.precision; G.chunk = R.chunk; G.precond = R.precond;
-  G.gs = g.s; G.gr = g.r; G.gc = g.c;
+  G.gs = g.s; G.gr = g.r; G.gc = g.c; G.profile = R.profile;
+  hipError_t e;
+  if (R.profile && (e = make_events(&G.ev, R.chunk)) != hipSuccess) {
+    free_graph(G);
+    return e;
+  }
+  if (graph) {
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { free_graph(G); return e; }
+    hipError_t el = launch_iterations(hd, R, g, R.chunk, st, nullptr);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(st, &graph);
+    if (el != hipSuccess || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      free_graph(G);
+      return el != hipSuccess ? el : e;
+    }
+    e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) { free_graph(G); return e; }
+  }
   if (hd->graphs.size() >= 16) {
-    (void)hipGraphExecDestroy(hd->graphs.front().exec);
+    free_graph(hd->graphs.front());
     hd->graphs.erase(hd->graphs.begin());
   }
   hd->graphs.push_back(G);
-  return hipGraphLaunch(G.exec, st);
+  Graph* gp = &hd->graphs.back();
+  *used = gp;
+  if (gp->exec) return hipGraphLaunch(gp->exec, st);
+  return launch_iterations(hd, R, g, R.chunk, st, R.profile ? &gp->ev : nullptr);
 }
 
 }  // namespace
 
-#define BHX_CHECK(x)                                \
-  do {                                              \
-    hipError_t _e = (x);                            \
-    if (_e != hipSuccess) {                         \
-      return _e == hipErrorOutOfMemory ? BHX_ERR_NOMEM : BHX_ERR_HIP; \
-    }                                               \
+thread_local char g_last_error[512] = "";
+
+void set_last_error(const char* what, int line, hipError_t e) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s (bhx_runtime.cpp:%d): %s", what, line,
+           hipGetErrorString(e));
+}
+
+const char* last_error() { return g_last_error; }
+
+#define BHX_CHECK(x)                                                      \
+  do {                                                                    \
+    hipError_t _e = (x);                                                  \
+    if (_e != hipSuccess) {                                               \
+      set_last_error(#x, __LINE__, _e);                                   \
+      return _e == hipErrorOutOfMemory ? BHX_ERR_NOMEM : BHX_ERR_HIP;     \
+    }                                                                     \
   } while (0)
 
 int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
@@ -550,12 +621,31 @@ int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
     }
     BHX_CHECK(hipStreamSynchronize(st));
   }
+  double pass_ms[4] = {0, 0, 0, 0};
+  int pass_cnt[4] = {0, 0, 0, 0};
+  std::vector<int> iter_before(n);
   if (active > 0) {
     BHX_CHECK(launch_precond(hd, R, g, st));
     for (;;) {
-      BHX_CHECK(run_chunk(hd, R, g, st));
+      for (int i = 0; i < n; ++i) iter_before[i] = ch[i].iter;
+      Graph* used = nullptr;
+      BHX_CHECK(run_chunk(hd, R, g, st, &used));
       BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
       BHX_CHECK(hipStreamSynchronize(st));
+      if (R.profile && used && !used->ev.empty()) {
+        int worked = 0;
+        for (int i = 0; i < n; ++i) worked = std::max(worked, ch[i].iter - iter_before[i]);
+        for (int p = 0; p < 4; ++p) {
+          if (!(R.profile & (1 << p))) continue;
+          for (int c = 0; c < worked && c < R.chunk; ++c) {
+            float ms = 0;
+            BHX_CHECK(hipEventElapsedTime(&ms, ev_at(&used->ev, R.chunk, p, c, 0),
+                                          ev_at(&used->ev, R.chunk, p, c, 1)));
+            pass_ms[p] += ms;
+            pass_cnt[p] += 1;
+          }
+        }
+      }
       bool all_done = true;
       for (int i = 0; i < n; ++i)
         if (ch[i].done == kRunning) all_done = false;
@@ -599,6 +689,10 @@ int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
       o.rel_residual = (preset[i] || !(bb0 > 0)) ? 0.0 : std::sqrt(ch[i].rr / bb0);
       o.true_rel_residual = (preset[i] || !(bb0 > 0)) ? 0.0 : std::sqrt(ch[i].true_rr / bb0);
       o.seconds = secs;
+      for (int p = 0; p < 4; ++p) {
+        o.pass_ms[p] = pass_ms[p];
+        o.pass_launches[p] = pass_cnt[p];
+      }
     }
   }
   return ret;

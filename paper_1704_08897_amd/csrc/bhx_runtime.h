@@ -64,7 +64,7 @@ int core_length(int n);
 bool length_supported(int n, int prec);
 
 struct Resolved {           // options after defaults
-  int precision, maxit_user, precond, accurate, flexible, chunk;
+  int precision, maxit_user, precond, accurate, flexible, chunk, profile;
   double tol_inner;
 };
 Resolved resolve_opts(const bhx_opts* o);
@@ -72,7 +72,8 @@ Resolved resolve_opts(const bhx_opts* o);
 struct Graph {
   hipGraphExec_t exec = nullptr;
   hipStream_t stream = nullptr;
-  int prec = -1, chunk = 0, precond = -1, gs = 0, gr = 0, gc = 0;
+  int prec = -1, chunk = 0, precond = -1, gs = 0, gr = 0, gc = 0, profile = 0;
+  std::vector<hipEvent_t> ev;   // [pass][iteration][start, end] when profiling
 };
 
 }  // namespace bhx
@@ -106,6 +107,7 @@ int validate(const double* phi, const double* F, int nx, int ny, double h, int b
 int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
                 hipStream_t stream, bhx_stats* stats);
 size_t instance_bytes(int nx, int ny, int prec);
+const char* last_error();
 int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, double* out, int nx,
                 int ny, int bcx, int bcy, int precision, hipStream_t stream);
 int init_handle(bhx_handle* hd, int device);
