@@ -9,13 +9,28 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Device pointers inside descriptors carry the global address space in
+// device code, so loads through them are global (not flat) accesses.
+// Read-only descriptors (batch header, instances, work lists, plans) use the
+// constant address space, so kernels fetch them with scalar loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define BHX_GLOBAL __attribute__((address_space(1)))
+#define BHX_CONST __attribute__((address_space(4)))
+#else
+#define BHX_GLOBAL
+#define BHX_CONST
+#endif
+
 namespace bhx {
 
 constexpr int kThreads = 256;          // threads per workgroup, every kernel
 constexpr int kTileX = 64;             // stencil tile (nodes)
-constexpr int kTileY = 16;
-constexpr int kLdsBytes = 64 * 1024;   // dynamic LDS of each transform kernel
-constexpr int kMaxPairs = 12;          // (k, n-k) pairs held in registers per thread
+constexpr int kTileY = 32;
+constexpr int kLdsBytes = 80 * 1024;   // LDS for the packed rows of one transform item
+constexpr int kLdsMax = 160 * 1024;    // LDS of a CU (gfx950)
+constexpr int kLdsDynMax = 152 * 1024; // dynamic LDS cap of a transform launch
+constexpr int kMaxPairs = 8;           // (k, n-k) pairs held in registers per thread
+constexpr int kTargetItems = 512;      // row/column items one instance should supply
 
 enum Bc { kNeumann = 0, kPeriodic = 1, kDirichlet = 2 };
 enum Pass { kPassS = 0, kPassR = 1, kPassC = 2, kNumPass = 3 };
@@ -43,6 +58,10 @@ struct AxisPlan {
   int off_bhat;    // FFT_m(conj chirp, wrapped) / m, length m   (complex table)
   int off_post;    // DCT: exp(-i pi k / (2n)), k < n; Dirichlet: unused
   int off_lam;     // eigenvalues lambda_k of T, k < n           (real table)
+  int pad;
+  // normalisations: DCT-II s_0 = sqrt(1/n), s_k = sqrt(2/n); its inverse's
+  // pre-scale g_0 = 1/sqrt(n), g_k = 1/sqrt(2n); Hartley 1/(2 sqrt(n))
+  double s0, s1, g0, g1, hs;
 };
 
 struct Ctl {
@@ -75,16 +94,16 @@ struct Inst {
   int maxit;
   int flexible;
   int pad0;
-  const double* phi;
-  double* F;
-  uint8_t* mask;        // 1 = unknown, 0 = known
-  double* r;
-  double* p[2];         // search direction, double-buffered by iteration parity
-  double* q;
-  double* z;
-  void* t;              // transform buffer, [nx][ny] (y fastest), double or float
-  double* part;         // partial sums, see PartLayout
-  Ctl* ctl;
+  BHX_GLOBAL const double* phi;
+  BHX_GLOBAL double* F;
+  BHX_GLOBAL uint8_t* mask;   // 1 = unknown, 0 = known
+  BHX_GLOBAL double* r;
+  BHX_GLOBAL double* p[2];    // search direction, double-buffered by iteration parity
+  BHX_GLOBAL double* q;
+  BHX_GLOBAL double* z;
+  BHX_GLOBAL void* t;         // transform buffer, [nx][ny] (y fastest), double or float
+  BHX_GLOBAL double* part;    // partial sums, see PartLayout
+  BHX_GLOBAL Ctl* ctl;
 };
 
 // Offsets (in doubles) of the partial-sum arrays inside Inst::part.
@@ -97,7 +116,8 @@ struct PartLayout {
   __host__ __device__ int rr() const { return 3 * nS; }             // [nR]
   __host__ __device__ int rz(int par) const { return 3 * nS + nR + par * nR; }    // 2 x [nR]
   __host__ __device__ int rzo(int par) const { return 3 * nS + 3 * nR + par * nR; } // 2 x [nR]
-  __host__ __device__ int total() const { return 3 * nS + 5 * nR; }
+  __host__ __device__ int rowcnt() const { return 3 * nS + 5 * nR; }   // [nR] unknowns per row group
+  __host__ __device__ int total() const { return 3 * nS + 6 * nR; }
 };
 
 // Flat work list of one pass: items[i] = (instance << 20) | local item.
@@ -109,11 +129,11 @@ constexpr int kItemMask = (1 << kItemShift) - 1;
 struct Batch {
   int count;                 // instances
   int n_items[kNumPass];     // total items per pass
-  const Inst* inst;          // [count]
-  const int* items[kNumPass];
-  const AxisPlan* plans;
-  const void* ctab[2];       // complex tables: [0] double2, [1] float2 (same layout)
-  const void* rtab[2];       // real tables (eigenvalues): [0] double, [1] float
+  BHX_CONST const Inst* inst;           // [count]
+  BHX_CONST const int* items[kNumPass];
+  BHX_CONST const AxisPlan* plans;
+  BHX_GLOBAL const void* ctab[2];       // complex tables: [0] double2, [1] float2
+  BHX_GLOBAL const void* rtab[2];       // real tables (eigenvalues): [0] double, [1] float
 };
 
 }  // namespace bhx
@@ -124,9 +144,14 @@ enum FinModeHost { kFinSetupH = 0, kFinResidH = 1 };
 hipError_t launch_setup(const Batch* B, int grid, hipStream_t st);
 hipError_t launch_stencil(const Batch* B, int mode, int grid, hipStream_t st);
 hipError_t launch_resid(const Batch* B, int grid, hipStream_t st);
-hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, hipStream_t st);
-hipError_t launch_col(const Batch* B, int prec, int count_iter, int grid, hipStream_t st);
-hipError_t launch_rowinv(const Batch* B, int prec, int grid, hipStream_t st);
+// Transform launches: `lds` dynamic LDS bytes, `twoff` complex-element offset
+// of the twiddle table staged in LDS (after the largest packed-row buffer).
+hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, int lds, int twoff,
+                         hipStream_t st);
+hipError_t launch_col(const Batch* B, int prec, int count_iter, int grid, int lds, int twoff,
+                      hipStream_t st);
+hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, hipStream_t st);
+hipError_t launch_setup_rows(const Batch* B, int grid, hipStream_t st);
 hipError_t launch_identity(const Batch* B, int grid, hipStream_t st);
 hipError_t launch_finalize(const Batch* B, int count, int mode, hipStream_t st);
 hipError_t launch_restart(const Batch* B, int count, hipStream_t st);

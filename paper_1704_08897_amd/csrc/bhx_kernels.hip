@@ -56,6 +56,28 @@ template <typename C> __device__ __forceinline__ C cmul_mi(C a) { return mk<C>(a
 // a * (+i)
 template <typename C> __device__ __forceinline__ C cmul_pi(C a) { return mk<C>(-a.y, a.x); }
 
+// 1 / x by the hardware reciprocal estimate refined with Newton-Raphson
+// steps r <- r + r (1 - x r) (quadratic convergence from the estimate).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+// Spectral weight 1 / s^2 for s = lambda_x + lambda_y, 0 when s = 0.
+template <typename R> __device__ __forceinline__ R inv_sq(R s) {
+  return s > (R)0 ? recip(s * s) : (R)0;
+}
+
+// Packed rows in LDS carry one pad element after every 8 complex values, so
+// the bit-reversed scatter and the small-stride butterfly stages spread over
+// the LDS banks.
+__device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
+
 __device__ __forceinline__ int bitrev(int k, int logm) {
   return (int)(__brev((unsigned)k) >> (32 - logm));
 }
@@ -67,7 +89,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum of a[0..n) by the whole block in a fixed order; every thread gets it.
-__device__ double block_sum_array(const double* __restrict__ a, int n, double* red) {
+__device__ double block_sum_array(BHX_GLOBAL const double* __restrict__ a, int n, double* red) {
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += kThreads) s += a[i];
   s = wave_sum(s);
@@ -78,6 +100,100 @@ __device__ double block_sum_array(const double* __restrict__ a, int n, double* r
   double t = (red[0] + red[1]) + (red[2] + red[3]);
   __syncthreads();
   return t;
+}
+
+// Sums of K partial arrays a[k][0..n[k]) in one pass (all loads in flight
+// together); the order of every sum is fixed, so each block of a launch
+// obtains bit-identical values.  red must hold 4*K doubles.
+template <int K>
+__device__ __forceinline__ void block_sums(BHX_GLOBAL const double* const (&a)[K],
+                                           const int (&n)[K], double (&out)[K], double* red) {
+  double s[K];
+  int nmax = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    s[k] = 0.0;
+    nmax = max(nmax, n[k]);
+  }
+  // Straight-line loads from clamped in-bounds indices; out-of-range and
+  // empty arrays contribute 0 through a select, so no load sits behind a
+  // branch and all of them are in flight together.
+  for (int i0 = 0; i0 < nmax; i0 += 4 * kThreads) {
+    double v[K][4];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * kThreads + threadIdx.x;
+        const int ic = min(i, max(n[k] - 1, 0));
+        v[k][u] = n[k] > 0 ? a[k][ic] : 0.0;
+      }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * kThreads + threadIdx.x;
+        s[k] += (i < n[k]) ? v[k][u] : 0.0;
+      }
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) s[k] = wave_sum(s[k]);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[w * K + k] = s[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    out[k] = (red[k] + red[K + k]) + (red[2 * K + k] + red[3 * K + k]);
+  __syncthreads();
+}
+
+// The same sums in two steps, so the loads can be issued early and overlap
+// other loads: sums_issue() loads the first 4*kThreads entries of each array
+// into registers; sums_finish() adds any remainder and reduces.
+template <int K>
+struct Partials {
+  double v[K][4];
+};
+template <int K>
+__device__ __forceinline__ void sums_issue(BHX_GLOBAL const double* const (&a)[K],
+                                           const int (&n)[K], Partials<K>& P) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = u * kThreads + threadIdx.x;
+      P.v[k][u] = n[k] > 0 ? a[k][min(i, max(n[k] - 1, 0))] : 0.0;
+    }
+}
+template <int K>
+__device__ __forceinline__ void sums_finish(BHX_GLOBAL const double* const (&a)[K],
+                                            const int (&n)[K], const Partials<K>& P,
+                                            double (&out)[K], double* red) {
+  double s[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    s[k] = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s[k] += (u * kThreads + (int)threadIdx.x < n[k]) ? P.v[k][u] : 0.0;
+    for (int i = 4 * kThreads + threadIdx.x; i < n[k]; i += kThreads) s[k] += a[k][i];
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) s[k] = wave_sum(s[k]);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[w * K + k] = s[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    out[k] = (red[k] + red[K + k]) + (red[2 * K + k] + red[3 * K + k]);
+  __syncthreads();
 }
 
 // Block reduction of one value per thread; result valid in every thread.
@@ -105,6 +221,28 @@ __device__ __forceinline__ int map_axis(int g, int n, int bc, double& s) {
   return g < 0 ? 0 : n - 1;
 }
 
+// Branch-free form of map_axis for g in [-2, n+1] (selects only); any other
+// g maps to index 0 with sign 0.
+__device__ __forceinline__ int map_axis_sel(int g, int n, int bc, double& s) {
+  const bool lo = g < 0, hi = g >= n;
+  const bool inside = !lo && !hi;
+  const bool valid = g >= -2 && g <= n + 1;
+  const int refl = lo ? -g - 1 : 2 * n - 1 - g;                // Neumann
+  const int wrap = lo ? g + n : g - n;                         // periodic
+  const int dir = lo ? 0 : n - 1;                              // Dirichlet, g = -2 or n+1
+  const double sdir = (g == -1 || g == n) ? 0.0 : -1.0;
+  const int ghost = bc == kNeumann ? refl : (bc == kPeriodic ? wrap : dir);
+  const double sghost = bc == kDirichlet ? sdir : 1.0;
+  s = inside ? 1.0 : (valid ? sghost : 0.0);
+  return inside ? g : (valid ? ghost : 0);
+}
+
+// Work item `it` of pass `p`: (instance << kItemShift) | local item.  A
+// single-instance batch needs no table.
+__device__ __forceinline__ int item_code(const Batch& B, int p, int it) {
+  return B.count == 1 ? it : B.items[p][it];
+}
+
 // Persistent-grid item loop with an XCD-aware block order: consecutive
 // logical blocks (neighbouring tiles / row groups) land on the same XCD,
 // whose L2 then serves their shared halo rows.
@@ -122,28 +260,57 @@ template <typename R>
 struct XPlan {
   using C = typename V2<R>::T;
   int n, m, logm, blue, bc;
-  const C* tw;
-  const C* chirp;
-  const C* bhat;
-  const C* post;
-  const R* lam;
+  R s0, s1, g0, g1, hs;
+  BHX_GLOBAL const C* twg;    // twiddles in device memory
+  const C* tw;                // twiddles in LDS once staged
+  BHX_GLOBAL const C* chirp;
+  BHX_GLOBAL const C* bhat;
+  BHX_GLOBAL const C* post;
+  BHX_GLOBAL const R* lam;
+  const C* postl;             // post-twiddles in LDS once staged
+  const R* laml;              // eigenvalues in LDS once staged
+  // Copy the plan's twiddles, DCT post-twiddles and eigenvalues into LDS at
+  // `lds` unless plan `idx` is staged there already; every thread of the
+  // block must call this at the same point.
+  __device__ void stage(C* lds, int idx, int& staged) {
+    C* tw_l = lds;
+    C* post_l = lds + (m >> 1);
+    R* lam_l = (R*)(post_l + n);
+    if (idx != staged) {
+      for (int k = threadIdx.x; k < (m >> 1); k += kThreads) tw_l[k] = twg[k];
+      if (bc == kNeumann)
+        for (int k = threadIdx.x; k < n; k += kThreads) post_l[k] = post[k];
+      for (int k = threadIdx.x; k < n; k += kThreads) lam_l[k] = lam[k];
+      __syncthreads();
+      staged = idx;
+    }
+    tw = tw_l;
+    postl = post_l;
+    laml = lam_l;
+  }
   __device__ XPlan(const Batch& B, int idx) {
-    const AxisPlan& P = B.plans[idx];
+    const AxisPlan P = B.plans[idx];
     n = P.n; m = P.m; logm = P.logm; blue = P.bluestein; bc = P.bc;
+    s0 = (R)P.s0; s1 = (R)P.s1; g0 = (R)P.g0; g1 = (R)P.g1; hs = (R)P.hs;
     const int pi = sizeof(R) == 8 ? 0 : 1;
-    const C* ct = (const C*)B.ctab[pi];
-    tw = ct + P.off_tw;
+    BHX_GLOBAL const C* ct = (BHX_GLOBAL const C*)B.ctab[pi];
+    twg = ct + P.off_tw;
+    tw = nullptr;
+    postl = nullptr;
+    laml = nullptr;
     chirp = ct + P.off_chirp;
     bhat = ct + P.off_bhat;
     post = ct + P.off_post;
-    lam = (const R*)B.rtab[pi] + P.off_lam;
+    lam = (BHX_GLOBAL const R*)B.rtab[pi] + P.off_lam;
   }
-  // LDS position of logical FFT input k
-  __device__ __forceinline__ int pos(int k) const { return bitrev(k, logm); }
+  // padded LDS position of logical FFT input k
+  __device__ __forceinline__ int pos(int k) const { return pad8(bitrev(k, logm)); }
+  // row stride of the packed rows (padded)
+  __device__ __forceinline__ int stride() const { return pad8(m); }
   // logical FFT output k of a row (after core())
   __device__ __forceinline__ C out(const C* row, int k) const {
-    if (!blue) return row[k];
-    return cmul(chirp[k], row[bitrev(k, logm)]);
+    if (!blue) return row[pad8(k)];
+    return cmul(chirp[k], row[pad8(bitrev(k, logm))]);
   }
 };
 
@@ -159,10 +326,11 @@ __device__ void fft_dit(typename V2<R>::T* buf, int rows, int st, int m, int log
     const int half = m >> 1;
     for (int idx = tid; idx < rows * half; idx += kThreads) {
       const int r = idx >> (logm - 1), b = (idx & (half - 1)) << 1;
-      C* a = buf + r * st + b;
-      C u = a[0], v = a[1];
-      a[0] = cadd(u, v);
-      a[1] = csub(u, v);
+      C* a = buf + r * st;
+      const int i0 = pad8(b), i1 = pad8(b + 1);
+      C u = a[i0], v = a[i1];
+      a[i0] = cadd(u, v);
+      a[i1] = csub(u, v);
     }
     __syncthreads();
     h = 2; lh = 1;
@@ -175,20 +343,22 @@ __device__ void fft_dit(typename V2<R>::T* buf, int rows, int st, int m, int log
       const int r = idx >> lq, rem = idx & (quarter - 1);
       const int k = rem & (h - 1);
       const int b = (rem - k) << 2;
-      C* a = buf + r * st + b + k;
+      C* a = buf + r * st;
+      const int i0 = pad8(b + k), i1 = pad8(b + k + h), i2 = pad8(b + k + 2 * h),
+                i3 = pad8(b + k + 3 * h);
       const C w1 = tw[k << ls1];
       const C w2 = tw[k << ls2];
-      C a0 = a[0], a1 = a[h], a2 = a[2 * h], a3 = a[3 * h];
+      C a0 = a[i0], a1 = a[i1], a2 = a[i2], a3 = a[i3];
       C t = cmul(w1, a1);
       C t0 = cadd(a0, t), t1 = csub(a0, t);
       t = cmul(w1, a3);
       C t2 = cadd(a2, t), t3 = csub(a2, t);
       t = cmul(w2, t2);
-      a[0] = cadd(t0, t);
-      a[2 * h] = csub(t0, t);
+      a[i0] = cadd(t0, t);
+      a[i2] = csub(t0, t);
       t = cmul_mi(cmul(w2, t3));          // W_4h^(k+h) = W_4h^k * (-i)
-      a[h] = cadd(t1, t);
-      a[3 * h] = csub(t1, t);
+      a[i1] = cadd(t1, t);
+      a[i3] = csub(t1, t);
     }
     __syncthreads();
   }
@@ -210,16 +380,18 @@ __device__ void fft_dif_inv(typename V2<R>::T* buf, int rows, int st, int m, int
       const int r = idx >> lq, rem = idx & (quarter - 1);
       const int k = rem & (h - 1);
       const int b = (rem - k) << 2;
-      C* a = buf + r * st + b + k;
+      C* a = buf + r * st;
+      const int i0 = pad8(b + k), i1 = pad8(b + k + h), i2 = pad8(b + k + 2 * h),
+                i3 = pad8(b + k + 3 * h);
       const C w1 = cconj(tw[k << ls1]);
       const C w2 = cconj(tw[k << ls2]);
-      C a0 = a[0], a1 = a[h], a2 = a[2 * h], a3 = a[3 * h];
+      C a0 = a[i0], a1 = a[i1], a2 = a[i2], a3 = a[i3];
       C t0 = cadd(a0, a2), t2 = cmul(csub(a0, a2), w2);
       C t1 = cadd(a1, a3), t3 = cmul_pi(cmul(csub(a1, a3), w2));   // conj(W_4h^(k+h))
-      a[0] = cadd(t0, t1);
-      a[h] = cmul(csub(t0, t1), w1);
-      a[2 * h] = cadd(t2, t3);
-      a[3 * h] = cmul(csub(t2, t3), w1);
+      a[i0] = cadd(t0, t1);
+      a[i1] = cmul(csub(t0, t1), w1);
+      a[i2] = cadd(t2, t3);
+      a[i3] = cmul(csub(t2, t3), w1);
     }
     __syncthreads();
     if (h == 1) break;
@@ -228,10 +400,11 @@ __device__ void fft_dif_inv(typename V2<R>::T* buf, int rows, int st, int m, int
     const int half = m >> 1;
     for (int idx = tid; idx < rows * half; idx += kThreads) {
       const int r = idx >> (logm - 1), b = (idx & (half - 1)) << 1;
-      C* a = buf + r * st + b;
-      C u = a[0], v = a[1];
-      a[0] = cadd(u, v);
-      a[1] = csub(u, v);
+      C* a = buf + r * st;
+      const int i0 = pad8(b), i1 = pad8(b + 1);
+      C u = a[i0], v = a[i1];
+      a[i0] = cadd(u, v);
+      a[i1] = csub(u, v);
     }
     __syncthreads();
   }
@@ -242,14 +415,14 @@ __device__ void fft_dif_inv(typename V2<R>::T* buf, int rows, int st, int m, int
 template <typename R>
 __device__ void dft_core(const XPlan<R>& X, typename V2<R>::T* buf, int rows) {
   using C = typename V2<R>::T;
-  const int st = X.m;
+  const int st = X.stride();
   if (X.blue) {
     for (int idx = threadIdx.x; idx < rows * X.m; idx += kThreads) {
       const int r = idx >> X.logm, k = idx & (X.m - 1);
       C* row = buf + r * st;
-      const int p = bitrev(k, X.logm);
-      if (k < X.n) row[p] = cmul(row[p], X.chirp[k]);
-      else row[p] = mk<C>(0, 0);
+      const int p = X.pos(k);
+      const C c = X.chirp[min(k, X.n - 1)];
+      row[p] = k < X.n ? cmul(row[p], c) : mk<C>(0, 0);
     }
     __syncthreads();
   }
@@ -257,7 +430,8 @@ __device__ void dft_core(const XPlan<R>& X, typename V2<R>::T* buf, int rows) {
   if (X.blue) {
     for (int idx = threadIdx.x; idx < rows * X.m; idx += kThreads) {
       const int r = idx >> X.logm, k = idx & (X.m - 1);
-      buf[r * st + k] = cmul(buf[r * st + k], X.bhat[k]);
+      const int p = r * st + pad8(k);
+      buf[p] = cmul(buf[p], X.bhat[k]);
     }
     __syncthreads();
     fft_dif_inv<R>(buf, rows, st, X.m, X.logm, X.tw);
@@ -287,21 +461,19 @@ __device__ __forceinline__ void fwd_post_pair(const XPlan<R>& X, typename V2<R>:
                                               typename V2<R>::T Dk, int k, int kk, R& xa_k,
                                               R& xb_k, R& xa_kk, R& xb_kk) {
   using C = typename V2<R>::T;
-  const R n = (R)X.n;
   if (X.bc == kNeumann) {
     const C va = mk<C>((Ck.x + Dk.x) * (R)0.5, (Ck.y - Dk.y) * (R)0.5);
     // (C - conj D)/(2i) = ((Ci + Di) - i (Cr - Dr)) / 2
     const C vb = mk<C>((Ck.y + Dk.y) * (R)0.5, -(Ck.x - Dk.x) * (R)0.5);
-    const R s0 = sqrt((R)1 / n), s1 = sqrt((R)2 / n);
-    const C tk = X.post[k];
-    xa_k = (k == 0 ? s0 : s1) * (tk.x * va.x - tk.y * va.y);
-    xb_k = (k == 0 ? s0 : s1) * (tk.x * vb.x - tk.y * vb.y);
+    const C tk = X.postl[k];
+    xa_k = (k == 0 ? X.s0 : X.s1) * (tk.x * va.x - tk.y * va.y);
+    xb_k = (k == 0 ? X.s0 : X.s1) * (tk.x * vb.x - tk.y * vb.y);
     // V[kk] = conj(V[k])
-    const C tkk = X.post[kk];
-    xa_kk = (kk == 0 ? s0 : s1) * (tkk.x * va.x + tkk.y * va.y);
-    xb_kk = (kk == 0 ? s0 : s1) * (tkk.x * vb.x + tkk.y * vb.y);
+    const C tkk = X.postl[kk];
+    xa_kk = (kk == 0 ? X.s0 : X.s1) * (tkk.x * va.x + tkk.y * va.y);
+    xb_kk = (kk == 0 ? X.s0 : X.s1) * (tkk.x * vb.x + tkk.y * vb.y);
   } else {
-    const R sc = (R)0.5 / sqrt(n);
+    const R sc = X.hs;
     xa_k = (Ck.x + Dk.x - Ck.y + Dk.y) * sc;
     xb_k = (Ck.y + Dk.y + Ck.x - Dk.x) * sc;
     xa_kk = (Dk.x + Ck.x - Dk.y + Ck.y) * sc;
@@ -320,9 +492,7 @@ __device__ __forceinline__ void inv_pre_pair(const XPlan<R>& X, R ya_k, R yb_k, 
                                              typename V2<R>::T& in_kk) {
   using C = typename V2<R>::T;
   if (X.bc == kNeumann) {
-    const R n = (R)X.n;
-    const R g0 = (R)1 / sqrt(n), g1 = (R)1 / sqrt((R)2 * n);
-    const R gk = k == 0 ? g0 : g1, gkk = kk == 0 ? g0 : g1;
+    const R gk = k == 0 ? X.g0 : X.g1, gkk = kk == 0 ? X.g0 : X.g1;
     C Pk = mk<C>(gk * ya_k, gk * yb_k);
     C Pkk = mk<C>(gkk * ya_kk, gkk * yb_kk);
     if (k == 0) {
@@ -330,8 +500,8 @@ __device__ __forceinline__ void inv_pre_pair(const XPlan<R>& X, R ya_k, R yb_k, 
       in_kk = in_k;
       return;
     }
-    const C tk = cconj(X.post[k]);         // exp(+i pi k / 2n)
-    const C tkk = cconj(X.post[kk]);
+    const C tk = cconj(X.postl[k]);        // exp(+i pi k / 2n)
+    const C tkk = cconj(X.postl[kk]);
     const C Wk = cmul(tk, csub(Pk, cmul_pi(Pkk)));    // P[k] - i P[n-k]
     const C Wkk = cmul(tkk, csub(Pkk, cmul_pi(Pk)));
     in_k = cconj(Wk);
@@ -347,11 +517,11 @@ __device__ __forceinline__ void inv_pre_pair(const XPlan<R>& X, R ya_k, R yb_k, 
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kThreads) k_setup(const Batch* __restrict__ Bp) {
-  const Batch& B = *Bp;
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   __shared__ double red[4];
   for (int it = logical_block(); it < B.n_items[kPassS]; it += gridDim.x) {
-    const int code = B.items[kPassS][it];
-    const Inst& I = B.inst[code >> kItemShift];
+    const int code = item_code(B, kPassS, it);
+    const Inst I = B.inst[code >> kItemShift];
     const int tile = code & kItemMask;
     if (I.ctl->done) continue;
     const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
@@ -379,39 +549,123 @@ __global__ void __launch_bounds__(kThreads) k_setup(const Batch* __restrict__ Bp
   }
 }
 
+// Unknown nodes per row group (row passes skip groups without any).
+__global__ void __launch_bounds__(kThreads) k_setup_rows(const Batch* __restrict__ Bp) {
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
+  __shared__ double red[4];
+  for (int it = logical_block(); it < B.n_items[kPassR]; it += gridDim.x) {
+    const int code = item_code(B, kPassR, it);
+    const Inst I = B.inst[code >> kItemShift];
+    const int g = code & kItemMask;
+    if (I.ctl->done) continue;
+    const int j0 = g * I.G;
+    const int E = min(I.G, I.ny - j0) * I.nx;
+    BHX_GLOBAL const uint8_t* mk = I.mask + (size_t)j0 * I.nx;
+    double cnt = 0;
+    for (int e = threadIdx.x; e < E; e += kThreads) cnt += mk[e];
+    cnt = block_sum(cnt, red);
+    if (threadIdx.x == 0) {
+      PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
+      I.part[PL.rowcnt() + g] = cnt;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Stencil pass: 13-point operator as L(L f) on an LDS tile with a two-node
 // halo whose ghost values follow each axis' rule.
 // ---------------------------------------------------------------------------
 
+constexpr int kUnroll = 4;                          // loads in flight per thread
+constexpr int kPre = 8;                             // elements per thread loaded up front
 constexpr int kPW = kTileX + 4, kPH = kTileY + 4;   // f tile with 2-node halo
 constexpr int kLW = kTileX + 2, kLH = kTileY + 2;   // L f with 1-node halo
+constexpr int kPL = (kPH * kPW + kThreads - 1) / kThreads;   // halo loads per thread
 
-__global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ Bp, int mode) {
-  const Batch& B = *Bp;
+template <int MODE>
+__global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ Bp) {
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   __shared__ double P[kPH][kPW + 1];
   __shared__ double L[kLH][kLW + 1];
-  __shared__ double red[4];
+  __shared__ double red[16];
+  constexpr int kOut = kTileX * kTileY / kThreads;
   for (int it = logical_block(); it < B.n_items[kPassS]; it += gridDim.x) {
-    const int code = B.items[kPassS][it];
-    const Inst& I = B.inst[code >> kItemShift];
+    const int code = item_code(B, kPassS, it);
+    const Inst I = B.inst[code >> kItemShift];
     const int tile = code & kItemMask;
-    Ctl* ctl = I.ctl;
-    if (ctl->done) continue;
-    const int nx = I.nx, ny = I.ny;
+    BHX_GLOBAL Ctl* ctl = I.ctl;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
+    // control fields and the tile's unknown count, loaded together
+    const int c_done = ctl->done, c_iter = ctl->iter, c_rit = ctl->restart_iter;
+    const double c_thresh = ctl->thresh;
+    const bool has_u = I.part[PL.aux2() + tile] != 0.0;     // unknown nodes in this tile
+    if (c_done) continue;
+    const int nx = I.nx, ny = I.ny;
+    const int out_slot = (MODE == kModeIter ? PL.pq() : PL.aux()) + tile;
+    if (!has_u && tile != 0) {             // nothing to compute or store here
+      if (threadIdx.x == 0) I.part[out_slot] = 0.0;
+      continue;
+    }
+    // 1. issue every load of the item: the partial sums behind alpha/beta,
+    //    the halo tile (z, p_old or F, mask) and the output masks
+    const int k = c_iter;
+    const int par = k & 1;
+    const bool first = (k == c_rit);
+    BHX_GLOBAL const double* pold = first ? I.z : ((k & 1) ? I.p[1] : I.p[0]);
+    BHX_GLOBAL double* pnew = (k & 1) ? I.p[0] : I.p[1];
+    BHX_GLOBAL const double* arrs[4] = {I.part + PL.rz(par), I.part + PL.rr(),
+                                        I.part + PL.rz(par ^ 1), I.part + PL.rzo(par)};
+    const int ns[4] = {MODE == kModeIter ? PL.nR : 0, (MODE == kModeIter && !first) ? PL.nR : 0,
+                       (MODE == kModeIter && !first) ? PL.nR : 0,
+                       (MODE == kModeIter && !first && I.flexible) ? PL.nR : 0};
+    Partials<4> PS;
+    sums_issue<4>(arrs, ns, PS);
+    const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
+    const int i0 = tx * kTileX, j0 = ty * kTileY;
+    int oo[kPL];
+    double sg[kPL], va[kPL], vb[kPL];
+    uint8_t vm[kPL], mo[kOut];
+#pragma unroll
+    for (int s = 0; s < kPL; ++s) {
+      const int e = min(threadIdx.x + s * kThreads, kPH * kPW - 1);
+      const int jj = e / kPW, ii = e - jj * kPW;
+      double sx, sy;
+      const int mi = map_axis_sel(i0 + ii - 2, nx, I.bcx, sx);
+      const int mj = map_axis_sel(j0 + jj - 2, ny, I.bcy, sy);
+      sg[s] = sx * sy;
+      oo[s] = mj * nx + mi;
+    }
+#pragma unroll
+    for (int s = 0; s < kPL; ++s) {
+      const int o = oo[s];
+      if (MODE == kModeIter) {
+        va[s] = I.z[o];
+        vb[s] = pold[o];
+      } else if (MODE == kModeRhs) {
+        va[s] = I.F[o];
+        vm[s] = I.mask[o];
+      } else {
+        va[s] = I.z[o];
+        vm[s] = I.mask[o];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kOut; ++s) {
+      const int e = threadIdx.x + s * kThreads;
+      const int jj = e / kTileX, ii = e - jj * kTileX;
+      const int gi = min(i0 + ii, nx - 1), gj = min(j0 + jj, ny - 1);
+      mo[s] = I.mask[gj * nx + gi];
+    }
+    // 2. scalars: convergence test and beta (the data loads stay in flight)
     double beta = 0.0;
-    const double* pold = nullptr;
-    double* pnew = nullptr;
-    if (mode == kModeIter) {
-      const int k = ctl->iter;
-      const int par = k & 1;
-      const double rz = block_sum_array(I.part + PL.rz(par), PL.nR, red);
-      const bool first = (k == ctl->restart_iter);
+    if (MODE == kModeIter) {
+      double sums[4];
+      sums_finish<4>(arrs, ns, PS, sums, red);
+      const double rz = sums[0];
       if (!first) {
-        const double rr = block_sum_array(I.part + PL.rr(), PL.nR, red);
+        const double rr = sums[1];
         int d = kRunning;
-        if (!(rr <= ctl->thresh)) {
+        if (!(rr <= c_thresh)) {
           if (k >= I.maxit) d = kMaxIt;
           else if (!(rr == rr) || rr > 1e300) d = kBreakdown;
         } else {
@@ -424,48 +678,29 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
           }
           continue;
         }
-        const double rzold = block_sum_array(I.part + PL.rz(par ^ 1), PL.nR, red);
-        if (I.flexible) {
-          const double rzo = block_sum_array(I.part + PL.rzo(par), PL.nR, red);
-          beta = (rz - rzo) / rzold;
-        } else {
-          beta = rz / rzold;
-        }
+        beta = I.flexible ? (rz - sums[3]) / sums[2] : rz / sums[2];
       }
       if (!(rz > 0.0) || !(beta == beta)) {
         if (tile == 0 && threadIdx.x == 0) ctl->done = kBreakdown;
         continue;
       }
-      pold = first ? nullptr : I.p[k & 1];
-      pnew = I.p[(k + 1) & 1];
     }
-    const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
-    const int i0 = tx * kTileX, j0 = ty * kTileY;
-    for (int e = threadIdx.x; e < kPH * kPW; e += kThreads) {
-      const int jj = e / kPW, ii = e - jj * kPW;
-      const int gi = i0 + ii - 2, gj = j0 + jj - 2;
-      double v = 0.0;
-      if (gi >= -2 && gi <= nx + 1 && gj >= -2 && gj <= ny + 1) {
-        double sx, sy;
-        const int mi = map_axis(gi, nx, I.bcx, sx);
-        const int mj = map_axis(gj, ny, I.bcy, sy);
-        const double s = sx * sy;
-        if (s != 0.0) {
-          const size_t o = (size_t)mj * nx + mi;
-          if (mode == kModeIter) {
-            v = I.z[o];
-            if (pold) v += beta * pold[o];
-          } else if (mode == kModeRhs) {
-            v = I.mask[o] ? 0.0 : I.F[o];
-          } else if (mode == kModeApply) {
-            v = I.mask[o] ? I.z[o] : 0.0;
-          } else {
-            v = I.F[o];
-          }
-          v *= s;
-        }
+    if (!has_u) {
+      if (threadIdx.x == 0) I.part[out_slot] = 0.0;
+      continue;
+    }
+    // 3. tile of the operand in LDS, L f on the one-node ring, then L L f
+#pragma unroll
+    for (int s = 0; s < kPL; ++s) {
+      const int e = threadIdx.x + s * kThreads;
+      double v;
+      if (MODE == kModeIter) v = va[s] + beta * vb[s];
+      else if (MODE == kModeRhs) v = vm[s] ? 0.0 : va[s];
+      else v = vm[s] ? va[s] : 0.0;
+      if (e < kPH * kPW) {
+        const int jj = e / kPW, ii = e - jj * kPW;
+        P[jj][ii] = sg[s] * v;
       }
-      P[jj][ii] = v;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < kLH * kLW; e += kThreads) {
@@ -475,30 +710,31 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
     }
     __syncthreads();
     double acc = 0.0;
-    for (int e = threadIdx.x; e < kTileX * kTileY; e += kThreads) {
+#pragma unroll
+    for (int s = 0; s < kOut; ++s) {
+      const int e = threadIdx.x + s * kThreads;
       const int jj = e / kTileX, ii = e - jj * kTileX;
       const int gi = i0 + ii, gj = j0 + jj;
-      if (gi < nx && gj < ny) {
-        const size_t o = (size_t)gj * nx + gi;
-        if (I.mask[o]) {
-          const double qv = 4.0 * L[jj + 1][ii + 1] - L[jj][ii + 1] - L[jj + 2][ii + 1] -
-                            L[jj + 1][ii] - L[jj + 1][ii + 2];
-          if (mode == kModeIter) {
-            const double pv = P[jj + 2][ii + 2];
-            pnew[o] = pv;
-            I.q[o] = qv;
-            acc += pv * qv;
-          } else if (mode == kModeApply) {
-            I.q[o] = qv;
-          } else {
-            I.r[o] = -qv;
-            acc += qv * qv;
-          }
+      const double qv = 4.0 * L[jj + 1][ii + 1] - L[jj][ii + 1] - L[jj + 2][ii + 1] -
+                        L[jj + 1][ii] - L[jj + 1][ii + 2];
+      const bool st = gi < nx && gj < ny && mo[s];
+      const int o = gj * nx + gi;
+      if (MODE == kModeIter) {
+        const double pv = P[jj + 2][ii + 2];
+        if (st) {
+          pnew[o] = pv;
+          I.q[o] = qv;
         }
+        acc += st ? pv * qv : 0.0;
+      } else if (MODE == kModeApply) {
+        if (st) I.q[o] = qv;
+      } else {
+        if (st) I.r[o] = -qv;
+        acc += st ? qv * qv : 0.0;
       }
     }
     acc = block_sum(acc, red);
-    if (threadIdx.x == 0) I.part[(mode == kModeIter ? PL.pq() : PL.aux()) + tile] = acc;
+    if (threadIdx.x == 0) I.part[out_slot] = acc;
   }
 }
 
@@ -535,19 +771,23 @@ __device__ __forceinline__ dd five_point_dd(dd c, dd n, dd s, dd w, dd e) {
 }
 
 __global__ void __launch_bounds__(kThreads) k_resid(const Batch* __restrict__ Bp) {
-  const Batch& B = *Bp;
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   __shared__ double P[kPH][kPW + 1];
   __shared__ double Lh[kLH][kLW + 1];
   __shared__ double Ll[kLH][kLW + 1];
   __shared__ double red[4];
   for (int it = logical_block(); it < B.n_items[kPassS]; it += gridDim.x) {
-    const int code = B.items[kPassS][it];
-    const Inst& I = B.inst[code >> kItemShift];
+    const int code = item_code(B, kPassS, it);
+    const Inst I = B.inst[code >> kItemShift];
     const int tile = code & kItemMask;
     const int dn = I.ctl->done;
     if (dn != kConverged && dn != kMaxIt) continue;
     const int nx = I.nx, ny = I.ny;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
+    if (I.part[PL.aux2() + tile] == 0.0) {
+      if (threadIdx.x == 0) I.part[PL.aux() + tile] = 0.0;
+      continue;
+    }
     const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
     const int i0 = tx * kTileX, j0 = ty * kTileY;
     for (int e = threadIdx.x; e < kPH * kPW; e += kThreads) {
@@ -602,55 +842,116 @@ __global__ void __launch_bounds__(kThreads) k_resid(const Batch* __restrict__ Bp
 // ---------------------------------------------------------------------------
 
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ Bp, int update) {
+__global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ Bp, int update,
+                                                     int twoff) {
   using C = typename V2<R>::T;
-  const Batch& B = *Bp;
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   extern __shared__ __align__(16) unsigned char smem[];
   C* buf = (C*)smem;
   R* stg = (R*)smem;
-  __shared__ double red[4];
+  C* twl = buf + twoff;
+  int staged = -1;
+  __shared__ double red[8];
   for (int itm = logical_block(); itm < B.n_items[kPassR]; itm += gridDim.x) {
-    const int code = B.items[kPassR][itm];
-    const Inst& I = B.inst[code >> kItemShift];
+    const int code = item_code(B, kPassR, itm);
+    const Inst I = B.inst[code >> kItemShift];
     const int g = code & kItemMask;
-    Ctl* ctl = I.ctl;
-    if (ctl->done) continue;
-    const int nx = I.nx, ny = I.ny, G = I.G, j0 = g * G;
+    BHX_GLOBAL Ctl* ctl = I.ctl;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
-    const int k_it = ctl->iter;
-    double alpha = 0.0;
-    const double* pcur = nullptr;
-    if (update) {
-      const double rz = block_sum_array(I.part + PL.rz(k_it & 1), PL.nR, red);
-      const double pq = block_sum_array(I.part + PL.pq(), PL.nS, red);
-      alpha = rz / pq;
-      pcur = I.p[(k_it + 1) & 1];
+    const int c_done = ctl->done, k_it = ctl->iter;
+    const double rowcnt = I.part[PL.rowcnt() + g];
+    if (c_done) continue;
+    const int nx = I.nx, ny = I.ny, G = I.G, j0 = g * G;
+    const int E = min(G, ny - j0) * nx;          // valid elements of this row group
+    const size_t base = (size_t)j0 * nx;
+    BHX_GLOBAL const uint8_t* __restrict__ mk = I.mask + base;
+    BHX_GLOBAL double* __restrict__ Fb = I.F + base;
+    BHX_GLOBAL double* __restrict__ rb = I.r + base;
+    BHX_GLOBAL const double* __restrict__ pb = ((k_it & 1) ? I.p[0] : I.p[1]) + base;
+    BHX_GLOBAL const double* __restrict__ qb = I.q + base;
+    // 1. issue: partial sums behind alpha, then the masks of the first
+    //    kPre elements per thread (rows j0 .. j0+G-1 are contiguous)
+    BHX_GLOBAL const double* arrs[2] = {I.part + PL.rz(k_it & 1), I.part + PL.pq()};
+    const int ns[2] = {update ? PL.nR : 0, update ? PL.nS : 0};
+    Partials<2> PS;
+    sums_issue<2>(arrs, ns, PS);
+    int m0[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      m0[u] = mk[min(e, E - 1)] && e < E;
     }
-    const XPlan<R> X(B, I.planx);
-    const int rows = G >> 1;
-    const int st = X.m;
-    double acc = 0.0;
-    // 1. update and place r into the packed rows
-    for (int e = threadIdx.x; e < G * nx; e += kThreads) {
-      const int jr = e / nx, i = e - jr * nx;
-      const int j = j0 + jr;
-      double rv = 0.0;
-      if (j < ny) {
-        const size_t o = (size_t)j * nx + i;
-        if (I.mask[o]) {
-          rv = I.r[o];
-          if (update) {
-            const double pv = pcur[o];
-            const double xv = (k_it == 0 ? 0.0 : I.F[o]) + alpha * pv;
-            I.F[o] = xv;
-            rv -= alpha * I.q[o];
-            I.r[o] = rv;
-            acc += rv * rv;
-          }
-        }
+    if (rowcnt == 0.0) {
+      // no unknown node in these rows: r = 0 there, so is its transform
+      BHX_GLOBAL R* t = (BHX_GLOBAL R*)I.t;
+      for (int e = threadIdx.x; e < nx * G; e += kThreads) {
+        const int kx = e / G, j = j0 + (e - kx * G);
+        if (j < ny) t[(size_t)kx * ny + j] = (R)0;
       }
-      R* cell = (R*)(buf + (jr >> 1) * st + X.pos(fwd_index(i, nx, X.bc)));
-      cell[jr & 1] = (R)rv;
+      if (update && threadIdx.x == 0) I.part[PL.rr() + g] = 0.0;
+      continue;
+    }
+    // 2. values at unknown nodes (lanes of known nodes read element 0: one
+    //    cached line per wave), in flight while tables and scalars settle
+    double rv0[kPre], pv0[kPre], qv0[kPre], xv0[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int ea = m0[u] ? threadIdx.x + u * kThreads : 0;
+      rv0[u] = rb[ea];
+      pv0[u] = update ? pb[ea] : 0.0;
+      qv0[u] = update ? qb[ea] : 0.0;
+      xv0[u] = update ? Fb[ea] : 0.0;
+    }
+    XPlan<R> X(B, I.planx);
+    if (update != 2) X.stage(twl, I.planx, staged);
+    double alpha = 0.0;
+    if (update) {
+      double sums[2];
+      sums_finish<2>(arrs, ns, PS, sums, red);
+      alpha = sums[0] / sums[1];
+    }
+    const int rows = G >> 1;
+    const int st = X.stride();
+    const bool first = k_it == 0;
+    double acc = 0.0;
+    // 3. update and place r into the packed rows
+    auto consume = [&](int e, int m, double rv, double pv, double qv, double xv) {
+      if (e >= G * nx) return;
+      double v = m ? rv : 0.0;
+      if (update && m) {
+        Fb[e] = (first ? 0.0 : xv) + alpha * pv;
+        v -= alpha * qv;
+        rb[e] = v;
+        acc += v * v;
+      }
+      if (update != 2) {
+        const int jr = e / nx, i = e - jr * nx;
+        R* cell = (R*)(buf + (jr >> 1) * st + X.pos(fwd_index(i, nx, X.bc)));
+        cell[jr & 1] = (R)v;
+      }
+    };
+#pragma unroll
+    for (int u = 0; u < kPre; ++u)
+      consume(threadIdx.x + u * kThreads, m0[u], rv0[u], pv0[u], qv0[u], xv0[u]);
+    for (int e0 = threadIdx.x + kPre * kThreads; e0 < G * nx; e0 += kUnroll * kThreads) {
+      int m[kUnroll];
+      double rv[kUnroll], pv[kUnroll], qv[kUnroll], xv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int e = e0 + u * kThreads;
+        m[u] = mk[min(e, E - 1)] && e < E;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int ea = m[u] ? e0 + u * kThreads : 0;
+        rv[u] = rb[ea];
+        pv[u] = update ? pb[ea] : 0.0;
+        qv[u] = update ? qb[ea] : 0.0;
+        xv[u] = update ? Fb[ea] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        consume(e0 + u * kThreads, m[u], rv[u], pv[u], qv[u], xv[u]);
     }
     __syncthreads();
     if (update) {
@@ -692,7 +993,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
     }
     __syncthreads();
     // 5. coalesced transposed store
-    R* t = (R*)I.t;
+    BHX_GLOBAL R* t = (BHX_GLOBAL R*)I.t;
     for (int e = threadIdx.x; e < nx * G; e += kThreads) {
       const int k = e / G, jr = e - k * G;
       const int j = j0 + jr;
@@ -708,31 +1009,44 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
 // ---------------------------------------------------------------------------
 
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, int count_iter) {
+__global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, int count_iter,
+                                                  int twoff) {
   using C = typename V2<R>::T;
-  const Batch& B = *Bp;
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   extern __shared__ __align__(16) unsigned char smem[];
   C* buf = (C*)smem;
+  C* twl = buf + twoff;
+  int staged = -1;
   for (int itm = logical_block(); itm < B.n_items[kPassC]; itm += gridDim.x) {
-    const int code = B.items[kPassC][itm];
-    const Inst& I = B.inst[code >> kItemShift];
+    const int code = item_code(B, kPassC, itm);
+    const Inst I = B.inst[code >> kItemShift];
     const int c = code & kItemMask;
-    Ctl* ctl = I.ctl;
+    BHX_GLOBAL Ctl* ctl = I.ctl;
     if (ctl->done) continue;
     const int nx = I.nx, ny = I.ny, Gc = I.Gc, kx0 = c * Gc;
-    const XPlan<R> X(B, I.plany);
+    BHX_GLOBAL R* t = (BHX_GLOBAL R*)I.t;
+    // 1. issue the first kPre loads of the item's rows of t (contiguous:
+    //    rows kx0 .. kx0+Gc-1 of t, clamped), then stage the plan tables
+    const int Et = min(Gc, nx - kx0) * ny;
+    BHX_GLOBAL const R* tb = t + (size_t)kx0 * ny;
+    R tv[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) tv[u] = tb[min((int)threadIdx.x + u * kThreads, Et - 1)];
+    XPlan<R> X(B, I.plany);
+    X.stage(twl, I.plany, staged);
     const XPlan<R> Xx(B, I.planx);
     const int rows = Gc >> 1;
-    const int st = X.m;
-    R* t = (R*)I.t;
-    // 1. load and place
-    for (int e = threadIdx.x; e < Gc * ny; e += kThreads) {
+    const int st = X.stride();
+    auto place = [&](int e, R v) {
+      if (e >= Gc * ny) return;
       const int cr = e / ny, j = e - cr * ny;
-      const int kx = kx0 + cr;
-      const R v = kx < nx ? t[(size_t)kx * ny + j] : (R)0;
       R* cell = (R*)(buf + (cr >> 1) * st + X.pos(fwd_index(j, ny, X.bc)));
-      cell[cr & 1] = v;
-    }
+      cell[cr & 1] = e < Et ? v : (R)0;
+    };
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) place(threadIdx.x + u * kThreads, tv[u]);
+    for (int e = threadIdx.x + kPre * kThreads; e < Gc * ny; e += kThreads)
+      place(e, tb[min(e, Et - 1)]);
     __syncthreads();
     dft_core<R>(X, buf, rows);
     // 2. spectra, scale by 1/(lambda_x + lambda_y)^2, inverse inputs
@@ -748,13 +1062,13 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
         R xa, xb, xak, xbk;
         fwd_post_pair<R>(X, X.out(row, k), X.out(row, kk), k, kk, xa, xb, xak, xbk);
         const int kxa = kx0 + 2 * rr, kxb = kxa + 1;
-        const R la = kxa < nx ? Xx.lam[kxa] : (R)0;
-        const R lb = kxb < nx ? Xx.lam[kxb] : (R)0;
-        R s1 = la + X.lam[k], s2 = lb + X.lam[k], s3 = la + X.lam[kk], s4 = lb + X.lam[kk];
-        xa = s1 > (R)0 ? xa / (s1 * s1) : (R)0;
-        xb = s2 > (R)0 ? xb / (s2 * s2) : (R)0;
-        xak = s3 > (R)0 ? xak / (s3 * s3) : (R)0;
-        xbk = s4 > (R)0 ? xbk / (s4 * s4) : (R)0;
+        const R la = Xx.lam[min(kxa, nx - 1)];
+        const R lb = Xx.lam[min(kxb, nx - 1)];
+        const R lk = X.laml[k], lkk = X.laml[kk];
+        xa *= inv_sq<R>(la + lk);
+        xb *= inv_sq<R>(lb + lk);
+        xak *= inv_sq<R>(la + lkk);
+        xbk *= inv_sq<R>(lb + lkk);
         inv_pre_pair<R>(X, xa, xb, xak, xbk, k, kk, vin[s][0], vin[s][1]);
       }
     }
@@ -783,7 +1097,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
         }
       }
     } else {
-      R vo[kMaxPairs][4];
+      // Hartley: the inverse is the forward transform; reuse vin's registers
 #pragma unroll
       for (int s = 0; s < kMaxPairs; ++s) {
         const int pidx = threadIdx.x + s * kThreads;
@@ -791,8 +1105,10 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
           const int rr = pidx / np, k = pidx - rr * np;
           const int kk = k == 0 ? 0 : ny - k;
           const C* row = buf + rr * st;
-          fwd_post_pair<R>(X, X.out(row, k), X.out(row, kk), k, kk, vo[s][0], vo[s][1],
-                           vo[s][2], vo[s][3]);
+          R a, b, ak, bk;
+          fwd_post_pair<R>(X, X.out(row, k), X.out(row, kk), k, kk, a, b, ak, bk);
+          vin[s][0] = mk<C>(a, b);
+          vin[s][1] = mk<C>(ak, bk);
         }
       }
 #pragma unroll
@@ -803,12 +1119,12 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
           const int kk = k == 0 ? 0 : ny - k;
           const int kxa = kx0 + 2 * rr, kxb = kxa + 1;
           if (kxa < nx) {
-            t[(size_t)kxa * ny + k] = vo[s][0];
-            if (kk != k) t[(size_t)kxa * ny + kk] = vo[s][2];
+            t[(size_t)kxa * ny + k] = vin[s][0].x;
+            if (kk != k) t[(size_t)kxa * ny + kk] = vin[s][1].x;
           }
           if (kxb < nx) {
-            t[(size_t)kxb * ny + k] = vo[s][1];
-            if (kk != k) t[(size_t)kxb * ny + kk] = vo[s][3];
+            t[(size_t)kxb * ny + k] = vin[s][0].y;
+            if (kk != k) t[(size_t)kxb * ny + kk] = vin[s][1].y;
           }
         }
       }
@@ -824,31 +1140,75 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
 // ---------------------------------------------------------------------------
 
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ Bp) {
+__global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ Bp, int twoff) {
   using C = typename V2<R>::T;
-  const Batch& B = *Bp;
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   extern __shared__ __align__(16) unsigned char smem[];
   C* buf = (C*)smem;
   R* stg = (R*)smem;
+  C* twl = buf + twoff;
+  int staged = -1;
   __shared__ double red[4];
   for (int itm = logical_block(); itm < B.n_items[kPassR]; itm += gridDim.x) {
-    const int code = B.items[kPassR][itm];
-    const Inst& I = B.inst[code >> kItemShift];
+    const int code = item_code(B, kPassR, itm);
+    const Inst I = B.inst[code >> kItemShift];
     const int g = code & kItemMask;
-    Ctl* ctl = I.ctl;
-    if (ctl->done) continue;
-    const int nx = I.nx, ny = I.ny, G = I.G, j0 = g * G;
+    BHX_GLOBAL Ctl* ctl = I.ctl;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
-    const int par = ctl->iter & 1;
-    const XPlan<R> X(B, I.planx);
-    const int rows = G >> 1;
-    const int st = X.m;
-    const R* t = (const R*)I.t;
-    // 1. coalesced transposed load: stg[k * G + jr] = t[k * ny + j0 + jr]
-    for (int e = threadIdx.x; e < nx * G; e += kThreads) {
+    const int c_done = ctl->done, par = ctl->iter & 1;
+    const double rowcnt = I.part[PL.rowcnt() + g];
+    if (c_done) continue;
+    const int nx = I.nx, ny = I.ny, G = I.G, j0 = g * G;
+    if (rowcnt == 0.0) {      // z stays 0 on rows without unknowns
+      if (threadIdx.x == 0) {
+        I.part[PL.rz(par) + g] = 0.0;
+        if (I.flexible) I.part[PL.rzo(par) + g] = 0.0;
+      }
+      continue;
+    }
+    BHX_GLOBAL const R* t = (BHX_GLOBAL const R*)I.t;
+    // 1. issue: the first kPre transposed loads of the spectra
+    //    (stg[k * G + jr] = t[k * ny + j0 + jr]) and the masks of the
+    //    output elements; then the output r (and z_old) values
+    const int jn = min(G, ny - j0);
+    R tv[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int e = min((int)threadIdx.x + u * kThreads, nx * G - 1);
       const int k = e / G, jr = e - k * G;
-      const int j = j0 + jr;
-      stg[e] = j < ny ? t[(size_t)k * ny + j] : (R)0;
+      tv[u] = t[(size_t)k * ny + j0 + min(jr, jn - 1)];
+    }
+    const int E = jn * nx;
+    const size_t base = (size_t)j0 * nx;
+    BHX_GLOBAL const uint8_t* __restrict__ mk = I.mask + base;
+    BHX_GLOBAL const double* __restrict__ rb = I.r + base;
+    BHX_GLOBAL double* __restrict__ zb = I.z + base;
+    const bool flex = I.flexible != 0;
+    int m0[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      m0[u] = mk[min(e, E - 1)] && e < E;
+    }
+    double rv0[kPre], zo0[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int ea = m0[u] ? threadIdx.x + u * kThreads : 0;
+      rv0[u] = rb[ea];
+      zo0[u] = flex ? zb[ea] : 0.0;
+    }
+    XPlan<R> X(B, I.planx);
+    X.stage(twl, I.planx, staged);
+    const int rows = G >> 1;
+    const int st = X.stride();
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int e = threadIdx.x + u * kThreads;
+      if (e < nx * G) stg[e] = (e % G) < jn ? tv[u] : (R)0;
+    }
+    for (int e = threadIdx.x + kPre * kThreads; e < nx * G; e += kThreads) {
+      const int k = e / G, jr = e - k * G;
+      stg[e] = jr < jn ? t[(size_t)k * ny + j0 + jr] : (R)0;
     }
     __syncthreads();
     // 2. inverse inputs of the pairs, through registers
@@ -880,13 +1240,9 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
     dft_core<R>(X, buf, rows);
     // 3. outputs: restrict, store z, dots
     double acc = 0.0, acco = 0.0;
-    const bool flex = I.flexible != 0;
-    for (int e = threadIdx.x; e < G * nx; e += kThreads) {
+    auto emit = [&](int e, int m, double rv, double zo) {
+      if (!m) return;
       const int jr = e / nx, i = e - jr * nx;
-      const int j = j0 + jr;
-      if (j >= ny) continue;
-      const size_t o = (size_t)j * nx + i;
-      if (!I.mask[o]) continue;
       const C* row = buf + (jr >> 1) * st;
       R v;
       if (X.bc == kNeumann) {
@@ -899,10 +1255,28 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
         v = (jr & 1) ? xb : xa;
       }
       const double zv = (double)v;
-      const double rv = I.r[o];
-      if (flex) acco += rv * I.z[o];
-      I.z[o] = zv;
+      zb[e] = zv;
       acc += rv * zv;
+      acco += rv * zo;
+    };
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) emit(threadIdx.x + u * kThreads, m0[u], rv0[u], zo0[u]);
+    for (int e0 = threadIdx.x + kPre * kThreads; e0 < E; e0 += kUnroll * kThreads) {
+      int m[kUnroll];
+      double rv[kUnroll], zo[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int e = e0 + u * kThreads;
+        m[u] = mk[min(e, E - 1)] && e < E;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int ea = m[u] ? e0 + u * kThreads : 0;
+        rv[u] = rb[ea];
+        zo[u] = flex ? zb[ea] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) emit(e0 + u * kThreads, m[u], rv[u], zo[u]);
     }
     acc = block_sum(acc, red);
     if (flex) acco = block_sum(acco, red);
@@ -915,13 +1289,13 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
 
 // Plain CG (no preconditioner): z = r at U; partial r.z (and r.z_old).
 __global__ void __launch_bounds__(kThreads) k_identity(const Batch* __restrict__ Bp) {
-  const Batch& B = *Bp;
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   __shared__ double red[4];
   for (int itm = logical_block(); itm < B.n_items[kPassR]; itm += gridDim.x) {
-    const int code = B.items[kPassR][itm];
-    const Inst& I = B.inst[code >> kItemShift];
+    const int code = item_code(B, kPassR, itm);
+    const Inst I = B.inst[code >> kItemShift];
     const int g = code & kItemMask;
-    Ctl* ctl = I.ctl;
+    BHX_GLOBAL Ctl* ctl = I.ctl;
     if (ctl->done) continue;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
     const int par = ctl->iter & 1;
@@ -953,12 +1327,12 @@ __global__ void __launch_bounds__(kThreads) k_identity(const Batch* __restrict__
 enum FinMode { kFinSetup = 0, kFinResid = 1 };
 
 __global__ void __launch_bounds__(kThreads) k_finalize(const Batch* __restrict__ Bp, int mode) {
-  const Batch& B = *Bp;
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   __shared__ double red[4];
   const int inst = blockIdx.x;
   if (inst >= B.count) return;
-  const Inst& I = B.inst[inst];
-  Ctl* ctl = I.ctl;
+  const Inst I = B.inst[inst];
+  BHX_GLOBAL Ctl* ctl = I.ctl;
   const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
   if (mode == kFinSetup) {
     if (ctl->done) return;
@@ -980,20 +1354,20 @@ __global__ void __launch_bounds__(kThreads) k_finalize(const Batch* __restrict__
 
 // Plain CG counts its iterations here (the preconditioned path counts in k_col).
 __global__ void k_bump(const Batch* __restrict__ Bp) {
-  const Batch& B = *Bp;
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   const int inst = blockIdx.x * blockDim.x + threadIdx.x;
   if (inst >= B.count) return;
-  Ctl* ctl = B.inst[inst].ctl;
+  BHX_GLOBAL Ctl* ctl = B.inst[inst].ctl;
   if (ctl->done) return;
   ctl->iter = ctl->iter + 1;
 }
 
 // Instances whose true residual misses the target restart from it.
 __global__ void k_restart(const Batch* __restrict__ Bp) {
-  const Batch& B = *Bp;
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   const int inst = blockIdx.x * blockDim.x + threadIdx.x;
   if (inst >= B.count) return;
-  Ctl* ctl = B.inst[inst].ctl;
+  BHX_GLOBAL Ctl* ctl = B.inst[inst].ctl;
   if (ctl->done != kConverged) return;
   if (ctl->true_rr <= ctl->accept) return;
   if (ctl->restarts >= ctl->max_restarts || ctl->iter >= B.inst[inst].maxit) return;
@@ -1007,12 +1381,12 @@ __global__ void k_restart(const Batch* __restrict__ Bp) {
 // F = 0 at the unknown nodes of instances flagged by `flag` (zero right-hand side).
 __global__ void __launch_bounds__(kThreads) k_zero_unknown(const Batch* __restrict__ Bp,
                                                            const int* __restrict__ flag) {
-  const Batch& B = *Bp;
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   for (int it = logical_block(); it < B.n_items[kPassS]; it += gridDim.x) {
-    const int code = B.items[kPassS][it];
+    const int code = item_code(B, kPassS, it);
     const int ins = code >> kItemShift;
     if (!flag[ins]) continue;
-    const Inst& I = B.inst[ins];
+    const Inst I = B.inst[ins];
     const int tile = code & kItemMask;
     const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
     for (int e = threadIdx.x; e < kTileX * kTileY; e += kThreads) {
@@ -1034,32 +1408,43 @@ hipError_t launch_setup(const Batch* B, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_stencil(const Batch* B, int mode, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_stencil, dim3(grid), dim3(kThreads), 0, st, B, mode);
+  switch (mode) {
+    case kModeIter: hipLaunchKernelGGL(k_stencil<kModeIter>, dim3(grid), dim3(kThreads), 0, st, B); break;
+    case kModeRhs: hipLaunchKernelGGL(k_stencil<kModeRhs>, dim3(grid), dim3(kThreads), 0, st, B); break;
+    case kModeApply: hipLaunchKernelGGL(k_stencil<kModeApply>, dim3(grid), dim3(kThreads), 0, st, B); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 hipError_t launch_resid(const Batch* B, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_resid, dim3(grid), dim3(kThreads), 0, st, B);
   return hipGetLastError();
 }
-hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, hipStream_t st) {
+hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, int lds, int twoff,
+                         hipStream_t st) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_rowfwd<double>, dim3(grid), dim3(kThreads), kLdsBytes, st, B, update);
+    hipLaunchKernelGGL(k_rowfwd<double>, dim3(grid), dim3(kThreads), lds, st, B, update, twoff);
   else
-    hipLaunchKernelGGL(k_rowfwd<float>, dim3(grid), dim3(kThreads), kLdsBytes, st, B, update);
+    hipLaunchKernelGGL(k_rowfwd<float>, dim3(grid), dim3(kThreads), lds, st, B, update, twoff);
   return hipGetLastError();
 }
-hipError_t launch_col(const Batch* B, int prec, int count_iter, int grid, hipStream_t st) {
+hipError_t launch_col(const Batch* B, int prec, int count_iter, int grid, int lds, int twoff,
+                      hipStream_t st) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_col<double>, dim3(grid), dim3(kThreads), kLdsBytes, st, B, count_iter);
+    hipLaunchKernelGGL(k_col<double>, dim3(grid), dim3(kThreads), lds, st, B, count_iter, twoff);
   else
-    hipLaunchKernelGGL(k_col<float>, dim3(grid), dim3(kThreads), kLdsBytes, st, B, count_iter);
+    hipLaunchKernelGGL(k_col<float>, dim3(grid), dim3(kThreads), lds, st, B, count_iter, twoff);
   return hipGetLastError();
 }
-hipError_t launch_rowinv(const Batch* B, int prec, int grid, hipStream_t st) {
+hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, hipStream_t st) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_rowinv<double>, dim3(grid), dim3(kThreads), kLdsBytes, st, B);
+    hipLaunchKernelGGL(k_rowinv<double>, dim3(grid), dim3(kThreads), lds, st, B, twoff);
   else
-    hipLaunchKernelGGL(k_rowinv<float>, dim3(grid), dim3(kThreads), kLdsBytes, st, B);
+    hipLaunchKernelGGL(k_rowinv<float>, dim3(grid), dim3(kThreads), lds, st, B, twoff);
+  return hipGetLastError();
+}
+hipError_t launch_setup_rows(const Batch* B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_setup_rows, dim3(grid), dim3(kThreads), 0, st, B);
   return hipGetLastError();
 }
 hipError_t launch_identity(const Batch* B, int grid, hipStream_t st) {
@@ -1086,7 +1471,8 @@ hipError_t launch_zero_unknown(const Batch* B, const int* flag, int grid, hipStr
 hipError_t set_kernel_attributes() {
   hipError_t e = hipSuccess;
   auto set = [&](const void* f) {
-    hipError_t x = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    hipError_t x = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       kLdsDynMax);
     if (x != hipSuccess) e = x;
   };
   set((const void*)k_rowfwd<double>);

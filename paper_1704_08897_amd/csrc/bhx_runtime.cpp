@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 
 namespace bhx {
 
@@ -73,6 +74,8 @@ void free_graph(Graph& G) {
 
 }  // namespace
 
+size_t vec_stride(int nx, int ny) { return align_up((size_t)nx * ny, 32); }
+
 int core_length(int n) {
   if (is_pow2(n)) return n;
   int m = 1;
@@ -80,11 +83,18 @@ int core_length(int n) {
   return m;
 }
 
+int padded(int m) { return m + (m >> 3); }
+
+// Complex elements of the plan tables staged in LDS: twiddles (m/2), DCT
+// post-twiddles (n) and eigenvalues (n reals = n/2 complex slots).
+int table_slots(int n, int m) { return m / 2 + n + (n + 1) / 2; }
+
 bool length_supported(int n, int prec) {
   if (n < 4) return false;
   const int csize = prec == 0 ? 16 : 8;
   const int m = core_length(n);
-  if ((long)m * csize > kLdsBytes) return false;             // one packed row must fit
+  if ((long)padded(m) * csize > kLdsBytes) return false;        // one packed row must fit
+  if ((long)(padded(m) + table_slots(n, m)) * csize > kLdsDynMax) return false;
   if ((n / 2 + 1) > kThreads * kMaxPairs) return false;
   return true;
 }
@@ -92,12 +102,15 @@ bool length_supported(int n, int prec) {
 bool make_layout(int nx, int ny, int prec, int mx, int my, Layout* L) {
   const int csize = prec == 0 ? 16 : 8;
   const int rows_cap = prec == 0 ? 4 : 8;
-  auto rows_for = [&](int n, int m) {
-    int r = std::min(rows_cap, kLdsBytes / (m * csize));
+  // packed rows per item: the most that fit LDS and the register pair pass,
+  // reduced until the instance supplies kTargetItems items (two per CU)
+  auto rows_for = [&](int n, int m, int lines) {
+    int r = std::min(rows_cap, kLdsBytes / (padded(m) * csize));
     r = std::min(r, (kThreads * kMaxPairs) / (n / 2 + 1));
+    while (r > 1 && (lines + 2 * r - 1) / (2 * r) < kTargetItems) --r;
     return r;
   };
-  const int rx = rows_for(nx, mx), ry = rows_for(ny, my);
+  const int rx = rows_for(nx, mx, ny), ry = rows_for(ny, my, nx);
   if (rx < 1 || ry < 1) return false;
   L->G = 2 * rx;
   L->Gc = 2 * ry;
@@ -107,10 +120,11 @@ bool make_layout(int nx, int ny, int prec, int mx, int my, Layout* L) {
   L->n_items[kPassR] = (ny + L->G - 1) / L->G;
   L->n_items[kPassC] = (nx + L->Gc - 1) / L->Gc;
   const size_t N = (size_t)nx * ny;
+  const size_t Np = vec_stride(nx, ny);
   const PartLayout PL(L->n_items[kPassS], L->n_items[kPassR]);
   size_t o = 0;
   L->off_mask = o; o = align_up(o + N);
-  L->off_vec = o;  o = align_up(o + 5 * N * sizeof(double));
+  L->off_vec = o;  o = align_up(o + 5 * Np * sizeof(double));
   L->off_t = o;    o = align_up(o + N * (prec == 0 ? sizeof(double) : sizeof(float)));
   L->off_part = o; o = align_up(o + (size_t)PL.total() * sizeof(double));
   L->off_ctl = o;  o = align_up(o + sizeof(Ctl));
@@ -191,6 +205,11 @@ int PlanCache::get(int n, int bc) {
   }
   P.off_post = (int)ctab_.size();
   for (int k = 0; k < n; ++k) ctab_.push_back(expi(-kPi * k / (2.0L * n)));
+  P.s0 = (double)sqrtl(1.0L / n);
+  P.s1 = (double)sqrtl(2.0L / n);
+  P.g0 = (double)(1.0L / sqrtl((long double)n));
+  P.g1 = (double)(1.0L / sqrtl(2.0L * n));
+  P.hs = (double)(0.5L / sqrtl((long double)n));
   P.off_lam = (int)rtab_.size();
   for (int k = 0; k < n; ++k) {
     // eigenvalues of the 1-D second difference, 4 sin^2(theta/2)
@@ -311,7 +330,9 @@ void free_handle(bhx_handle* hd) {
 namespace {
 
 struct Grids {
-  int s, r, c;
+  int s, r, c;             // persistent grid sizes of the stencil, row and column passes
+  int lds_r, tw_r;         // row passes: dynamic LDS bytes, twiddle offset (complex elements)
+  int lds_c, tw_c;         // column pass
 };
 
 int hd_count(bhx_handle* hd) { return hd->batch_count; }
@@ -319,9 +340,11 @@ int hd_count(bhx_handle* hd) { return hd->batch_count; }
 hipError_t launch_precond(bhx_handle* hd, const Resolved& R, const Grids& g, hipStream_t st) {
   hipError_t e;
   if (!R.precond) return launch_identity(hd->batch_d, g.r, st);
-  if ((e = launch_rowfwd(hd->batch_d, R.precision, 0, g.r, st)) != hipSuccess) return e;
-  if ((e = launch_col(hd->batch_d, R.precision, 0, g.c, st)) != hipSuccess) return e;
-  return launch_rowinv(hd->batch_d, R.precision, g.r, st);
+  if ((e = launch_rowfwd(hd->batch_d, R.precision, 0, g.r, g.lds_r, g.tw_r, st)) != hipSuccess)
+    return e;
+  if ((e = launch_col(hd->batch_d, R.precision, 0, g.c, g.lds_c, g.tw_c, st)) != hipSuccess)
+    return e;
+  return launch_rowinv(hd->batch_d, R.precision, g.r, g.lds_r, g.tw_r, st);
 }
 
 // Event of pass p, iteration c, edge e (0 start, 1 end) in a Graph's array.
@@ -343,18 +366,18 @@ hipError_t launch_iterations(bhx_handle* hd, const Resolved& R, const Grids& g, 
     BHX_TRY(rec(0, c, 1));
     if (R.precond) {
       BHX_TRY(rec(1, c, 0));
-      BHX_TRY(launch_rowfwd(hd->batch_d, R.precision, 1, g.r, st));
+      BHX_TRY(launch_rowfwd(hd->batch_d, R.precision, 1, g.r, g.lds_r, g.tw_r, st));
       BHX_TRY(rec(1, c, 1));
       BHX_TRY(rec(2, c, 0));
-      BHX_TRY(launch_col(hd->batch_d, R.precision, 1, g.c, st));
+      BHX_TRY(launch_col(hd->batch_d, R.precision, 1, g.c, g.lds_c, g.tw_c, st));
       BHX_TRY(rec(2, c, 1));
       BHX_TRY(rec(3, c, 0));
-      BHX_TRY(launch_rowinv(hd->batch_d, R.precision, g.r, st));
+      BHX_TRY(launch_rowinv(hd->batch_d, R.precision, g.r, g.lds_r, g.tw_r, st));
       BHX_TRY(rec(3, c, 1));
     } else {
       // plain CG: update-only row pass, iteration count, z = r
       BHX_TRY(rec(1, c, 0));
-      BHX_TRY(launch_rowfwd(hd->batch_d, R.precision, 2, g.r, st));
+      BHX_TRY(launch_rowfwd(hd->batch_d, R.precision, 2, g.r, g.lds_r, g.tw_r, st));
       BHX_TRY(rec(1, c, 1));
       BHX_TRY(launch_bump(hd->batch_d, hd_count(hd), st));
       BHX_TRY(rec(3, c, 0));
@@ -390,6 +413,7 @@ hipError_t run_chunk(bhx_handle* hd, const Resolved& R, const Grids& g, hipStrea
   for (auto& gr : hd->graphs) {
     if (gr.stream == st && gr.prec == R.precision && gr.chunk == R.chunk &&
         gr.precond == R.precond && gr.gs == g.s && gr.gr == g.r && gr.gc == g.c &&
+        gr.lds_r == g.lds_r && gr.tw_r == g.tw_r && gr.lds_c == g.lds_c && gr.tw_c == g.tw_c &&
         gr.profile == R.profile && (gr.exec != nullptr) == graph) {
       *used = &gr;
       if (gr.exec) return hipGraphLaunch(gr.exec, st);
@@ -399,6 +423,7 @@ hipError_t run_chunk(bhx_handle* hd, const Resolved& R, const Grids& g, hipStrea
   Graph G;
   G.stream = st; G.prec = R.precision; G.chunk = R.chunk; G.precond = R.precond;
   G.gs = g.s; G.gr = g.r; G.gc = g.c; G.profile = R.profile;
+  G.lds_r = g.lds_r; G.tw_r = g.tw_r; G.lds_c = g.lds_c; G.tw_c = g.tw_c;
   hipError_t e;
   if (R.profile && (e = make_events(&G.ev, R.chunk)) != hipSuccess) {
     free_graph(G);
@@ -496,16 +521,20 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
     for (int p = 0; p < kNumPass; ++p) I.n_items[p] = L.n_items[p];
     I.maxit = R.maxit_user > 0 ? R.maxit_user : 50 * std::max(S.nx, S.ny);
     I.flexible = R.flexible;
-    I.phi = S.phi;
-    I.F = S.F;
-    const size_t N = (size_t)S.nx * S.ny;
+    I.phi = (decltype(I.phi))S.phi;
+    I.F = (decltype(I.F))S.F;
+    const size_t Np = vec_stride(S.nx, S.ny);
     char* b = ws + base[i];
-    I.mask = (uint8_t*)(b + L.off_mask);
+    I.mask = (decltype(I.mask))(b + L.off_mask);
     double* v = (double*)(b + L.off_vec);
-    I.r = v; I.p[0] = v + N; I.p[1] = v + 2 * N; I.q = v + 3 * N; I.z = v + 4 * N;
-    I.t = b + L.off_t;
-    I.part = (double*)(b + L.off_part);
-    I.ctl = ctl_d + i;
+    I.r = (decltype(I.r))v;
+    I.p[0] = (decltype(I.r))(v + Np);
+    I.p[1] = (decltype(I.r))(v + 2 * Np);
+    I.q = (decltype(I.r))(v + 3 * Np);
+    I.z = (decltype(I.r))(v + 4 * Np);
+    I.t = (decltype(I.t))(b + L.off_t);
+    I.part = (decltype(I.part))(b + L.off_part);
+    I.ctl = (decltype(I.ctl))(ctl_d + i);
     for (int p = 0; p < kNumPass; ++p)
       for (int k = 0; k < L.n_items[p]; ++k) items[p].push_back((i << kItemShift) | k);
     Ctl& C = ctl[i];
@@ -550,13 +579,13 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
   hd->batch_count = n;
   for (int p = 0; p < kNumPass; ++p) {
     Bh.n_items[p] = (int)items[p].size();
-    Bh.items[p] = hd->items_d[p];
+    Bh.items[p] = (std::remove_reference_t<decltype(Bh.items[p])>)hd->items_d[p];
   }
-  Bh.inst = hd->inst_d;
-  Bh.plans = hd->plans.plans_d();
+  Bh.inst = (decltype(Bh.inst))hd->inst_d;
+  Bh.plans = (decltype(Bh.plans))hd->plans.plans_d();
   for (int p = 0; p < 2; ++p) {
-    Bh.ctab[p] = hd->plans.ctab(p);
-    Bh.rtab[p] = hd->plans.rtab(p);
+    Bh.ctab[p] = (std::remove_reference_t<decltype(Bh.ctab[p])>)hd->plans.ctab(p);
+    Bh.rtab[p] = (std::remove_reference_t<decltype(Bh.rtab[p])>)hd->plans.rtab(p);
   }
   BHX_CHECK(hipStreamSynchronize(st));
   BHX_CHECK(hipMemcpy(hd->inst_d, inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
@@ -570,6 +599,24 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
   g.s = std::max(1, std::min(Bh.n_items[kPassS], hd->num_cu * 8));
   g.r = std::max(1, std::min(Bh.n_items[kPassR], hd->num_cu * 2));
   g.c = std::max(1, std::min(Bh.n_items[kPassC], hd->num_cu * 2));
+  {
+    // dynamic LDS: packed rows (padded) followed by the staged plan tables
+    const int csize = R.precision == 0 ? 16 : 8;
+    int buf_r = 0, tab_r = 0, buf_c = 0, tab_c = 0;
+    for (int i = 0; i < n; ++i) {
+      const AxisPlan& PX = hd->plans.plan(px[i]);
+      const AxisPlan& PY = hd->plans.plan(py[i]);
+      buf_r = std::max(buf_r, (lay[i].G / 2) * padded(PX.m));
+      tab_r = std::max(tab_r, table_slots(PX.n, PX.m));
+      buf_c = std::max(buf_c, (lay[i].Gc / 2) * padded(PY.m));
+      tab_c = std::max(tab_c, table_slots(PY.n, PY.m));
+    }
+    g.tw_r = buf_r;
+    g.lds_r = (buf_r + tab_r) * csize;
+    g.tw_c = buf_c;
+    g.lds_c = (buf_c + tab_c) * csize;
+    if (g.lds_r > kLdsDynMax || g.lds_c > kLdsDynMax) return BHX_ERR_ARG;
+  }
   *gout = g;
   return BHX_OK;
 }
@@ -586,6 +633,7 @@ int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
   Ctl* ctl_d = (Ctl*)hd->ws;
   // setup: mask, right-hand side, counts
   BHX_CHECK(launch_setup(hd->batch_d, g.s, st));
+  BHX_CHECK(launch_setup_rows(hd->batch_d, g.r, st));
   BHX_CHECK(launch_stencil(hd->batch_d, kModeRhs, g.s, st));
   BHX_CHECK(launch_finalize(hd->batch_d, n, kFinSetupH, st));
   Ctl* ch = hd->ctl_h;
@@ -712,11 +760,13 @@ int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, dou
   Layout L;
   make_layout(nx, ny, precision, core_length(nx), core_length(ny), &L);
   const size_t N = (size_t)nx * ny;
+  const size_t Np = vec_stride(nx, ny);
   double* v = (double*)((char*)hd->ws + align_up(sizeof(Ctl)) + L.off_vec);
   double* r = v;
-  double* q = v + 3 * N;
-  double* z = v + 4 * N;
+  double* q = v + 3 * Np;
+  double* z = v + 4 * Np;
   BHX_CHECK(launch_setup(hd->batch_d, g.s, st));
+  BHX_CHECK(launch_setup_rows(hd->batch_d, g.r, st));
   if (op == 0) {
     BHX_CHECK(hipMemcpyAsync(z, in, N * sizeof(double), hipMemcpyDeviceToDevice, st));
     BHX_CHECK(launch_stencil(hd->batch_d, kModeApply, g.s, st));

@@ -60,6 +60,8 @@ struct Layout {
 bool make_layout(int nx, int ny, int prec, int mx, int my, Layout* L);
 // Core FFT length of a transform of length n (power of two, or Bluestein).
 int core_length(int n);
+// Spacing of the float64 workspace vectors (elements), 256-byte aligned.
+size_t vec_stride(int nx, int ny);
 // Largest supported transform length for a precision (0 fp64, 1 fp32).
 bool length_supported(int n, int prec);
 
@@ -73,6 +75,7 @@ struct Graph {
   hipGraphExec_t exec = nullptr;
   hipStream_t stream = nullptr;
   int prec = -1, chunk = 0, precond = -1, gs = 0, gr = 0, gc = 0, profile = 0;
+  int lds_r = 0, tw_r = 0, lds_c = 0, tw_c = 0;
   std::vector<hipEvent_t> ev;   // [pass][iteration][start, end] when profiling
 };
 
