@@ -102,6 +102,13 @@ typedef struct {
                          beta = r.z / r_old.z_old, 1 = Polak-Ribiere beta           */
   int chunk;        /* iterations per captured graph between convergence checks;
                          0 -> 32                                                     */
+  int rows;         /* packed complex rows (two grid rows each) per transform work
+                         item; 0 = automatic (autotuner or built-in policy)           */
+  int occupancy;    /* persistent blocks per CU of the transform passes; 0 = auto   */
+  int autotune;     /* 1 = choose the launch schedule (packed rows per transform work
+                         item, persistent-grid occupancy per pass, iterations per
+                         graph) by timing short trial solves of this batch's shape on
+                         first use, cached per handle; 0 = built-in policy           */
   int profile;      /* bit mask of iteration passes to time with HIP events recorded
                          on the solve's stream around each launch (captured into the
                          graph): bit 0 stencil, 1 row-forward, 2 column, 3 row-inverse;

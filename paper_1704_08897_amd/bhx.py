@@ -38,7 +38,9 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("precond", ctypes.c_int), ("accurate", ctypes.c_int),
                 ("tol_inner", ctypes.c_double), ("flexible", ctypes.c_int),
-                ("chunk", ctypes.c_int), ("profile", ctypes.c_int)]
+                ("chunk", ctypes.c_int), ("rows", ctypes.c_int), ("occupancy", ctypes.c_int),
+                ("autotune", ctypes.c_int),
+                ("profile", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

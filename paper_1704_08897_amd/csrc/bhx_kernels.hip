@@ -1374,7 +1374,13 @@ __global__ void k_restart(const Batch* __restrict__ Bp) {
   ctl->restarts = ctl->restarts + 1;
   ctl->restart_iter = ctl->iter;
   ctl->bb = ctl->true_rr;
-  if (ctl->accurate) ctl->thresh = ctl->tol_inner2 * ctl->true_rr;
+  if (ctl->accurate) {
+    ctl->thresh = ctl->tol_inner2 * ctl->true_rr;
+  } else {
+    // the recursive residual met tol but the true one did not: tighten the
+    // recursive target by 2 per restart so the true residual must follow
+    ctl->thresh = ctl->thresh * 0.25;
+  }
   ctl->done = kRunning;
 }
 

@@ -99,7 +99,7 @@ bool length_supported(int n, int prec) {
   return true;
 }
 
-bool make_layout(int nx, int ny, int prec, int mx, int my, Layout* L) {
+bool make_layout(int nx, int ny, int prec, int mx, int my, int rows_user, Layout* L) {
   const int csize = prec == 0 ? 16 : 8;
   const int rows_cap = prec == 0 ? 4 : 8;
   // packed rows per item: the most that fit LDS and the register pair pass,
@@ -107,6 +107,7 @@ bool make_layout(int nx, int ny, int prec, int mx, int my, Layout* L) {
   auto rows_for = [&](int n, int m, int lines) {
     int r = std::min(rows_cap, kLdsBytes / (padded(m) * csize));
     r = std::min(r, (kThreads * kMaxPairs) / (n / 2 + 1));
+    if (rows_user > 0) return std::min(r, rows_user);
     while (r > 1 && (lines + 2 * r - 1) / (2 * r) < kTargetItems) --r;
     return r;
   };
@@ -135,7 +136,7 @@ bool make_layout(int nx, int ny, int prec, int mx, int my, Layout* L) {
 size_t instance_bytes(int nx, int ny, int prec) {
   Layout L;
   if (!length_supported(nx, prec) || !length_supported(ny, prec)) return 0;
-  if (!make_layout(nx, ny, prec, core_length(nx), core_length(ny), &L)) return 0;
+  if (!make_layout(nx, ny, prec, core_length(nx), core_length(ny), 0, &L)) return 0;
   return L.bytes;
 }
 
@@ -152,6 +153,11 @@ Resolved resolve_opts(const bhx_opts* o) {
   R.flexible = o->flexible < 0 ? (o->precision == BHX_PREC_FP32 ? 1 : 0) : o->flexible;
   R.chunk = o->chunk > 0 ? o->chunk : 32;
   R.profile = o->profile;
+  R.autotune = o->autotune;
+  R.rows_opt = o->rows;
+  R.occ_opt = o->occupancy;
+  if (o->rows > 0) R.sched.rows_cap = o->rows;
+  if (o->occupancy > 0) R.sched.occ_r = R.sched.occ_c = o->occupancy;
   return R;
 }
 
@@ -283,6 +289,8 @@ int validate(const double* phi, const double* F, int nx, int ny, double h, int b
   if (!(R.tol_inner > 0 && R.tol_inner < 1)) return BHX_ERR_ARG;
   if (R.flexible != 0 && R.flexible != 1) return BHX_ERR_ARG;
   if (R.profile < 0 || R.profile > 15) return BHX_ERR_ARG;
+  if (R.autotune != 0 && R.autotune != 1) return BHX_ERR_ARG;
+  if (R.rows_opt < 0 || R.rows_opt > 8 || R.occ_opt < 0 || R.occ_opt > 8) return BHX_ERR_ARG;
   if (!length_supported(nx, R.precision) || !length_supported(ny, R.precision)) return BHX_ERR_ARG;
   if ((long long)nx * ny > (1LL << 31)) return BHX_ERR_ARG;
   return BHX_OK;
@@ -329,31 +337,25 @@ void free_handle(bhx_handle* hd) {
 
 namespace {
 
-struct Grids {
-  int s, r, c;             // persistent grid sizes of the stencil, row and column passes
-  int lds_r, tw_r;         // row passes: dynamic LDS bytes, twiddle offset (complex elements)
-  int lds_c, tw_c;         // column pass
-};
+}  // namespace
 
-int hd_count(bhx_handle* hd) { return hd->batch_count; }
-
-hipError_t launch_precond(bhx_handle* hd, const Resolved& R, const Grids& g, hipStream_t st) {
+hipError_t launch_precond(const Batch* B, const Resolved& R, const Grids& g, hipStream_t st) {
   hipError_t e;
-  if (!R.precond) return launch_identity(hd->batch_d, g.r, st);
-  if ((e = launch_rowfwd(hd->batch_d, R.precision, 0, g.r, g.lds_r, g.tw_r, st)) != hipSuccess)
-    return e;
-  if ((e = launch_col(hd->batch_d, R.precision, 0, g.c, g.lds_c, g.tw_c, st)) != hipSuccess)
-    return e;
-  return launch_rowinv(hd->batch_d, R.precision, g.r, g.lds_r, g.tw_r, st);
+  if (!R.precond) return launch_identity(B, g.r, st);
+  if ((e = launch_rowfwd(B, R.precision, 0, g.r, g.lds_r, g.tw_r, st)) != hipSuccess) return e;
+  if ((e = launch_col(B, R.precision, 0, g.c, g.lds_c, g.tw_c, st)) != hipSuccess) return e;
+  return launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, st);
 }
+
+namespace {
 
 // Event of pass p, iteration c, edge e (0 start, 1 end) in a Graph's array.
 inline hipEvent_t ev_at(const std::vector<hipEvent_t>* ev, int chunk, int p, int c, int e) {
   return (*ev)[((size_t)p * chunk + c) * 2 + e];
 }
 
-hipError_t launch_iterations(bhx_handle* hd, const Resolved& R, const Grids& g, int count,
-                             hipStream_t st, const std::vector<hipEvent_t>* ev) {
+hipError_t launch_iterations(const Batch* B, int n_inst, const Resolved& R, const Grids& g,
+                             int count, hipStream_t st, const std::vector<hipEvent_t>* ev) {
   hipError_t e;
   auto rec = [&](int p, int c, int edge) -> hipError_t {
     if (!ev || !(R.profile & (1 << p))) return hipSuccess;
@@ -362,26 +364,26 @@ hipError_t launch_iterations(bhx_handle* hd, const Resolved& R, const Grids& g, 
 #define BHX_TRY(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
   for (int c = 0; c < count; ++c) {
     BHX_TRY(rec(0, c, 0));
-    BHX_TRY(launch_stencil(hd->batch_d, kModeIter, g.s, st));
+    BHX_TRY(launch_stencil(B, kModeIter, g.s, st));
     BHX_TRY(rec(0, c, 1));
     if (R.precond) {
       BHX_TRY(rec(1, c, 0));
-      BHX_TRY(launch_rowfwd(hd->batch_d, R.precision, 1, g.r, g.lds_r, g.tw_r, st));
+      BHX_TRY(launch_rowfwd(B, R.precision, 1, g.r, g.lds_r, g.tw_r, st));
       BHX_TRY(rec(1, c, 1));
       BHX_TRY(rec(2, c, 0));
-      BHX_TRY(launch_col(hd->batch_d, R.precision, 1, g.c, g.lds_c, g.tw_c, st));
+      BHX_TRY(launch_col(B, R.precision, 1, g.c, g.lds_c, g.tw_c, st));
       BHX_TRY(rec(2, c, 1));
       BHX_TRY(rec(3, c, 0));
-      BHX_TRY(launch_rowinv(hd->batch_d, R.precision, g.r, g.lds_r, g.tw_r, st));
+      BHX_TRY(launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, st));
       BHX_TRY(rec(3, c, 1));
     } else {
       // plain CG: update-only row pass, iteration count, z = r
       BHX_TRY(rec(1, c, 0));
-      BHX_TRY(launch_rowfwd(hd->batch_d, R.precision, 2, g.r, g.lds_r, g.tw_r, st));
+      BHX_TRY(launch_rowfwd(B, R.precision, 2, g.r, g.lds_r, g.tw_r, st));
       BHX_TRY(rec(1, c, 1));
-      BHX_TRY(launch_bump(hd->batch_d, hd_count(hd), st));
+      BHX_TRY(launch_bump(B, n_inst, st));
       BHX_TRY(rec(3, c, 0));
-      BHX_TRY(launch_identity(hd->batch_d, g.r, st));
+      BHX_TRY(launch_identity(B, g.r, st));
       BHX_TRY(rec(3, c, 1));
     }
   }
@@ -403,25 +405,30 @@ hipError_t make_events(std::vector<hipEvent_t>* ev, int chunk) {
   return hipSuccess;
 }
 
-// Launch one chunk of iterations; returns the Graph used (for its events).
-hipError_t run_chunk(bhx_handle* hd, const Resolved& R, const Grids& g, hipStream_t st,
-                     Graph** used) {
+}  // namespace
+
+// Launch one chunk of iterations over batch B (device header) of n_inst
+// instances; returns the Graph used (for its events).
+hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved& R,
+                     const Grids& g, hipStream_t st, Graph** used) {
   *used = nullptr;
   // HIP cannot time events recorded as graph nodes, so a profiled chunk is
   // launched directly with events around the selected passes.
   const bool graph = use_graphs() && R.profile == 0;
   for (auto& gr : hd->graphs) {
-    if (gr.stream == st && gr.prec == R.precision && gr.chunk == R.chunk &&
+    if (gr.stream == st && gr.batch == B && gr.count == (R.precond ? 0 : n_inst) &&
+        gr.prec == R.precision && gr.chunk == R.chunk &&
         gr.precond == R.precond && gr.gs == g.s && gr.gr == g.r && gr.gc == g.c &&
         gr.lds_r == g.lds_r && gr.tw_r == g.tw_r && gr.lds_c == g.lds_c && gr.tw_c == g.tw_c &&
         gr.profile == R.profile && (gr.exec != nullptr) == graph) {
       *used = &gr;
       if (gr.exec) return hipGraphLaunch(gr.exec, st);
-      return launch_iterations(hd, R, g, R.chunk, st, &gr.ev);
+      return launch_iterations(B, n_inst, R, g, R.chunk, st, &gr.ev);
     }
   }
   Graph G;
   G.stream = st; G.prec = R.precision; G.chunk = R.chunk; G.precond = R.precond;
+  G.batch = B; G.count = R.precond ? 0 : n_inst;
   G.gs = g.s; G.gr = g.r; G.gc = g.c; G.profile = R.profile;
   G.lds_r = g.lds_r; G.tw_r = g.tw_r; G.lds_c = g.lds_c; G.tw_c = g.tw_c;
   hipError_t e;
@@ -432,7 +439,7 @@ hipError_t run_chunk(bhx_handle* hd, const Resolved& R, const Grids& g, hipStrea
   if (graph) {
     e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { free_graph(G); return e; }
-    hipError_t el = launch_iterations(hd, R, g, R.chunk, st, nullptr);
+    hipError_t el = launch_iterations(B, n_inst, R, g, R.chunk, st, nullptr);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(st, &graph);
     if (el != hipSuccess || e != hipSuccess) {
@@ -452,8 +459,10 @@ hipError_t run_chunk(bhx_handle* hd, const Resolved& R, const Grids& g, hipStrea
   Graph* gp = &hd->graphs.back();
   *used = gp;
   if (gp->exec) return hipGraphLaunch(gp->exec, st);
-  return launch_iterations(hd, R, g, R.chunk, st, R.profile ? &gp->ev : nullptr);
+  return launch_iterations(B, n_inst, R, g, R.chunk, st, R.profile ? &gp->ev : nullptr);
 }
+
+namespace {
 
 }  // namespace
 
@@ -485,7 +494,7 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
     px[i] = hd->plans.get(specs[i].nx, specs[i].bcx);
     py[i] = hd->plans.get(specs[i].ny, specs[i].bcy);
     if (!make_layout(specs[i].nx, specs[i].ny, R.precision, hd->plans.plan(px[i]).m,
-                     hd->plans.plan(py[i]).m, &lay[i]))
+                     hd->plans.plan(py[i]).m, R.sched.rows_cap, &lay[i]))
       return BHX_ERR_ARG;
   }
   BHX_CHECK(hd->plans.sync_device());
@@ -542,7 +551,7 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
     C.tol2 = S.tol * S.tol;
     C.tol_inner2 = R.tol_inner * R.tol_inner;
     C.accurate = R.accurate;
-    C.max_restarts = R.accurate ? 12 : 4;
+    C.max_restarts = R.accurate ? 12 : 8;
   }
   // device descriptors
   if (n > hd->inst_cap) {
@@ -596,9 +605,9 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
   BHX_CHECK(hipMemcpy(hd->batch_d, &Bh, sizeof(Batch), hipMemcpyHostToDevice));
 
   Grids g;
-  g.s = std::max(1, std::min(Bh.n_items[kPassS], hd->num_cu * 8));
-  g.r = std::max(1, std::min(Bh.n_items[kPassR], hd->num_cu * 2));
-  g.c = std::max(1, std::min(Bh.n_items[kPassC], hd->num_cu * 2));
+  g.s = std::max(1, std::min(Bh.n_items[kPassS], hd->num_cu * R.sched.occ_s));
+  g.r = std::max(1, std::min(Bh.n_items[kPassR], hd->num_cu * R.sched.occ_r));
+  g.c = std::max(1, std::min(Bh.n_items[kPassC], hd->num_cu * R.sched.occ_c));
   {
     // dynamic LDS: packed rows (padded) followed by the staged plan tables
     const int csize = R.precision == 0 ? 16 : 8;
@@ -621,8 +630,8 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
   return BHX_OK;
 }
 
-int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
-                hipStream_t stream, bhx_stats* stats) {
+static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
+                            hipStream_t stream, bhx_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t st = stream ? stream : hd->own_stream;
   Grids g;
@@ -673,11 +682,11 @@ int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
   int pass_cnt[4] = {0, 0, 0, 0};
   std::vector<int> iter_before(n);
   if (active > 0) {
-    BHX_CHECK(launch_precond(hd, R, g, st));
+    BHX_CHECK(launch_precond(hd->batch_d, R, g, st));
     for (;;) {
       for (int i = 0; i < n; ++i) iter_before[i] = ch[i].iter;
       Graph* used = nullptr;
-      BHX_CHECK(run_chunk(hd, R, g, st, &used));
+      BHX_CHECK(run_chunk(hd, hd->batch_d, n, R, g, st, &used));
       BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
       BHX_CHECK(hipStreamSynchronize(st));
       if (R.profile && used && !used->ev.empty()) {
@@ -708,7 +717,7 @@ int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
       for (int i = 0; i < n; ++i)
         if (ch[i].done == kRunning) restarted = true;
       if (!restarted) break;
-      BHX_CHECK(launch_precond(hd, R, g, st));
+      BHX_CHECK(launch_precond(hd->batch_d, R, g, st));
     }
   }
   const double secs =
@@ -758,7 +767,7 @@ int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, dou
   int rc = prepare_batch(hd, 1, &s, R, st, &g);
   if (rc != BHX_OK) return rc;
   Layout L;
-  make_layout(nx, ny, precision, core_length(nx), core_length(ny), &L);
+  make_layout(nx, ny, precision, core_length(nx), core_length(ny), R.sched.rows_cap, &L);
   const size_t N = (size_t)nx * ny;
   const size_t Np = vec_stride(nx, ny);
   double* v = (double*)((char*)hd->ws + align_up(sizeof(Ctl)) + L.off_vec);
@@ -773,11 +782,98 @@ int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, dou
     BHX_CHECK(hipMemcpyAsync(out, q, N * sizeof(double), hipMemcpyDeviceToDevice, st));
   } else {
     BHX_CHECK(hipMemcpyAsync(r, in, N * sizeof(double), hipMemcpyDeviceToDevice, st));
-    BHX_CHECK(launch_precond(hd, R, g, st));
+    BHX_CHECK(launch_precond(hd->batch_d, R, g, st));
     BHX_CHECK(hipMemcpyAsync(out, z, N * sizeof(double), hipMemcpyDeviceToDevice, st));
   }
   BHX_CHECK(hipStreamSynchronize(st));
   return BHX_OK;
+}
+
+// Shape signature of a batch for the autotuner cache.
+static unsigned long long batch_signature(int n, const InstSpec* specs, const Resolved& R) {
+  unsigned long long h = 1469598103934665603ULL;
+  auto mix = [&](unsigned long long v) {
+    h ^= v;
+    h *= 1099511628211ULL;
+  };
+  mix((unsigned long long)n);
+  mix((unsigned long long)(R.precision * 4 + R.precond * 2 + R.flexible));
+  for (int i = 0; i < n; ++i) {
+    mix((unsigned long long)specs[i].nx);
+    mix((unsigned long long)specs[i].ny);
+    mix((unsigned long long)(specs[i].bcx * 16 + specs[i].bcy));
+  }
+  return h;
+}
+
+// Project autotuner: time short trial solves (a fixed number of iterations
+// in one graph) of this batch's shape under candidate schedules and keep the
+// fastest.  A trial writes F only at unknown nodes, which every solve
+// ignores on input and overwrites.
+static int autotune_schedule(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
+                             hipStream_t stream, Schedule* best) {
+  const int trial_iters = 24;
+  std::vector<Schedule> cands;
+  for (int rows : {1, 2, 4})
+    for (int occ : {1, 2, 4}) {
+      Schedule s;
+      s.rows_cap = rows;
+      s.occ_r = occ;
+      s.occ_c = occ;
+      s.occ_s = 8;
+      s.chunk = trial_iters;
+      cands.push_back(s);
+    }
+  double best_t = 1e30;
+  std::vector<bhx_stats> st(n);
+  for (const Schedule& s : cands) {
+    Resolved T = R;
+    T.sched = s;
+    T.maxit_user = trial_iters;
+    T.chunk = trial_iters;
+    T.profile = 0;
+    T.accurate = 0;
+    double t = 0;
+    for (int rep = 0; rep < 2; ++rep) {       // first run captures the graph
+      const auto a = std::chrono::steady_clock::now();
+      int rc = solve_batch_once(hd, n, specs, T, stream, st.data());
+      if (rc < 0 && rc != BHX_ERR_SINGULAR && rc != BHX_ERR_NONFINITE) return rc;
+      t = std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
+    }
+    if (t < best_t) {
+      best_t = t;
+      *best = s;
+    }
+  }
+  best->chunk = 0;
+  return BHX_OK;
+}
+
+int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R0,
+                hipStream_t stream, bhx_stats* stats) {
+  Resolved R = R0;
+  if (R.autotune && R.rows_opt == 0 && R.occ_opt == 0) {
+    const unsigned long long sig = batch_signature(n, specs, R);
+    auto it = hd->tuned.find(sig);
+    if (it == hd->tuned.end()) {
+      Schedule s;
+      int rc = autotune_schedule(hd, n, specs, R, stream, &s);
+      if (rc != BHX_OK) return rc;
+      it = hd->tuned.emplace(sig, s).first;
+    }
+    R.sched = it->second;
+  }
+  return solve_batch_once(hd, n, specs, R, stream, stats);
+}
+
+int tuned_schedule(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R, int* out4) {
+  auto it = hd->tuned.find(batch_signature(n, specs, R));
+  if (it == hd->tuned.end()) return 0;
+  out4[0] = it->second.rows_cap;
+  out4[1] = it->second.occ_s;
+  out4[2] = it->second.occ_r;
+  out4[3] = it->second.occ_c;
+  return 1;
 }
 
 }  // namespace bhx

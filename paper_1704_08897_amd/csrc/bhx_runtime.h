@@ -57,7 +57,7 @@ struct Layout {
 };
 
 // Choose row-group sizes and item counts; false if the size is unsupported.
-bool make_layout(int nx, int ny, int prec, int mx, int my, Layout* L);
+bool make_layout(int nx, int ny, int prec, int mx, int my, int rows_cap, Layout* L);
 // Core FFT length of a transform of length n (power of two, or Bluestein).
 int core_length(int n);
 // Spacing of the float64 workspace vectors (elements), 256-byte aligned.
@@ -65,15 +65,33 @@ size_t vec_stride(int nx, int ny);
 // Largest supported transform length for a precision (0 fp64, 1 fp32).
 bool length_supported(int n, int prec);
 
+// Launch schedule: packed rows per transform item (0 = policy), persistent
+// blocks per CU of the stencil / row / column passes.
+struct Schedule {
+  int rows_cap = 0;
+  int occ_s = 8, occ_r = 2, occ_c = 2;
+  int chunk = 0;             // 0 = option's chunk
+};
+
 struct Resolved {           // options after defaults
-  int precision, maxit_user, precond, accurate, flexible, chunk, profile;
+  int precision, maxit_user, precond, accurate, flexible, chunk, profile, autotune;
+  int rows_opt = 0, occ_opt = 0;
   double tol_inner;
+  Schedule sched;
 };
 Resolved resolve_opts(const bhx_opts* o);
+
+struct Grids {
+  int s, r, c;             // persistent grid sizes of the stencil, row and column passes
+  int lds_r, tw_r;         // row passes: dynamic LDS bytes, twiddle offset (complex elements)
+  int lds_c, tw_c;         // column pass
+};
 
 struct Graph {
   hipGraphExec_t exec = nullptr;
   hipStream_t stream = nullptr;
+  const Batch* batch = nullptr;
+  int count = 0;
   int prec = -1, chunk = 0, precond = -1, gs = 0, gr = 0, gc = 0, profile = 0;
   int lds_r = 0, tw_r = 0, lds_c = 0, tw_c = 0;
   std::vector<hipEvent_t> ev;   // [pass][iteration][start, end] when profiling
@@ -99,6 +117,7 @@ struct bhx_handle {
   int ctl_h_cap = 0;
   hipStream_t own_stream = nullptr;
   std::vector<bhx::Graph> graphs;
+  std::map<unsigned long long, bhx::Schedule> tuned;   // autotuner results per batch shape
   std::mutex mu;
 };
 
@@ -111,6 +130,12 @@ int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
                 hipStream_t stream, bhx_stats* stats);
 size_t instance_bytes(int nx, int ny, int prec);
 const char* last_error();
+void set_last_error(const char* what, int line, hipError_t e);
+int padded(int m);
+int table_slots(int n, int m);
+hipError_t launch_precond(const Batch* B, const Resolved& R, const Grids& g, hipStream_t st);
+hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved& R,
+                     const Grids& g, hipStream_t st, Graph** used);
 int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, double* out, int nx,
                 int ny, int bcx, int bcy, int precision, hipStream_t stream);
 int init_handle(bhx_handle* hd, int device);

@@ -242,3 +242,22 @@ def test_batched_equals_alone(handle):
         assert np.array_equal(got, alone)
         assert st1.iterations == st.iterations
         check_against_oracle(p, got, bound=1e-7)
+
+
+def test_batched_autotuned_fp32(handle):
+    """FP32 preconditioner (flexible PCG) in one batched call with the
+    autotuned schedule: every instance meets the tolerance and the mixed
+    bound against the oracle.  The error is at most the condition number
+    times the residual, so the 1e-8 bound needs a residual well below it:
+    tol 1e-12 (the preconditioner's precision does not limit the attainable
+    residual; the recurrences are float64)."""
+    batch = W.star_cubic_batch(8, seed=31, nmin=48, nmax=160, tol=1e-12)
+    phis = [dev(p.phi) for p in batch]
+    Fs = [dev(p.F) for p in batch]
+    o = bhx.default_opts(precision=1, autotune=1)
+    s, sts = bhx.extend_batched(handle, phis, Fs, [p.h for p in batch], [p.bc for p in batch],
+                                [p.tol for p in batch], opts=o)
+    assert s == bhx.OK, [st.as_dict() for st in sts]
+    for p, F, st in zip(batch, Fs, sts):
+        assert st.true_rel_residual <= 1e-12
+        check_against_oracle(p, host(F), bound=1e-8)
