@@ -135,7 +135,10 @@ void bhx_default_opts(bhx_opts* o);
 
 /* Create / destroy a handle bound to HIP device `device`.  The handle owns
  * transform tables, a growable device workspace and captured graphs.
- * Returns BHX_OK, BHX_ERR_ARG (null out / bad device) or BHX_ERR_HIP. */
+ * Returns BHX_OK, BHX_ERR_ARG (null out, device < 0 or >= the device
+ * count) or BHX_ERR_HIP (no usable HIP device; bhx_last_error() says why).
+ * Processes that also use another HIP runtime (PyTorch bundles one) must
+ * load it first, so that this library binds to that runtime. */
 int bhx_create(bhx_handle** out, int device);
 void bhx_destroy(bhx_handle* h);
 

@@ -21,6 +21,14 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "bhx.h")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_1704_08897_amd/build.py")
+# torch ships its own HIP runtime.  Loaded after this library, it would be a
+# second runtime in the process, and the one that reaches the GPU second finds
+# no device.  Loaded first, it also satisfies this library's libamdhip64
+# dependency, so the process holds one runtime.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = ctypes.CDLL(LIB_PATH)
 
 NEUMANN, PERIODIC, DIRICHLET = 0, 1, 2

@@ -182,15 +182,14 @@ int upload_batch(bhx_engine* E, DevBatch& db, const std::vector<Req*>& reqs, hip
     B.rtab[p] = (std::remove_reference_t<decltype(B.rtab[p])>)E->hd->plans.rtab(p);
   }
   db.count = n;
-  // synchronous copies: the host arrays are temporaries, and the previous
-  // launches reading this header have completed
+  // previous launches reading this header have completed; the copies are
+  // stream-ordered before the launches that follow on st
   ENG_CHECK(hipStreamSynchronize(st));
-  ENG_CHECK(hipMemcpy(db.inst, inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
+  Upload u[2 + kNumPass] = {{db.inst, inst.data(), n * sizeof(Inst)},
+                            {db.hdr, &B, sizeof(Batch)}};
   for (int p = 0; p < kNumPass; ++p)
-    if (!items[p].empty())
-      ENG_CHECK(hipMemcpy(db.items[p], items[p].data(), items[p].size() * sizeof(int),
-                          hipMemcpyHostToDevice));
-  ENG_CHECK(hipMemcpy(db.hdr, &B, sizeof(Batch), hipMemcpyHostToDevice));
+    u[2 + p] = {db.items[p], items[p].data(), items[p].size() * sizeof(int)};
+  ENG_CHECK(upload_ordered(E->hd, st, u, 2 + kNumPass));
   return BHX_OK;
 }
 
@@ -274,7 +273,7 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
     ENG_CHECK(hipMemcpyAsync(E->ctl_d + q->slot, &E->ctl_h[q->slot], sizeof(Ctl),
                              hipMemcpyHostToDevice, st));
   }
-  ENG_CHECK(hd->plans.sync_device());
+  ENG_CHECK(hd->plans.sync_device(st));
   int rc = upload_batch(E, E->aux, news, st);
   if (rc != BHX_OK) return rc;
   const Grids g = engine_grids(E, news);
@@ -314,7 +313,8 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
   if (any_zero) {
     int* flag_d = nullptr;
     ENG_CHECK(hipMalloc((void**)&flag_d, n * sizeof(int)));
-    ENG_CHECK(hipMemcpyAsync(flag_d, zero_flag.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+    const Upload u{flag_d, zero_flag.data(), n * sizeof(int)};
+    ENG_CHECK(upload_ordered(E->hd, st, &u, 1));
     ENG_CHECK(launch_zero_unknown(E->aux.hdr, flag_d, g.s, st));
     ENG_CHECK(hipStreamSynchronize(st));
     ENG_CHECK(hipFree(flag_d));

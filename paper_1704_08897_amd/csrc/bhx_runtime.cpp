@@ -230,9 +230,10 @@ int PlanCache::get(int n, int bc) {
   return idx;
 }
 
-hipError_t PlanCache::sync_device() {
+hipError_t PlanCache::sync_device(hipStream_t st) {
   if (!dirty_) return hipSuccess;
   hipError_t e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;   // before tables move
   if ((e = grow(&plans_d_, &cap_plans_, plans_.size())) != hipSuccess) return e;
   size_t cc = cap_c_;
   if ((e = grow(&ctab_d_, &cap_c_, ctab_.size())) != hipSuccess) return e;
@@ -254,16 +255,17 @@ hipError_t PlanCache::sync_device() {
     rd[i] = (double)rtab_[i];
     rf[i] = (float)rtab_[i];
   }
-  if ((e = hipMemcpy(plans_d_, plans_.data(), plans_.size() * sizeof(AxisPlan),
-                     hipMemcpyHostToDevice)) != hipSuccess) return e;
-  if ((e = hipMemcpy(ctab_d_, cd.data(), cd.size() * sizeof(double2), hipMemcpyHostToDevice)) !=
-      hipSuccess) return e;
-  if ((e = hipMemcpy(ctab_f_, cf.data(), cf.size() * sizeof(float2), hipMemcpyHostToDevice)) !=
-      hipSuccess) return e;
-  if ((e = hipMemcpy(rtab_d_, rd.data(), rd.size() * sizeof(double), hipMemcpyHostToDevice)) !=
-      hipSuccess) return e;
-  if ((e = hipMemcpy(rtab_f_, rf.data(), rf.size() * sizeof(float), hipMemcpyHostToDevice)) !=
-      hipSuccess) return e;
+  // stream-ordered: launches on st must not read tables still in transit
+  const Upload u[5] = {{plans_d_, plans_.data(), plans_.size() * sizeof(AxisPlan)},
+                       {ctab_d_, cd.data(), cd.size() * sizeof(double2)},
+                       {ctab_f_, cf.data(), cf.size() * sizeof(float2)},
+                       {rtab_d_, rd.data(), rd.size() * sizeof(double)},
+                       {rtab_f_, rf.data(), rf.size() * sizeof(float)}};
+  for (const Upload& x : u)
+    if ((e = hipMemcpyAsync(x.dst, x.src, x.bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
+      return e;
+  // the host vectors above are temporaries: finish the copies here
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
   dirty_ = false;
   return hipSuccess;
 }
@@ -301,8 +303,14 @@ int validate(const double* phi, const double* F, int nx, int ny, double h, int b
 // ---------------------------------------------------------------------------
 
 int init_handle(bhx_handle* hd, int device) {
+  if (device < 0) return BHX_ERR_ARG;
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return BHX_ERR_ARG;
+  const hipError_t ec = hipGetDeviceCount(&ndev);
+  if (ec != hipSuccess) {
+    set_last_error("hipGetDeviceCount", __LINE__, ec);
+    return BHX_ERR_HIP;
+  }
+  if (device >= ndev) return BHX_ERR_ARG;
   hd->device = device;
   if (hipSetDevice(device) != hipSuccess) return BHX_ERR_HIP;
   hipDeviceProp_t prop;
@@ -312,6 +320,30 @@ int init_handle(bhx_handle* hd, int device) {
   if (hipMalloc((void**)&hd->batch_d, sizeof(Batch)) != hipSuccess) return BHX_ERR_NOMEM;
   if (hipStreamCreate(&hd->own_stream) != hipSuccess) return BHX_ERR_HIP;
   return BHX_OK;
+}
+
+hipError_t upload_ordered(bhx_handle* hd, hipStream_t st, const Upload* u, int n) {
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) total += align_up(u[i].bytes);
+  if (total > hd->stage_cap) {
+    if (hd->stage_h) (void)hipHostFree(hd->stage_h);
+    hd->stage_h = nullptr;
+    hd->stage_cap = 0;
+    const size_t cap = std::max(total, 2 * hd->stage_cap);
+    hipError_t e = hipHostMalloc((void**)&hd->stage_h, cap);
+    if (e != hipSuccess) return e;
+    hd->stage_cap = cap;
+  }
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    if (u[i].bytes == 0) continue;
+    std::memcpy(hd->stage_h + off, u[i].src, u[i].bytes);
+    hipError_t e = hipMemcpyAsync(u[i].dst, hd->stage_h + off, u[i].bytes,
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    off += align_up(u[i].bytes);
+  }
+  return hipSuccess;
 }
 
 void free_handle(bhx_handle* hd) {
@@ -328,6 +360,7 @@ void free_handle(bhx_handle* hd) {
     if (hd->items_d[p]) (void)hipFree(hd->items_d[p]);
   if (hd->flag_d) (void)hipFree(hd->flag_d);
   if (hd->ctl_h) (void)hipHostFree(hd->ctl_h);
+  if (hd->stage_h) (void)hipHostFree(hd->stage_h);
   if (hd->own_stream) (void)hipStreamDestroy(hd->own_stream);
 }
 
@@ -487,6 +520,9 @@ const char* last_error() { return g_last_error; }
 int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
                   hipStream_t st, Grids* gout) {
   BHX_CHECK(hipSetDevice(hd->device));
+  // earlier launches on st may still read the descriptors, tables and
+  // staging buffer replaced below
+  BHX_CHECK(hipStreamSynchronize(st));
   // plans and layouts
   std::vector<int> px(n), py(n);
   std::vector<Layout> lay(n);
@@ -497,7 +533,7 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
                      hd->plans.plan(py[i]).m, R.sched.rows_cap, &lay[i]))
       return BHX_ERR_ARG;
   }
-  BHX_CHECK(hd->plans.sync_device());
+  BHX_CHECK(hd->plans.sync_device(st));
   const size_t ctl_bytes = align_up((size_t)n * sizeof(Ctl));
   size_t total = ctl_bytes;
   std::vector<size_t> base(n);
@@ -506,7 +542,6 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
     total += lay[i].bytes;
   }
   if (total > hd->ws_cap) {
-    BHX_CHECK(hipStreamSynchronize(st));
     if (hd->ws) BHX_CHECK(hipFree(hd->ws));
     hd->ws = nullptr;
     hd->ws_cap = 0;
@@ -596,13 +631,15 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
     Bh.ctab[p] = (std::remove_reference_t<decltype(Bh.ctab[p])>)hd->plans.ctab(p);
     Bh.rtab[p] = (std::remove_reference_t<decltype(Bh.rtab[p])>)hd->plans.rtab(p);
   }
-  BHX_CHECK(hipStreamSynchronize(st));
-  BHX_CHECK(hipMemcpy(hd->inst_d, inst.data(), n * sizeof(Inst), hipMemcpyHostToDevice));
-  for (int p = 0; p < kNumPass; ++p)
-    BHX_CHECK(hipMemcpy(hd->items_d[p], items[p].data(), items[p].size() * sizeof(int),
-                        hipMemcpyHostToDevice));
-  BHX_CHECK(hipMemcpy(ctl_d, ctl.data(), n * sizeof(Ctl), hipMemcpyHostToDevice));
-  BHX_CHECK(hipMemcpy(hd->batch_d, &Bh, sizeof(Batch), hipMemcpyHostToDevice));
+  // stream-ordered: the setup launches that follow on st read all of these
+  {
+    Upload u[3 + kNumPass] = {{hd->inst_d, inst.data(), n * sizeof(Inst)},
+                              {ctl_d, ctl.data(), n * sizeof(Ctl)},
+                              {hd->batch_d, &Bh, sizeof(Batch)}};
+    for (int p = 0; p < kNumPass; ++p)
+      u[3 + p] = {hd->items_d[p], items[p].data(), items[p].size() * sizeof(int)};
+    BHX_CHECK(upload_ordered(hd, st, u, 3 + kNumPass));
+  }
 
   Grids g;
   g.s = std::max(1, std::min(Bh.n_items[kPassS], hd->num_cu * R.sched.occ_s));
@@ -672,8 +709,8 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
   if (active < n) {
     BHX_CHECK(hipMemcpyAsync(ctl_d, ch, n * sizeof(Ctl), hipMemcpyHostToDevice, st));
     if (any_zero) {
-      BHX_CHECK(hipMemcpyAsync(hd->flag_d, zero_flag.data(), n * sizeof(int),
-                               hipMemcpyHostToDevice, st));
+      const Upload u{hd->flag_d, zero_flag.data(), n * sizeof(int)};
+      BHX_CHECK(upload_ordered(hd, st, &u, 1));
       BHX_CHECK(launch_zero_unknown(hd->batch_d, hd->flag_d, g.s, st));
     }
     BHX_CHECK(hipStreamSynchronize(st));

@@ -20,7 +20,9 @@ class PlanCache {
  public:
   ~PlanCache();
   int get(int n, int bc);                // plan index, created on first use
-  hipError_t sync_device();              // upload if new plans were added
+  // Upload the tables if new plans were added: stream-ordered on `st`, and
+  // complete on return.
+  hipError_t sync_device(hipStream_t st);
   const AxisPlan& plan(int i) const { return plans_[i]; }
   const AxisPlan* plans_d() const { return plans_d_; }
   const void* ctab(int p) const { return p == 0 ? (const void*)ctab_d_ : (const void*)ctab_f_; }
@@ -116,6 +118,8 @@ struct bhx_handle {
   bhx::Ctl* ctl_h = nullptr;   // pinned copy of the control blocks
   int ctl_h_cap = 0;
   hipStream_t own_stream = nullptr;
+  unsigned char* stage_h = nullptr;   // pinned staging of host->device uploads
+  size_t stage_cap = 0;
   std::vector<bhx::Graph> graphs;
   std::map<unsigned long long, bhx::Schedule> tuned;   // autotuner results per batch shape
   std::mutex mu;
@@ -139,5 +143,16 @@ hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved&
 int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, double* out, int nx,
                 int ny, int bcx, int bcy, int precision, hipStream_t stream);
 int init_handle(bhx_handle* hd, int device);
+// One host array to copy to device memory.
+struct Upload {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+// Copy `n` host arrays to the device in stream order on `st`, through the
+// handle's pinned staging buffer, so every later launch on `st` sees them.
+// The caller has synchronised `st` since the previous upload (the staging
+// buffer is then free); the host sources may be reused on return.
+hipError_t upload_ordered(bhx_handle* hd, hipStream_t st, const Upload* u, int n);
 void free_handle(bhx_handle* hd);
 }  // namespace bhx

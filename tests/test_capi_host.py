@@ -2,6 +2,7 @@
 function include/bhx.h declares, and rejects bad arguments before touching a
 GPU.  No compute call is made here."""
 import ctypes
+import os
 
 import pytest
 
@@ -14,6 +15,18 @@ def test_exports_every_declared_symbol():
     assert "bhx_engine_submit" in names and "bhx_workspace_bytes" in names
     missing = [n for n in names if not bhx.exported(n)]
     assert not missing, missing
+
+
+def test_one_hip_runtime_in_process():
+    """torch bundles a HIP runtime; importing the binding must not add a
+    second one (two runtimes in one process cannot both reach the GPU)."""
+    paths = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 6 and "libamdhip64" in parts[-1]:
+                paths.add(os.path.realpath(parts[-1]))
+    assert len(paths) <= 1, sorted(paths)
 
 
 def test_default_opts_and_strings():
