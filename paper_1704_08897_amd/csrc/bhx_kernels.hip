@@ -588,6 +588,15 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
   __shared__ double P[kPH][kPW + 1];
   __shared__ double L[kLH][kLW + 1];
   __shared__ double red[16];
+  // `done` is the one control field this pass writes (the block owning tile 0
+  // of an instance sets it when the instance stops) while other blocks of the
+  // same launch read it.  Waves of one block that read it at different times
+  // could disagree and take different barrier sequences, so one thread reads
+  // it for the block; two slots alternate between items, so a slow wave still
+  // finds its item's value (the writer cannot pass the next item's barrier
+  // before that wave arrives there).
+  __shared__ int s_done[2];
+  int slot = 0;
   constexpr int kOut = kTileX * kTileY / kThreads;
   for (int it = logical_block(); it < B.n_items[kPassS]; it += gridDim.x) {
     const int code = item_code(B, kPassS, it);
@@ -595,10 +604,15 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
     const int tile = code & kItemMask;
     BHX_GLOBAL Ctl* ctl = I.ctl;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
-    // control fields and the tile's unknown count, loaded together
-    const int c_done = ctl->done, c_iter = ctl->iter, c_rit = ctl->restart_iter;
+    // control fields and the tile's unknown count, loaded together; none but
+    // `done` changes during the pass
+    if (threadIdx.x == 0) s_done[slot] = ctl->done;
+    const int c_iter = ctl->iter, c_rit = ctl->restart_iter;
     const double c_thresh = ctl->thresh;
     const bool has_u = I.part[PL.aux2() + tile] != 0.0;     // unknown nodes in this tile
+    __syncthreads();
+    const int c_done = s_done[slot];
+    slot ^= 1;
     if (c_done) continue;
     const int nx = I.nx, ny = I.ny;
     const int out_slot = (MODE == kModeIter ? PL.pq() : PL.aux()) + tile;

@@ -261,3 +261,32 @@ def test_batched_autotuned_fp32(handle):
     for p, F, st in zip(batch, Fs, sts):
         assert st.true_rel_residual <= 1e-12
         check_against_oracle(p, host(F), bound=1e-8)
+
+
+def test_large_batch_deterministic(handle):
+    """A batch whose stencil tiles outnumber the persistent grid (each block
+    takes several items, instances converge while others iterate): every
+    instance converges, repeated solves are bit-identical, and sampled
+    instances equal their solo solves bit for bit."""
+    batch = W.star_cubic_batch(256, seed=4, tol=1e-8)
+    tiles = sum(-(-p.phi.shape[1] // 64) * -(-p.phi.shape[0] // 32) for p in batch)
+    assert tiles > 2 * 256 * 8
+    phis = [dev(p.phi) for p in batch]
+    o = bhx.default_opts(rows=1, occupancy=1)
+    runs = []
+    for _ in range(3):
+        Fs = [dev(p.F) for p in batch]
+        s, sts = bhx.extend_batched(handle, phis, Fs, [p.h for p in batch],
+                                    [p.bc for p in batch], [p.tol for p in batch], opts=o)
+        assert s == bhx.OK, [(i, st.status, st.iterations) for i, st in enumerate(sts)
+                             if st.status != bhx.OK]
+        runs.append((Fs, [st.iterations for st in sts]))
+    for Fs, its in runs[1:]:
+        assert its == runs[0][1]
+        assert all(torch.equal(a, b) for a, b in zip(Fs, runs[0][0]))
+    for i in (74, 152, 220, 255):
+        p = batch[i]
+        F = dev(p.F)
+        s, st = bhx.extend_ex(handle, phis[i], F, bc=p.bc, h=p.h, tol=p.tol, opts=o)
+        assert s == bhx.OK and st.iterations == runs[0][1][i]
+        assert torch.equal(F, runs[0][0][i])
