@@ -141,18 +141,24 @@ struct Batch {
 // Launch wrappers (defined with the kernels).
 namespace bhx {
 enum FinModeHost { kFinSetupH = 0, kFinResidH = 1 };
+// The pass launches take an optional pair of events that the dispatch itself
+// records at kernel start and end (hipExtLaunchKernelGGL), so their elapsed
+// time is the kernel's execution time.
 hipError_t launch_setup(const Batch* B, int grid, hipStream_t st);
-hipError_t launch_stencil(const Batch* B, int mode, int grid, hipStream_t st);
+hipError_t launch_stencil(const Batch* B, int mode, int grid, hipStream_t st,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_resid(const Batch* B, int grid, hipStream_t st);
 // Transform launches: `lds` dynamic LDS bytes, `twoff` complex-element offset
 // of the twiddle table staged in LDS (after the largest packed-row buffer).
 hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, int lds, int twoff,
-                         hipStream_t st);
+                         hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_col(const Batch* B, int prec, int count_iter, int grid, int lds, int twoff,
-                      hipStream_t st);
-hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, hipStream_t st);
+                      hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, hipStream_t st,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_setup_rows(const Batch* B, int grid, hipStream_t st);
-hipError_t launch_identity(const Batch* B, int grid, hipStream_t st);
+hipError_t launch_identity(const Batch* B, int grid, hipStream_t st, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);
 hipError_t launch_finalize(const Batch* B, int count, int mode, hipStream_t st);
 hipError_t launch_restart(const Batch* B, int count, hipStream_t st);
 hipError_t launch_bump(const Batch* B, int count, hipStream_t st);

@@ -28,6 +28,7 @@
 // a fixed order, so each block computes bit-identical alpha/beta and the
 // result does not depend on scheduling or on the batch composition.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include "bhx_internal.h"
@@ -1427,11 +1428,23 @@ hipError_t launch_setup(const Batch* B, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_setup, dim3(grid), dim3(kThreads), 0, st, B);
   return hipGetLastError();
 }
-hipError_t launch_stencil(const Batch* B, int mode, int grid, hipStream_t st) {
+// Launch on `st`; given events, through hipExtLaunchKernelGGL, whose dispatch
+// records them at kernel start and end.
+#define BHX_LAUNCH(kernel, grid, lds, st, e0, e1, ...)                                  \
+  do {                                                                                \
+    if (e0)                                                                           \
+      hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), lds, st, e0, e1, 0,   \
+                            __VA_ARGS__);                                             \
+    else                                                                              \
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), lds, st, __VA_ARGS__);   \
+  } while (0)
+
+hipError_t launch_stencil(const Batch* B, int mode, int grid, hipStream_t st, hipEvent_t e0,
+                          hipEvent_t e1) {
   switch (mode) {
-    case kModeIter: hipLaunchKernelGGL(k_stencil<kModeIter>, dim3(grid), dim3(kThreads), 0, st, B); break;
-    case kModeRhs: hipLaunchKernelGGL(k_stencil<kModeRhs>, dim3(grid), dim3(kThreads), 0, st, B); break;
-    case kModeApply: hipLaunchKernelGGL(k_stencil<kModeApply>, dim3(grid), dim3(kThreads), 0, st, B); break;
+    case kModeIter: BHX_LAUNCH(k_stencil<kModeIter>, grid, 0, st, e0, e1, B); break;
+    case kModeRhs: BHX_LAUNCH(k_stencil<kModeRhs>, grid, 0, st, e0, e1, B); break;
+    case kModeApply: BHX_LAUNCH(k_stencil<kModeApply>, grid, 0, st, e0, e1, B); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1441,34 +1454,36 @@ hipError_t launch_resid(const Batch* B, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, int lds, int twoff,
-                         hipStream_t st) {
+                         hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_rowfwd<double>, dim3(grid), dim3(kThreads), lds, st, B, update, twoff);
+    BHX_LAUNCH(k_rowfwd<double>, grid, lds, st, e0, e1, B, update, twoff);
   else
-    hipLaunchKernelGGL(k_rowfwd<float>, dim3(grid), dim3(kThreads), lds, st, B, update, twoff);
+    BHX_LAUNCH(k_rowfwd<float>, grid, lds, st, e0, e1, B, update, twoff);
   return hipGetLastError();
 }
 hipError_t launch_col(const Batch* B, int prec, int count_iter, int grid, int lds, int twoff,
-                      hipStream_t st) {
+                      hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_col<double>, dim3(grid), dim3(kThreads), lds, st, B, count_iter, twoff);
+    BHX_LAUNCH(k_col<double>, grid, lds, st, e0, e1, B, count_iter, twoff);
   else
-    hipLaunchKernelGGL(k_col<float>, dim3(grid), dim3(kThreads), lds, st, B, count_iter, twoff);
+    BHX_LAUNCH(k_col<float>, grid, lds, st, e0, e1, B, count_iter, twoff);
   return hipGetLastError();
 }
-hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, hipStream_t st) {
+hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, hipStream_t st,
+                         hipEvent_t e0, hipEvent_t e1) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_rowinv<double>, dim3(grid), dim3(kThreads), lds, st, B, twoff);
+    BHX_LAUNCH(k_rowinv<double>, grid, lds, st, e0, e1, B, twoff);
   else
-    hipLaunchKernelGGL(k_rowinv<float>, dim3(grid), dim3(kThreads), lds, st, B, twoff);
+    BHX_LAUNCH(k_rowinv<float>, grid, lds, st, e0, e1, B, twoff);
   return hipGetLastError();
 }
 hipError_t launch_setup_rows(const Batch* B, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_setup_rows, dim3(grid), dim3(kThreads), 0, st, B);
   return hipGetLastError();
 }
-hipError_t launch_identity(const Batch* B, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_identity, dim3(grid), dim3(kThreads), 0, st, B);
+hipError_t launch_identity(const Batch* B, int grid, hipStream_t st, hipEvent_t e0,
+                           hipEvent_t e1) {
+  BHX_LAUNCH(k_identity, grid, 0, st, e0, e1, B);
   return hipGetLastError();
 }
 hipError_t launch_finalize(const Batch* B, int count, int mode, hipStream_t st) {

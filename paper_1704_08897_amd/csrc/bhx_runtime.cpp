@@ -390,34 +390,25 @@ inline hipEvent_t ev_at(const std::vector<hipEvent_t>* ev, int chunk, int p, int
 hipError_t launch_iterations(const Batch* B, int n_inst, const Resolved& R, const Grids& g,
                              int count, hipStream_t st, const std::vector<hipEvent_t>* ev) {
   hipError_t e;
-  auto rec = [&](int p, int c, int edge) -> hipError_t {
-    if (!ev || !(R.profile & (1 << p))) return hipSuccess;
-    return hipEventRecord(ev_at(ev, count, p, c, edge), st);
+  // events of pass p, iteration c (null unless the pass is profiled)
+  auto e0 = [&](int p, int c) -> hipEvent_t {
+    return ev && (R.profile & (1 << p)) ? ev_at(ev, count, p, c, 0) : nullptr;
+  };
+  auto e1 = [&](int p, int c) -> hipEvent_t {
+    return ev && (R.profile & (1 << p)) ? ev_at(ev, count, p, c, 1) : nullptr;
   };
 #define BHX_TRY(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
   for (int c = 0; c < count; ++c) {
-    BHX_TRY(rec(0, c, 0));
-    BHX_TRY(launch_stencil(B, kModeIter, g.s, st));
-    BHX_TRY(rec(0, c, 1));
+    BHX_TRY(launch_stencil(B, kModeIter, g.s, st, e0(0, c), e1(0, c)));
     if (R.precond) {
-      BHX_TRY(rec(1, c, 0));
-      BHX_TRY(launch_rowfwd(B, R.precision, 1, g.r, g.lds_r, g.tw_r, st));
-      BHX_TRY(rec(1, c, 1));
-      BHX_TRY(rec(2, c, 0));
-      BHX_TRY(launch_col(B, R.precision, 1, g.c, g.lds_c, g.tw_c, st));
-      BHX_TRY(rec(2, c, 1));
-      BHX_TRY(rec(3, c, 0));
-      BHX_TRY(launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, st));
-      BHX_TRY(rec(3, c, 1));
+      BHX_TRY(launch_rowfwd(B, R.precision, 1, g.r, g.lds_r, g.tw_r, st, e0(1, c), e1(1, c)));
+      BHX_TRY(launch_col(B, R.precision, 1, g.c, g.lds_c, g.tw_c, st, e0(2, c), e1(2, c)));
+      BHX_TRY(launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, st, e0(3, c), e1(3, c)));
     } else {
       // plain CG: update-only row pass, iteration count, z = r
-      BHX_TRY(rec(1, c, 0));
-      BHX_TRY(launch_rowfwd(B, R.precision, 2, g.r, g.lds_r, g.tw_r, st));
-      BHX_TRY(rec(1, c, 1));
+      BHX_TRY(launch_rowfwd(B, R.precision, 2, g.r, g.lds_r, g.tw_r, st, e0(1, c), e1(1, c)));
       BHX_TRY(launch_bump(B, n_inst, st));
-      BHX_TRY(rec(3, c, 0));
-      BHX_TRY(launch_identity(B, g.r, st));
-      BHX_TRY(rec(3, c, 1));
+      BHX_TRY(launch_identity(B, g.r, st, e0(3, c), e1(3, c)));
     }
   }
 #undef BHX_TRY

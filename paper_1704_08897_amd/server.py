@@ -73,18 +73,24 @@ class Server:
             pass
 
 
-def serve_stream(server: Server, requests, on_done=None, idle_sleep: float = 2e-4):
+def serve_stream(server: Server, requests, on_done=None, idle_sleep: float = 2e-4,
+                 stall_timeout: float = 120.0):
     """Submit each request at its arrival time (relative to now), keep the
     ones that do not fit in a FIFO, collect completions.  Returns the list of
-    Result in completion order."""
+    Result in completion order.  Raises TimeoutError if requests are in
+    flight and none completes for `stall_timeout` seconds."""
     pending = sorted(range(len(requests)), key=lambda i: requests[i].arrival)
     waiting = []                      # arrived, not yet admitted (FIFO)
     live = {}                         # id -> (index, t_arrival, t_submit)
     results = []
     t0 = time.perf_counter()
+    last_progress = t0
     nxt = 0
     while nxt < len(pending) or waiting or live:
         now = time.perf_counter() - t0
+        if live and now + t0 - last_progress > stall_timeout:
+            raise TimeoutError(f"{len(live)} requests in flight, none completed in "
+                               f"{stall_timeout:.0f} s")
         while nxt < len(pending) and requests[pending[nxt]].arrival <= now:
             waiting.append((pending[nxt], t0 + requests[pending[nxt]].arrival))
             nxt += 1
@@ -96,6 +102,8 @@ def serve_stream(server: Server, requests, on_done=None, idle_sleep: float = 2e-
             live[rid] = (i, ta, time.perf_counter())
             waiting.pop(0)
         done = server.poll()
+        if done or not live:
+            last_progress = time.perf_counter()
         for rid, st in done:
             i, ta, ts = live.pop(rid)
             r = Result(requests[i], st.as_dict(), ta, ts, ts + st.seconds)
