@@ -101,7 +101,7 @@ typedef struct {
   int flexible;     /* -1 = default (flexible iff precision is FP32), 0 = standard
                          beta = r.z / r_old.z_old, 1 = Polak-Ribiere beta           */
   int chunk;        /* iterations per captured graph between convergence checks;
-                         0 -> 32                                                     */
+                         0 -> 32; an odd value is rounded up to even                 */
   int rows;         /* packed complex rows (two grid rows each) per transform work
                          item; 0 = automatic (autotuner or built-in policy)           */
   int occupancy;    /* persistent blocks per CU of the transform passes; 0 = auto   */

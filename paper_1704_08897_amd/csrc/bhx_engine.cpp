@@ -207,9 +207,9 @@ Grids engine_grids(bhx_engine* E, const std::vector<Req*>& reqs) {
   for (Req* q : reqs) {
     const AxisPlan& PX = E->hd->plans.plan(q->inst.planx);
     const AxisPlan& PY = E->hd->plans.plan(q->inst.plany);
-    buf_r = std::max(buf_r, (q->inst.G / 2) * padded(PX.m));
+    buf_r = std::max(buf_r, (q->inst.G / 2) * row_slots(PX.m));
     tab_r = std::max(tab_r, table_slots(PX.n, PX.m));
-    buf_c = std::max(buf_c, (q->inst.Gc / 2) * padded(PY.m));
+    buf_c = std::max(buf_c, (q->inst.Gc / 2) * row_slots(PY.m));
     tab_c = std::max(tab_c, table_slots(PY.n, PY.m));
   }
   // round the LDS up to 16 KiB steps so graphs are reused across batches
@@ -280,7 +280,7 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
   const int n = (int)news.size();
   ENG_CHECK(launch_setup(E->aux.hdr, g.s, st));
   ENG_CHECK(launch_setup_rows(E->aux.hdr, g.r, st));
-  ENG_CHECK(launch_stencil(E->aux.hdr, kModeRhs, g.s, st));
+  ENG_CHECK(launch_stencil(E->aux.hdr, kModeRhs, g.s, 0, st));
   ENG_CHECK(launch_finalize(E->aux.hdr, n, kFinSetupH, st));
   ENG_CHECK(hipMemcpyAsync(E->ctl_h, E->ctl_d, E->max_slots * sizeof(Ctl), hipMemcpyDeviceToHost,
                            st));
@@ -452,6 +452,7 @@ int bhx_engine_create(bhx_engine** out, int device, size_t hbm_budget, int max_s
   E->device = device;
   E->R = R;
   E->R.chunk = o && o->chunk > 0 ? o->chunk : 16;   // short chunks: new requests join quickly
+  E->R.chunk += E->R.chunk & 1;                       // even (buffer parity restarts each chunk)
   E->R.profile = 0;
   E->budget = hbm_budget;
   E->max_slots = max_slots;

@@ -30,9 +30,21 @@ constexpr int kLdsBytes = 80 * 1024;   // LDS for the packed rows of one transfo
 constexpr int kLdsMax = 160 * 1024;    // LDS of a CU (gfx950)
 constexpr int kLdsDynMax = 152 * 1024; // dynamic LDS cap of a transform launch
 constexpr int kMaxPairs = 8;           // (k, n-k) pairs held in registers per thread
+constexpr int kMaxGc = 16;             // columns per column-pass item (2 x rows cap)
 constexpr int kTargetItems = 512;      // row/column items one instance should supply
 
 enum Bc { kNeumann = 0, kPeriodic = 1, kDirichlet = 2 };
+
+// Shift of the second pad term of an FFT row in LDS (see rpos in the kernels):
+// rows of length 2^logm >= 256 get one extra slot every 2^(logm-4) elements.
+__host__ __device__ inline int rpos_shift(int logm) { return logm >= 8 ? logm - 4 : 31; }
+// Complex slots of the per-stage twiddle tables of a length-2^logm FFT: h
+// for each radix-4 stage of span h (h = 1, 4, 16, ... or 2, 8, 32, ...).
+__host__ __device__ inline int stage_twiddles(int logm) {
+  int t = 0;
+  for (int h = (logm & 1) ? 2 : 1; h < (1 << logm); h <<= 2) t += h;
+  return t;
+}
 enum Pass { kPassS = 0, kPassR = 1, kPassC = 2, kNumPass = 3 };
 
 // Stencil kernel modes.
@@ -145,20 +157,24 @@ enum FinModeHost { kFinSetupH = 0, kFinResidH = 1 };
 // records at kernel start and end (hipExtLaunchKernelGGL), so their elapsed
 // time is the kernel's execution time.
 hipError_t launch_setup(const Batch* B, int grid, hipStream_t st);
-hipError_t launch_stencil(const Batch* B, int mode, int grid, hipStream_t st,
+// `lpar` is the buffer parity of an iteration's launches: consecutive
+// iterations alternate it; the preconditioner applied after setup or a
+// restart runs with parity 1, so the first iteration runs with parity 0.
+hipError_t launch_stencil(const Batch* B, int mode, int grid, int lpar, hipStream_t st,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_resid(const Batch* B, int grid, hipStream_t st);
 // Transform launches: `lds` dynamic LDS bytes, `twoff` complex-element offset
 // of the twiddle table staged in LDS (after the largest packed-row buffer).
 hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, int lds, int twoff,
-                         hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                         int lpar, hipStream_t st, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
 hipError_t launch_col(const Batch* B, int prec, int count_iter, int grid, int lds, int twoff,
                       hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, hipStream_t st,
-                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, int lpar,
+                         hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_setup_rows(const Batch* B, int grid, hipStream_t st);
-hipError_t launch_identity(const Batch* B, int grid, hipStream_t st, hipEvent_t e0 = nullptr,
-                           hipEvent_t e1 = nullptr);
+hipError_t launch_identity(const Batch* B, int grid, int lpar, hipStream_t st,
+                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_finalize(const Batch* B, int count, int mode, hipStream_t st);
 hipError_t launch_restart(const Batch* B, int count, hipStream_t st);
 hipError_t launch_bump(const Batch* B, int count, hipStream_t st);

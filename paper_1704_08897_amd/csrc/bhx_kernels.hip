@@ -74,10 +74,13 @@ template <typename R> __device__ __forceinline__ R inv_sq(R s) {
   return s > (R)0 ? recip(s * s) : (R)0;
 }
 
-// Packed rows in LDS carry one pad element after every 8 complex values, so
-// the bit-reversed scatter and the small-stride butterfly stages spread over
-// the LDS banks.
-__device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
+// LDS position of element i of a packed FFT row: one pad slot after every 8
+// elements, and for rows of length m >= 256 one more after every m/16
+// (sh = log2(m) - 4; sh = 31 adds nothing).  The first spreads the
+// small-stride butterfly stages over the banks, the second the bit-reversed
+// scatter of the inputs, whose consecutive indices differ in the top bits.
+__device__ __forceinline__ int rpos(int i, int sh) { return i + (i >> 3) + (i >> sh); }
+
 
 __device__ __forceinline__ int bitrev(int k, int logm) {
   return (int)(__brev((unsigned)k) >> (32 - logm));
@@ -159,15 +162,20 @@ template <int K>
 struct Partials {
   double v[K][4];
 };
+// sums_issue() takes the arrays' lengths (>= 1), sums_finish() the counts of
+// entries to add (<= length, 0 to skip an array), so the loads need nothing
+// decided at run time.  The loads are unconditional, from clamped indices: a
+// load behind a branch is followed by a wait for it, which would serialise
+// the round trips.
 template <int K>
 __device__ __forceinline__ void sums_issue(BHX_GLOBAL const double* const (&a)[K],
-                                           const int (&n)[K], Partials<K>& P) {
+                                           const int (&len)[K], Partials<K>& P) {
 #pragma unroll
   for (int k = 0; k < K; ++k)
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = u * kThreads + threadIdx.x;
-      P.v[k][u] = n[k] > 0 ? a[k][min(i, max(n[k] - 1, 0))] : 0.0;
+      P.v[k][u] = a[k][min(i, len[k] - 1)];
     }
 }
 template <int K>
@@ -260,10 +268,10 @@ __device__ __forceinline__ int logical_block() {
 template <typename R>
 struct XPlan {
   using C = typename V2<R>::T;
-  int n, m, logm, blue, bc;
+  int n, m, logm, blue, bc, sh;
   R s0, s1, g0, g1, hs;
-  BHX_GLOBAL const C* twg;    // twiddles in device memory
-  const C* tw;                // twiddles in LDS once staged
+  BHX_GLOBAL const C* twg;    // W_m^k, k < m/2, in device memory
+  const C* tw;                // per-stage twiddle tables in LDS once staged
   BHX_GLOBAL const C* chirp;
   BHX_GLOBAL const C* bhat;
   BHX_GLOBAL const C* post;
@@ -272,13 +280,20 @@ struct XPlan {
   const R* laml;              // eigenvalues in LDS once staged
   // Copy the plan's twiddles, DCT post-twiddles and eigenvalues into LDS at
   // `lds` unless plan `idx` is staged there already; every thread of the
-  // block must call this at the same point.
+  // block must call this at the same point.  The twiddles are laid out per
+  // radix-4 stage of span h: W_4h^k for k < h (stage_twiddles), so each
+  // stage reads them at unit stride; the stage squares them for W_2h^k.
   __device__ void stage(C* lds, int idx, int& staged) {
     C* tw_l = lds;
-    C* post_l = lds + (m >> 1);
+    C* post_l = lds + stage_twiddles(logm);
     R* lam_l = (R*)(post_l + n);
     if (idx != staged) {
-      for (int k = threadIdx.x; k < (m >> 1); k += kThreads) tw_l[k] = twg[k];
+      int off = 0;
+      for (int h = (logm & 1) ? 2 : 1; h < m; h <<= 2) {
+        const int ls = logm - 2 - (31 - __clz(h));     // W_4h^k = twg[k << ls]
+        for (int k = threadIdx.x; k < h; k += kThreads) tw_l[off + k] = twg[k << ls];
+        off += h;
+      }
       if (bc == kNeumann)
         for (int k = threadIdx.x; k < n; k += kThreads) post_l[k] = post[k];
       for (int k = threadIdx.x; k < n; k += kThreads) lam_l[k] = lam[k];
@@ -292,6 +307,7 @@ struct XPlan {
   __device__ XPlan(const Batch& B, int idx) {
     const AxisPlan P = B.plans[idx];
     n = P.n; m = P.m; logm = P.logm; blue = P.bluestein; bc = P.bc;
+    sh = rpos_shift(logm);
     s0 = (R)P.s0; s1 = (R)P.s1; g0 = (R)P.g0; g1 = (R)P.g1; hs = (R)P.hs;
     const int pi = sizeof(R) == 8 ? 0 : 1;
     BHX_GLOBAL const C* ct = (BHX_GLOBAL const C*)B.ctab[pi];
@@ -304,62 +320,63 @@ struct XPlan {
     post = ct + P.off_post;
     lam = (BHX_GLOBAL const R*)B.rtab[pi] + P.off_lam;
   }
-  // padded LDS position of logical FFT input k
-  __device__ __forceinline__ int pos(int k) const { return pad8(bitrev(k, logm)); }
-  // row stride of the packed rows (padded)
-  __device__ __forceinline__ int stride() const { return pad8(m); }
+  // LDS position of logical FFT input k (bit-reversed)
+  __device__ __forceinline__ int pos(int k) const { return rpos(bitrev(k, logm), sh); }
+  // row stride of the packed rows
+  __device__ __forceinline__ int stride() const { return rpos(m, sh); }
   // logical FFT output k of a row (after core())
   __device__ __forceinline__ C out(const C* row, int k) const {
-    if (!blue) return row[pad8(k)];
-    return cmul(chirp[k], row[pad8(bitrev(k, logm))]);
+    if (!blue) return row[rpos(k, sh)];
+    return cmul(chirp[k], row[rpos(bitrev(k, logm), sh)]);
   }
 };
 
 // In-place radix-4/2 DIT FFT of `rows` rows (stride `st`) of length m held in
-// LDS in bit-reversed order; natural-order output; sign -1.
+// LDS in bit-reversed order (positions rpos(., sh)); natural-order output;
+// sign -1.  `tw`: the per-stage twiddle tables of XPlan::stage().
 template <typename R>
-__device__ void fft_dit(typename V2<R>::T* buf, int rows, int st, int m, int logm,
+__device__ void fft_dit(typename V2<R>::T* buf, int rows, int st, int m, int logm, int sh,
                         const typename V2<R>::T* __restrict__ tw) {
   using C = typename V2<R>::T;
   const int tid = threadIdx.x;
-  int h = 1, lh = 0;
+  int h = 1;
   if (logm & 1) {
     const int half = m >> 1;
     for (int idx = tid; idx < rows * half; idx += kThreads) {
       const int r = idx >> (logm - 1), b = (idx & (half - 1)) << 1;
       C* a = buf + r * st;
-      const int i0 = pad8(b), i1 = pad8(b + 1);
+      const int i0 = rpos(b, sh), i1 = rpos(b + 1, sh);
       C u = a[i0], v = a[i1];
       a[i0] = cadd(u, v);
       a[i1] = csub(u, v);
     }
     __syncthreads();
-    h = 2; lh = 1;
+    h = 2;
   }
   const int lq = logm - 2;
-  for (; h < m; h <<= 2, lh += 2) {
+  for (int toff = 0; h < m; toff += h, h <<= 2) {
     const int quarter = m >> 2;
-    const int ls1 = logm - 1 - lh, ls2 = logm - 2 - lh;   // table strides m/(2h), m/(4h)
+    const C* __restrict__ t2 = tw + toff;      // W_4h^k
     for (int idx = tid; idx < rows * quarter; idx += kThreads) {
       const int r = idx >> lq, rem = idx & (quarter - 1);
       const int k = rem & (h - 1);
       const int b = (rem - k) << 2;
       C* a = buf + r * st;
-      const int i0 = pad8(b + k), i1 = pad8(b + k + h), i2 = pad8(b + k + 2 * h),
-                i3 = pad8(b + k + 3 * h);
-      const C w1 = tw[k << ls1];
-      const C w2 = tw[k << ls2];
+      const int i0 = rpos(b + k, sh), i1 = rpos(b + k + h, sh), i2 = rpos(b + k + 2 * h, sh),
+                i3 = rpos(b + k + 3 * h, sh);
+      const C w2 = t2[k];
+      const C w1 = cmul(w2, w2);           // W_2h^k
       C a0 = a[i0], a1 = a[i1], a2 = a[i2], a3 = a[i3];
       C t = cmul(w1, a1);
-      C t0 = cadd(a0, t), t1 = csub(a0, t);
+      C t0 = cadd(a0, t), tt1 = csub(a0, t);
       t = cmul(w1, a3);
-      C t2 = cadd(a2, t), t3 = csub(a2, t);
-      t = cmul(w2, t2);
+      C tt2 = cadd(a2, t), tt3 = csub(a2, t);
+      t = cmul(w2, tt2);
       a[i0] = cadd(t0, t);
       a[i2] = csub(t0, t);
-      t = cmul_mi(cmul(w2, t3));          // W_4h^(k+h) = W_4h^k * (-i)
-      a[i1] = cadd(t1, t);
-      a[i3] = csub(t1, t);
+      t = cmul_mi(cmul(w2, tt3));          // W_4h^(k+h) = W_4h^k * (-i)
+      a[i1] = cadd(tt1, t);
+      a[i3] = csub(tt1, t);
     }
     __syncthreads();
   }
@@ -368,41 +385,43 @@ __device__ void fft_dit(typename V2<R>::T* buf, int rows, int st, int m, int log
 // In-place radix-4/2 DIF FFT, natural-order input, bit-reversed output,
 // sign +1, unnormalised (inverse of fft_dit up to the factor m).
 template <typename R>
-__device__ void fft_dif_inv(typename V2<R>::T* buf, int rows, int st, int m, int logm,
+__device__ void fft_dif_inv(typename V2<R>::T* buf, int rows, int st, int m, int logm, int sh,
                             const typename V2<R>::T* __restrict__ tw) {
   using C = typename V2<R>::T;
   const int tid = threadIdx.x;
   const int lq = logm - 2;
-  int lh = logm - 2;
-  for (int h = m >> 2; h >= 1; h >>= 2, lh -= 2) {
+  // the stages run from the largest span down: start at the last table
+  int toff = stage_twiddles(logm) - (m >> 2);
+  for (int h = m >> 2; h >= 1; h >>= 2) {
     const int quarter = m >> 2;
-    const int ls1 = logm - 1 - lh, ls2 = logm - 2 - lh;
+    const C* __restrict__ t2 = tw + toff;
     for (int idx = tid; idx < rows * quarter; idx += kThreads) {
       const int r = idx >> lq, rem = idx & (quarter - 1);
       const int k = rem & (h - 1);
       const int b = (rem - k) << 2;
       C* a = buf + r * st;
-      const int i0 = pad8(b + k), i1 = pad8(b + k + h), i2 = pad8(b + k + 2 * h),
-                i3 = pad8(b + k + 3 * h);
-      const C w1 = cconj(tw[k << ls1]);
-      const C w2 = cconj(tw[k << ls2]);
+      const int i0 = rpos(b + k, sh), i1 = rpos(b + k + h, sh), i2 = rpos(b + k + 2 * h, sh),
+                i3 = rpos(b + k + 3 * h, sh);
+      const C w2 = cconj(t2[k]);
+      const C w1 = cmul(w2, w2);
       C a0 = a[i0], a1 = a[i1], a2 = a[i2], a3 = a[i3];
-      C t0 = cadd(a0, a2), t2 = cmul(csub(a0, a2), w2);
-      C t1 = cadd(a1, a3), t3 = cmul_pi(cmul(csub(a1, a3), w2));   // conj(W_4h^(k+h))
-      a[i0] = cadd(t0, t1);
-      a[i1] = cmul(csub(t0, t1), w1);
-      a[i2] = cadd(t2, t3);
-      a[i3] = cmul(csub(t2, t3), w1);
+      C t0 = cadd(a0, a2), t2v = cmul(csub(a0, a2), w2);
+      C t1v = cadd(a1, a3), t3 = cmul_pi(cmul(csub(a1, a3), w2));   // conj(W_4h^(k+h))
+      a[i0] = cadd(t0, t1v);
+      a[i1] = cmul(csub(t0, t1v), w1);
+      a[i2] = cadd(t2v, t3);
+      a[i3] = cmul(csub(t2v, t3), w1);
     }
     __syncthreads();
-    if (h == 1) break;
+    if (h == 1 || h == 2) break;
+    toff -= h >> 2;
   }
   if (logm & 1) {
     const int half = m >> 1;
     for (int idx = tid; idx < rows * half; idx += kThreads) {
       const int r = idx >> (logm - 1), b = (idx & (half - 1)) << 1;
       C* a = buf + r * st;
-      const int i0 = pad8(b), i1 = pad8(b + 1);
+      const int i0 = rpos(b, sh), i1 = rpos(b + 1, sh);
       C u = a[i0], v = a[i1];
       a[i0] = cadd(u, v);
       a[i1] = csub(u, v);
@@ -427,15 +446,15 @@ __device__ void dft_core(const XPlan<R>& X, typename V2<R>::T* buf, int rows) {
     }
     __syncthreads();
   }
-  fft_dit<R>(buf, rows, st, X.m, X.logm, X.tw);
+  fft_dit<R>(buf, rows, st, X.m, X.logm, X.sh, X.tw);
   if (X.blue) {
     for (int idx = threadIdx.x; idx < rows * X.m; idx += kThreads) {
       const int r = idx >> X.logm, k = idx & (X.m - 1);
-      const int p = r * st + pad8(k);
+      const int p = r * st + rpos(k, X.sh);
       buf[p] = cmul(buf[p], X.bhat[k]);
     }
     __syncthreads();
-    fft_dif_inv<R>(buf, rows, st, X.m, X.logm, X.tw);
+    fft_dif_inv<R>(buf, rows, st, X.m, X.logm, X.sh, X.tw);
   }
 }
 
@@ -583,8 +602,12 @@ constexpr int kPW = kTileX + 4, kPH = kTileY + 4;   // f tile with 2-node halo
 constexpr int kLW = kTileX + 2, kLH = kTileY + 2;   // L f with 1-node halo
 constexpr int kPL = (kPH * kPW + kThreads - 1) / kThreads;   // halo loads per thread
 
+// `lpar` is the buffer parity of this launch: p_old = p[lpar], p_new =
+// p[lpar ^ 1], and the current / previous r.z partials are rz(lpar) /
+// rz(lpar ^ 1).  Launches alternate it, so addresses never wait for the
+// control block.
 template <int MODE>
-__global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ Bp) {
+__global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ Bp, int lpar) {
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   __shared__ double P[kPH][kPW + 1];
   __shared__ double L[kLH][kLW + 1];
@@ -605,12 +628,22 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
     const int tile = code & kItemMask;
     BHX_GLOBAL Ctl* ctl = I.ctl;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
-    // control fields and the tile's unknown count, loaded together; none but
-    // `done` changes during the pass
-    if (threadIdx.x == 0) s_done[slot] = ctl->done;
+    // 1. loads that need nothing from the control block go out with it: the
+    //    control fields, the tile's unknown count and the partial sums behind
+    //    alpha/beta; none but `done` changes during the pass
+    const int par = lpar;
+    BHX_GLOBAL const double* pold = par ? I.p[1] : I.p[0];
+    BHX_GLOBAL double* pnew = par ? I.p[0] : I.p[1];
+    BHX_GLOBAL const double* arrs[4] = {I.part + PL.rz(par), I.part + PL.rr(),
+                                        I.part + PL.rz(par ^ 1), I.part + PL.rzo(par)};
+    const int lens[4] = {PL.nR, PL.nR, PL.nR, PL.nR};
+    Partials<4> PS;
+    if (MODE == kModeIter) sums_issue<4>(arrs, lens, PS);
+    const int ld_done = ctl->done;
     const int c_iter = ctl->iter, c_rit = ctl->restart_iter;
     const double c_thresh = ctl->thresh;
     const bool has_u = I.part[PL.aux2() + tile] != 0.0;     // unknown nodes in this tile
+    if (threadIdx.x == 0) s_done[slot] = ld_done;
     __syncthreads();
     const int c_done = s_done[slot];
     slot ^= 1;
@@ -621,20 +654,12 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
       if (threadIdx.x == 0) I.part[out_slot] = 0.0;
       continue;
     }
-    // 1. issue every load of the item: the partial sums behind alpha/beta,
-    //    the halo tile (z, p_old or F, mask) and the output masks
+    // 2. the halo tile (z and p_old, or F, and the mask) and the output masks
     const int k = c_iter;
-    const int par = k & 1;
-    const bool first = (k == c_rit);
-    BHX_GLOBAL const double* pold = first ? I.z : ((k & 1) ? I.p[1] : I.p[0]);
-    BHX_GLOBAL double* pnew = (k & 1) ? I.p[0] : I.p[1];
-    BHX_GLOBAL const double* arrs[4] = {I.part + PL.rz(par), I.part + PL.rr(),
-                                        I.part + PL.rz(par ^ 1), I.part + PL.rzo(par)};
+    const bool first = (k == c_rit);       // beta = 0: p = z
     const int ns[4] = {MODE == kModeIter ? PL.nR : 0, (MODE == kModeIter && !first) ? PL.nR : 0,
                        (MODE == kModeIter && !first) ? PL.nR : 0,
                        (MODE == kModeIter && !first && I.flexible) ? PL.nR : 0};
-    Partials<4> PS;
-    sums_issue<4>(arrs, ns, PS);
     const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
     const int i0 = tx * kTileX, j0 = ty * kTileY;
     int oo[kPL];
@@ -671,7 +696,10 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
       const int gi = min(i0 + ii, nx - 1), gj = min(j0 + jj, ny - 1);
       mo[s] = I.mask[gj * nx + gi];
     }
-    // 2. scalars: convergence test and beta (the data loads stay in flight)
+    // every load of the item is issued above; keep the arithmetic on any of
+    // them from being scheduled before the last one is issued
+    __builtin_amdgcn_sched_barrier(0);
+    // 3. scalars: convergence test and beta (the data loads stay in flight)
     double beta = 0.0;
     if (MODE == kModeIter) {
       double sums[4];
@@ -704,12 +732,12 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
       if (threadIdx.x == 0) I.part[out_slot] = 0.0;
       continue;
     }
-    // 3. tile of the operand in LDS, L f on the one-node ring, then L L f
+    // 4. tile of the operand in LDS, L f on the one-node ring, then L L f
 #pragma unroll
     for (int s = 0; s < kPL; ++s) {
       const int e = threadIdx.x + s * kThreads;
       double v;
-      if (MODE == kModeIter) v = va[s] + beta * vb[s];
+      if (MODE == kModeIter) v = first ? va[s] : va[s] + beta * vb[s];
       else if (MODE == kModeRhs) v = vm[s] ? 0.0 : va[s];
       else v = vm[s] ? va[s] : 0.0;
       if (e < kPH * kPW) {
@@ -856,9 +884,11 @@ __global__ void __launch_bounds__(kThreads) k_resid(const Batch* __restrict__ Bp
 // for G rows, written transposed to t[k * ny + j].
 // ---------------------------------------------------------------------------
 
+// `lpar`: buffer parity of the iteration (as in k_stencil): p_new = p[lpar ^ 1],
+// current r.z partials rz(lpar).
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ Bp, int update,
-                                                     int twoff) {
+                                                     int twoff, int lpar) {
   using C = typename V2<R>::T;
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   extern __shared__ __align__(16) unsigned char smem[];
@@ -873,29 +903,32 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
     const int g = code & kItemMask;
     BHX_GLOBAL Ctl* ctl = I.ctl;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
-    const int c_done = ctl->done, k_it = ctl->iter;
-    const double rowcnt = I.part[PL.rowcnt() + g];
-    if (c_done) continue;
     const int nx = I.nx, ny = I.ny, G = I.G, j0 = g * G;
     const int E = min(G, ny - j0) * nx;          // valid elements of this row group
     const size_t base = (size_t)j0 * nx;
     BHX_GLOBAL const uint8_t* __restrict__ mk = I.mask + base;
     BHX_GLOBAL double* __restrict__ Fb = I.F + base;
     BHX_GLOBAL double* __restrict__ rb = I.r + base;
-    BHX_GLOBAL const double* __restrict__ pb = ((k_it & 1) ? I.p[0] : I.p[1]) + base;
+    BHX_GLOBAL const double* __restrict__ pb = (lpar ? I.p[0] : I.p[1]) + base;
     BHX_GLOBAL const double* __restrict__ qb = I.q + base;
-    // 1. issue: partial sums behind alpha, then the masks of the first
-    //    kPre elements per thread (rows j0 .. j0+G-1 are contiguous)
-    BHX_GLOBAL const double* arrs[2] = {I.part + PL.rz(k_it & 1), I.part + PL.pq()};
+    // 1. issue together: control fields, the row group's unknown count, the
+    //    partial sums behind alpha and the masks of the first kPre elements
+    //    per thread (rows j0 .. j0+G-1 are contiguous); `done` and the counts
+    //    do not change during the pass
+    BHX_GLOBAL const double* arrs[2] = {I.part + PL.rz(lpar), I.part + PL.pq()};
+    const int lens[2] = {PL.nR, PL.nS};
     const int ns[2] = {update ? PL.nR : 0, update ? PL.nS : 0};
     Partials<2> PS;
-    sums_issue<2>(arrs, ns, PS);
+    sums_issue<2>(arrs, lens, PS);             // unconditional: no branch before the loads
     int m0[kPre];
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       const int e = threadIdx.x + u * kThreads;
       m0[u] = mk[min(e, E - 1)] && e < E;
     }
+    const int c_done = ctl->done, k_it = ctl->iter;
+    const double rowcnt = I.part[PL.rowcnt() + g];
+    if (c_done) continue;
     if (rowcnt == 0.0) {
       // no unknown node in these rows: r = 0 there, so is its transform
       BHX_GLOBAL R* t = (BHX_GLOBAL R*)I.t;
@@ -1031,25 +1064,29 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
   extern __shared__ __align__(16) unsigned char smem[];
   C* buf = (C*)smem;
   C* twl = buf + twoff;
+  __shared__ R s_lamx[kMaxGc];     // x eigenvalues of the item's rows of t
   int staged = -1;
   for (int itm = logical_block(); itm < B.n_items[kPassC]; itm += gridDim.x) {
     const int code = item_code(B, kPassC, itm);
     const Inst I = B.inst[code >> kItemShift];
     const int c = code & kItemMask;
     BHX_GLOBAL Ctl* ctl = I.ctl;
-    if (ctl->done) continue;
     const int nx = I.nx, ny = I.ny, Gc = I.Gc, kx0 = c * Gc;
     BHX_GLOBAL R* t = (BHX_GLOBAL R*)I.t;
-    // 1. issue the first kPre loads of the item's rows of t (contiguous:
-    //    rows kx0 .. kx0+Gc-1 of t, clamped), then stage the plan tables
+    // 1. issue together: the first kPre loads of the item's rows of t
+    //    (contiguous: rows kx0 .. kx0+Gc-1 of t, clamped), the x eigenvalues
+    //    of those rows and `done` (unchanged during the pass); then stage the
+    //    plan tables
     const int Et = min(Gc, nx - kx0) * ny;
     BHX_GLOBAL const R* tb = t + (size_t)kx0 * ny;
     R tv[kPre];
 #pragma unroll
     for (int u = 0; u < kPre; ++u) tv[u] = tb[min((int)threadIdx.x + u * kThreads, Et - 1)];
+    const XPlan<R> Xx(B, I.planx);
+    const R lam_x = Xx.lam[min(kx0 + min((int)threadIdx.x, kMaxGc - 1), nx - 1)];
+    if (ctl->done) continue;
     XPlan<R> X(B, I.plany);
     X.stage(twl, I.plany, staged);
-    const XPlan<R> Xx(B, I.planx);
     const int rows = Gc >> 1;
     const int st = X.stride();
     auto place = [&](int e, R v) {
@@ -1062,6 +1099,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
     for (int u = 0; u < kPre; ++u) place(threadIdx.x + u * kThreads, tv[u]);
     for (int e = threadIdx.x + kPre * kThreads; e < Gc * ny; e += kThreads)
       place(e, tb[min(e, Et - 1)]);
+    if (threadIdx.x < kMaxGc) s_lamx[threadIdx.x] = lam_x;
     __syncthreads();
     dft_core<R>(X, buf, rows);
     // 2. spectra, scale by 1/(lambda_x + lambda_y)^2, inverse inputs
@@ -1076,9 +1114,8 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
         const C* row = buf + rr * st;
         R xa, xb, xak, xbk;
         fwd_post_pair<R>(X, X.out(row, k), X.out(row, kk), k, kk, xa, xb, xak, xbk);
-        const int kxa = kx0 + 2 * rr, kxb = kxa + 1;
-        const R la = Xx.lam[min(kxa, nx - 1)];
-        const R lb = Xx.lam[min(kxb, nx - 1)];
+        const R la = s_lamx[2 * rr];
+        const R lb = s_lamx[2 * rr + 1];
         const R lk = X.laml[k], lkk = X.laml[kk];
         xa *= inv_sq<R>(la + lk);
         xb *= inv_sq<R>(lb + lk);
@@ -1155,7 +1192,10 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
 // ---------------------------------------------------------------------------
 
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ Bp, int twoff) {
+// `lpar`: buffer parity of the iteration; the r.z partials written here are
+// the next iteration's current ones, rz(lpar ^ 1) (and rzo(lpar ^ 1)).
+__global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ Bp, int twoff,
+                                                     int lpar) {
   using C = typename V2<R>::T;
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1170,21 +1210,13 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
     const int g = code & kItemMask;
     BHX_GLOBAL Ctl* ctl = I.ctl;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
-    const int c_done = ctl->done, par = ctl->iter & 1;
-    const double rowcnt = I.part[PL.rowcnt() + g];
-    if (c_done) continue;
+    const int par = lpar ^ 1;
     const int nx = I.nx, ny = I.ny, G = I.G, j0 = g * G;
-    if (rowcnt == 0.0) {      // z stays 0 on rows without unknowns
-      if (threadIdx.x == 0) {
-        I.part[PL.rz(par) + g] = 0.0;
-        if (I.flexible) I.part[PL.rzo(par) + g] = 0.0;
-      }
-      continue;
-    }
     BHX_GLOBAL const R* t = (BHX_GLOBAL const R*)I.t;
-    // 1. issue: the first kPre transposed loads of the spectra
-    //    (stg[k * G + jr] = t[k * ny + j0 + jr]) and the masks of the
-    //    output elements; then the output r (and z_old) values
+    // 1. issue together: `done` and the row group's unknown count (both
+    //    unchanged during the pass), the first kPre transposed loads of the
+    //    spectra (stg[k * G + jr] = t[k * ny + j0 + jr]) and the masks of
+    //    the output elements; then the output r (and z_old) values
     const int jn = min(G, ny - j0);
     R tv[kPre];
 #pragma unroll
@@ -1204,6 +1236,16 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
     for (int u = 0; u < kPre; ++u) {
       const int e = threadIdx.x + u * kThreads;
       m0[u] = mk[min(e, E - 1)] && e < E;
+    }
+    const int c_done = ctl->done;
+    const double rowcnt = I.part[PL.rowcnt() + g];
+    if (c_done) continue;
+    if (rowcnt == 0.0) {      // z stays 0 on rows without unknowns
+      if (threadIdx.x == 0) {
+        I.part[PL.rz(par) + g] = 0.0;
+        if (I.flexible) I.part[PL.rzo(par) + g] = 0.0;
+      }
+      continue;
     }
     double rv0[kPre], zo0[kPre];
 #pragma unroll
@@ -1303,7 +1345,7 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
 }
 
 // Plain CG (no preconditioner): z = r at U; partial r.z (and r.z_old).
-__global__ void __launch_bounds__(kThreads) k_identity(const Batch* __restrict__ Bp) {
+__global__ void __launch_bounds__(kThreads) k_identity(const Batch* __restrict__ Bp, int lpar) {
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   __shared__ double red[4];
   for (int itm = logical_block(); itm < B.n_items[kPassR]; itm += gridDim.x) {
@@ -1313,7 +1355,7 @@ __global__ void __launch_bounds__(kThreads) k_identity(const Batch* __restrict__
     BHX_GLOBAL Ctl* ctl = I.ctl;
     if (ctl->done) continue;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
-    const int par = ctl->iter & 1;
+    const int par = lpar ^ 1;          // as in k_rowinv
     const int nx = I.nx, ny = I.ny, j0 = g * I.G;
     const int jn = min(I.G, ny - j0);
     const bool flex = I.flexible != 0;
@@ -1439,12 +1481,12 @@ hipError_t launch_setup(const Batch* B, int grid, hipStream_t st) {
       hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), lds, st, __VA_ARGS__);   \
   } while (0)
 
-hipError_t launch_stencil(const Batch* B, int mode, int grid, hipStream_t st, hipEvent_t e0,
-                          hipEvent_t e1) {
+hipError_t launch_stencil(const Batch* B, int mode, int grid, int lpar, hipStream_t st,
+                          hipEvent_t e0, hipEvent_t e1) {
   switch (mode) {
-    case kModeIter: BHX_LAUNCH(k_stencil<kModeIter>, grid, 0, st, e0, e1, B); break;
-    case kModeRhs: BHX_LAUNCH(k_stencil<kModeRhs>, grid, 0, st, e0, e1, B); break;
-    case kModeApply: BHX_LAUNCH(k_stencil<kModeApply>, grid, 0, st, e0, e1, B); break;
+    case kModeIter: BHX_LAUNCH(k_stencil<kModeIter>, grid, 0, st, e0, e1, B, lpar); break;
+    case kModeRhs: BHX_LAUNCH(k_stencil<kModeRhs>, grid, 0, st, e0, e1, B, lpar); break;
+    case kModeApply: BHX_LAUNCH(k_stencil<kModeApply>, grid, 0, st, e0, e1, B, lpar); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1454,11 +1496,11 @@ hipError_t launch_resid(const Batch* B, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, int lds, int twoff,
-                         hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+                         int lpar, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (prec == 0)
-    BHX_LAUNCH(k_rowfwd<double>, grid, lds, st, e0, e1, B, update, twoff);
+    BHX_LAUNCH(k_rowfwd<double>, grid, lds, st, e0, e1, B, update, twoff, lpar);
   else
-    BHX_LAUNCH(k_rowfwd<float>, grid, lds, st, e0, e1, B, update, twoff);
+    BHX_LAUNCH(k_rowfwd<float>, grid, lds, st, e0, e1, B, update, twoff, lpar);
   return hipGetLastError();
 }
 hipError_t launch_col(const Batch* B, int prec, int count_iter, int grid, int lds, int twoff,
@@ -1469,21 +1511,21 @@ hipError_t launch_col(const Batch* B, int prec, int count_iter, int grid, int ld
     BHX_LAUNCH(k_col<float>, grid, lds, st, e0, e1, B, count_iter, twoff);
   return hipGetLastError();
 }
-hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, hipStream_t st,
-                         hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, int lpar,
+                         hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (prec == 0)
-    BHX_LAUNCH(k_rowinv<double>, grid, lds, st, e0, e1, B, twoff);
+    BHX_LAUNCH(k_rowinv<double>, grid, lds, st, e0, e1, B, twoff, lpar);
   else
-    BHX_LAUNCH(k_rowinv<float>, grid, lds, st, e0, e1, B, twoff);
+    BHX_LAUNCH(k_rowinv<float>, grid, lds, st, e0, e1, B, twoff, lpar);
   return hipGetLastError();
 }
 hipError_t launch_setup_rows(const Batch* B, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_setup_rows, dim3(grid), dim3(kThreads), 0, st, B);
   return hipGetLastError();
 }
-hipError_t launch_identity(const Batch* B, int grid, hipStream_t st, hipEvent_t e0,
+hipError_t launch_identity(const Batch* B, int grid, int lpar, hipStream_t st, hipEvent_t e0,
                            hipEvent_t e1) {
-  BHX_LAUNCH(k_identity, grid, 0, st, e0, e1, B);
+  BHX_LAUNCH(k_identity, grid, 0, st, e0, e1, B, lpar);
   return hipGetLastError();
 }
 hipError_t launch_finalize(const Batch* B, int count, int mode, hipStream_t st) {

@@ -83,18 +83,20 @@ int core_length(int n) {
   return m;
 }
 
-int padded(int m) { return m + (m >> 3); }
+// Complex slots of one packed FFT row in LDS, pad slots included (the
+// kernels' rpos(m, shift)).
+int row_slots(int m) { return m + (m >> 3) + (m >> rpos_shift(ilog2(m))); }
 
-// Complex elements of the plan tables staged in LDS: twiddles (m/2), DCT
-// post-twiddles (n) and eigenvalues (n reals = n/2 complex slots).
-int table_slots(int n, int m) { return m / 2 + n + (n + 1) / 2; }
+// Complex elements of the plan tables staged in LDS: per-stage twiddles,
+// DCT post-twiddles (n) and eigenvalues (n reals = n/2 complex slots).
+int table_slots(int n, int m) { return stage_twiddles(ilog2(m)) + n + (n + 1) / 2; }
 
 bool length_supported(int n, int prec) {
   if (n < 4) return false;
   const int csize = prec == 0 ? 16 : 8;
   const int m = core_length(n);
-  if ((long)padded(m) * csize > kLdsBytes) return false;        // one packed row must fit
-  if ((long)(padded(m) + table_slots(n, m)) * csize > kLdsDynMax) return false;
+  if ((long)row_slots(m) * csize > kLdsBytes) return false;        // one packed row must fit
+  if ((long)(row_slots(m) + table_slots(n, m)) * csize > kLdsDynMax) return false;
   if ((n / 2 + 1) > kThreads * kMaxPairs) return false;
   return true;
 }
@@ -105,7 +107,7 @@ bool make_layout(int nx, int ny, int prec, int mx, int my, int rows_user, Layout
   // packed rows per item: the most that fit LDS and the register pair pass,
   // reduced until the instance supplies kTargetItems items (two per CU)
   auto rows_for = [&](int n, int m, int lines) {
-    int r = std::min(rows_cap, kLdsBytes / (padded(m) * csize));
+    int r = std::min(rows_cap, kLdsBytes / (row_slots(m) * csize));
     r = std::min(r, (kThreads * kMaxPairs) / (n / 2 + 1));
     if (rows_user > 0) return std::min(r, rows_user);
     while (r > 1 && (lines + 2 * r - 1) / (2 * r) < kTargetItems) --r;
@@ -115,6 +117,7 @@ bool make_layout(int nx, int ny, int prec, int mx, int my, int rows_user, Layout
   if (rx < 1 || ry < 1) return false;
   L->G = 2 * rx;
   L->Gc = 2 * ry;
+  if (L->Gc > kMaxGc) return false;
   L->tiles_x = (nx + kTileX - 1) / kTileX;
   L->tiles_y = (ny + kTileY - 1) / kTileY;
   L->n_items[kPassS] = L->tiles_x * L->tiles_y;
@@ -152,6 +155,7 @@ Resolved resolve_opts(const bhx_opts* o) {
   R.tol_inner = o->tol_inner > 0 ? o->tol_inner : 1e-8;
   R.flexible = o->flexible < 0 ? (o->precision == BHX_PREC_FP32 ? 1 : 0) : o->flexible;
   R.chunk = o->chunk > 0 ? o->chunk : 32;
+  R.chunk += R.chunk & 1;     // even: the buffer parity restarts at 0 every chunk
   R.profile = o->profile;
   R.autotune = o->autotune;
   R.rows_opt = o->rows;
@@ -374,10 +378,12 @@ namespace {
 
 hipError_t launch_precond(const Batch* B, const Resolved& R, const Grids& g, hipStream_t st) {
   hipError_t e;
-  if (!R.precond) return launch_identity(B, g.r, st);
-  if ((e = launch_rowfwd(B, R.precision, 0, g.r, g.lds_r, g.tw_r, st)) != hipSuccess) return e;
+  // parity 1: the r.z partials it writes are the ones the first iteration
+  // (parity 0) reads
+  if (!R.precond) return launch_identity(B, g.r, 1, st);
+  if ((e = launch_rowfwd(B, R.precision, 0, g.r, g.lds_r, g.tw_r, 1, st)) != hipSuccess) return e;
   if ((e = launch_col(B, R.precision, 0, g.c, g.lds_c, g.tw_c, st)) != hipSuccess) return e;
-  return launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, st);
+  return launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, 1, st);
 }
 
 namespace {
@@ -399,16 +405,19 @@ hipError_t launch_iterations(const Batch* B, int n_inst, const Resolved& R, cons
   };
 #define BHX_TRY(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
   for (int c = 0; c < count; ++c) {
-    BHX_TRY(launch_stencil(B, kModeIter, g.s, st, e0(0, c), e1(0, c)));
+    const int par = c & 1;               // count is even: every chunk starts at 0
+    BHX_TRY(launch_stencil(B, kModeIter, g.s, par, st, e0(0, c), e1(0, c)));
     if (R.precond) {
-      BHX_TRY(launch_rowfwd(B, R.precision, 1, g.r, g.lds_r, g.tw_r, st, e0(1, c), e1(1, c)));
+      BHX_TRY(launch_rowfwd(B, R.precision, 1, g.r, g.lds_r, g.tw_r, par, st, e0(1, c),
+                            e1(1, c)));
       BHX_TRY(launch_col(B, R.precision, 1, g.c, g.lds_c, g.tw_c, st, e0(2, c), e1(2, c)));
-      BHX_TRY(launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, st, e0(3, c), e1(3, c)));
+      BHX_TRY(launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, par, st, e0(3, c), e1(3, c)));
     } else {
       // plain CG: update-only row pass, iteration count, z = r
-      BHX_TRY(launch_rowfwd(B, R.precision, 2, g.r, g.lds_r, g.tw_r, st, e0(1, c), e1(1, c)));
+      BHX_TRY(launch_rowfwd(B, R.precision, 2, g.r, g.lds_r, g.tw_r, par, st, e0(1, c),
+                            e1(1, c)));
       BHX_TRY(launch_bump(B, n_inst, st));
-      BHX_TRY(launch_identity(B, g.r, st, e0(3, c), e1(3, c)));
+      BHX_TRY(launch_identity(B, g.r, par, st, e0(3, c), e1(3, c)));
     }
   }
 #undef BHX_TRY
@@ -637,15 +646,15 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
   g.r = std::max(1, std::min(Bh.n_items[kPassR], hd->num_cu * R.sched.occ_r));
   g.c = std::max(1, std::min(Bh.n_items[kPassC], hd->num_cu * R.sched.occ_c));
   {
-    // dynamic LDS: packed rows (padded) followed by the staged plan tables
+    // dynamic LDS: packed rows followed by the staged plan tables
     const int csize = R.precision == 0 ? 16 : 8;
     int buf_r = 0, tab_r = 0, buf_c = 0, tab_c = 0;
     for (int i = 0; i < n; ++i) {
       const AxisPlan& PX = hd->plans.plan(px[i]);
       const AxisPlan& PY = hd->plans.plan(py[i]);
-      buf_r = std::max(buf_r, (lay[i].G / 2) * padded(PX.m));
+      buf_r = std::max(buf_r, (lay[i].G / 2) * row_slots(PX.m));
       tab_r = std::max(tab_r, table_slots(PX.n, PX.m));
-      buf_c = std::max(buf_c, (lay[i].Gc / 2) * padded(PY.m));
+      buf_c = std::max(buf_c, (lay[i].Gc / 2) * row_slots(PY.m));
       tab_c = std::max(tab_c, table_slots(PY.n, PY.m));
     }
     g.tw_r = buf_r;
@@ -671,7 +680,7 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
   // setup: mask, right-hand side, counts
   BHX_CHECK(launch_setup(hd->batch_d, g.s, st));
   BHX_CHECK(launch_setup_rows(hd->batch_d, g.r, st));
-  BHX_CHECK(launch_stencil(hd->batch_d, kModeRhs, g.s, st));
+  BHX_CHECK(launch_stencil(hd->batch_d, kModeRhs, g.s, 0, st));
   BHX_CHECK(launch_finalize(hd->batch_d, n, kFinSetupH, st));
   Ctl* ch = hd->ctl_h;
   BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -806,7 +815,7 @@ int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, dou
   BHX_CHECK(launch_setup_rows(hd->batch_d, g.r, st));
   if (op == 0) {
     BHX_CHECK(hipMemcpyAsync(z, in, N * sizeof(double), hipMemcpyDeviceToDevice, st));
-    BHX_CHECK(launch_stencil(hd->batch_d, kModeApply, g.s, st));
+    BHX_CHECK(launch_stencil(hd->batch_d, kModeApply, g.s, 0, st));
     BHX_CHECK(hipMemcpyAsync(out, q, N * sizeof(double), hipMemcpyDeviceToDevice, st));
   } else {
     BHX_CHECK(hipMemcpyAsync(r, in, N * sizeof(double), hipMemcpyDeviceToDevice, st));

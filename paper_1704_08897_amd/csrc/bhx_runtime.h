@@ -135,7 +135,7 @@ int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
 size_t instance_bytes(int nx, int ny, int prec);
 const char* last_error();
 void set_last_error(const char* what, int line, hipError_t e);
-int padded(int m);
+int row_slots(int m);
 int table_slots(int n, int m);
 hipError_t launch_precond(const Batch* B, const Resolved& R, const Grids& g, hipStream_t st);
 hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved& R,
