@@ -106,7 +106,7 @@ def cpu_baseline(p, samples):
 def bench_batch(args, handle, log):
     """256 uneven instances per step (one batched call, autotuned schedule).
     The headline is the FP64 batched solve; the FP32-preconditioner form
-    (flexible PCG) and the plain FP64 PCG solving the same instances one call
+    (standard PCG) and the plain FP64 PCG solving the same instances one call
     each are measured beside it."""
     import numpy as np
     import torch
@@ -164,7 +164,7 @@ def bench_batch(args, handle, log):
     alg = sum(pass_bytes(dom, s.n_unknown, p.nx * p.ny, 0) for s, p in zip(stp, probs))
     avg_ms = dom_ms / max(1, dom_n)
     achieved = alg / (avg_ms * 1e-3) / 1e9
-    # FP32 preconditioner (flexible PCG), batched
+    # FP32 preconditioner (standard PCG, the default), batched
     run(1)
     el32, _, st32 = timed(1, max(1, args.steps // 5))
     v32 = len(probs) * max(1, args.steps // 5) / el32

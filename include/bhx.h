@@ -98,8 +98,9 @@ typedef struct {
                          relative to a compensated true residual until the true
                          residual meets tol                                         */
   double tol_inner; /* inner tolerance for accurate mode; 0 -> 1e-8                 */
-  int flexible;     /* -1 = default (flexible iff precision is FP32), 0 = standard
-                         beta = r.z / r_old.z_old, 1 = Polak-Ribiere beta           */
+  int flexible;     /* -1 = default (standard), 0 = standard beta = r.z / r_old.z_old,
+                         1 = Polak-Ribiere beta (flexible PCG, for a preconditioner
+                         that varies between applications)                          */
   int chunk;        /* iterations per captured graph between convergence checks;
                          0 -> 32; an odd value is rounded up to even                 */
   int rows;         /* packed complex rows (two grid rows each) per transform work

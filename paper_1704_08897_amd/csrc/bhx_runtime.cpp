@@ -153,7 +153,9 @@ Resolved resolve_opts(const bhx_opts* o) {
   R.precond = o->precond;
   R.accurate = o->accurate;
   R.tol_inner = o->tol_inner > 0 ? o->tol_inner : 1e-8;
-  R.flexible = o->flexible < 0 ? (o->precision == BHX_PREC_FP32 ? 1 : 0) : o->flexible;
+  // standard PCG by default, also with the FP32 preconditioner (it needed fewer
+  // iterations than the flexible form on every case measured)
+  R.flexible = o->flexible < 0 ? 0 : o->flexible;
   R.chunk = o->chunk > 0 ? o->chunk : 32;
   R.chunk += R.chunk & 1;     // even: the buffer parity restarts at 0 every chunk
   R.profile = o->profile;

@@ -150,11 +150,15 @@ def test_random_star_fp64(handle, nx, ny, bx, by, tol):
     check_against_oracle(p, got)
 
 
-def test_fp32_preconditioner_flexible(handle):
-    p = W.periodic_circles_problem(128, seed=2, circles=8, tol=1e-10)
-    s, st, got = solve(handle, p, precision=1)
+@pytest.mark.parametrize("flexible", [0, 1])
+def test_fp32_preconditioner(handle, flexible):
+    """FP32 transforms with standard (default) or flexible PCG.  The error is
+    at most the condition number times the residual; the mixed bar 1e-8
+    needs tol 1e-12 here (at tol 1e-10 standard PCG left 4.2e-8)."""
+    p = W.periodic_circles_problem(128, seed=2, circles=8, tol=1e-12)
+    s, st, got = solve(handle, p, precision=1, flexible=flexible)
     assert s == bhx.OK
-    assert st.true_rel_residual <= 1e-10
+    assert st.true_rel_residual <= 1e-12
     check_against_oracle(p, got, bound=1e-8)
 
 
