@@ -112,7 +112,8 @@ size_t bhx_workspace_bytes(int nx, int ny, int bc, const bhx_opts* o) {
   const Resolved R = bhx::resolve_opts(o);
   static const double dummy = 0;
   if (bhx::validate(&dummy, (double*)&dummy, nx, ny, 1.0, bc, 0.5, R) != BHX_OK) return 0;
-  return bhx::instance_bytes(nx, ny, R.precision) + sizeof(bhx::Inst) + 64;
+  return bhx::instance_bytes(nx, ny, bc & 15, (bc >> 4) & 15, R.precision) + sizeof(bhx::Inst) +
+         64;
 }
 
 int bhx_debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, double* out,

@@ -295,7 +295,8 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
     int s = BHX_OK;
     bool fin = true;
     if (C.n_unknown == 0) s = BHX_OK;
-    else if (C.n_unknown == N) s = BHX_ERR_SINGULAR;
+    else if (C.n_unknown == N && q->spec.bcx != kDirichlet && q->spec.bcy != kDirichlet)
+      s = BHX_ERR_SINGULAR;
     else if (!std::isfinite(C.bb)) s = BHX_ERR_NONFINITE;
     else if (C.bb == 0.0) { zero_flag[i] = 1; any_zero = true; }
     else fin = false;
@@ -475,7 +476,7 @@ int bhx_engine_submit(bhx_engine* E, const double* phi, double* F, int nx, int n
   if (!E || !id) return BHX_ERR_ARG;
   int v = bhx::validate(phi, F, nx, ny, h, bc, tol, E->R);
   if (v != BHX_OK) return v;
-  const size_t bytes = bhx::instance_bytes(nx, ny, E->R.precision);
+  const size_t bytes = bhx::instance_bytes(nx, ny, bc & 15, (bc >> 4) & 15, E->R.precision);
   if (bytes == 0 || bytes > E->budget) return BHX_ERR_ARG;      // can never fit
   bhx::Req* q = new (std::nothrow) bhx::Req();
   if (!q) return BHX_ERR_NOMEM;

@@ -62,17 +62,19 @@ enum Done { kRunning = 0, kConverged = 1, kMaxIt = 2, kBreakdown = 3, kSkip = 4 
 struct AxisPlan {
   int n;
   int bc;          // Bc
-  int m;           // power-of-two core length (== n, or >= 2n-1 for Bluestein)
+  int m;           // power-of-two core length (== nf, or >= 2nf-1 for Bluestein)
   int logm;
   int bluestein;   // 0: direct radix-4/2 core; 1: chirp-z through length m
   int off_tw;      // W_m^k = exp(-2 pi i k / m), k < m/2        (complex table)
-  int off_chirp;   // exp(-i pi k^2 / n), k < n                  (complex table)
+  int off_chirp;   // exp(-i pi k^2 / nf), k < nf                (complex table)
   int off_bhat;    // FFT_m(conj chirp, wrapped) / m, length m   (complex table)
   int off_post;    // DCT: exp(-i pi k / (2n)), k < n; Dirichlet: unused
   int off_lam;     // eigenvalues lambda_k of T, k < n           (real table)
-  int pad;
+  int nf;          // length of the DFT computed: n (DCT-II via Makhoul, Hartley);
+                   // 2(n+1) for DST-I (odd extension 0, x, 0, -reversed x)
   // normalisations: DCT-II s_0 = sqrt(1/n), s_k = sqrt(2/n); its inverse's
-  // pre-scale g_0 = 1/sqrt(n), g_k = 1/sqrt(2n); Hartley 1/(2 sqrt(n))
+  // pre-scale g_0 = 1/sqrt(n), g_k = 1/sqrt(2n); hs: Hartley 1/(2 sqrt(n)),
+  // DST-I sqrt(2/(n+1)) / 2
   double s0, s1, g0, g1, hs;
 };
 

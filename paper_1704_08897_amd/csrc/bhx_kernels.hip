@@ -265,10 +265,22 @@ __device__ __forceinline__ int logical_block() {
 // Transform plan access
 // ---------------------------------------------------------------------------
 
+// Logical FFT input index of spatial sample i for the forward transform:
+// DCT-II reorders evens ascending then odds descending (Makhoul); the
+// Hartley transform takes the samples in order.
+__device__ __forceinline__ int fwd_index(int i, int n, int bc) {
+  if (bc != kNeumann) return i;
+  return (i & 1) ? n - 1 - (i >> 1) : (i >> 1);
+}
+// Position in the inverse DCT's FFT output holding spatial sample j.
+__device__ __forceinline__ int inv_index(int j, int n) {
+  return (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
+}
+
 template <typename R>
 struct XPlan {
   using C = typename V2<R>::T;
-  int n, m, logm, blue, bc, sh;
+  int n, nf, m, logm, blue, bc, sh;
   R s0, s1, g0, g1, hs;
   BHX_GLOBAL const C* twg;    // W_m^k, k < m/2, in device memory
   const C* tw;                // per-stage twiddle tables in LDS once staged
@@ -306,7 +318,7 @@ struct XPlan {
   }
   __device__ XPlan(const Batch& B, int idx) {
     const AxisPlan P = B.plans[idx];
-    n = P.n; m = P.m; logm = P.logm; blue = P.bluestein; bc = P.bc;
+    n = P.n; nf = P.nf; m = P.m; logm = P.logm; blue = P.bluestein; bc = P.bc;
     sh = rpos_shift(logm);
     s0 = (R)P.s0; s1 = (R)P.s1; g0 = (R)P.g0; g1 = (R)P.g1; hs = (R)P.hs;
     const int pi = sizeof(R) == 8 ? 0 : 1;
@@ -328,6 +340,50 @@ struct XPlan {
   __device__ __forceinline__ C out(const C* row, int k) const {
     if (!blue) return row[rpos(k, sh)];
     return cmul(chirp[k], row[rpos(bitrev(k, logm), sh)]);
+  }
+  // Spectral indices are handled in pairs (k, partner(k)): k < pairs().
+  // DCT / Hartley: (k, n - k) mod n, k <= n/2; DST-I: (k, n - 1 - k).
+  __device__ __forceinline__ int pairs() const {
+    return bc == kDirichlet ? (n + 1) >> 1 : (n >> 1) + 1;
+  }
+  __device__ __forceinline__ int partner(int k) const {
+    return bc == kDirichlet ? n - 1 - k : (k == 0 ? 0 : n - k);
+  }
+  // FFT bin holding spectral index k (DST-I: bin k+1 of the odd extension)
+  __device__ __forceinline__ int bin(int k) const { return bc == kDirichlet ? k + 1 : k; }
+  // Forward-transform input: sample i of half h (one of two real rows) of a
+  // packed row.  DCT-II: Makhoul order; Hartley: in order; DST-I: +x at
+  // i+1 and -x at nf-1-i (odd extension), see zero_ends().
+  __device__ __forceinline__ void put(C* row, int i, int h, R v) const {
+    if (bc == kDirichlet) {
+      ((R*)(row + pos(i + 1)))[h] = v;
+      ((R*)(row + pos(nf - 1 - i)))[h] = -v;
+    } else {
+      ((R*)(row + pos(fwd_index(i, n, bc))))[h] = v;
+    }
+  }
+  // Inputs of the second transform of a pass (values a at k, b at partner
+  // kk), placed like put() but for both halves at once.
+  __device__ __forceinline__ void put_pair(C* row, int k, int kk, C a, C b) const {
+    if (bc == kDirichlet) {
+      row[pos(k + 1)] = a;
+      row[pos(nf - 1 - k)] = mk<C>(-a.x, -a.y);
+      if (kk != k) {
+        row[pos(kk + 1)] = b;
+        row[pos(nf - 1 - kk)] = mk<C>(-b.x, -b.y);
+      }
+    } else {
+      row[pos(k)] = a;
+      if (kk != k) row[pos(kk)] = b;
+    }
+  }
+  // DST-I: the odd extension is zero at 0 and n+1 (no other rule writes them)
+  __device__ __forceinline__ void zero_ends(C* buf, int rows, int st) const {
+    if (bc != kDirichlet) return;
+    for (int r = threadIdx.x; r < rows; r += kThreads) {
+      buf[r * st + pos(0)] = mk<C>(0, 0);
+      buf[r * st + pos(n + 1)] = mk<C>(0, 0);
+    }
   }
 };
 
@@ -441,8 +497,8 @@ __device__ void dft_core(const XPlan<R>& X, typename V2<R>::T* buf, int rows) {
       const int r = idx >> X.logm, k = idx & (X.m - 1);
       C* row = buf + r * st;
       const int p = X.pos(k);
-      const C c = X.chirp[min(k, X.n - 1)];
-      row[p] = k < X.n ? cmul(row[p], c) : mk<C>(0, 0);
+      const C c = X.chirp[min(k, X.nf - 1)];
+      row[p] = k < X.nf ? cmul(row[p], c) : mk<C>(0, 0);
     }
     __syncthreads();
   }
@@ -458,24 +514,15 @@ __device__ void dft_core(const XPlan<R>& X, typename V2<R>::T* buf, int rows) {
   }
 }
 
-// Logical FFT input index of spatial sample i for the forward transform:
-// DCT-II reorders evens ascending then odds descending (Makhoul); the
-// Hartley transform takes the samples in order.
-__device__ __forceinline__ int fwd_index(int i, int n, int bc) {
-  if (bc != kNeumann) return i;
-  return (i & 1) ? n - 1 - (i >> 1) : (i >> 1);
-}
-// Position in the inverse DCT's FFT output holding spatial sample j.
-__device__ __forceinline__ int inv_index(int j, int n) {
-  return (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
-}
-
 // Forward real spectra of the two rows packed in one complex FFT output, at
 // the pair (k, kk = (n - k) mod n).  C = out(k), D = out(kk).
 //   DCT-II (orthonormal): V_a = (C + conj D)/2, V_b = (C - conj D)/(2i),
 //     X[k] = s_k Re(exp(-i pi k/2n) V[k]), s_0 = sqrt(1/n), s_k = sqrt(2/n).
 //   Hartley (orthonormal): H_a = (Cr + Dr - Ci + Di) / (2 sqrt n),
 //                          H_b = (Ci + Di + Cr - Dr) / (2 sqrt n).
+//   DST-I (orthonormal; C = out(k+1), D = out(kk+1)): the odd extensions'
+//     spectra are imaginary, so X_a[k] = -Im(C) hs, X_b[k] = Re(C) hs with
+//     hs = sqrt(2/(n+1)) / 2.
 template <typename R>
 __device__ __forceinline__ void fwd_post_pair(const XPlan<R>& X, typename V2<R>::T Ck,
                                               typename V2<R>::T Dk, int k, int kk, R& xa_k,
@@ -492,6 +539,11 @@ __device__ __forceinline__ void fwd_post_pair(const XPlan<R>& X, typename V2<R>:
     const C tkk = X.postl[kk];
     xa_kk = (kk == 0 ? X.s0 : X.s1) * (tkk.x * va.x + tkk.y * va.y);
     xb_kk = (kk == 0 ? X.s0 : X.s1) * (tkk.x * vb.x + tkk.y * vb.y);
+  } else if (X.bc == kDirichlet) {
+    xa_k = -Ck.y * X.hs;
+    xb_k = Ck.x * X.hs;
+    xa_kk = -Dk.y * X.hs;
+    xb_kk = Dk.x * X.hs;
   } else {
     const R sc = X.hs;
     xa_k = (Ck.x + Dk.x - Ck.y + Dk.y) * sc;
@@ -505,7 +557,8 @@ __device__ __forceinline__ void fwd_post_pair(const XPlan<R>& X, typename V2<R>:
 // spectra.  DCT: W[k] = exp(i pi k/2n) (P[k] - i P[n-k]) with
 // P = g (Y_a + i Y_b), g_0 = 1/sqrt n, g_k = 1/sqrt(2n), P[n] = 0; the
 // unnormalised inverse DFT is taken as conj(DFT(conj W)), so conj(W) is
-// returned.  Hartley: the forward transform again, inputs Y_a + i Y_b.
+// returned.  Hartley and DST-I: the forward transform again (both are their
+// own inverses), inputs Y_a + i Y_b.
 template <typename R>
 __device__ __forceinline__ void inv_pre_pair(const XPlan<R>& X, R ya_k, R yb_k, R ya_kk,
                                              R yb_kk, int k, int kk, typename V2<R>::T& in_k,
@@ -974,8 +1027,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
       }
       if (update != 2) {
         const int jr = e / nx, i = e - jr * nx;
-        R* cell = (R*)(buf + (jr >> 1) * st + X.pos(fwd_index(i, nx, X.bc)));
-        cell[jr & 1] = (R)v;
+        X.put(buf + (jr >> 1) * st, i, jr & 1, (R)v);
       }
     };
 #pragma unroll
@@ -1001,6 +1053,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
       for (int u = 0; u < kUnroll; ++u)
         consume(e0 + u * kThreads, m[u], rv[u], pv[u], qv[u], xv[u]);
     }
+    if (update != 2) X.zero_ends(buf, rows, st);
     __syncthreads();
     if (update) {
       acc = block_sum(acc, red);
@@ -1010,17 +1063,17 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
     // 2. FFT
     dft_core<R>(X, buf, rows);
     // 3. real spectra of the pairs (k, n-k) into registers
-    const int np = (nx >> 1) + 1;
+    const int np = X.pairs();
     R va[kMaxPairs][4];
 #pragma unroll
     for (int s = 0; s < kMaxPairs; ++s) {
       const int pidx = threadIdx.x + s * kThreads;
       if (pidx < rows * np) {
         const int rr = pidx / np, k = pidx - rr * np;
-        const int kk = k == 0 ? 0 : nx - k;
+        const int kk = X.partner(k);
         const C* row = buf + rr * st;
-        fwd_post_pair<R>(X, X.out(row, k), X.out(row, kk), k, kk, va[s][0], va[s][1],
-                         va[s][2], va[s][3]);
+        fwd_post_pair<R>(X, X.out(row, X.bin(k)), X.out(row, X.bin(kk)), k, kk, va[s][0],
+                         va[s][1], va[s][2], va[s][3]);
       }
     }
     __syncthreads();
@@ -1030,7 +1083,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
       const int pidx = threadIdx.x + s * kThreads;
       if (pidx < rows * np) {
         const int rr = pidx / np, k = pidx - rr * np;
-        const int kk = k == 0 ? 0 : nx - k;
+        const int kk = X.partner(k);
         stg[k * G + 2 * rr] = va[s][0];
         stg[k * G + 2 * rr + 1] = va[s][1];
         if (kk != k) {
@@ -1092,28 +1145,29 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
     auto place = [&](int e, R v) {
       if (e >= Gc * ny) return;
       const int cr = e / ny, j = e - cr * ny;
-      R* cell = (R*)(buf + (cr >> 1) * st + X.pos(fwd_index(j, ny, X.bc)));
-      cell[cr & 1] = e < Et ? v : (R)0;
+      X.put(buf + (cr >> 1) * st, j, cr & 1, e < Et ? v : (R)0);
     };
 #pragma unroll
     for (int u = 0; u < kPre; ++u) place(threadIdx.x + u * kThreads, tv[u]);
     for (int e = threadIdx.x + kPre * kThreads; e < Gc * ny; e += kThreads)
       place(e, tb[min(e, Et - 1)]);
     if (threadIdx.x < kMaxGc) s_lamx[threadIdx.x] = lam_x;
+    X.zero_ends(buf, rows, st);
     __syncthreads();
     dft_core<R>(X, buf, rows);
     // 2. spectra, scale by 1/(lambda_x + lambda_y)^2, inverse inputs
-    const int np = (ny >> 1) + 1;
+    const int np = X.pairs();
     C vin[kMaxPairs][2];
 #pragma unroll
     for (int s = 0; s < kMaxPairs; ++s) {
       const int pidx = threadIdx.x + s * kThreads;
       if (pidx < rows * np) {
         const int rr = pidx / np, k = pidx - rr * np;
-        const int kk = k == 0 ? 0 : ny - k;
+        const int kk = X.partner(k);
         const C* row = buf + rr * st;
         R xa, xb, xak, xbk;
-        fwd_post_pair<R>(X, X.out(row, k), X.out(row, kk), k, kk, xa, xb, xak, xbk);
+        fwd_post_pair<R>(X, X.out(row, X.bin(k)), X.out(row, X.bin(kk)), k, kk, xa, xb, xak,
+                         xbk);
         const R la = s_lamx[2 * rr];
         const R lb = s_lamx[2 * rr + 1];
         const R lk = X.laml[k], lkk = X.laml[kk];
@@ -1130,12 +1184,10 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
       const int pidx = threadIdx.x + s * kThreads;
       if (pidx < rows * np) {
         const int rr = pidx / np, k = pidx - rr * np;
-        const int kk = k == 0 ? 0 : ny - k;
-        C* row = buf + rr * st;
-        row[X.pos(k)] = vin[s][0];
-        if (kk != k) row[X.pos(kk)] = vin[s][1];
+        X.put_pair(buf + rr * st, k, X.partner(k), vin[s][0], vin[s][1]);
       }
     }
+    X.zero_ends(buf, rows, st);
     __syncthreads();
     dft_core<R>(X, buf, rows);
     // 3. inverse outputs back into t
@@ -1149,16 +1201,16 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
         }
       }
     } else {
-      // Hartley: the inverse is the forward transform; reuse vin's registers
+      // Hartley, DST-I: the inverse is the forward transform; reuse vin's registers
 #pragma unroll
       for (int s = 0; s < kMaxPairs; ++s) {
         const int pidx = threadIdx.x + s * kThreads;
         if (pidx < rows * np) {
           const int rr = pidx / np, k = pidx - rr * np;
-          const int kk = k == 0 ? 0 : ny - k;
+          const int kk = X.partner(k);
           const C* row = buf + rr * st;
           R a, b, ak, bk;
-          fwd_post_pair<R>(X, X.out(row, k), X.out(row, kk), k, kk, a, b, ak, bk);
+          fwd_post_pair<R>(X, X.out(row, X.bin(k)), X.out(row, X.bin(kk)), k, kk, a, b, ak, bk);
           vin[s][0] = mk<C>(a, b);
           vin[s][1] = mk<C>(ak, bk);
         }
@@ -1168,7 +1220,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
         const int pidx = threadIdx.x + s * kThreads;
         if (pidx < rows * np) {
           const int rr = pidx / np, k = pidx - rr * np;
-          const int kk = k == 0 ? 0 : ny - k;
+          const int kk = X.partner(k);
           const int kxa = kx0 + 2 * rr, kxb = kxa + 1;
           if (kxa < nx) {
             t[(size_t)kxa * ny + k] = vin[s][0].x;
@@ -1269,14 +1321,14 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
     }
     __syncthreads();
     // 2. inverse inputs of the pairs, through registers
-    const int np = (nx >> 1) + 1;
+    const int np = X.pairs();
     C vin[kMaxPairs][2];
 #pragma unroll
     for (int s = 0; s < kMaxPairs; ++s) {
       const int pidx = threadIdx.x + s * kThreads;
       if (pidx < rows * np) {
         const int rr = pidx / np, k = pidx - rr * np;
-        const int kk = k == 0 ? 0 : nx - k;
+        const int kk = X.partner(k);
         inv_pre_pair<R>(X, stg[k * G + 2 * rr], stg[k * G + 2 * rr + 1], stg[kk * G + 2 * rr],
                         stg[kk * G + 2 * rr + 1], k, kk, vin[s][0], vin[s][1]);
       }
@@ -1287,12 +1339,10 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
       const int pidx = threadIdx.x + s * kThreads;
       if (pidx < rows * np) {
         const int rr = pidx / np, k = pidx - rr * np;
-        const int kk = k == 0 ? 0 : nx - k;
-        C* row = buf + rr * st;
-        row[X.pos(k)] = vin[s][0];
-        if (kk != k) row[X.pos(kk)] = vin[s][1];
+        X.put_pair(buf + rr * st, k, X.partner(k), vin[s][0], vin[s][1]);
       }
     }
+    X.zero_ends(buf, rows, st);
     __syncthreads();
     dft_core<R>(X, buf, rows);
     // 3. outputs: restrict, store z, dots
@@ -1305,6 +1355,9 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
       if (X.bc == kNeumann) {
         const C c = X.out(row, inv_index(i, nx));
         v = (jr & 1) ? -c.y : c.x;
+      } else if (X.bc == kDirichlet) {
+        const C c = X.out(row, i + 1);
+        v = (jr & 1) ? c.x * X.hs : -c.y * X.hs;
       } else {
         const int ii = i == 0 ? 0 : nx - i;
         R xa, xb, xak, xbk;

@@ -91,10 +91,13 @@ int row_slots(int m) { return m + (m >> 3) + (m >> rpos_shift(ilog2(m))); }
 // DCT post-twiddles (n) and eigenvalues (n reals = n/2 complex slots).
 int table_slots(int n, int m) { return stage_twiddles(ilog2(m)) + n + (n + 1) / 2; }
 
-bool length_supported(int n, int prec) {
+// Length of the DFT behind the 1-D transform of an axis of n nodes.
+int fft_length(int n, int bc) { return bc == kDirichlet ? 2 * (n + 1) : n; }
+
+bool length_supported(int n, int bc, int prec) {
   if (n < 4) return false;
   const int csize = prec == 0 ? 16 : 8;
-  const int m = core_length(n);
+  const int m = core_length(fft_length(n, bc));
   if ((long)row_slots(m) * csize > kLdsBytes) return false;        // one packed row must fit
   if ((long)(row_slots(m) + table_slots(n, m)) * csize > kLdsDynMax) return false;
   if ((n / 2 + 1) > kThreads * kMaxPairs) return false;
@@ -136,10 +139,12 @@ bool make_layout(int nx, int ny, int prec, int mx, int my, int rows_user, Layout
   return true;
 }
 
-size_t instance_bytes(int nx, int ny, int prec) {
+size_t instance_bytes(int nx, int ny, int bcx, int bcy, int prec) {
   Layout L;
-  if (!length_supported(nx, prec) || !length_supported(ny, prec)) return 0;
-  if (!make_layout(nx, ny, prec, core_length(nx), core_length(ny), 0, &L)) return 0;
+  if (!length_supported(nx, bcx, prec) || !length_supported(ny, bcy, prec)) return 0;
+  if (!make_layout(nx, ny, prec, core_length(fft_length(nx, bcx)),
+                   core_length(fft_length(ny, bcy)), 0, &L))
+    return 0;
   return L.bytes;
 }
 
@@ -192,9 +197,11 @@ int PlanCache::get(int n, int bc) {
   std::memset(&P, 0, sizeof(P));
   P.n = n;
   P.bc = bc;
-  P.m = core_length(n);
+  P.nf = fft_length(n, bc);
+  const int nf = P.nf;
+  P.m = core_length(nf);
   P.logm = ilog2(P.m);
-  P.bluestein = P.m != n;
+  P.bluestein = P.m != nf;
   using cl = std::complex<long double>;
   auto expi = [](long double a) { return cl(cosl(a), sinl(a)); };
   P.off_tw = (int)ctab_.size();
@@ -202,15 +209,15 @@ int PlanCache::get(int n, int bc) {
   P.off_chirp = (int)ctab_.size();
   P.off_bhat = P.off_chirp;
   if (P.bluestein) {
-    std::vector<cl> w(n);
-    for (int k = 0; k < n; ++k) {
-      const long long kk = ((long long)k * k) % (2LL * n);   // exact argument reduction
-      w[k] = expi(-kPi * (long double)kk / n);
+    std::vector<cl> w(nf);
+    for (int k = 0; k < nf; ++k) {
+      const long long kk = ((long long)k * k) % (2LL * nf);  // exact argument reduction
+      w[k] = expi(-kPi * (long double)kk / nf);
     }
-    for (int k = 0; k < n; ++k) ctab_.push_back(w[k]);
+    for (int k = 0; k < nf; ++k) ctab_.push_back(w[k]);
     std::vector<cl> b(P.m, cl(0, 0));
-    for (int l = 0; l < n; ++l) b[l] = std::conj(w[l]);
-    for (int l = 1; l < n; ++l) b[P.m - l] = std::conj(w[l]);
+    for (int l = 0; l < nf; ++l) b[l] = std::conj(w[l]);
+    for (int l = 1; l < nf; ++l) b[P.m - l] = std::conj(w[l]);
     host_fft(b);
     P.off_bhat = (int)ctab_.size();
     for (int k = 0; k < P.m; ++k) ctab_.push_back(b[k] / (long double)P.m);
@@ -221,11 +228,15 @@ int PlanCache::get(int n, int bc) {
   P.s1 = (double)sqrtl(2.0L / n);
   P.g0 = (double)(1.0L / sqrtl((long double)n));
   P.g1 = (double)(1.0L / sqrtl(2.0L * n));
-  P.hs = (double)(0.5L / sqrtl((long double)n));
+  P.hs = bc == kDirichlet ? (double)(0.5L * sqrtl(2.0L / (n + 1)))
+                          : (double)(0.5L / sqrtl((long double)n));
   P.off_lam = (int)rtab_.size();
   for (int k = 0; k < n; ++k) {
-    // eigenvalues of the 1-D second difference, 4 sin^2(theta/2)
-    const long double th = bc == kNeumann ? kPi * k / n : 2 * kPi * k / n;
+    // eigenvalues of the 1-D second difference, 4 sin^2(theta/2):
+    // Neumann theta = pi k / n, periodic 2 pi k / n, Dirichlet pi (k+1) / (n+1)
+    const long double th = bc == kNeumann    ? kPi * k / n
+                           : bc == kPeriodic ? 2 * kPi * k / n
+                                             : kPi * (k + 1) / (n + 1);
     const long double s = sinl(th / 2);
     rtab_.push_back(4 * s * s);
   }
@@ -288,8 +299,7 @@ int validate(const double* phi, const double* F, int nx, int ny, double h, int b
   if (!std::isfinite(tol) || !(tol > 0) || !(tol < 1)) return BHX_ERR_ARG;
   if (bc < 0 || (bc >> 8) != 0) return BHX_ERR_ARG;
   const int bx = bc & 15, by = (bc >> 4) & 15;
-  if ((bx != BHX_NEUMANN && bx != BHX_PERIODIC) || (by != BHX_NEUMANN && by != BHX_PERIODIC))
-    return BHX_ERR_ARG;
+  if (bx > BHX_DIRICHLET || by > BHX_DIRICHLET) return BHX_ERR_ARG;
   if (R.precision != BHX_PREC_FP64 && R.precision != BHX_PREC_FP32) return BHX_ERR_ARG;
   if (R.precond != 0 && R.precond != 1) return BHX_ERR_ARG;
   if (R.accurate != 0 && R.accurate != 1) return BHX_ERR_ARG;
@@ -299,7 +309,8 @@ int validate(const double* phi, const double* F, int nx, int ny, double h, int b
   if (R.profile < 0 || R.profile > 15) return BHX_ERR_ARG;
   if (R.autotune != 0 && R.autotune != 1) return BHX_ERR_ARG;
   if (R.rows_opt < 0 || R.rows_opt > 8 || R.occ_opt < 0 || R.occ_opt > 8) return BHX_ERR_ARG;
-  if (!length_supported(nx, R.precision) || !length_supported(ny, R.precision)) return BHX_ERR_ARG;
+  if (!length_supported(nx, bx, R.precision) || !length_supported(ny, by, R.precision))
+    return BHX_ERR_ARG;
   if ((long long)nx * ny > (1LL << 31)) return BHX_ERR_ARG;
   return BHX_OK;
 }
@@ -694,7 +705,9 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
     const double nu = ch[i].n_unknown;
     if (nu == 0) {
       preset[i] = 1;
-    } else if (nu == N) {
+    } else if (nu == N && specs[i].bcx != kDirichlet && specs[i].bcy != kDirichlet) {
+      // nothing known and only Neumann/periodic axes: u is fixed up to a
+      // constant (with a Dirichlet axis, b = 0 and the extension is 0)
       preset[i] = 1;
       status[i] = BHX_ERR_SINGULAR;
     } else if (!std::isfinite(ch[i].bb)) {
@@ -806,7 +819,8 @@ int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, dou
   int rc = prepare_batch(hd, 1, &s, R, st, &g);
   if (rc != BHX_OK) return rc;
   Layout L;
-  make_layout(nx, ny, precision, core_length(nx), core_length(ny), R.sched.rows_cap, &L);
+  make_layout(nx, ny, precision, core_length(fft_length(nx, bcx)),
+              core_length(fft_length(ny, bcy)), R.sched.rows_cap, &L);
   const size_t N = (size_t)nx * ny;
   const size_t Np = vec_stride(nx, ny);
   double* v = (double*)((char*)hd->ws + align_up(sizeof(Ctl)) + L.off_vec);

@@ -132,7 +132,7 @@ int validate(const double* phi, const double* F, int nx, int ny, double h, int b
 // Solve `n` instances on `hd`; stats[n] filled (may be null).
 int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
                 hipStream_t stream, bhx_stats* stats);
-size_t instance_bytes(int nx, int ny, int prec);
+size_t instance_bytes(int nx, int ny, int bcx, int bcy, int prec);
 const char* last_error();
 void set_last_error(const char* what, int line, hipError_t e);
 int row_slots(int m);

@@ -87,8 +87,13 @@ def test_workspace_bytes():
     assert 45 * N <= w32 < 45 * N + 2 * 1024 * 1024
     assert bhx.workspace_bytes(3, 64, 0) == 0
     assert bhx.workspace_bytes(100, 77, bhx.BC(1, 0)) > 0
-    # Dirichlet axes are solved by the oracle only
-    assert bhx.workspace_bytes(64, 64, bhx.BC(2, 0)) == 0
+    # Dirichlet axes: DST-I through an FFT of the odd extension, length 2(n+1)
+    assert bhx.workspace_bytes(64, 64, bhx.BC(2, 0)) > 0
+    assert bhx.workspace_bytes(1023, 1023, bhx.BC(2, 2)) > 0          # core length 2048
+    assert bhx.workspace_bytes(1000, 64, bhx.BC(2, 0)) > 0            # Bluestein core 4096
+    assert bhx.workspace_bytes(1100, 64, bhx.BC(2, 0)) == 0           # core 8192: too long
+    assert bhx.workspace_bytes(1100, 64, bhx.BC(2, 0), bhx.default_opts(precision=1)) > 0
+    assert bhx.workspace_bytes(64, 64, bhx.BC(3, 0)) == 0             # no such rule
 
 
 def test_engine_rejects_without_device():
