@@ -41,9 +41,10 @@
  *   - Entry points that take a stream enqueue their GPU work on it; they
  *     synchronise with it before returning (stats are valid on return).
  *     Calls on one handle are serialised by a lock inside the handle.
- *   - Boundary rules: Neumann and periodic axes are solved on the GPU;
- *     BHX_DIRICHLET is part of the interface but rejected with BHX_ERR_ARG by
- *     this version of the GPU library.
+ *   - Boundary rules: Neumann, periodic and Dirichlet axes, one rule per axis.
+ *     A Dirichlet axis of n nodes is transformed through a DFT of length
+ *     2(n+1) (its odd extension), which must fit LDS like any transform: in
+ *     FP64 n <= 1023 or n = 2047, in FP32 n <= 2047; otherwise BHX_ERR_ARG.
  */
 #ifndef BHX_H
 #define BHX_H
