@@ -111,10 +111,18 @@ typedef struct {
                          item, persistent-grid occupancy per pass, iterations per
                          graph) by timing short trial solves of this batch's shape on
                          first use, cached per handle; 0 = built-in policy           */
-  int profile;      /* bit mask of iteration passes to time with HIP events recorded
-                         on the solve's stream around each launch (captured into the
-                         graph): bit 0 stencil, 1 row-forward, 2 column, 3 row-inverse;
-                         results in bhx_stats.pass_ms / pass_launches; 0 = off       */
+  int profile;      /* bit mask of iteration passes to time: each launch of such a
+                         pass carries start/stop events recorded by its dispatch
+                         (kernel execution time; the iterations are then launched
+                         directly, not from a graph): bit 0 stencil, 1 row-forward,
+                         2 column, 3 row-inverse; results in bhx_stats.pass_ms /
+                         pass_launches; 0 = off                                      */
+  int warm_start;   /* 1 = the values of F at the unknown nodes on input are the
+                         first iterate x0 (e.g. the previous time step's extension);
+                         the stopping rule stays ||b - A x|| <= tol ||b||; a start
+                         that already meets it returns with 0 iterations and F
+                         unchanged; a non-finite start gives BHX_ERR_NONFINITE.
+                         0 = x0 = 0 (Algorithm 1), input values at U are ignored    */
 } bhx_opts;
 
 typedef struct {
@@ -166,6 +174,17 @@ int bhx_extend_ex(bhx_handle* hd, const double* phi, double* F, int nx, int ny, 
 int bhx_extend_batched(bhx_handle* hd, int count, const double* const* phi, double* const* F,
                        const int* nx, const int* ny, const double* h, const int* bc,
                        const double* tol, const bhx_opts* o, void* stream, bhx_stats* out);
+
+/* `nfields` fields known on the same region (one phi, e.g. the components of
+ * a velocity, or a field and its gradient components in a level-set step)
+ * extended in one batched solve: F is a host array of `nfields` device
+ * pointers, each (ny, nx) like phi; one tolerance for all; out (may be NULL)
+ * receives `nfields` records.  Each result is bit-identical to the same field
+ * solved alone with bhx_extend_ex and the same options (warm_start applies to
+ * every field).  Returns as bhx_extend_batched. */
+int bhx_extend_fields(bhx_handle* hd, int nfields, const double* phi, double* const* F, int nx,
+                      int ny, double h, int bc, double tol, const bhx_opts* o, void* stream,
+                      bhx_stats* out);
 
 /* Device bytes the library needs for one instance (workspace vectors, mask,
  * partial sums, control block), excluding phi and F.  Host-only; 0 for

@@ -264,14 +264,22 @@ def spectral_preconditioner(r, known, bcx, bcy):
 
 
 def pcg(known, F, bcx, bcy, tol, maxit, precond=True, flexible=False,
-        precond_dtype=np.float64):
+        precond_dtype=np.float64, x0=None):
     """Matrix-free (preconditioned) conjugate gradients on A_UU u = b, as in
     Algorithm 1: x0 = 0, stop when the recursive residual satisfies
     ||r|| <= tol ||b||.  Vectors live on the full grid and are zero at known
     nodes.  ``flexible`` uses the Polak-Ribiere form of beta,
     r_new.(z_new - z_old) / (r_old.z_old), which tolerates an inexact
     preconditioner; ``precond_dtype`` float32 runs the transforms in single
-    precision.  Returns (x_full, iterations, relres_history)."""
+    precision.
+
+    ``x0`` (a full grid; its values at known nodes are ignored) is a first
+    iterate other than zero, the textbook generalisation of CG's start:
+    r0 = b - A_UU x0, which is -(A f) at U with f = F at known nodes and x0
+    at unknown ones; the stopping rule is unchanged, so a start that already
+    meets it returns after 0 iterations.  A non-finite r0 raises ValueError.
+
+    Returns (x_full, iterations, relres_history)."""
     F = np.asarray(F, dtype=np.float64)
     unknown = ~known
     f0 = np.where(known, F, 0.0)
@@ -281,6 +289,15 @@ def pcg(known, F, bcx, bcy, tol, maxit, precond=True, flexible=False,
     hist = [1.0]
     if bnorm == 0.0:
         return x, 0, hist
+    r = b.copy()
+    if x0 is not None:
+        x = np.where(unknown, np.asarray(x0, dtype=np.float64), 0.0)
+        r = np.where(unknown, -stencil_padded(np.where(known, F, x), bcx, bcy), 0.0)
+        if not np.all(np.isfinite(r)):
+            raise ValueError("non-finite residual of the first iterate")
+        hist = [np.sqrt(np.sum(r * r)) / bnorm]
+        if hist[0] <= tol:
+            return x, 0, hist
 
     def M(v):
         if not precond:
@@ -288,7 +305,6 @@ def pcg(known, F, bcx, bcy, tol, maxit, precond=True, flexible=False,
         z = spectral_preconditioner(v.astype(precond_dtype), known, bcx, bcy)
         return np.where(unknown, z.astype(np.float64), 0.0)
 
-    r = b.copy()
     z = M(r)
     rz = np.sum(r * z)
     p = z.copy()

@@ -48,7 +48,7 @@ class Opts(ctypes.Structure):
                 ("tol_inner", ctypes.c_double), ("flexible", ctypes.c_int),
                 ("chunk", ctypes.c_int), ("rows", ctypes.c_int), ("occupancy", ctypes.c_int),
                 ("autotune", ctypes.c_int),
-                ("profile", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("warm_start", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -77,6 +77,8 @@ _sig = {
                                  ctypes.POINTER(_ci), ctypes.POINTER(_ci), ctypes.POINTER(_cd),
                                  ctypes.POINTER(_ci), ctypes.POINTER(_cd), ctypes.POINTER(Opts),
                                  _vp, ctypes.POINTER(Stats)]),
+    "bhx_extend_fields": (_ci, [_vp, _ci, _vp, ctypes.POINTER(_vp), _ci, _ci, _cd, _ci, _cd,
+                                ctypes.POINTER(Opts), _vp, ctypes.POINTER(Stats)]),
     "bhx_workspace_bytes": (ctypes.c_size_t, [_ci, _ci, _ci, ctypes.POINTER(Opts)]),
     "bhx_engine_create": (_ci, [ctypes.POINTER(_vp), _ci, ctypes.c_size_t, _ci,
                                 ctypes.POINTER(Opts)]),
@@ -241,6 +243,22 @@ def extend_batched(handle, phis, Fs, hs, bcs, tols, opts=None, stream=None, size
     s = _lib.bhx_extend_batched(hp, n, P, Fp, NX, NY, H, B, T,
                                 ctypes.byref(opts) if opts is not None else None,
                                 _stream(stream), st)
+    return s, list(st)
+
+
+def extend_fields(handle, phi, Fs, h=1.0, bc=0, tol=1e-8, opts=None, stream=None, nx=None,
+                  ny=None):
+    """``bhx_extend_fields``: several fields known on one region; returns
+    (status, [Stats])."""
+    if nx is None:
+        nx, ny = _dims(phi)
+    n = len(Fs)
+    hp = handle.ptr if isinstance(handle, Handle) else handle
+    Fp = (_vp * n)(*[_ptr(f) for f in Fs])
+    st = (Stats * n)()
+    s = _lib.bhx_extend_fields(hp, n, _ptr(phi), Fp, nx, ny, float(h), int(bc), float(tol),
+                               ctypes.byref(opts) if opts is not None else None,
+                               _stream(stream), st)
     return s, list(st)
 
 

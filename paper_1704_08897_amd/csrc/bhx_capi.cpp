@@ -108,6 +108,23 @@ int bhx_extend_batched(bhx_handle* hd, int count, const double* const* phi, doub
   return bhx::solve_batch(hd, count, specs.data(), R, (hipStream_t)stream, out);
 }
 
+int bhx_extend_fields(bhx_handle* hd, int nfields, const double* phi, double* const* F, int nx,
+                      int ny, double h, int bc, double tol, const bhx_opts* o, void* stream,
+                      bhx_stats* out) {
+  if (!hd || nfields < 1 || nfields > (1 << (31 - bhx::kItemShift)) || !F) return BHX_ERR_ARG;
+  const Resolved R = bhx::resolve_opts(o);
+  std::vector<bhx::InstSpec> specs(nfields);
+  for (int i = 0; i < nfields; ++i) {
+    int v = bhx::validate(phi, F[i], nx, ny, h, bc, tol, R);
+    if (v != BHX_OK) return v;
+    for (int j = 0; j < i; ++j)
+      if (F[j] == F[i]) return BHX_ERR_ARG;     // two solves writing one array
+    specs[i] = bhx::InstSpec{phi, F[i], nx, ny, bc & 15, (bc >> 4) & 15, tol};
+  }
+  std::lock_guard<std::mutex> lk(hd->mu);
+  return bhx::solve_batch(hd, nfields, specs.data(), R, (hipStream_t)stream, out);
+}
+
 size_t bhx_workspace_bytes(int nx, int ny, int bc, const bhx_opts* o) {
   const Resolved R = bhx::resolve_opts(o);
   static const double dummy = 0;

@@ -249,6 +249,7 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
     for (int p = 0; p < kNumPass; ++p) I.n_items[p] = L.n_items[p];
     I.maxit = E->R.maxit_user > 0 ? E->R.maxit_user : 50 * std::max(S.nx, S.ny);
     I.flexible = E->R.flexible;
+    I.warm = E->R.warm;
     I.phi = (decltype(I.phi))S.phi;
     I.F = (decltype(I.F))S.F;
     char* b = E->arena_base + q->off;
@@ -319,6 +320,32 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
     ENG_CHECK(launch_zero_unknown(E->aux.hdr, flag_d, g.s, st));
     ENG_CHECK(hipStreamSynchronize(st));
     ENG_CHECK(hipFree(flag_d));
+  }
+  if (E->R.warm && !keep.empty()) {
+    // warm start: r0 = b - A x0; requests whose start already meets the
+    // tolerance, or whose residual is not finite, end here with F untouched
+    ENG_CHECK(launch_stencil(E->aux.hdr, kModeWarm, g.s, 0, st));
+    ENG_CHECK(launch_finalize(E->aux.hdr, n, kFinWarmH, st));
+    ENG_CHECK(hipMemcpyAsync(E->ctl_h, E->ctl_d, E->max_slots * sizeof(Ctl),
+                             hipMemcpyDeviceToHost, st));
+    ENG_CHECK(hipStreamSynchronize(st));
+    std::vector<Req*> still;
+    for (Req* q : keep) {
+      Ctl& C = E->ctl_h[q->slot];
+      const int w = warm_start_outcome(C);
+      if (w == 0) {
+        still.push_back(q);
+        continue;
+      }
+      C.done = kSkip;
+      ENG_CHECK(hipMemcpyAsync(E->ctl_d + q->slot, &C, sizeof(Ctl), hipMemcpyHostToDevice, st));
+      std::memset(&q->st, 0, sizeof(q->st));
+      q->st.status = w == 1 ? BHX_OK : BHX_ERR_NONFINITE;
+      q->st.n_unknown = (int)C.n_unknown;
+      if (C.bb0 > 0) q->st.rel_residual = q->st.true_rel_residual = std::sqrt(C.rr / C.bb0);
+      done_now.push_back(q);
+    }
+    keep.swap(still);
   }
   if (!keep.empty()) {
     // preconditioner of r0 for the requests that iterate (skipped ones are

@@ -53,6 +53,8 @@ enum SMode {
   kModeIter = 1,    // p = z + beta p; q = A p at U; partial p.q; convergence test
   kModeResid = 2,   // r = -(A F) at U in double-double (true residual); partial ||r||^2
   kModeApply = 3,   // q = A (z at U, 0 at K) at U (diagnostic operator application)
+  kModeWarm = 4,    // r = -(A F) at U with F's values at U as the start x0 (b - A_UU x0);
+                    // partial ||r||^2
 };
 
 // Done codes in Ctl::done.
@@ -107,7 +109,7 @@ struct Inst {
   int n_items[kNumPass];
   int maxit;
   int flexible;
-  int pad0;
+  int warm;             // 1: F's values at U on input are the first iterate x0
   BHX_GLOBAL const double* phi;
   BHX_GLOBAL double* F;
   BHX_GLOBAL uint8_t* mask;   // 1 = unknown, 0 = known
@@ -154,7 +156,7 @@ struct Batch {
 
 // Launch wrappers (defined with the kernels).
 namespace bhx {
-enum FinModeHost { kFinSetupH = 0, kFinResidH = 1 };
+enum FinModeHost { kFinSetupH = 0, kFinResidH = 1, kFinWarmH = 2 };
 // The pass launches take an optional pair of events that the dispatch itself
 // records at kernel start and end (hipExtLaunchKernelGGL), so their elapsed
 // time is the kernel's execution time.

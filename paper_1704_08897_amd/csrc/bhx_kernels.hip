@@ -734,7 +734,7 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
       if (MODE == kModeIter) {
         va[s] = I.z[o];
         vb[s] = pold[o];
-      } else if (MODE == kModeRhs) {
+      } else if (MODE == kModeRhs || MODE == kModeWarm) {
         va[s] = I.F[o];
         vm[s] = I.mask[o];
       } else {
@@ -792,6 +792,7 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
       double v;
       if (MODE == kModeIter) v = first ? va[s] : va[s] + beta * vb[s];
       else if (MODE == kModeRhs) v = vm[s] ? 0.0 : va[s];
+      else if (MODE == kModeWarm) v = va[s];
       else v = vm[s] ? va[s] : 0.0;
       if (e < kPH * kPW) {
         const int jj = e / kPW, ii = e - jj * kPW;
@@ -1020,7 +1021,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
       if (e >= G * nx) return;
       double v = m ? rv : 0.0;
       if (update && m) {
-        Fb[e] = (first ? 0.0 : xv) + alpha * pv;
+        Fb[e] = (first && !I.warm ? 0.0 : xv) + alpha * pv;
         v -= alpha * qv;
         rb[e] = v;
         acc += v * v;
@@ -1434,7 +1435,7 @@ __global__ void __launch_bounds__(kThreads) k_identity(const Batch* __restrict__
 // Per-instance finalisation (one block per instance) and helpers.
 // ---------------------------------------------------------------------------
 
-enum FinMode { kFinSetup = 0, kFinResid = 1 };
+enum FinMode { kFinSetup = 0, kFinResid = 1, kFinWarm = 2 };
 
 __global__ void __launch_bounds__(kThreads) k_finalize(const Batch* __restrict__ Bp, int mode) {
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
@@ -1454,6 +1455,18 @@ __global__ void __launch_bounds__(kThreads) k_finalize(const Batch* __restrict__
       ctl->bb0 = bb;
       ctl->accept = ctl->tol2 * bb;
       ctl->thresh = (ctl->accurate ? ctl->tol_inner2 : ctl->tol2) * bb;
+    }
+  } else if (mode == kFinWarm) {
+    // residual of the given start x0 (the host compares it with the target)
+    if (ctl->done) return;
+    const double rr = block_sum_array(I.part + PL.aux(), PL.nS, red);
+    if (threadIdx.x == 0) {
+      ctl->true_rr = rr;
+      ctl->rr = rr;
+      if (ctl->accurate) {           // the first inner solve reduces this residual
+        ctl->bb = rr;
+        ctl->thresh = ctl->tol_inner2 * rr;
+      }
     }
   } else {
     if (ctl->done != kConverged && ctl->done != kMaxIt) return;
@@ -1540,6 +1553,7 @@ hipError_t launch_stencil(const Batch* B, int mode, int grid, int lpar, hipStrea
     case kModeIter: BHX_LAUNCH(k_stencil<kModeIter>, grid, 0, st, e0, e1, B, lpar); break;
     case kModeRhs: BHX_LAUNCH(k_stencil<kModeRhs>, grid, 0, st, e0, e1, B, lpar); break;
     case kModeApply: BHX_LAUNCH(k_stencil<kModeApply>, grid, 0, st, e0, e1, B, lpar); break;
+    case kModeWarm: BHX_LAUNCH(k_stencil<kModeWarm>, grid, 0, st, e0, e1, B, lpar); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -165,6 +165,7 @@ Resolved resolve_opts(const bhx_opts* o) {
   R.chunk += R.chunk & 1;     // even: the buffer parity restarts at 0 every chunk
   R.profile = o->profile;
   R.autotune = o->autotune;
+  R.warm = o->warm_start;
   R.rows_opt = o->rows;
   R.occ_opt = o->occupancy;
   if (o->rows > 0) R.sched.rows_cap = o->rows;
@@ -308,6 +309,7 @@ int validate(const double* phi, const double* F, int nx, int ny, double h, int b
   if (R.flexible != 0 && R.flexible != 1) return BHX_ERR_ARG;
   if (R.profile < 0 || R.profile > 15) return BHX_ERR_ARG;
   if (R.autotune != 0 && R.autotune != 1) return BHX_ERR_ARG;
+  if (R.warm != 0 && R.warm != 1) return BHX_ERR_ARG;
   if (R.rows_opt < 0 || R.rows_opt > 8 || R.occ_opt < 0 || R.occ_opt > 8) return BHX_ERR_ARG;
   if (!length_supported(nx, bx, R.precision) || !length_supported(ny, by, R.precision))
     return BHX_ERR_ARG;
@@ -578,6 +580,7 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
     for (int p = 0; p < kNumPass; ++p) I.n_items[p] = L.n_items[p];
     I.maxit = R.maxit_user > 0 ? R.maxit_user : 50 * std::max(S.nx, S.ny);
     I.flexible = R.flexible;
+    I.warm = R.warm;
     I.phi = (decltype(I.phi))S.phi;
     I.F = (decltype(I.F))S.F;
     const size_t Np = vec_stride(S.nx, S.ny);
@@ -730,6 +733,32 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
     }
     BHX_CHECK(hipStreamSynchronize(st));
   }
+  // warm start: r0 = b - A x0 for the instances still active; those whose
+  // start already meets the tolerance, or whose residual is not finite, end
+  // here with F untouched
+  std::vector<int> warm_done(n, 0);
+  if (R.warm && active > 0) {
+    BHX_CHECK(launch_stencil(hd->batch_d, kModeWarm, g.s, 0, st));
+    BHX_CHECK(launch_finalize(hd->batch_d, n, kFinWarmH, st));
+    BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    BHX_CHECK(hipStreamSynchronize(st));
+    int ended = 0;
+    for (int i = 0; i < n; ++i) {
+      if (preset[i]) continue;
+      const int w = warm_start_outcome(ch[i]);
+      if (w == 0) continue;
+      preset[i] = 1;
+      warm_done[i] = 1;
+      status[i] = w == 1 ? BHX_OK : BHX_ERR_NONFINITE;
+      ch[i].done = kSkip;
+      --active;
+      ++ended;
+    }
+    if (ended) {
+      BHX_CHECK(hipMemcpyAsync(ctl_d, ch, n * sizeof(Ctl), hipMemcpyHostToDevice, st));
+      BHX_CHECK(hipStreamSynchronize(st));
+    }
+  }
   double pass_ms[4] = {0, 0, 0, 0};
   int pass_cnt[4] = {0, 0, 0, 0};
   std::vector<int> iter_before(n);
@@ -795,8 +824,9 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
       o.restarts = preset[i] ? 0 : ch[i].restarts;
       o.n_unknown = (int)ch[i].n_unknown;
       const double bb0 = ch[i].bb0;
-      o.rel_residual = (preset[i] || !(bb0 > 0)) ? 0.0 : std::sqrt(ch[i].rr / bb0);
-      o.true_rel_residual = (preset[i] || !(bb0 > 0)) ? 0.0 : std::sqrt(ch[i].true_rr / bb0);
+      const bool rep = (!preset[i] || warm_done[i]) && bb0 > 0;   // residuals to report
+      o.rel_residual = rep ? std::sqrt(ch[i].rr / bb0) : 0.0;
+      o.true_rel_residual = rep ? std::sqrt(ch[i].true_rr / bb0) : 0.0;
       o.seconds = secs;
       for (int p = 0; p < 4; ++p) {
         o.pass_ms[p] = pass_ms[p];
@@ -805,6 +835,11 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
     }
   }
   return ret;
+}
+
+int warm_start_outcome(const Ctl& c) {
+  if (!std::isfinite(c.rr)) return 2;
+  return c.rr <= c.accept ? 1 : 0;
 }
 
 int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, double* out, int nx,
@@ -861,8 +896,9 @@ static unsigned long long batch_signature(int n, const InstSpec* specs, const Re
 
 // Project autotuner: time short trial solves (a fixed number of iterations
 // in one graph) of this batch's shape under candidate schedules and keep the
-// fastest.  A trial writes F only at unknown nodes, which every solve
-// ignores on input and overwrites.
+// fastest.  A trial writes F only at unknown nodes, which a cold solve
+// ignores on input and overwrites; a warm start is saved before the trials
+// and put back after them (solve_batch).
 static int autotune_schedule(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
                              hipStream_t stream, Schedule* best) {
   const int trial_iters = 24;
@@ -886,6 +922,7 @@ static int autotune_schedule(bhx_handle* hd, int n, const InstSpec* specs, const
     T.chunk = trial_iters;
     T.profile = 0;
     T.accurate = 0;
+    T.warm = 0;                               // timed from x0 = 0, whatever F holds
     double t = 0;
     for (int rep = 0; rep < 2; ++rep) {       // first run captures the graph
       const auto a = std::chrono::steady_clock::now();
@@ -902,6 +939,41 @@ static int autotune_schedule(bhx_handle* hd, int n, const InstSpec* specs, const
   return BHX_OK;
 }
 
+// The autotuner with the fields' contents kept: F (the warm start) is copied
+// to a temporary device buffer before the trial solves and back after them.
+static int autotune_keeping_fields(bhx_handle* hd, int n, const InstSpec* specs,
+                                   const Resolved& R, hipStream_t stream, Schedule* best) {
+  hipStream_t st = stream ? stream : hd->own_stream;
+  BHX_CHECK(hipSetDevice(hd->device));
+  size_t total = 0;
+  std::vector<size_t> off(n);
+  for (int i = 0; i < n; ++i) {
+    off[i] = total;
+    total += align_up((size_t)specs[i].nx * specs[i].ny * sizeof(double));
+  }
+  char* keep = nullptr;
+  BHX_CHECK(hipMalloc((void**)&keep, total));
+  int rc = BHX_OK;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < n && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(keep + off[i], specs[i].F,
+                       (size_t)specs[i].nx * specs[i].ny * sizeof(double),
+                       hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) rc = autotune_schedule(hd, n, specs, R, stream, best);
+  for (int i = 0; i < n && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(specs[i].F, keep + off[i],
+                       (size_t)specs[i].nx * specs[i].ny * sizeof(double),
+                       hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  const hipError_t ef = hipFree(keep);
+  if (e == hipSuccess) e = ef;
+  if (e != hipSuccess) {
+    set_last_error("autotune_keeping_fields", __LINE__, e);
+    return BHX_ERR_HIP;
+  }
+  return rc;
+}
+
 int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R0,
                 hipStream_t stream, bhx_stats* stats) {
   Resolved R = R0;
@@ -910,7 +982,8 @@ int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R0
     auto it = hd->tuned.find(sig);
     if (it == hd->tuned.end()) {
       Schedule s;
-      int rc = autotune_schedule(hd, n, specs, R, stream, &s);
+      int rc = R.warm ? autotune_keeping_fields(hd, n, specs, R, stream, &s)
+                      : autotune_schedule(hd, n, specs, R, stream, &s);
       if (rc != BHX_OK) return rc;
       it = hd->tuned.emplace(sig, s).first;
     }

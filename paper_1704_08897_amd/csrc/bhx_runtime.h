@@ -76,7 +76,7 @@ struct Schedule {
 };
 
 struct Resolved {           // options after defaults
-  int precision, maxit_user, precond, accurate, flexible, chunk, profile, autotune;
+  int precision, maxit_user, precond, accurate, flexible, chunk, profile, autotune, warm;
   int rows_opt = 0, occ_opt = 0;
   double tol_inner;
   Schedule sched;
@@ -130,6 +130,7 @@ namespace bhx {
 int validate(const double* phi, const double* F, int nx, int ny, double h, int bc, double tol,
              const Resolved& R);
 // Solve `n` instances on `hd`; stats[n] filled (may be null).
+// With R.warm the values of F at the unknown nodes are the first iterate.
 int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
                 hipStream_t stream, bhx_stats* stats);
 size_t instance_bytes(int nx, int ny, int bcx, int bcy, int prec);
@@ -154,5 +155,10 @@ struct Upload {
 // The caller has synchronised `st` since the previous upload (the staging
 // buffer is then free); the host sources may be reused on return.
 hipError_t upload_ordered(bhx_handle* hd, hipStream_t st, const Upload* u, int n);
+// Outcome of the residual of a given first iterate (warm start), decided on
+// the host from the control block after the kFinWarm finalisation:
+// 0 = iterate from it, 1 = it already meets the tolerance (0 iterations),
+// 2 = its residual is not finite.
+int warm_start_outcome(const Ctl& c);
 void free_handle(bhx_handle* hd);
 }  // namespace bhx

@@ -41,8 +41,10 @@ class Result:
 
 class Server:
     def __init__(self, device: int = 0, hbm_budget: int = 8 << 30, max_slots: int = 64,
-                 precision: int = 0, chunk: int = 16):
-        self.opts = bhx.default_opts(precision=precision, chunk=chunk)
+                 precision: int = 0, chunk: int = 16, warm_start: int = 0):
+        # warm_start=1: each request's F holds its first iterate at the unknown
+        # nodes (e.g. the extension of the previous time step)
+        self.opts = bhx.default_opts(precision=precision, chunk=chunk, warm_start=warm_start)
         self.engine = bhx.engine_create(device, hbm_budget, max_slots, self.opts)
 
     def submit(self, req: Request):

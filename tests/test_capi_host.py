@@ -32,6 +32,7 @@ def test_one_hip_runtime_in_process():
 def test_default_opts_and_strings():
     o = bhx.default_opts()
     assert (o.precision, o.maxit, o.precond, o.accurate, o.flexible, o.chunk) == (0, 0, 1, 0, -1, 0)
+    assert o.warm_start == 0               # x0 = 0 unless asked
     assert bhx.status_string(bhx.OK) == "ok"
     assert "singular" in bhx.status_string(bhx.ERR_SINGULAR)
     assert bhx.status_string(12345) == "unknown status"
@@ -67,11 +68,21 @@ def test_null_pointers_and_handles():
     st = (bhx.Stats * 1)()
     assert bhx._lib.bhx_extend_batched(None, 1, None, None, None, None, None, None, None, None,
                                        None, st) == bhx.ERR_ARG
+    s, _ = bhx.extend_fields(None, FAKE, [FAKE], nx=8, ny=8)
+    assert s == bhx.ERR_ARG
+    s, _ = bhx.extend_fields(FAKE, FAKE, [], nx=8, ny=8)          # no field
+    assert s == bhx.ERR_ARG
+    s, _ = bhx.extend_fields(FAKE, None, [FAKE], nx=8, ny=8)      # no phi
+    assert s == bhx.ERR_ARG
+    s, _ = bhx.extend_fields(FAKE, FAKE, [FAKE, FAKE + 64, FAKE], nx=8, ny=8)   # one F twice
+    assert s == bhx.ERR_ARG
+    s, _ = bhx.extend_fields(FAKE, FAKE, [FAKE], nx=3, ny=8)      # bad size
+    assert s == bhx.ERR_ARG
 
 
 def test_bad_options_rejected():
     for kw in ({"precision": 2}, {"precond": 3}, {"maxit": -1}, {"flexible": 2},
-               {"tol_inner": 2.0}, {"accurate": 5}):
+               {"tol_inner": 2.0}, {"accurate": 5}, {"warm_start": 2}, {"warm_start": -1}):
         o = bhx.default_opts(**kw)
         s, _ = bhx.extend_ex(FAKE, FAKE, FAKE, 8, 8, 1.0, 0, 1e-8, opts=o)
         assert s == bhx.ERR_ARG, kw

@@ -306,6 +306,52 @@ def test_pcg_matches_direct_and_flexible_fp32():
     assert it2 >= it * 0.5
 
 
+def test_pcg_first_iterate():
+    """PCG from a first iterate x0 other than zero (r0 = b - A_UU x0): the
+    recorded initial residual equals the one formed with the assembled sparse
+    A_UU (not the stencil); x0 = 0 is the default bit for bit; the exact
+    solution stops at once; any start reaches the direct solution, and values
+    of x0 at known nodes are ignored."""
+    p = W.circle_problem(64, tol=1e-10)
+    K = O.known_mask(p.phi)
+    U = ~K
+    Fo, _ = O.extend_direct(p.phi, p.F, p.bcx, p.bcy)
+    x, it, _ = O.pcg(K, p.F, p.bcx, p.bcy, 1e-10, 2000)
+    xz, itz, _ = O.pcg(K, p.F, p.bcx, p.bcy, 1e-10, 2000, x0=np.zeros_like(p.F))
+    assert itz == it and np.array_equal(xz, x)
+    xe, ite, he = O.pcg(K, p.F, p.bcx, p.bcy, 1e-10, 2000, x0=Fo)
+    assert ite == 0 and np.array_equal(xe[U], Fo[U]) and he[0] < 1e-13
+    rng = np.random.default_rng(11)
+    g = rng.normal(scale=100.0, size=p.F.shape)
+    A = O.reduced_system(K, p.bcx, p.bcy)
+    b = O.rhs(p.F, K, p.bcx, p.bcy)
+    r0 = b - A @ g[U]
+    xg, itg, hg = O.pcg(K, p.F, p.bcx, p.bcy, 1e-12, 5000, x0=np.where(K, 1e9, g))
+    assert abs(hg[0] - np.linalg.norm(r0) / np.linalg.norm(b)) <= 1e-12 * hg[0]
+    assert itg > 0
+    assert O.relative_l2(np.where(K, p.F, xg), Fo) < 1e-9
+    with pytest.raises(ValueError):
+        O.pcg(K, p.F, p.bcx, p.bcy, 1e-10, 10, x0=np.where(U, np.nan, 0.0))
+
+
+def test_pcg_previous_solution_saves_iterations():
+    """The use of a first iterate: known values change by a smooth 1 % (a
+    time step); starting from the previous extension needs fewer iterations
+    than starting from zero, to the same solution."""
+    p = W.circle_problem(64, tol=1e-10)
+    K = O.known_mask(p.phi)
+    Fo, _ = O.extend_direct(p.phi, p.F, p.bcx, p.bcy)
+    ny, nx = p.F.shape
+    X, Y = np.meshgrid(np.arange(nx) / nx, np.arange(ny) / ny)
+    F1 = p.F + 0.01 * np.abs(p.F).max() * np.sin(2 * np.pi * X) * np.cos(np.pi * Y)
+    F1o, _ = O.extend_direct(p.phi, F1, p.bcx, p.bcy)
+    x, it, _ = O.pcg(K, F1, p.bcx, p.bcy, 1e-10, 5000)
+    xw, itw, hw = O.pcg(K, F1, p.bcx, p.bcy, 1e-10, 5000, x0=Fo)
+    assert hw[0] < 0.05
+    assert itw < it
+    assert O.relative_l2(np.where(K, F1, xw), F1o) < 1e-9
+
+
 # -- P10: the oracle's own accuracy ---------------------------------------------------
 
 def test_refinement_reaches_cubic_to_rounding():
