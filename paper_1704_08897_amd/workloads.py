@@ -257,3 +257,81 @@ def annulus_problem(n: int, bcx: int, bcy: int, tol: float = 1e-6) -> Problem:
     with np.errstate(divide="ignore", invalid="ignore"):
         F = np.where(r > 0, Y / np.log1p(r), 0.0)
     return Problem(phi, F, bcx, bcy, 4.0 / n, tol, f"annulus{n}")
+
+
+# ----------------------------------------------------------------------------
+# Three dimensions (Sec. 3.2, Example 2)
+# ----------------------------------------------------------------------------
+
+def bc_code3(bcx: int, bcy: int, bcz: int) -> int:
+    """Per-axis boundary rules of a 3-D problem packed for the C interface."""
+    return int(bcx) | (int(bcy) << 4) | (int(bcz) << 8)
+
+
+@dataclass
+class Problem3:
+    phi: np.ndarray          # (nz, ny, nx) float64, known where phi < 0
+    F: np.ndarray            # (nz, ny, nx) float64, values used at known nodes
+    bcx: int
+    bcy: int
+    bcz: int
+    h: float
+    tol: float
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nx(self) -> int:
+        return int(self.phi.shape[2])
+
+    @property
+    def ny(self) -> int:
+        return int(self.phi.shape[1])
+
+    @property
+    def nz(self) -> int:
+        return int(self.phi.shape[0])
+
+    @property
+    def bc(self) -> int:
+        return bc_code3(self.bcx, self.bcy, self.bcz)
+
+
+def _mesh3(nx, ny, nz, box, bcx, bcy, bcz):
+    (x0, x1), (y0, y1), (z0, z1) = box
+    z, y, x = (axis_nodes(nz, z0, z1, bcz), axis_nodes(ny, y0, y1, bcy),
+               axis_nodes(nx, x0, x1, bcx))
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")     # X[k, j, i] = x_i
+    return X, Y, Z
+
+
+def peanut3d_problem(n: int, bcx: int = PERIODIC, bcy: int = PERIODIC, bcz: int = PERIODIC,
+                     tol: float = 1e-6) -> Problem3:
+    """Example 2: D = [-pi, pi]^3, f = cos x sin y sin(pi/4 - z) known inside
+    the union of two unit balls centred at (+-0.8, 0, 0); periodic in the
+    paper."""
+    box = ((-np.pi, np.pi),) * 3
+    X, Y, Z = _mesh3(n, n, n, box, bcx, bcy, bcz)
+    phi = np.minimum(np.sqrt((X - 0.8) ** 2 + Y**2 + Z**2) - 1,
+                     np.sqrt((X + 0.8) ** 2 + Y**2 + Z**2) - 1)
+    F = np.cos(X) * np.sin(Y) * np.sin(np.pi / 4 - Z)
+    return Problem3(phi, F, bcx, bcy, bcz, 2 * np.pi / n, tol, f"peanut3d_{n}")
+
+
+def ball_problem3(nx: int, ny: int, nz: int, bcx: int, bcy: int, bcz: int, seed: int = 0,
+                  tol: float = 1e-10, inside: bool = True) -> Problem3:
+    """[-1, 1]^3 with a ball of radius U[0.3, 0.45] about a random centre
+    within 0.2 of the origin; F a random cubic plus sin(2y) cos(z); known
+    inside the ball (or outside it)."""
+    rng = np.random.default_rng(seed)
+    X, Y, Z = _mesh3(nx, ny, nz, ((-1, 1),) * 3, bcx, bcy, bcz)
+    c = rng.uniform(-0.2, 0.2, size=3)
+    rad = rng.uniform(0.3, 0.45)
+    phi = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) - rad
+    if not inside:
+        phi = -phi
+    a = rng.normal(size=6)
+    F = (a[0] * X**3 + a[1] * X * Y * Z + a[2] * Y**2 + a[3] * Z + a[4]
+         + a[5] * np.sin(2 * Y) * np.cos(Z))
+    return Problem3(phi, F, bcx, bcy, bcz, 2.0 / max(nx, ny, nz), tol,
+                    f"ball{nx}x{ny}x{nz}")
