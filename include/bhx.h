@@ -64,6 +64,8 @@ enum {
 };
 /* Both axes packed into one int: low nibble x axis, next nibble y axis. */
 #define BHX_BC(bx, by) ((bx) | ((by) << 4))
+/* Three axes (three-dimensional entry points): third nibble z axis. */
+#define BHX_BC3(bx, by, bz) ((bx) | ((by) << 4) | ((bz) << 8))
 
 /* Status codes. */
 enum {
@@ -191,6 +193,20 @@ int bhx_extend_fields(bhx_handle* hd, int nfields, const double* phi, double* co
  * invalid arguments. */
 size_t bhx_workspace_bytes(int nx, int ny, int bc, const bhx_opts* o);
 
+/* ---- Three dimensions (Sec. 3, Example 2) -------------------------------
+ * The same extension on an nx x ny x nz grid: arrays (nz, ny, nx), x fastest,
+ * a[(k*ny + j)*nx + i]; the operator is the square of the negative 7-point
+ * Laplacian, the 25-point discrete biharmonic operator, with two ghost
+ * layers per face by each axis' rule; the preconditioner transforms along x,
+ * y and z and divides by (lambda_x + lambda_y + lambda_z)^2.  bc =
+ * BHX_BC3(bx, by, bz).  nx, ny, nz >= 4, each a supported transform length,
+ * and nx*ny*nz < 2^31.  Options, stopping rule, statuses and the handling of
+ * F are those of bhx_extend_ex (warm_start included). */
+int bhx_extend3d(bhx_handle* hd, const double* phi, double* F, int nx, int ny, int nz, double h,
+                 int bc, double tol, const bhx_opts* o, void* stream, bhx_stats* out);
+/* Device bytes of one three-dimensional instance; 0 for invalid arguments. */
+size_t bhx_workspace_bytes3d(int nx, int ny, int nz, int bc, const bhx_opts* o);
+
 /* ---- Serving engine: continuous batching of requests --------------------
  * The engine owns a worker thread and a stream on `device`.  Requests are
  * admitted while their workspace fits in `hbm_budget` bytes and a slot is
@@ -224,6 +240,10 @@ void bhx_engine_destroy(bhx_engine* e);
  * Synchronises with the stream.  Returns a status code. */
 int bhx_debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, double* out,
                     int nx, int ny, int bc, int precision, void* stream);
+/* bhx_debug_apply in three dimensions: op 0 the masked 25-point operator,
+ * op 1 the three-axis preconditioner; bc = BHX_BC3(bx, by, bz). */
+int bhx_debug_apply3d(bhx_handle* hd, int op, const double* phi, const double* in, double* out,
+                      int nx, int ny, int nz, int bc, int precision, void* stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* bhx_status_string(int status);

@@ -42,6 +42,10 @@ def BC(bx: int, by: int) -> int:
     return int(bx) | (int(by) << 4)
 
 
+def BC3(bx: int, by: int, bz: int) -> int:
+    return int(bx) | (int(by) << 4) | (int(bz) << 8)
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("precond", ctypes.c_int), ("accurate", ctypes.c_int),
@@ -80,6 +84,10 @@ _sig = {
     "bhx_extend_fields": (_ci, [_vp, _ci, _vp, ctypes.POINTER(_vp), _ci, _ci, _cd, _ci, _cd,
                                 ctypes.POINTER(Opts), _vp, ctypes.POINTER(Stats)]),
     "bhx_workspace_bytes": (ctypes.c_size_t, [_ci, _ci, _ci, ctypes.POINTER(Opts)]),
+    "bhx_extend3d": (_ci, [_vp, _vp, _vp, _ci, _ci, _ci, _cd, _ci, _cd, ctypes.POINTER(Opts), _vp,
+                           ctypes.POINTER(Stats)]),
+    "bhx_workspace_bytes3d": (ctypes.c_size_t, [_ci, _ci, _ci, _ci, ctypes.POINTER(Opts)]),
+    "bhx_debug_apply3d": (_ci, [_vp, _ci, _vp, _vp, _vp, _ci, _ci, _ci, _ci, _ci, _vp]),
     "bhx_engine_create": (_ci, [ctypes.POINTER(_vp), _ci, ctypes.c_size_t, _ci,
                                 ctypes.POINTER(Opts)]),
     "bhx_engine_submit": (_ci, [_vp, _vp, _vp, _ci, _ci, _cd, _ci, _cd,
@@ -103,7 +111,7 @@ def header_functions(path: str = HEADER_PATH) -> list:
     """Names of the functions declared in include/bhx.h."""
     text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(bhx_[a-z_]+)\s*\(", text)) - {"bhx_BC"})
+    return sorted(set(re.findall(r"\b(bhx_[a-z0-9_]+)\s*\(", text)) - {"bhx_BC"})
 
 
 def exported(name: str) -> bool:
@@ -144,6 +152,12 @@ def _dims(a):
     if hasattr(a, "shape") and len(a.shape) == 2:
         return int(a.shape[1]), int(a.shape[0])
     raise ValueError("pass (ny, nx) arrays or explicit sizes")
+
+
+def _dims3(a):
+    if hasattr(a, "shape") and len(a.shape) == 3:
+        return int(a.shape[2]), int(a.shape[1]), int(a.shape[0])
+    raise ValueError("pass (nz, ny, nx) arrays or explicit sizes")
 
 
 def default_opts(**kw) -> Opts:
@@ -260,6 +274,34 @@ def extend_fields(handle, phi, Fs, h=1.0, bc=0, tol=1e-8, opts=None, stream=None
                                ctypes.byref(opts) if opts is not None else None,
                                _stream(stream), st)
     return s, list(st)
+
+
+def extend3d(handle, phi, F, nx=None, ny=None, nz=None, h=1.0, bc=0, tol=1e-8, opts=None,
+             stream=None):
+    """``bhx_extend3d``; arrays (nz, ny, nx); returns (status, Stats)."""
+    if nx is None:
+        nx, ny, nz = _dims3(phi)
+    hp = handle.ptr if isinstance(handle, Handle) else handle
+    st = Stats()
+    s = _lib.bhx_extend3d(hp, _ptr(phi), _ptr(F), nx, ny, nz, float(h), int(bc), float(tol),
+                          ctypes.byref(opts) if opts is not None else None, _stream(stream),
+                          ctypes.byref(st))
+    return s, st
+
+
+def workspace_bytes3d(nx, ny, nz, bc, opts=None) -> int:
+    return int(_lib.bhx_workspace_bytes3d(nx, ny, nz, bc,
+                                          ctypes.byref(opts) if opts is not None else None))
+
+
+def debug_apply3d(handle, op, phi, x, out, nx=None, ny=None, nz=None, bc=0, precision=0,
+                  stream=None):
+    """``bhx_debug_apply3d``: op 0 masked 25-point operator, op 1 preconditioner."""
+    if nx is None:
+        nx, ny, nz = _dims3(phi)
+    hp = handle.ptr if isinstance(handle, Handle) else handle
+    return _lib.bhx_debug_apply3d(hp, int(op), _ptr(phi), _ptr(x), _ptr(out), nx, ny, nz,
+                                  int(bc), int(precision), _stream(stream))
 
 
 def workspace_bytes(nx, ny, bc, opts=None) -> int:

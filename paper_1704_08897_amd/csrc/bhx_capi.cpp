@@ -125,6 +125,43 @@ int bhx_extend_fields(bhx_handle* hd, int nfields, const double* phi, double* co
   return bhx::solve_batch(hd, nfields, specs.data(), R, (hipStream_t)stream, out);
 }
 
+int bhx_extend3d(bhx_handle* hd, const double* phi, double* F, int nx, int ny, int nz, double h,
+                 int bc, double tol, const bhx_opts* o, void* stream, bhx_stats* out) {
+  if (!hd) return BHX_ERR_ARG;
+  const Resolved R = bhx::resolve_opts(o);
+  int v = bhx::validate3(phi, F, nx, ny, nz, h, bc, tol, R);
+  if (v != BHX_OK) return v;
+  bhx::InstSpec s{phi, F, nx, ny, bc & 15, (bc >> 4) & 15, tol};
+  s.nz = nz;
+  s.bcz = (bc >> 8) & 15;
+  s.dim = 3;
+  std::lock_guard<std::mutex> lk(hd->mu);
+  return bhx::solve_batch(hd, 1, &s, R, (hipStream_t)stream, out);
+}
+
+size_t bhx_workspace_bytes3d(int nx, int ny, int nz, int bc, const bhx_opts* o) {
+  const Resolved R = bhx::resolve_opts(o);
+  static const double dummy = 0;
+  if (bhx::validate3(&dummy, (double*)&dummy, nx, ny, nz, 1.0, bc, 0.5, R) != BHX_OK) return 0;
+  return bhx::instance_bytes3(nx, ny, nz, bc & 15, (bc >> 4) & 15, (bc >> 8) & 15,
+                              R.precision) +
+         sizeof(bhx::Inst) + 64;
+}
+
+int bhx_debug_apply3d(bhx_handle* hd, int op, const double* phi, const double* in, double* out,
+                      int nx, int ny, int nz, int bc, int precision, void* stream) {
+  if (!hd || !in || (op != 0 && op != 1)) return BHX_ERR_ARG;
+  bhx_opts o;
+  bhx_default_opts(&o);
+  o.precision = precision;
+  const Resolved R = bhx::resolve_opts(&o);
+  int v = bhx::validate3(phi, out, nx, ny, nz, 1.0, bc, 0.5, R);
+  if (v != BHX_OK) return v;
+  std::lock_guard<std::mutex> lk(hd->mu);
+  return bhx::debug_apply(hd, op, phi, in, out, nx, ny, nz, bc & 15, (bc >> 4) & 15,
+                          (bc >> 8) & 15, precision, (hipStream_t)stream);
+}
+
 size_t bhx_workspace_bytes(int nx, int ny, int bc, const bhx_opts* o) {
   const Resolved R = bhx::resolve_opts(o);
   static const double dummy = 0;
@@ -143,7 +180,7 @@ int bhx_debug_apply(bhx_handle* hd, int op, const double* phi, const double* in,
   int v = bhx::validate(phi, out, nx, ny, 1.0, bc, 0.5, R);
   if (v != BHX_OK) return v;
   std::lock_guard<std::mutex> lk(hd->mu);
-  return bhx::debug_apply(hd, op, phi, in, out, nx, ny, bc & 15, (bc >> 4) & 15, precision,
+  return bhx::debug_apply(hd, op, phi, in, out, nx, ny, 1, bc & 15, (bc >> 4) & 15, 0, precision,
                           (hipStream_t)stream);
 }
 

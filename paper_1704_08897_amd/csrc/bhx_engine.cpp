@@ -243,9 +243,10 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
     make_layout(S.nx, S.ny, E->R.precision, hd->plans.plan(px).m, hd->plans.plan(py).m, 0, &L);
     Inst& I = q->inst;
     std::memset(&I, 0, sizeof(I));
-    I.nx = S.nx; I.ny = S.ny; I.bcx = S.bcx; I.bcy = S.bcy;
+    I.nx = S.nx; I.ny = S.ny; I.nz = 1; I.nrows = S.ny;
+    I.bcx = S.bcx; I.bcy = S.bcy;
     I.planx = px; I.plany = py;
-    I.G = L.G; I.Gc = L.Gc; I.tiles_x = L.tiles_x; I.tiles_y = L.tiles_y;
+    I.G = L.G; I.Gc = L.Gc; I.tiles_x = L.tiles_x; I.tiles_y = L.tiles_y; I.tiles_z = 1;
     for (int p = 0; p < kNumPass; ++p) I.n_items[p] = L.n_items[p];
     I.maxit = E->R.maxit_user > 0 ? E->R.maxit_user : 50 * std::max(S.nx, S.ny);
     I.flexible = E->R.flexible;
@@ -279,9 +280,9 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
   if (rc != BHX_OK) return rc;
   const Grids g = engine_grids(E, news);
   const int n = (int)news.size();
-  ENG_CHECK(launch_setup(E->aux.hdr, g.s, st));
+  ENG_CHECK(launch_setup(E->aux.hdr, 2, g.s, st));
   ENG_CHECK(launch_setup_rows(E->aux.hdr, g.r, st));
-  ENG_CHECK(launch_stencil(E->aux.hdr, kModeRhs, g.s, 0, st));
+  ENG_CHECK(launch_stencil(E->aux.hdr, 2, kModeRhs, g.s, 0, st));
   ENG_CHECK(launch_finalize(E->aux.hdr, n, kFinSetupH, st));
   ENG_CHECK(hipMemcpyAsync(E->ctl_h, E->ctl_d, E->max_slots * sizeof(Ctl), hipMemcpyDeviceToHost,
                            st));
@@ -317,14 +318,14 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
     ENG_CHECK(hipMalloc((void**)&flag_d, n * sizeof(int)));
     const Upload u{flag_d, zero_flag.data(), n * sizeof(int)};
     ENG_CHECK(upload_ordered(E->hd, st, &u, 1));
-    ENG_CHECK(launch_zero_unknown(E->aux.hdr, flag_d, g.s, st));
+    ENG_CHECK(launch_zero_unknown(E->aux.hdr, 2, flag_d, g.s, st));
     ENG_CHECK(hipStreamSynchronize(st));
     ENG_CHECK(hipFree(flag_d));
   }
   if (E->R.warm && !keep.empty()) {
     // warm start: r0 = b - A x0; requests whose start already meets the
     // tolerance, or whose residual is not finite, end here with F untouched
-    ENG_CHECK(launch_stencil(E->aux.hdr, kModeWarm, g.s, 0, st));
+    ENG_CHECK(launch_stencil(E->aux.hdr, 2, kModeWarm, g.s, 0, st));
     ENG_CHECK(launch_finalize(E->aux.hdr, n, kFinWarmH, st));
     ENG_CHECK(hipMemcpyAsync(E->ctl_h, E->ctl_d, E->max_slots * sizeof(Ctl),
                              hipMemcpyDeviceToHost, st));
@@ -377,7 +378,7 @@ int step_active(bhx_engine* E, hipStream_t st) {
   for (Req* q : E->active)
     if (E->ctl_h[q->slot].done != kRunning) any_done = true;
   if (!any_done) return BHX_OK;
-  ENG_CHECK(launch_resid(E->run.hdr, g.s, st));
+  ENG_CHECK(launch_resid(E->run.hdr, 2, g.s, st));
   ENG_CHECK(launch_finalize(E->run.hdr, n, kFinResidH, st));
   ENG_CHECK(launch_restart(E->run.hdr, n, st));
   ENG_CHECK(hipMemcpyAsync(E->ctl_h, E->ctl_d, E->max_slots * sizeof(Ctl), hipMemcpyDeviceToHost,

@@ -24,8 +24,11 @@
 namespace bhx {
 
 constexpr int kThreads = 256;          // threads per workgroup, every kernel
-constexpr int kTileX = 64;             // stencil tile (nodes)
+constexpr int kTileX = 64;             // stencil tile (nodes), two dimensions
 constexpr int kTileY = 32;
+constexpr int kTileX3 = 16;            // stencil tile (nodes), three dimensions
+constexpr int kTileY3 = 8;
+constexpr int kTileZ3 = 8;
 constexpr int kLdsBytes = 80 * 1024;   // LDS for the packed rows of one transform item
 constexpr int kLdsMax = 160 * 1024;    // LDS of a CU (gfx950)
 constexpr int kLdsDynMax = 152 * 1024; // dynamic LDS cap of a transform launch
@@ -45,7 +48,16 @@ __host__ __device__ inline int stage_twiddles(int logm) {
   for (int h = (logm & 1) ? 2 : 1; h < (1 << logm); h <<= 2) t += h;
   return t;
 }
-enum Pass { kPassS = 0, kPassR = 1, kPassC = 2, kNumPass = 3 };
+// Work lists: stencil tiles, row groups (x rows), column groups (y pencils of
+// the transposed buffer) and, in three dimensions, z-pencil groups.
+enum Pass { kPassS = 0, kPassR = 1, kPassC = 2, kPassZ = 3, kNumPass = 4 };
+
+// Kinds of column-transform launch.  Two dimensions: one launch transforms
+// along y, scales by 1/(lambda_x + lambda_y)^2 and transforms back.  Three
+// dimensions: forward along y, then along z with the scale by
+// 1/(lambda_x + lambda_y + lambda_z)^2 and the inverse along z, then the
+// inverse along y.
+enum ColKind { kCol2D = 0, kColYFwd = 1, kColZ = 2, kColYInv = 3 };
 
 // Stencil kernel modes.
 enum SMode {
@@ -100,12 +112,14 @@ struct Ctl {
 };
 
 struct Inst {
-  int nx, ny;
-  int bcx, bcy;
-  int planx, plany;     // AxisPlan indices
+  int nx, ny, nz;       // nz = 1 in two dimensions
+  int nrows;            // x rows: ny * nz
+  int bcx, bcy, bcz;
+  int planx, plany, planz;   // AxisPlan indices (planz unused in two dimensions)
   int G;                // rows per item in the row passes (even)
   int Gc;               // columns per item in the column pass (even)
-  int tiles_x, tiles_y; // stencil tiles
+  int Gz;               // z pencils per item in the z pass (even; three dimensions)
+  int tiles_x, tiles_y, tiles_z; // stencil tiles
   int n_items[kNumPass];
   int maxit;
   int flexible;
@@ -117,7 +131,7 @@ struct Inst {
   BHX_GLOBAL double* p[2];    // search direction, double-buffered by iteration parity
   BHX_GLOBAL double* q;
   BHX_GLOBAL double* z;
-  BHX_GLOBAL void* t;         // transform buffer, [nx][ny] (y fastest), double or float
+  BHX_GLOBAL void* t;         // transform buffer, [nx][nz][ny] (y fastest), double or float
   BHX_GLOBAL double* part;    // partial sums, see PartLayout
   BHX_GLOBAL Ctl* ctl;
 };
@@ -160,20 +174,23 @@ enum FinModeHost { kFinSetupH = 0, kFinResidH = 1, kFinWarmH = 2 };
 // The pass launches take an optional pair of events that the dispatch itself
 // records at kernel start and end (hipExtLaunchKernelGGL), so their elapsed
 // time is the kernel's execution time.
-hipError_t launch_setup(const Batch* B, int grid, hipStream_t st);
+// The stencil-family launches (setup, stencil, residual, zeroing) take the
+// batch's dimension `dim` (2 or 3; a batch holds one dimension).
+hipError_t launch_setup(const Batch* B, int dim, int grid, hipStream_t st);
 // `lpar` is the buffer parity of an iteration's launches: consecutive
 // iterations alternate it; the preconditioner applied after setup or a
 // restart runs with parity 1, so the first iteration runs with parity 0.
-hipError_t launch_stencil(const Batch* B, int mode, int grid, int lpar, hipStream_t st,
+hipError_t launch_stencil(const Batch* B, int dim, int mode, int grid, int lpar, hipStream_t st,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-hipError_t launch_resid(const Batch* B, int grid, hipStream_t st);
+hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st);
 // Transform launches: `lds` dynamic LDS bytes, `twoff` complex-element offset
 // of the twiddle table staged in LDS (after the largest packed-row buffer).
 hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, int lds, int twoff,
                          int lpar, hipStream_t st, hipEvent_t e0 = nullptr,
                          hipEvent_t e1 = nullptr);
-hipError_t launch_col(const Batch* B, int prec, int count_iter, int grid, int lds, int twoff,
-                      hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_col(const Batch* B, int prec, int kind, int count_iter, int grid, int lds,
+                      int twoff, hipStream_t st, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr);
 hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, int lpar,
                          hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_setup_rows(const Batch* B, int grid, hipStream_t st);
@@ -182,6 +199,7 @@ hipError_t launch_identity(const Batch* B, int grid, int lpar, hipStream_t st,
 hipError_t launch_finalize(const Batch* B, int count, int mode, hipStream_t st);
 hipError_t launch_restart(const Batch* B, int count, hipStream_t st);
 hipError_t launch_bump(const Batch* B, int count, hipStream_t st);
-hipError_t launch_zero_unknown(const Batch* B, const int* flag, int grid, hipStream_t st);
+hipError_t launch_zero_unknown(const Batch* B, int dim, const int* flag, int grid,
+                               hipStream_t st);
 hipError_t set_kernel_attributes();
 }  // namespace bhx

@@ -586,10 +586,69 @@ __device__ __forceinline__ void inv_pre_pair(const XPlan<R>& X, R ya_k, R yb_k, 
 }
 
 // ---------------------------------------------------------------------------
+// Stencil tile geometry.  An item of the stencil-family passes is a tile of
+// TX x TY (x TZ) nodes; the operand is staged with a two-node halo (PX x PY x
+// PZ) and L f computed on the one-node ring (LX x LY x LZ).  Two dimensions:
+// L is the 5-point negative Laplacian; three dimensions (Sec. 3, Example 2):
+// the 7-point one.  LDS arrays are [z][y][x]; HZ is the z offset of a halo
+// layer (0 in two dimensions, where z has no halo).
+// ---------------------------------------------------------------------------
+
+template <int DIM> struct Geo;
+
+template <> struct Geo<2> {
+  static constexpr int TX = kTileX, TY = kTileY, TZ = 1;
+  static constexpr int PX = TX + 4, PY = TY + 4, PZ = 1;
+  static constexpr int LX = TX + 2, LY = TY + 2, LZ = 1;
+  static constexpr int HZ = 0;
+  __device__ static void origin(const Inst& I, int tile, int& i0, int& j0, int& k0) {
+    const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
+    i0 = tx * TX;
+    j0 = ty * TY;
+    k0 = 0;
+  }
+  // element e of an X x Y box -> (i, j, k)
+  template <int X, int Y> __device__ static void coords(int e, int& i, int& j, int& k) {
+    j = e / X;
+    i = e - j * X;
+    k = 0;
+  }
+  template <typename A> __device__ static double lap(const A& a, int k, int j, int i) {
+    return 4.0 * a[k][j][i] - a[k][j - 1][i] - a[k][j + 1][i] - a[k][j][i - 1] - a[k][j][i + 1];
+  }
+};
+
+template <> struct Geo<3> {
+  static constexpr int TX = kTileX3, TY = kTileY3, TZ = kTileZ3;
+  static constexpr int PX = TX + 4, PY = TY + 4, PZ = TZ + 4;
+  static constexpr int LX = TX + 2, LY = TY + 2, LZ = TZ + 2;
+  static constexpr int HZ = 1;
+  __device__ static void origin(const Inst& I, int tile, int& i0, int& j0, int& k0) {
+    const int tx = tile % I.tiles_x, r = tile / I.tiles_x;
+    const int ty = r % I.tiles_y, tz = r / I.tiles_y;
+    i0 = tx * TX;
+    j0 = ty * TY;
+    k0 = tz * TZ;
+  }
+  template <int X, int Y> __device__ static void coords(int e, int& i, int& j, int& k) {
+    const int r = e / X;
+    i = e - r * X;
+    k = r / Y;
+    j = r - k * Y;
+  }
+  template <typename A> __device__ static double lap(const A& a, int k, int j, int i) {
+    return 6.0 * a[k][j][i] - a[k - 1][j][i] - a[k + 1][j][i] - a[k][j - 1][i] -
+           a[k][j + 1][i] - a[k][j][i - 1] - a[k][j][i + 1];
+  }
+};
+
+// ---------------------------------------------------------------------------
 // Setup: mask from the sign of phi; zero the workspace vectors; count |U|.
 // ---------------------------------------------------------------------------
 
+template <int DIM>
 __global__ void __launch_bounds__(kThreads) k_setup(const Batch* __restrict__ Bp) {
+  using G = Geo<DIM>;
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   __shared__ double red[4];
   for (int it = logical_block(); it < B.n_items[kPassS]; it += gridDim.x) {
@@ -597,13 +656,15 @@ __global__ void __launch_bounds__(kThreads) k_setup(const Batch* __restrict__ Bp
     const Inst I = B.inst[code >> kItemShift];
     const int tile = code & kItemMask;
     if (I.ctl->done) continue;
-    const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
-    const int i0 = tx * kTileX, j0 = ty * kTileY;
+    int i0, j0, k0;
+    G::origin(I, tile, i0, j0, k0);
     double cnt = 0;
-    for (int e = threadIdx.x; e < kTileX * kTileY; e += kThreads) {
-      const int i = i0 + (e & (kTileX - 1)), j = j0 + e / kTileX;
-      if (i < I.nx && j < I.ny) {
-        const size_t o = (size_t)j * I.nx + i;
+    for (int e = threadIdx.x; e < G::TX * G::TY * G::TZ; e += kThreads) {
+      int ii, jj, kk;
+      G::template coords<G::TX, G::TY>(e, ii, jj, kk);
+      const int i = i0 + ii, j = j0 + jj, k = k0 + kk;
+      if (i < I.nx && j < I.ny && k < I.nz) {
+        const size_t o = ((size_t)k * I.ny + j) * I.nx + i;
         const uint8_t u = !(I.phi[o] < 0.0);
         I.mask[o] = u;
         cnt += u;
@@ -632,7 +693,7 @@ __global__ void __launch_bounds__(kThreads) k_setup_rows(const Batch* __restrict
     const int g = code & kItemMask;
     if (I.ctl->done) continue;
     const int j0 = g * I.G;
-    const int E = min(I.G, I.ny - j0) * I.nx;
+    const int E = min(I.G, I.nrows - j0) * I.nx;
     BHX_GLOBAL const uint8_t* mk = I.mask + (size_t)j0 * I.nx;
     double cnt = 0;
     for (int e = threadIdx.x; e < E; e += kThreads) cnt += mk[e];
@@ -645,25 +706,26 @@ __global__ void __launch_bounds__(kThreads) k_setup_rows(const Batch* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Stencil pass: 13-point operator as L(L f) on an LDS tile with a two-node
-// halo whose ghost values follow each axis' rule.
+// Stencil pass: the 13-point (two dimensions) or 25-point (three) operator
+// as L(L f) on an LDS tile with a two-node halo whose ghost values follow
+// each axis' rule.
 // ---------------------------------------------------------------------------
 
 constexpr int kUnroll = 4;                          // loads in flight per thread
 constexpr int kPre = 8;                             // elements per thread loaded up front
-constexpr int kPW = kTileX + 4, kPH = kTileY + 4;   // f tile with 2-node halo
-constexpr int kLW = kTileX + 2, kLH = kTileY + 2;   // L f with 1-node halo
-constexpr int kPL = (kPH * kPW + kThreads - 1) / kThreads;   // halo loads per thread
 
 // `lpar` is the buffer parity of this launch: p_old = p[lpar], p_new =
 // p[lpar ^ 1], and the current / previous r.z partials are rz(lpar) /
 // rz(lpar ^ 1).  Launches alternate it, so addresses never wait for the
 // control block.
-template <int MODE>
+template <int MODE, int DIM>
 __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ Bp, int lpar) {
+  using G = Geo<DIM>;
+  constexpr int kPN = G::PX * G::PY * G::PZ;               // halo tile nodes
+  constexpr int kPL = (kPN + kThreads - 1) / kThreads;     // halo loads per thread
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
-  __shared__ double P[kPH][kPW + 1];
-  __shared__ double L[kLH][kLW + 1];
+  __shared__ double P[G::PZ][G::PY][G::PX + 1];
+  __shared__ double L[G::LZ][G::LY][G::LX + 1];
   __shared__ double red[16];
   // `done` is the one control field this pass writes (the block owning tile 0
   // of an instance sets it when the instance stops) while other blocks of the
@@ -674,7 +736,7 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
   // before that wave arrives there).
   __shared__ int s_done[2];
   int slot = 0;
-  constexpr int kOut = kTileX * kTileY / kThreads;
+  constexpr int kOut = G::TX * G::TY * G::TZ / kThreads;
   for (int it = logical_block(); it < B.n_items[kPassS]; it += gridDim.x) {
     const int code = item_code(B, kPassS, it);
     const Inst I = B.inst[code >> kItemShift];
@@ -701,7 +763,7 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
     const int c_done = s_done[slot];
     slot ^= 1;
     if (c_done) continue;
-    const int nx = I.nx, ny = I.ny;
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
     const int out_slot = (MODE == kModeIter ? PL.pq() : PL.aux()) + tile;
     if (!has_u && tile != 0) {             // nothing to compute or store here
       if (threadIdx.x == 0) I.part[out_slot] = 0.0;
@@ -713,20 +775,28 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
     const int ns[4] = {MODE == kModeIter ? PL.nR : 0, (MODE == kModeIter && !first) ? PL.nR : 0,
                        (MODE == kModeIter && !first) ? PL.nR : 0,
                        (MODE == kModeIter && !first && I.flexible) ? PL.nR : 0};
-    const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
-    const int i0 = tx * kTileX, j0 = ty * kTileY;
+    int i0, j0, k0;
+    G::origin(I, tile, i0, j0, k0);
     int oo[kPL];
     double sg[kPL], va[kPL], vb[kPL];
     uint8_t vm[kPL], mo[kOut];
 #pragma unroll
     for (int s = 0; s < kPL; ++s) {
-      const int e = min(threadIdx.x + s * kThreads, kPH * kPW - 1);
-      const int jj = e / kPW, ii = e - jj * kPW;
+      const int e = min((int)threadIdx.x + s * kThreads, kPN - 1);
+      int ii, jj, kk;
+      G::template coords<G::PX, G::PY>(e, ii, jj, kk);
       double sx, sy;
       const int mi = map_axis_sel(i0 + ii - 2, nx, I.bcx, sx);
       const int mj = map_axis_sel(j0 + jj - 2, ny, I.bcy, sy);
-      sg[s] = sx * sy;
-      oo[s] = mj * nx + mi;
+      if constexpr (DIM == 2) {
+        sg[s] = sx * sy;
+        oo[s] = mj * nx + mi;
+      } else {
+        double sz;
+        const int mk = map_axis_sel(k0 + kk - 2, nz, I.bcz, sz);
+        sg[s] = sx * sy * sz;
+        oo[s] = (mk * ny + mj) * nx + mi;
+      }
     }
 #pragma unroll
     for (int s = 0; s < kPL; ++s) {
@@ -745,9 +815,11 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
 #pragma unroll
     for (int s = 0; s < kOut; ++s) {
       const int e = threadIdx.x + s * kThreads;
-      const int jj = e / kTileX, ii = e - jj * kTileX;
+      int ii, jj, kk;
+      G::template coords<G::TX, G::TY>(e, ii, jj, kk);
       const int gi = min(i0 + ii, nx - 1), gj = min(j0 + jj, ny - 1);
-      mo[s] = I.mask[gj * nx + gi];
+      const int gk = min(k0 + kk, nz - 1);
+      mo[s] = I.mask[(gk * ny + gj) * nx + gi];
     }
     // every load of the item is issued above; keep the arithmetic on any of
     // them from being scheduled before the last one is issued
@@ -794,30 +866,31 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
       else if (MODE == kModeRhs) v = vm[s] ? 0.0 : va[s];
       else if (MODE == kModeWarm) v = va[s];
       else v = vm[s] ? va[s] : 0.0;
-      if (e < kPH * kPW) {
-        const int jj = e / kPW, ii = e - jj * kPW;
-        P[jj][ii] = sg[s] * v;
+      if (e < kPN) {
+        int ii, jj, kk;
+        G::template coords<G::PX, G::PY>(e, ii, jj, kk);
+        P[kk][jj][ii] = sg[s] * v;
       }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kLH * kLW; e += kThreads) {
-      const int jj = e / kLW, ii = e - jj * kLW;
-      L[jj][ii] = 4.0 * P[jj + 1][ii + 1] - P[jj][ii + 1] - P[jj + 2][ii + 1] - P[jj + 1][ii] -
-                  P[jj + 1][ii + 2];
+    for (int e = threadIdx.x; e < G::LX * G::LY * G::LZ; e += kThreads) {
+      int ii, jj, kk;
+      G::template coords<G::LX, G::LY>(e, ii, jj, kk);
+      L[kk][jj][ii] = G::lap(P, kk + G::HZ, jj + 1, ii + 1);
     }
     __syncthreads();
     double acc = 0.0;
 #pragma unroll
     for (int s = 0; s < kOut; ++s) {
       const int e = threadIdx.x + s * kThreads;
-      const int jj = e / kTileX, ii = e - jj * kTileX;
-      const int gi = i0 + ii, gj = j0 + jj;
-      const double qv = 4.0 * L[jj + 1][ii + 1] - L[jj][ii + 1] - L[jj + 2][ii + 1] -
-                        L[jj + 1][ii] - L[jj + 1][ii + 2];
-      const bool st = gi < nx && gj < ny && mo[s];
-      const int o = gj * nx + gi;
+      int ii, jj, kk;
+      G::template coords<G::TX, G::TY>(e, ii, jj, kk);
+      const int gi = i0 + ii, gj = j0 + jj, gk = k0 + kk;
+      const double qv = G::lap(L, kk + G::HZ, jj + 1, ii + 1);
+      const bool st = gi < nx && gj < ny && gk < nz && mo[s];
+      const int o = (gk * ny + gj) * nx + gi;
       if (MODE == kModeIter) {
-        const double pv = P[jj + 2][ii + 2];
+        const double pv = P[kk + 2 * G::HZ][jj + 2][ii + 2];
         if (st) {
           pnew[o] = pv;
           I.q[o] = qv;
@@ -861,17 +934,40 @@ __device__ __forceinline__ dd dd_add(dd a, dd b) {
 __device__ __forceinline__ dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
 __device__ __forceinline__ dd dd_x4(dd a) { return {4.0 * a.hi, 4.0 * a.lo}; }
 
+__device__ __forceinline__ dd dd_x2(dd a) { return {2.0 * a.hi, 2.0 * a.lo}; }
+
 __device__ __forceinline__ dd five_point_dd(dd c, dd n, dd s, dd w, dd e) {
   dd t = dd_add(dd_neg(n), dd_neg(s));
   t = dd_add(t, dd_add(dd_neg(w), dd_neg(e)));
   return dd_add(dd_x4(c), t);
 }
 
+// 6 c - (six neighbours); 6 c as 4 c + 2 c keeps the scaling exact
+__device__ __forceinline__ dd seven_point_dd(dd c, dd zm, dd zp, dd ym, dd yp, dd xm, dd xp) {
+  dd t = dd_add(dd_neg(zm), dd_neg(zp));
+  t = dd_add(t, dd_add(dd_neg(ym), dd_neg(yp)));
+  t = dd_add(t, dd_add(dd_neg(xm), dd_neg(xp)));
+  return dd_add(dd_add(dd_x4(c), dd_x2(c)), t);
+}
+
+// L at (k, j, i) of the double-double values at(k, j, i).
+template <int DIM, typename F>
+__device__ __forceinline__ dd lap_dd(const F& at, int k, int j, int i) {
+  if constexpr (DIM == 2)
+    return five_point_dd(at(k, j, i), at(k, j - 1, i), at(k, j + 1, i), at(k, j, i - 1),
+                         at(k, j, i + 1));
+  else
+    return seven_point_dd(at(k, j, i), at(k - 1, j, i), at(k + 1, j, i), at(k, j - 1, i),
+                          at(k, j + 1, i), at(k, j, i - 1), at(k, j, i + 1));
+}
+
+template <int DIM>
 __global__ void __launch_bounds__(kThreads) k_resid(const Batch* __restrict__ Bp) {
+  using G = Geo<DIM>;
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
-  __shared__ double P[kPH][kPW + 1];
-  __shared__ double Lh[kLH][kLW + 1];
-  __shared__ double Ll[kLH][kLW + 1];
+  __shared__ double P[G::PZ][G::PY][G::PX + 1];
+  __shared__ double Lh[G::LZ][G::LY][G::LX + 1];
+  __shared__ double Ll[G::LZ][G::LY][G::LX + 1];
   __shared__ double red[4];
   for (int it = logical_block(); it < B.n_items[kPassS]; it += gridDim.x) {
     const int code = item_code(B, kPassS, it);
@@ -879,49 +975,50 @@ __global__ void __launch_bounds__(kThreads) k_resid(const Batch* __restrict__ Bp
     const int tile = code & kItemMask;
     const int dn = I.ctl->done;
     if (dn != kConverged && dn != kMaxIt) continue;
-    const int nx = I.nx, ny = I.ny;
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
     if (I.part[PL.aux2() + tile] == 0.0) {
       if (threadIdx.x == 0) I.part[PL.aux() + tile] = 0.0;
       continue;
     }
-    const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
-    const int i0 = tx * kTileX, j0 = ty * kTileY;
-    for (int e = threadIdx.x; e < kPH * kPW; e += kThreads) {
-      const int jj = e / kPW, ii = e - jj * kPW;
+    int i0, j0, k0;
+    G::origin(I, tile, i0, j0, k0);
+    for (int e = threadIdx.x; e < G::PX * G::PY * G::PZ; e += kThreads) {
+      int ii, jj, kk;
+      G::template coords<G::PX, G::PY>(e, ii, jj, kk);
       const int gi = i0 + ii - 2, gj = j0 + jj - 2;
+      const int gk = DIM == 2 ? 0 : k0 + kk - 2;
       double v = 0.0;
-      if (gi >= -2 && gi <= nx + 1 && gj >= -2 && gj <= ny + 1) {
-        double sx, sy;
+      if (gi >= -2 && gi <= nx + 1 && gj >= -2 && gj <= ny + 1 && gk >= -2 && gk <= nz + 1) {
+        double sx, sy, sz = 1.0;
         const int mi = map_axis(gi, nx, I.bcx, sx);
         const int mj = map_axis(gj, ny, I.bcy, sy);
-        const double s = sx * sy;
-        if (s != 0.0) v = s * I.F[(size_t)mj * nx + mi];
+        const int mk = DIM == 2 ? 0 : map_axis(gk, nz, I.bcz, sz);
+        const double s = sx * sy * sz;
+        if (s != 0.0) v = s * I.F[((size_t)mk * ny + mj) * nx + mi];
       }
-      P[jj][ii] = v;
+      P[kk][jj][ii] = v;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kLH * kLW; e += kThreads) {
-      const int jj = e / kLW, ii = e - jj * kLW;
-      const dd l = five_point_dd({P[jj + 1][ii + 1], 0.0}, {P[jj][ii + 1], 0.0},
-                                 {P[jj + 2][ii + 1], 0.0}, {P[jj + 1][ii], 0.0},
-                                 {P[jj + 1][ii + 2], 0.0});
-      Lh[jj][ii] = l.hi;
-      Ll[jj][ii] = l.lo;
+    auto atP = [&](int k, int j, int i) { return dd{P[k][j][i], 0.0}; };
+    auto atL = [&](int k, int j, int i) { return dd{Lh[k][j][i], Ll[k][j][i]}; };
+    for (int e = threadIdx.x; e < G::LX * G::LY * G::LZ; e += kThreads) {
+      int ii, jj, kk;
+      G::template coords<G::LX, G::LY>(e, ii, jj, kk);
+      const dd l = lap_dd<DIM>(atP, kk + G::HZ, jj + 1, ii + 1);
+      Lh[kk][jj][ii] = l.hi;
+      Ll[kk][jj][ii] = l.lo;
     }
     __syncthreads();
     double acc = 0.0;
-    for (int e = threadIdx.x; e < kTileX * kTileY; e += kThreads) {
-      const int jj = e / kTileX, ii = e - jj * kTileX;
-      const int gi = i0 + ii, gj = j0 + jj;
-      if (gi < nx && gj < ny) {
-        const size_t o = (size_t)gj * nx + gi;
+    for (int e = threadIdx.x; e < G::TX * G::TY * G::TZ; e += kThreads) {
+      int ii, jj, kk;
+      G::template coords<G::TX, G::TY>(e, ii, jj, kk);
+      const int gi = i0 + ii, gj = j0 + jj, gk = k0 + kk;
+      if (gi < nx && gj < ny && gk < nz) {
+        const size_t o = ((size_t)gk * ny + gj) * nx + gi;
         if (I.mask[o]) {
-          const dd q = five_point_dd({Lh[jj + 1][ii + 1], Ll[jj + 1][ii + 1]},
-                                     {Lh[jj][ii + 1], Ll[jj][ii + 1]},
-                                     {Lh[jj + 2][ii + 1], Ll[jj + 2][ii + 1]},
-                                     {Lh[jj + 1][ii], Ll[jj + 1][ii]},
-                                     {Lh[jj + 1][ii + 2], Ll[jj + 1][ii + 2]});
+          const dd q = lap_dd<DIM>(atL, kk + G::HZ, jj + 1, ii + 1);
           const double rv = -(q.hi + q.lo);
           I.r[o] = rv;
           acc += rv * rv;
@@ -935,7 +1032,8 @@ __global__ void __launch_bounds__(kThreads) k_resid(const Batch* __restrict__ Bp
 
 // ---------------------------------------------------------------------------
 // Row pass, forward: optional CG update, then forward transform of r along x
-// for G rows, written transposed to t[k * ny + j].
+// for G rows, written transposed to t[k * nrows + j].  Rows are the x lines:
+// j = y in two dimensions, j = z * ny + y in three (nrows = ny * nz).
 // ---------------------------------------------------------------------------
 
 // `lpar`: buffer parity of the iteration (as in k_stencil): p_new = p[lpar ^ 1],
@@ -957,7 +1055,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
     const int g = code & kItemMask;
     BHX_GLOBAL Ctl* ctl = I.ctl;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
-    const int nx = I.nx, ny = I.ny, G = I.G, j0 = g * G;
+    const int nx = I.nx, ny = I.nrows, G = I.G, j0 = g * G;   // ny: rows of the pass
     const int E = min(G, ny - j0) * nx;          // valid elements of this row group
     const size_t base = (size_t)j0 * nx;
     BHX_GLOBAL const uint8_t* __restrict__ mk = I.mask + base;
@@ -1106,77 +1204,180 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
 }
 
 // ---------------------------------------------------------------------------
-// Column pass: forward transform along y, scale, inverse transform along y,
-// in place on rows kx of t (length ny).
+// Column passes on the transposed buffer t ([nx][nz][ny], y fastest).  A
+// pencil is a line of t along y (contiguous) or, in three dimensions, along z
+// (stride ny); the pencils of one item are transformed two to a complex FFT.
+//   kCol2D    forward along y, scale by 1/(lambda_x + lambda_y)^2, inverse;
+//   kColYFwd  forward along y (three dimensions);
+//   kColZ     forward along z, scale by 1/(lambda_x + lambda_y + lambda_z)^2,
+//             inverse along z;
+//   kColYInv  inverse along y.
+// All in place on t.
 // ---------------------------------------------------------------------------
 
-template <typename R>
+template <typename R, int KIND>
 __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, int count_iter,
                                                   int twoff) {
   using C = typename V2<R>::T;
+  constexpr int kPass = KIND == kColZ ? kPassZ : kPassC;
+  constexpr bool kStrided = KIND == kColZ;       // z pencils: stride ny
+  constexpr bool kScale = KIND == kCol2D || KIND == kColZ;
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   extern __shared__ __align__(16) unsigned char smem[];
   C* buf = (C*)smem;
+  R* stg = (R*)smem;
   C* twl = buf + twoff;
-  __shared__ R s_lamx[kMaxGc];     // x eigenvalues of the item's rows of t
+  __shared__ R s_lam[kMaxGc];      // per pencil: eigenvalue sum of the other axes
   int staged = -1;
-  for (int itm = logical_block(); itm < B.n_items[kPassC]; itm += gridDim.x) {
-    const int code = item_code(B, kPassC, itm);
+  for (int itm = logical_block(); itm < B.n_items[kPass]; itm += gridDim.x) {
+    const int code = item_code(B, kPass, itm);
     const Inst I = B.inst[code >> kItemShift];
     const int c = code & kItemMask;
     BHX_GLOBAL Ctl* ctl = I.ctl;
-    const int nx = I.nx, ny = I.ny, Gc = I.Gc, kx0 = c * Gc;
     BHX_GLOBAL R* t = (BHX_GLOBAL R*)I.t;
-    // 1. issue together: the first kPre loads of the item's rows of t
-    //    (contiguous: rows kx0 .. kx0+Gc-1 of t, clamped), the x eigenvalues
-    //    of those rows and `done` (unchanged during the pass); then stage the
+    // 1. the item's pencils: cnt <= Gp of length n; element j of pencil cr at
+    //    t[pb + cr * ps + j * js]
+    int n, Gp, cnt, ps, js, plan, c0 = 0, kx = 0, ky0 = 0;
+    size_t pb;
+    if constexpr (kStrided) {
+      n = I.nz;
+      Gp = I.Gz;
+      plan = I.planz;
+      const int ngy = (I.ny + Gp - 1) / Gp;
+      kx = c / ngy;
+      ky0 = (c - kx * ngy) * Gp;
+      cnt = min(Gp, I.ny - ky0);
+      pb = (size_t)kx * I.nz * I.ny + ky0;
+      ps = 1;
+      js = I.ny;
+    } else {
+      n = I.ny;
+      Gp = I.Gc;
+      plan = I.plany;
+      c0 = c * Gp;
+      cnt = min(Gp, I.nx * I.nz - c0);    // pencils (kx, z); nz = 1 in two dimensions
+      pb = (size_t)c0 * n;
+      ps = n;
+      js = 1;
+    }
+    // element e of the load/store order -> (pencil, index): y pencils
+    // pencil-major; z pencils index-major, so neighbouring lanes touch
+    // neighbouring pencils, adjacent in memory
+    auto split = [&](int e, int& cr, int& j) {
+      if constexpr (kStrided) {
+        j = e / Gp;
+        cr = e - j * Gp;
+      } else {
+        cr = e / n;
+        j = e - cr * n;
+      }
+    };
+    auto at = [&](int cr, int j) { return pb + (size_t)cr * ps + (size_t)j * js; };
+    const int Et = Gp * n;
+    //    issue together: the first kPre loads of the item, the eigenvalues of
+    //    its pencils and `done` (unchanged during the pass); then stage the
     //    plan tables
-    const int Et = min(Gc, nx - kx0) * ny;
-    BHX_GLOBAL const R* tb = t + (size_t)kx0 * ny;
     R tv[kPre];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) tv[u] = tb[min((int)threadIdx.x + u * kThreads, Et - 1)];
-    const XPlan<R> Xx(B, I.planx);
-    const R lam_x = Xx.lam[min(kx0 + min((int)threadIdx.x, kMaxGc - 1), nx - 1)];
+    for (int u = 0; u < kPre; ++u) {
+      int cr, j;
+      split(min((int)threadIdx.x + u * kThreads, Et - 1), cr, j);
+      tv[u] = t[cr < cnt ? at(cr, j) : pb];
+    }
+    R lam = (R)0;
+    if constexpr (KIND == kCol2D) {
+      const XPlan<R> Xx(B, I.planx);
+      lam = Xx.lam[min(c0 + min((int)threadIdx.x, kMaxGc - 1), I.nx - 1)];
+    } else if constexpr (KIND == kColZ) {
+      const XPlan<R> Xx(B, I.planx);
+      const XPlan<R> Xy(B, I.plany);
+      lam = Xx.lam[kx] + Xy.lam[min(ky0 + min((int)threadIdx.x, kMaxGc - 1), I.ny - 1)];
+    }
     if (ctl->done) continue;
-    XPlan<R> X(B, I.plany);
-    X.stage(twl, I.plany, staged);
-    const int rows = Gc >> 1;
+    XPlan<R> X(B, plan);
+    X.stage(twl, plan, staged);
+    const int rows = Gp >> 1;
     const int st = X.stride();
-    auto place = [&](int e, R v) {
-      if (e >= Gc * ny) return;
-      const int cr = e / ny, j = e - cr * ny;
-      X.put(buf + (cr >> 1) * st, j, cr & 1, e < Et ? v : (R)0);
-    };
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) place(threadIdx.x + u * kThreads, tv[u]);
-    for (int e = threadIdx.x + kPre * kThreads; e < Gc * ny; e += kThreads)
-      place(e, tb[min(e, Et - 1)]);
-    if (threadIdx.x < kMaxGc) s_lamx[threadIdx.x] = lam_x;
-    X.zero_ends(buf, rows, st);
-    __syncthreads();
-    dft_core<R>(X, buf, rows);
-    // 2. spectra, scale by 1/(lambda_x + lambda_y)^2, inverse inputs
     const int np = X.pairs();
     C vin[kMaxPairs][2];
+    if constexpr (KIND != kColYInv) {
+      // 2. forward: place the pencils into the packed rows, FFT, spectra
+      auto place = [&](int e, R v) {
+        if (e >= Et) return;
+        int cr, j;
+        split(e, cr, j);
+        X.put(buf + (cr >> 1) * st, j, cr & 1, cr < cnt ? v : (R)0);
+      };
 #pragma unroll
-    for (int s = 0; s < kMaxPairs; ++s) {
-      const int pidx = threadIdx.x + s * kThreads;
-      if (pidx < rows * np) {
-        const int rr = pidx / np, k = pidx - rr * np;
-        const int kk = X.partner(k);
-        const C* row = buf + rr * st;
-        R xa, xb, xak, xbk;
-        fwd_post_pair<R>(X, X.out(row, X.bin(k)), X.out(row, X.bin(kk)), k, kk, xa, xb, xak,
-                         xbk);
-        const R la = s_lamx[2 * rr];
-        const R lb = s_lamx[2 * rr + 1];
-        const R lk = X.laml[k], lkk = X.laml[kk];
-        xa *= inv_sq<R>(la + lk);
-        xb *= inv_sq<R>(lb + lk);
-        xak *= inv_sq<R>(la + lkk);
-        xbk *= inv_sq<R>(lb + lkk);
-        inv_pre_pair<R>(X, xa, xb, xak, xbk, k, kk, vin[s][0], vin[s][1]);
+      for (int u = 0; u < kPre; ++u) place(threadIdx.x + u * kThreads, tv[u]);
+      for (int e = threadIdx.x + kPre * kThreads; e < Et; e += kThreads) {
+        int cr, j;
+        split(e, cr, j);
+        place(e, t[cr < cnt ? at(cr, j) : pb]);
+      }
+      if (kScale && threadIdx.x < kMaxGc) s_lam[threadIdx.x] = lam;
+      X.zero_ends(buf, rows, st);
+      __syncthreads();
+      dft_core<R>(X, buf, rows);
+#pragma unroll
+      for (int s = 0; s < kMaxPairs; ++s) {
+        const int pidx = threadIdx.x + s * kThreads;
+        if (pidx < rows * np) {
+          const int rr = pidx / np, k = pidx - rr * np;
+          const int kk = X.partner(k);
+          const C* row = buf + rr * st;
+          R xa, xb, xak, xbk;
+          fwd_post_pair<R>(X, X.out(row, X.bin(k)), X.out(row, X.bin(kk)), k, kk, xa, xb, xak,
+                           xbk);
+          if constexpr (KIND == kColYFwd) {
+            const int ca = 2 * rr, cb = ca + 1;
+            if (ca < cnt) {
+              t[at(ca, k)] = xa;
+              if (kk != k) t[at(ca, kk)] = xak;
+            }
+            if (cb < cnt) {
+              t[at(cb, k)] = xb;
+              if (kk != k) t[at(cb, kk)] = xbk;
+            }
+          } else {
+            // 3. scale by the inverse squared eigenvalue sums, inverse inputs
+            const R la = s_lam[2 * rr];
+            const R lb = s_lam[2 * rr + 1];
+            const R lk = X.laml[k], lkk = X.laml[kk];
+            xa *= inv_sq<R>(la + lk);
+            xb *= inv_sq<R>(lb + lk);
+            xak *= inv_sq<R>(la + lkk);
+            xbk *= inv_sq<R>(lb + lkk);
+            inv_pre_pair<R>(X, xa, xb, xak, xbk, k, kk, vin[s][0], vin[s][1]);
+          }
+        }
+      }
+      if constexpr (KIND == kColYFwd) {
+        __syncthreads();
+        continue;
+      }
+    } else {
+      // 2. inverse only: the spectra staged as stg[cr * n + k], inverse inputs
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        if (e < Et) stg[e] = (e / n) < cnt ? tv[u] : (R)0;
+      }
+      for (int e = threadIdx.x + kPre * kThreads; e < Et; e += kThreads) {
+        int cr, j;
+        split(e, cr, j);
+        stg[e] = cr < cnt ? t[at(cr, j)] : (R)0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < kMaxPairs; ++s) {
+        const int pidx = threadIdx.x + s * kThreads;
+        if (pidx < rows * np) {
+          const int rr = pidx / np, k = pidx - rr * np;
+          const int kk = X.partner(k);
+          const R* ra = stg + 2 * rr * n;
+          inv_pre_pair<R>(X, ra[k], ra[n + k], ra[kk], ra[n + kk], k, kk, vin[s][0], vin[s][1]);
+        }
       }
     }
     __syncthreads();
@@ -1191,14 +1392,14 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
     X.zero_ends(buf, rows, st);
     __syncthreads();
     dft_core<R>(X, buf, rows);
-    // 3. inverse outputs back into t
+    // 4. inverse outputs back into t
     if (X.bc == kNeumann) {
-      for (int e = threadIdx.x; e < Gc * ny; e += kThreads) {
-        const int cr = e / ny, j = e - cr * ny;
-        const int kx = kx0 + cr;
-        if (kx < nx) {
-          const C v = X.out(buf + (cr >> 1) * st, inv_index(j, ny));
-          t[(size_t)kx * ny + j] = (cr & 1) ? -v.y : v.x;
+      for (int e = threadIdx.x; e < Et; e += kThreads) {
+        int cr, j;
+        split(e, cr, j);
+        if (cr < cnt) {
+          const C v = X.out(buf + (cr >> 1) * st, inv_index(j, n));
+          t[at(cr, j)] = (cr & 1) ? -v.y : v.x;
         }
       }
     } else {
@@ -1216,20 +1417,45 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
           vin[s][1] = mk<C>(ak, bk);
         }
       }
+      if constexpr (kStrided) {
+        // through LDS, index-major (stg[k * Gp + cr]), for coalesced stores
+        __syncthreads();
 #pragma unroll
-      for (int s = 0; s < kMaxPairs; ++s) {
-        const int pidx = threadIdx.x + s * kThreads;
-        if (pidx < rows * np) {
-          const int rr = pidx / np, k = pidx - rr * np;
-          const int kk = X.partner(k);
-          const int kxa = kx0 + 2 * rr, kxb = kxa + 1;
-          if (kxa < nx) {
-            t[(size_t)kxa * ny + k] = vin[s][0].x;
-            if (kk != k) t[(size_t)kxa * ny + kk] = vin[s][1].x;
+        for (int s = 0; s < kMaxPairs; ++s) {
+          const int pidx = threadIdx.x + s * kThreads;
+          if (pidx < rows * np) {
+            const int rr = pidx / np, k = pidx - rr * np;
+            const int kk = X.partner(k);
+            stg[k * Gp + 2 * rr] = vin[s][0].x;
+            stg[k * Gp + 2 * rr + 1] = vin[s][0].y;
+            if (kk != k) {
+              stg[kk * Gp + 2 * rr] = vin[s][1].x;
+              stg[kk * Gp + 2 * rr + 1] = vin[s][1].y;
+            }
           }
-          if (kxb < nx) {
-            t[(size_t)kxb * ny + k] = vin[s][0].y;
-            if (kk != k) t[(size_t)kxb * ny + kk] = vin[s][1].y;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < Et; e += kThreads) {
+          int cr, j;
+          split(e, cr, j);
+          if (cr < cnt) t[at(cr, j)] = stg[e];
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < kMaxPairs; ++s) {
+          const int pidx = threadIdx.x + s * kThreads;
+          if (pidx < rows * np) {
+            const int rr = pidx / np, k = pidx - rr * np;
+            const int kk = X.partner(k);
+            const int ca = 2 * rr, cb = ca + 1;
+            if (ca < cnt) {
+              t[at(ca, k)] = vin[s][0].x;
+              if (kk != k) t[at(ca, kk)] = vin[s][1].x;
+            }
+            if (cb < cnt) {
+              t[at(cb, k)] = vin[s][0].y;
+              if (kk != k) t[at(cb, kk)] = vin[s][1].y;
+            }
           }
         }
       }
@@ -1264,7 +1490,7 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
     BHX_GLOBAL Ctl* ctl = I.ctl;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
     const int par = lpar ^ 1;
-    const int nx = I.nx, ny = I.ny, G = I.G, j0 = g * G;
+    const int nx = I.nx, ny = I.nrows, G = I.G, j0 = g * G;   // ny: rows of the pass
     BHX_GLOBAL const R* t = (BHX_GLOBAL const R*)I.t;
     // 1. issue together: `done` and the row group's unknown count (both
     //    unchanged during the pass), the first kPre transposed loads of the
@@ -1410,7 +1636,7 @@ __global__ void __launch_bounds__(kThreads) k_identity(const Batch* __restrict__
     if (ctl->done) continue;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
     const int par = lpar ^ 1;          // as in k_rowinv
-    const int nx = I.nx, ny = I.ny, j0 = g * I.G;
+    const int nx = I.nx, ny = I.nrows, j0 = g * I.G;
     const int jn = min(I.G, ny - j0);
     const bool flex = I.flexible != 0;
     double acc = 0.0, acco = 0.0;
@@ -1508,8 +1734,10 @@ __global__ void k_restart(const Batch* __restrict__ Bp) {
 }
 
 // F = 0 at the unknown nodes of instances flagged by `flag` (zero right-hand side).
+template <int DIM>
 __global__ void __launch_bounds__(kThreads) k_zero_unknown(const Batch* __restrict__ Bp,
                                                            const int* __restrict__ flag) {
+  using G = Geo<DIM>;
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   for (int it = logical_block(); it < B.n_items[kPassS]; it += gridDim.x) {
     const int code = item_code(B, kPassS, it);
@@ -1517,11 +1745,14 @@ __global__ void __launch_bounds__(kThreads) k_zero_unknown(const Batch* __restri
     if (!flag[ins]) continue;
     const Inst I = B.inst[ins];
     const int tile = code & kItemMask;
-    const int tx = tile % I.tiles_x, ty = tile / I.tiles_x;
-    for (int e = threadIdx.x; e < kTileX * kTileY; e += kThreads) {
-      const int i = tx * kTileX + (e & (kTileX - 1)), j = ty * kTileY + e / kTileX;
-      if (i < I.nx && j < I.ny) {
-        const size_t o = (size_t)j * I.nx + i;
+    int i0, j0, k0;
+    G::origin(I, tile, i0, j0, k0);
+    for (int e = threadIdx.x; e < G::TX * G::TY * G::TZ; e += kThreads) {
+      int ii, jj, kk;
+      G::template coords<G::TX, G::TY>(e, ii, jj, kk);
+      const int i = i0 + ii, j = j0 + jj, k = k0 + kk;
+      if (i < I.nx && j < I.ny && k < I.nz) {
+        const size_t o = ((size_t)k * I.ny + j) * I.nx + i;
         if (I.mask[o]) I.F[o] = 0.0;
       }
     }
@@ -1532,8 +1763,11 @@ __global__ void __launch_bounds__(kThreads) k_zero_unknown(const Batch* __restri
 // Launch wrappers (host side)
 // ---------------------------------------------------------------------------
 
-hipError_t launch_setup(const Batch* B, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_setup, dim3(grid), dim3(kThreads), 0, st, B);
+hipError_t launch_setup(const Batch* B, int dim, int grid, hipStream_t st) {
+  if (dim == 3)
+    hipLaunchKernelGGL(k_setup<3>, dim3(grid), dim3(kThreads), 0, st, B);
+  else
+    hipLaunchKernelGGL(k_setup<2>, dim3(grid), dim3(kThreads), 0, st, B);
   return hipGetLastError();
 }
 // Launch on `st`; given events, through hipExtLaunchKernelGGL, whose dispatch
@@ -1547,19 +1781,28 @@ hipError_t launch_setup(const Batch* B, int grid, hipStream_t st) {
       hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), lds, st, __VA_ARGS__);   \
   } while (0)
 
-hipError_t launch_stencil(const Batch* B, int mode, int grid, int lpar, hipStream_t st,
-                          hipEvent_t e0, hipEvent_t e1) {
+template <int DIM>
+static hipError_t launch_stencil_dim(const Batch* B, int mode, int grid, int lpar,
+                                     hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   switch (mode) {
-    case kModeIter: BHX_LAUNCH(k_stencil<kModeIter>, grid, 0, st, e0, e1, B, lpar); break;
-    case kModeRhs: BHX_LAUNCH(k_stencil<kModeRhs>, grid, 0, st, e0, e1, B, lpar); break;
-    case kModeApply: BHX_LAUNCH(k_stencil<kModeApply>, grid, 0, st, e0, e1, B, lpar); break;
-    case kModeWarm: BHX_LAUNCH(k_stencil<kModeWarm>, grid, 0, st, e0, e1, B, lpar); break;
+    case kModeIter: BHX_LAUNCH((k_stencil<kModeIter, DIM>), grid, 0, st, e0, e1, B, lpar); break;
+    case kModeRhs: BHX_LAUNCH((k_stencil<kModeRhs, DIM>), grid, 0, st, e0, e1, B, lpar); break;
+    case kModeApply: BHX_LAUNCH((k_stencil<kModeApply, DIM>), grid, 0, st, e0, e1, B, lpar); break;
+    case kModeWarm: BHX_LAUNCH((k_stencil<kModeWarm, DIM>), grid, 0, st, e0, e1, B, lpar); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
-hipError_t launch_resid(const Batch* B, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_resid, dim3(grid), dim3(kThreads), 0, st, B);
+hipError_t launch_stencil(const Batch* B, int dim, int mode, int grid, int lpar, hipStream_t st,
+                          hipEvent_t e0, hipEvent_t e1) {
+  return dim == 3 ? launch_stencil_dim<3>(B, mode, grid, lpar, st, e0, e1)
+                  : launch_stencil_dim<2>(B, mode, grid, lpar, st, e0, e1);
+}
+hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st) {
+  if (dim == 3)
+    hipLaunchKernelGGL(k_resid<3>, dim3(grid), dim3(kThreads), 0, st, B);
+  else
+    hipLaunchKernelGGL(k_resid<2>, dim3(grid), dim3(kThreads), 0, st, B);
   return hipGetLastError();
 }
 hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, int lds, int twoff,
@@ -1570,13 +1813,22 @@ hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, int lds
     BHX_LAUNCH(k_rowfwd<float>, grid, lds, st, e0, e1, B, update, twoff, lpar);
   return hipGetLastError();
 }
-hipError_t launch_col(const Batch* B, int prec, int count_iter, int grid, int lds, int twoff,
-                      hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  if (prec == 0)
-    BHX_LAUNCH(k_col<double>, grid, lds, st, e0, e1, B, count_iter, twoff);
-  else
-    BHX_LAUNCH(k_col<float>, grid, lds, st, e0, e1, B, count_iter, twoff);
+template <typename R>
+static hipError_t launch_col_prec(const Batch* B, int kind, int count_iter, int grid, int lds,
+                                  int twoff, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  switch (kind) {
+    case kCol2D: BHX_LAUNCH((k_col<R, kCol2D>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
+    case kColYFwd: BHX_LAUNCH((k_col<R, kColYFwd>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
+    case kColZ: BHX_LAUNCH((k_col<R, kColZ>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
+    case kColYInv: BHX_LAUNCH((k_col<R, kColYInv>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+hipError_t launch_col(const Batch* B, int prec, int kind, int count_iter, int grid, int lds,
+                      int twoff, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  return prec == 0 ? launch_col_prec<double>(B, kind, count_iter, grid, lds, twoff, st, e0, e1)
+                   : launch_col_prec<float>(B, kind, count_iter, grid, lds, twoff, st, e0, e1);
 }
 hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, int lpar,
                          hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
@@ -1607,8 +1859,12 @@ hipError_t launch_bump(const Batch* B, int count, hipStream_t st) {
   hipLaunchKernelGGL(k_bump, dim3((count + 255) / 256), dim3(256), 0, st, B);
   return hipGetLastError();
 }
-hipError_t launch_zero_unknown(const Batch* B, const int* flag, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_unknown, dim3(grid), dim3(kThreads), 0, st, B, flag);
+hipError_t launch_zero_unknown(const Batch* B, int dim, const int* flag, int grid,
+                               hipStream_t st) {
+  if (dim == 3)
+    hipLaunchKernelGGL(k_zero_unknown<3>, dim3(grid), dim3(kThreads), 0, st, B, flag);
+  else
+    hipLaunchKernelGGL(k_zero_unknown<2>, dim3(grid), dim3(kThreads), 0, st, B, flag);
   return hipGetLastError();
 }
 
@@ -1621,8 +1877,14 @@ hipError_t set_kernel_attributes() {
   };
   set((const void*)k_rowfwd<double>);
   set((const void*)k_rowfwd<float>);
-  set((const void*)k_col<double>);
-  set((const void*)k_col<float>);
+  set((const void*)k_col<double, kCol2D>);
+  set((const void*)k_col<float, kCol2D>);
+  set((const void*)k_col<double, kColYFwd>);
+  set((const void*)k_col<float, kColYFwd>);
+  set((const void*)k_col<double, kColZ>);
+  set((const void*)k_col<float, kColZ>);
+  set((const void*)k_col<double, kColYInv>);
+  set((const void*)k_col<float, kColYInv>);
   set((const void*)k_rowinv<double>);
   set((const void*)k_rowinv<float>);
   return e;

@@ -104,30 +104,44 @@ bool length_supported(int n, int bc, int prec) {
   return true;
 }
 
-bool make_layout(int nx, int ny, int prec, int mx, int my, int rows_user, Layout* L) {
+bool make_layout(int nx, int ny, int nz, int prec, int mx, int my, int mz, int rows_user,
+                 Layout* L) {
+  const bool d3 = mz > 0;
   const int csize = prec == 0 ? 16 : 8;
   const int rows_cap = prec == 0 ? 4 : 8;
   // packed rows per item: the most that fit LDS and the register pair pass,
   // reduced until the instance supplies kTargetItems items (two per CU)
-  auto rows_for = [&](int n, int m, int lines) {
-    int r = std::min(rows_cap, kLdsBytes / (row_slots(m) * csize));
+  auto rows_for = [&](int n, int m, long lines, int cap) {
+    int r = std::min(cap, kLdsBytes / (row_slots(m) * csize));
     r = std::min(r, (kThreads * kMaxPairs) / (n / 2 + 1));
     if (rows_user > 0) return std::min(r, rows_user);
     while (r > 1 && (lines + 2 * r - 1) / (2 * r) < kTargetItems) --r;
     return r;
   };
-  const int rx = rows_for(nx, mx, ny), ry = rows_for(ny, my, nx);
-  if (rx < 1 || ry < 1) return false;
+  const long nrows = (long)ny * nz;                      // x rows
+  const int rx = rows_for(nx, mx, nrows, rows_cap);
+  const int ry = rows_for(ny, my, (long)nx * nz, rows_cap);
+  // z pencils are strided: wider groups give longer contiguous runs
+  const int rz = d3 ? rows_for(nz, mz, (long)nx * ny, kMaxGc / 2) : 1;
+  if (rx < 1 || ry < 1 || rz < 1) return false;
   L->G = 2 * rx;
   L->Gc = 2 * ry;
-  if (L->Gc > kMaxGc) return false;
-  L->tiles_x = (nx + kTileX - 1) / kTileX;
-  L->tiles_y = (ny + kTileY - 1) / kTileY;
-  L->n_items[kPassS] = L->tiles_x * L->tiles_y;
-  L->n_items[kPassR] = (ny + L->G - 1) / L->G;
-  L->n_items[kPassC] = (nx + L->Gc - 1) / L->Gc;
-  const size_t N = (size_t)nx * ny;
-  const size_t Np = vec_stride(nx, ny);
+  L->Gz = d3 ? 2 * rz : 0;
+  if (L->Gc > kMaxGc || L->Gz > kMaxGc) return false;
+  const int tx = d3 ? kTileX3 : kTileX, ty = d3 ? kTileY3 : kTileY, tz = d3 ? kTileZ3 : 1;
+  L->tiles_x = (nx + tx - 1) / tx;
+  L->tiles_y = (ny + ty - 1) / ty;
+  L->tiles_z = (nz + tz - 1) / tz;
+  const long items[kNumPass] = {(long)L->tiles_x * L->tiles_y * L->tiles_z,
+                                (nrows + L->G - 1) / L->G,
+                                ((long)nx * nz + L->Gc - 1) / L->Gc,
+                                d3 ? (long)nx * ((ny + L->Gz - 1) / L->Gz) : 0};
+  for (int p = 0; p < kNumPass; ++p) {
+    if (items[p] > kItemMask) return false;
+    L->n_items[p] = (int)items[p];
+  }
+  const size_t N = (size_t)nx * ny * nz;
+  const size_t Np = vec_stride(nx, ny * nz);
   const PartLayout PL(L->n_items[kPassS], L->n_items[kPassR]);
   size_t o = 0;
   L->off_mask = o; o = align_up(o + N);
@@ -144,6 +158,17 @@ size_t instance_bytes(int nx, int ny, int bcx, int bcy, int prec) {
   if (!length_supported(nx, bcx, prec) || !length_supported(ny, bcy, prec)) return 0;
   if (!make_layout(nx, ny, prec, core_length(fft_length(nx, bcx)),
                    core_length(fft_length(ny, bcy)), 0, &L))
+    return 0;
+  return L.bytes;
+}
+
+size_t instance_bytes3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int prec) {
+  Layout L;
+  if (!length_supported(nx, bcx, prec) || !length_supported(ny, bcy, prec) ||
+      !length_supported(nz, bcz, prec))
+    return 0;
+  if (!make_layout(nx, ny, nz, prec, core_length(fft_length(nx, bcx)),
+                   core_length(fft_length(ny, bcy)), core_length(fft_length(nz, bcz)), 0, &L))
     return 0;
   return L.bytes;
 }
@@ -317,6 +342,18 @@ int validate(const double* phi, const double* F, int nx, int ny, double h, int b
   return BHX_OK;
 }
 
+int validate3(const double* phi, const double* F, int nx, int ny, int nz, double h, int bc,
+              double tol, const Resolved& R) {
+  if (bc < 0 || (bc >> 12) != 0) return BHX_ERR_ARG;
+  const int bz = (bc >> 8) & 15;
+  if (bz > BHX_DIRICHLET || nz < 4) return BHX_ERR_ARG;
+  const int v = validate(phi, F, nx, ny, h, bc & 0xff, tol, R);
+  if (v != BHX_OK) return v;
+  if (!length_supported(nz, bz, R.precision)) return BHX_ERR_ARG;
+  if ((long long)nx * ny * nz >= (1LL << 31)) return BHX_ERR_ARG;
+  return BHX_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Handle
 // ---------------------------------------------------------------------------
@@ -391,13 +428,34 @@ namespace {
 
 }  // namespace
 
+// The column-transform launches of one preconditioner application: one in
+// two dimensions; y forward, z (with the scale) and y inverse in three.
+// Given events, they time the whole group (in three dimensions, recorded on
+// the stream around the three launches).
+hipError_t launch_columns(const Batch* B, const Resolved& R, const Grids& g, int count_iter,
+                          hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (g.dim == 2)
+    return launch_col(B, R.precision, kCol2D, count_iter, g.c, g.lds_c, g.tw_c, st, e0, e1);
+  hipError_t e;
+  if (e0 && (e = hipEventRecord(e0, st)) != hipSuccess) return e;
+  if ((e = launch_col(B, R.precision, kColYFwd, 0, g.c, g.lds_c, g.tw_c, st)) != hipSuccess)
+    return e;
+  if ((e = launch_col(B, R.precision, kColZ, count_iter, g.z, g.lds_z, g.tw_z, st)) !=
+      hipSuccess)
+    return e;
+  if ((e = launch_col(B, R.precision, kColYInv, 0, g.c, g.lds_c, g.tw_c, st)) != hipSuccess)
+    return e;
+  if (e1) return hipEventRecord(e1, st);
+  return hipSuccess;
+}
+
 hipError_t launch_precond(const Batch* B, const Resolved& R, const Grids& g, hipStream_t st) {
   hipError_t e;
   // parity 1: the r.z partials it writes are the ones the first iteration
   // (parity 0) reads
   if (!R.precond) return launch_identity(B, g.r, 1, st);
   if ((e = launch_rowfwd(B, R.precision, 0, g.r, g.lds_r, g.tw_r, 1, st)) != hipSuccess) return e;
-  if ((e = launch_col(B, R.precision, 0, g.c, g.lds_c, g.tw_c, st)) != hipSuccess) return e;
+  if ((e = launch_columns(B, R, g, 0, st, nullptr, nullptr)) != hipSuccess) return e;
   return launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, 1, st);
 }
 
@@ -421,11 +479,11 @@ hipError_t launch_iterations(const Batch* B, int n_inst, const Resolved& R, cons
 #define BHX_TRY(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
   for (int c = 0; c < count; ++c) {
     const int par = c & 1;               // count is even: every chunk starts at 0
-    BHX_TRY(launch_stencil(B, kModeIter, g.s, par, st, e0(0, c), e1(0, c)));
+    BHX_TRY(launch_stencil(B, g.dim, kModeIter, g.s, par, st, e0(0, c), e1(0, c)));
     if (R.precond) {
       BHX_TRY(launch_rowfwd(B, R.precision, 1, g.r, g.lds_r, g.tw_r, par, st, e0(1, c),
                             e1(1, c)));
-      BHX_TRY(launch_col(B, R.precision, 1, g.c, g.lds_c, g.tw_c, st, e0(2, c), e1(2, c)));
+      BHX_TRY(launch_columns(B, R, g, 1, st, e0(2, c), e1(2, c)));
       BHX_TRY(launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, par, st, e0(3, c), e1(3, c)));
     } else {
       // plain CG: update-only row pass, iteration count, z = r
@@ -468,6 +526,7 @@ hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved&
         gr.prec == R.precision && gr.chunk == R.chunk &&
         gr.precond == R.precond && gr.gs == g.s && gr.gr == g.r && gr.gc == g.c &&
         gr.lds_r == g.lds_r && gr.tw_r == g.tw_r && gr.lds_c == g.lds_c && gr.tw_c == g.tw_c &&
+        gr.dim == g.dim && gr.gz == g.z && gr.lds_z == g.lds_z && gr.tw_z == g.tw_z &&
         gr.profile == R.profile && (gr.exec != nullptr) == graph) {
       *used = &gr;
       if (gr.exec) return hipGraphLaunch(gr.exec, st);
@@ -479,6 +538,7 @@ hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved&
   G.batch = B; G.count = R.precond ? 0 : n_inst;
   G.gs = g.s; G.gr = g.r; G.gc = g.c; G.profile = R.profile;
   G.lds_r = g.lds_r; G.tw_r = g.tw_r; G.lds_c = g.lds_c; G.tw_c = g.tw_c;
+  G.dim = g.dim; G.gz = g.z; G.lds_z = g.lds_z; G.tw_z = g.tw_z;
   hipError_t e;
   if (R.profile && (e = make_events(&G.ev, R.chunk)) != hipSuccess) {
     free_graph(G);
@@ -538,14 +598,19 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
   // earlier launches on st may still read the descriptors, tables and
   // staging buffer replaced below
   BHX_CHECK(hipStreamSynchronize(st));
-  // plans and layouts
-  std::vector<int> px(n), py(n);
+  // plans and layouts; a batch holds instances of one dimension
+  const int dim = specs[0].dim;
+  std::vector<int> px(n), py(n), pz(n, 0);
   std::vector<Layout> lay(n);
   for (int i = 0; i < n; ++i) {
-    px[i] = hd->plans.get(specs[i].nx, specs[i].bcx);
-    py[i] = hd->plans.get(specs[i].ny, specs[i].bcy);
-    if (!make_layout(specs[i].nx, specs[i].ny, R.precision, hd->plans.plan(px[i]).m,
-                     hd->plans.plan(py[i]).m, R.sched.rows_cap, &lay[i]))
+    const InstSpec& S = specs[i];
+    if (S.dim != dim) return BHX_ERR_ARG;
+    px[i] = hd->plans.get(S.nx, S.bcx);
+    py[i] = hd->plans.get(S.ny, S.bcy);
+    if (dim == 3) pz[i] = hd->plans.get(S.nz, S.bcz);
+    const int mz = dim == 3 ? hd->plans.plan(pz[i]).m : 0;
+    if (!make_layout(S.nx, S.ny, dim == 3 ? S.nz : 1, R.precision, hd->plans.plan(px[i]).m,
+                     hd->plans.plan(py[i]).m, mz, R.sched.rows_cap, &lay[i]))
       return BHX_ERR_ARG;
   }
   BHX_CHECK(hd->plans.sync_device(st));
@@ -574,16 +639,19 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
     const Layout& L = lay[i];
     Inst& I = inst[i];
     std::memset(&I, 0, sizeof(I));
-    I.nx = S.nx; I.ny = S.ny; I.bcx = S.bcx; I.bcy = S.bcy;
-    I.planx = px[i]; I.plany = py[i];
-    I.G = L.G; I.Gc = L.Gc; I.tiles_x = L.tiles_x; I.tiles_y = L.tiles_y;
+    const int nz = dim == 3 ? S.nz : 1;
+    I.nx = S.nx; I.ny = S.ny; I.nz = nz; I.nrows = S.ny * nz;
+    I.bcx = S.bcx; I.bcy = S.bcy; I.bcz = dim == 3 ? S.bcz : 0;
+    I.planx = px[i]; I.plany = py[i]; I.planz = pz[i];
+    I.G = L.G; I.Gc = L.Gc; I.Gz = L.Gz;
+    I.tiles_x = L.tiles_x; I.tiles_y = L.tiles_y; I.tiles_z = L.tiles_z;
     for (int p = 0; p < kNumPass; ++p) I.n_items[p] = L.n_items[p];
-    I.maxit = R.maxit_user > 0 ? R.maxit_user : 50 * std::max(S.nx, S.ny);
+    I.maxit = R.maxit_user > 0 ? R.maxit_user : 50 * std::max(std::max(S.nx, S.ny), nz);
     I.flexible = R.flexible;
     I.warm = R.warm;
     I.phi = (decltype(I.phi))S.phi;
     I.F = (decltype(I.F))S.F;
-    const size_t Np = vec_stride(S.nx, S.ny);
+    const size_t Np = vec_stride(S.nx, S.ny * nz);
     char* b = ws + base[i];
     I.mask = (decltype(I.mask))(b + L.off_mask);
     double* v = (double*)(b + L.off_vec);
@@ -658,13 +726,15 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
   }
 
   Grids g;
+  g.dim = dim;
   g.s = std::max(1, std::min(Bh.n_items[kPassS], hd->num_cu * R.sched.occ_s));
   g.r = std::max(1, std::min(Bh.n_items[kPassR], hd->num_cu * R.sched.occ_r));
   g.c = std::max(1, std::min(Bh.n_items[kPassC], hd->num_cu * R.sched.occ_c));
+  g.z = dim == 3 ? std::max(1, std::min(Bh.n_items[kPassZ], hd->num_cu * R.sched.occ_c)) : 0;
   {
     // dynamic LDS: packed rows followed by the staged plan tables
     const int csize = R.precision == 0 ? 16 : 8;
-    int buf_r = 0, tab_r = 0, buf_c = 0, tab_c = 0;
+    int buf_r = 0, tab_r = 0, buf_c = 0, tab_c = 0, buf_z = 0, tab_z = 0;
     for (int i = 0; i < n; ++i) {
       const AxisPlan& PX = hd->plans.plan(px[i]);
       const AxisPlan& PY = hd->plans.plan(py[i]);
@@ -672,12 +742,19 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
       tab_r = std::max(tab_r, table_slots(PX.n, PX.m));
       buf_c = std::max(buf_c, (lay[i].Gc / 2) * row_slots(PY.m));
       tab_c = std::max(tab_c, table_slots(PY.n, PY.m));
+      if (dim == 3) {
+        const AxisPlan& PZ = hd->plans.plan(pz[i]);
+        buf_z = std::max(buf_z, (lay[i].Gz / 2) * row_slots(PZ.m));
+        tab_z = std::max(tab_z, table_slots(PZ.n, PZ.m));
+      }
     }
     g.tw_r = buf_r;
     g.lds_r = (buf_r + tab_r) * csize;
     g.tw_c = buf_c;
     g.lds_c = (buf_c + tab_c) * csize;
-    if (g.lds_r > kLdsDynMax || g.lds_c > kLdsDynMax) return BHX_ERR_ARG;
+    g.tw_z = buf_z;
+    g.lds_z = (buf_z + tab_z) * csize;
+    if (g.lds_r > kLdsDynMax || g.lds_c > kLdsDynMax || g.lds_z > kLdsDynMax) return BHX_ERR_ARG;
   }
   *gout = g;
   return BHX_OK;
@@ -694,9 +771,9 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
   }
   Ctl* ctl_d = (Ctl*)hd->ws;
   // setup: mask, right-hand side, counts
-  BHX_CHECK(launch_setup(hd->batch_d, g.s, st));
+  BHX_CHECK(launch_setup(hd->batch_d, g.dim, g.s, st));
   BHX_CHECK(launch_setup_rows(hd->batch_d, g.r, st));
-  BHX_CHECK(launch_stencil(hd->batch_d, kModeRhs, g.s, 0, st));
+  BHX_CHECK(launch_stencil(hd->batch_d, g.dim, kModeRhs, g.s, 0, st));
   BHX_CHECK(launch_finalize(hd->batch_d, n, kFinSetupH, st));
   Ctl* ch = hd->ctl_h;
   BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -704,11 +781,14 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
   std::vector<int> status(n, BHX_OK), preset(n, 0), zero_flag(n, 0);
   int active = 0, any_zero = 0;
   for (int i = 0; i < n; ++i) {
-    const double N = (double)specs[i].nx * specs[i].ny;
+    const InstSpec& S = specs[i];
+    const double N = (double)S.nx * S.ny * (S.dim == 3 ? S.nz : 1);
+    const bool dirichlet = S.bcx == kDirichlet || S.bcy == kDirichlet ||
+                           (S.dim == 3 && S.bcz == kDirichlet);
     const double nu = ch[i].n_unknown;
     if (nu == 0) {
       preset[i] = 1;
-    } else if (nu == N && specs[i].bcx != kDirichlet && specs[i].bcy != kDirichlet) {
+    } else if (nu == N && !dirichlet) {
       // nothing known and only Neumann/periodic axes: u is fixed up to a
       // constant (with a Dirichlet axis, b = 0 and the extension is 0)
       preset[i] = 1;
@@ -729,7 +809,7 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
     if (any_zero) {
       const Upload u{hd->flag_d, zero_flag.data(), n * sizeof(int)};
       BHX_CHECK(upload_ordered(hd, st, &u, 1));
-      BHX_CHECK(launch_zero_unknown(hd->batch_d, hd->flag_d, g.s, st));
+      BHX_CHECK(launch_zero_unknown(hd->batch_d, g.dim, hd->flag_d, g.s, st));
     }
     BHX_CHECK(hipStreamSynchronize(st));
   }
@@ -738,7 +818,7 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
   // here with F untouched
   std::vector<int> warm_done(n, 0);
   if (R.warm && active > 0) {
-    BHX_CHECK(launch_stencil(hd->batch_d, kModeWarm, g.s, 0, st));
+    BHX_CHECK(launch_stencil(hd->batch_d, g.dim, kModeWarm, g.s, 0, st));
     BHX_CHECK(launch_finalize(hd->batch_d, n, kFinWarmH, st));
     BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
     BHX_CHECK(hipStreamSynchronize(st));
@@ -789,7 +869,7 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
         if (ch[i].done == kRunning) all_done = false;
       if (!all_done) continue;
       // true residual of finished instances; restart those that miss the target
-      BHX_CHECK(launch_resid(hd->batch_d, g.s, st));
+      BHX_CHECK(launch_resid(hd->batch_d, g.dim, g.s, st));
       BHX_CHECK(launch_finalize(hd->batch_d, n, kFinResidH, st));
       BHX_CHECK(launch_restart(hd->batch_d, n, st));
       BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -843,30 +923,37 @@ int warm_start_outcome(const Ctl& c) {
 }
 
 int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, double* out, int nx,
-                int ny, int bcx, int bcy, int precision, hipStream_t stream) {
+                int ny, int nz, int bcx, int bcy, int bcz, int precision, hipStream_t stream) {
   bhx_opts o;
   bhx_default_opts(&o);
   o.precision = precision;
   const Resolved R = resolve_opts(&o);
   hipStream_t st = stream ? stream : hd->own_stream;
   InstSpec s{phi, out, nx, ny, bcx, bcy, 0.5};
+  const bool d3 = nz > 1;
+  if (d3) {
+    s.nz = nz;
+    s.bcz = bcz;
+    s.dim = 3;
+  }
   Grids g;
   int rc = prepare_batch(hd, 1, &s, R, st, &g);
   if (rc != BHX_OK) return rc;
   Layout L;
-  make_layout(nx, ny, precision, core_length(fft_length(nx, bcx)),
-              core_length(fft_length(ny, bcy)), R.sched.rows_cap, &L);
-  const size_t N = (size_t)nx * ny;
-  const size_t Np = vec_stride(nx, ny);
+  make_layout(nx, ny, nz, precision, core_length(fft_length(nx, bcx)),
+              core_length(fft_length(ny, bcy)), d3 ? core_length(fft_length(nz, bcz)) : 0,
+              R.sched.rows_cap, &L);
+  const size_t N = (size_t)nx * ny * nz;
+  const size_t Np = vec_stride(nx, ny * nz);
   double* v = (double*)((char*)hd->ws + align_up(sizeof(Ctl)) + L.off_vec);
   double* r = v;
   double* q = v + 3 * Np;
   double* z = v + 4 * Np;
-  BHX_CHECK(launch_setup(hd->batch_d, g.s, st));
+  BHX_CHECK(launch_setup(hd->batch_d, g.dim, g.s, st));
   BHX_CHECK(launch_setup_rows(hd->batch_d, g.r, st));
   if (op == 0) {
     BHX_CHECK(hipMemcpyAsync(z, in, N * sizeof(double), hipMemcpyDeviceToDevice, st));
-    BHX_CHECK(launch_stencil(hd->batch_d, kModeApply, g.s, 0, st));
+    BHX_CHECK(launch_stencil(hd->batch_d, g.dim, kModeApply, g.s, 0, st));
     BHX_CHECK(hipMemcpyAsync(out, q, N * sizeof(double), hipMemcpyDeviceToDevice, st));
   } else {
     BHX_CHECK(hipMemcpyAsync(r, in, N * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -889,7 +976,8 @@ static unsigned long long batch_signature(int n, const InstSpec* specs, const Re
   for (int i = 0; i < n; ++i) {
     mix((unsigned long long)specs[i].nx);
     mix((unsigned long long)specs[i].ny);
-    mix((unsigned long long)(specs[i].bcx * 16 + specs[i].bcy));
+    mix((unsigned long long)(specs[i].dim == 3 ? specs[i].nz : 1));
+    mix((unsigned long long)(specs[i].bcx * 16 + specs[i].bcy + 256 * specs[i].bcz));
   }
   return h;
 }
@@ -939,6 +1027,10 @@ static int autotune_schedule(bhx_handle* hd, int n, const InstSpec* specs, const
   return BHX_OK;
 }
 
+static size_t field_bytes(const InstSpec& S) {
+  return (size_t)S.nx * S.ny * (S.dim == 3 ? S.nz : 1) * sizeof(double);
+}
+
 // The autotuner with the fields' contents kept: F (the warm start) is copied
 // to a temporary device buffer before the trial solves and back after them.
 static int autotune_keeping_fields(bhx_handle* hd, int n, const InstSpec* specs,
@@ -949,20 +1041,18 @@ static int autotune_keeping_fields(bhx_handle* hd, int n, const InstSpec* specs,
   std::vector<size_t> off(n);
   for (int i = 0; i < n; ++i) {
     off[i] = total;
-    total += align_up((size_t)specs[i].nx * specs[i].ny * sizeof(double));
+    total += align_up(field_bytes(specs[i]));
   }
   char* keep = nullptr;
   BHX_CHECK(hipMalloc((void**)&keep, total));
   int rc = BHX_OK;
   hipError_t e = hipSuccess;
   for (int i = 0; i < n && e == hipSuccess; ++i)
-    e = hipMemcpyAsync(keep + off[i], specs[i].F,
-                       (size_t)specs[i].nx * specs[i].ny * sizeof(double),
+    e = hipMemcpyAsync(keep + off[i], specs[i].F, field_bytes(specs[i]),
                        hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) rc = autotune_schedule(hd, n, specs, R, stream, best);
   for (int i = 0; i < n && e == hipSuccess; ++i)
-    e = hipMemcpyAsync(specs[i].F, keep + off[i],
-                       (size_t)specs[i].nx * specs[i].ny * sizeof(double),
+    e = hipMemcpyAsync(specs[i].F, keep + off[i], field_bytes(specs[i]),
                        hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   const hipError_t ef = hipFree(keep);

@@ -49,17 +49,24 @@ struct InstSpec {
   double* F;
   int nx, ny, bcx, bcy;
   double tol;
+  int nz = 1, bcz = 0;       // three dimensions: nz >= 4 and dim = 3
+  int dim = 2;
 };
 
 // Per-instance layout decisions.
 struct Layout {
-  int G, Gc, tiles_x, tiles_y;
+  int G, Gc, Gz, tiles_x, tiles_y, tiles_z;
   int n_items[kNumPass];
   size_t off_mask, off_vec, off_t, off_part, off_ctl, bytes;
 };
 
 // Choose row-group sizes and item counts; false if the size is unsupported.
-bool make_layout(int nx, int ny, int prec, int mx, int my, int rows_cap, Layout* L);
+// mz = 0: two dimensions (nz = 1); otherwise the z core length.
+bool make_layout(int nx, int ny, int nz, int prec, int mx, int my, int mz, int rows_cap,
+                 Layout* L);
+inline bool make_layout(int nx, int ny, int prec, int mx, int my, int rows_cap, Layout* L) {
+  return make_layout(nx, ny, 1, prec, mx, my, 0, rows_cap, L);
+}
 // Core FFT length of a transform of length n (power of two, or Bluestein).
 int core_length(int n);
 // Spacing of the float64 workspace vectors (elements), 256-byte aligned.
@@ -86,7 +93,9 @@ Resolved resolve_opts(const bhx_opts* o);
 struct Grids {
   int s, r, c;             // persistent grid sizes of the stencil, row and column passes
   int lds_r, tw_r;         // row passes: dynamic LDS bytes, twiddle offset (complex elements)
-  int lds_c, tw_c;         // column pass
+  int lds_c, tw_c;         // column (y) passes
+  int dim = 2;             // 3: column passes along y, z, y
+  int z = 0, lds_z = 0, tw_z = 0;   // z pass (three dimensions)
 };
 
 struct Graph {
@@ -96,6 +105,7 @@ struct Graph {
   int count = 0;
   int prec = -1, chunk = 0, precond = -1, gs = 0, gr = 0, gc = 0, profile = 0;
   int lds_r = 0, tw_r = 0, lds_c = 0, tw_c = 0;
+  int dim = 2, gz = 0, lds_z = 0, tw_z = 0;
   std::vector<hipEvent_t> ev;   // [pass][iteration][start, end] when profiling
 };
 
@@ -129,11 +139,15 @@ namespace bhx {
 // Validate one instance's arguments (host only).  Returns BHX_OK or BHX_ERR_ARG.
 int validate(const double* phi, const double* F, int nx, int ny, double h, int bc, double tol,
              const Resolved& R);
+// Three dimensions: bc packs three rules (x, y, z nibbles).
+int validate3(const double* phi, const double* F, int nx, int ny, int nz, double h, int bc,
+              double tol, const Resolved& R);
 // Solve `n` instances on `hd`; stats[n] filled (may be null).
 // With R.warm the values of F at the unknown nodes are the first iterate.
 int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
                 hipStream_t stream, bhx_stats* stats);
 size_t instance_bytes(int nx, int ny, int bcx, int bcy, int prec);
+size_t instance_bytes3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int prec);
 const char* last_error();
 void set_last_error(const char* what, int line, hipError_t e);
 int row_slots(int m);
@@ -141,8 +155,10 @@ int table_slots(int n, int m);
 hipError_t launch_precond(const Batch* B, const Resolved& R, const Grids& g, hipStream_t st);
 hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved& R,
                      const Grids& g, hipStream_t st, Graph** used);
+// One application of the masked operator (op 0) or the preconditioner (op 1)
+// to `in`; nz = 1 in two dimensions.
 int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, double* out, int nx,
-                int ny, int bcx, int bcy, int precision, hipStream_t stream);
+                int ny, int nz, int bcx, int bcy, int bcz, int precision, hipStream_t stream);
 int init_handle(bhx_handle* hd, int device);
 // One host array to copy to device memory.
 struct Upload {

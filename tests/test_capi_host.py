@@ -110,3 +110,28 @@ def test_workspace_bytes():
 def test_engine_rejects_without_device():
     e = ctypes.c_void_p()
     assert bhx._lib.bhx_engine_create(ctypes.byref(e), -1, 1 << 30, 4, None) == bhx.ERR_ARG
+
+
+def test_three_dimensional_arguments():
+    """bhx_extend3d / bhx_workspace_bytes3d / bhx_debug_apply3d reject bad
+    arguments on the host."""
+    n3 = 64 ** 3
+    w = bhx.workspace_bytes3d(64, 64, 64, bhx.BC3(1, 1, 1))
+    # mask + five float64 vectors + transform buffer (+ small tails)
+    assert 49 * n3 <= w < 49 * n3 + 2 * 1024 * 1024
+    assert bhx.workspace_bytes3d(64, 64, 3, 0) == 0                  # nz < 4
+    assert bhx.workspace_bytes3d(64, 64, 64, 0x300) == 0             # no such z rule
+    assert bhx.workspace_bytes3d(64, 64, 64, 0x1000) == 0            # bits beyond z
+    assert bhx.workspace_bytes3d(1024, 1024, 2048, 0) == 0           # 2^31 nodes
+    assert bhx.workspace_bytes3d(100, 75, 33, bhx.BC3(2, 1, 0)) > 0  # Bluestein, Dirichlet
+    assert bhx.workspace_bytes3d(64, 64, 1100, bhx.BC3(0, 0, 2)) == 0   # z core too long
+    s, _ = bhx.extend3d(None, FAKE, FAKE, 8, 8, 8)
+    assert s == bhx.ERR_ARG
+    for args in [(8, 8, 3, 0), (8, 8, 8, 0x300), (3, 8, 8, 0), (8, 8, 8, -1)]:
+        nx, ny, nz, bc = args
+        s, _ = bhx.extend3d(FAKE, FAKE, FAKE, nx, ny, nz, bc=bc)
+        assert s == bhx.ERR_ARG, args
+    s, _ = bhx.extend3d(FAKE, FAKE, FAKE, 8, 8, 8, tol=2.0)
+    assert s == bhx.ERR_ARG
+    assert bhx.debug_apply3d(FAKE, 2, FAKE, FAKE, FAKE, 8, 8, 8) == bhx.ERR_ARG
+    assert bhx.debug_apply3d(FAKE, 0, FAKE, FAKE, FAKE, 8, 8, 2) == bhx.ERR_ARG
