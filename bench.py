@@ -295,6 +295,74 @@ def bench_serve(args, log):
     return out
 
 
+def bench_time_step(p, phi, F, handle, stream, bhx, log, reps=5):
+    """A level-set time step: the known values move by a smooth 1 % of their
+    range; the new extension is solved from zero and from the previous
+    extension (warm start), same tolerance."""
+    import numpy as np
+    import torch
+    o = bhx.default_opts()
+    s, st = bhx.extend_ex(handle, phi, F, bc=p.bc, h=p.h, tol=p.tol, opts=o, stream=stream)
+    torch.cuda.synchronize()
+    prev = F.cpu().numpy()
+    jj, ii = np.meshgrid(np.arange(p.ny) / p.ny, np.arange(p.nx) / p.nx, indexing="ij")
+    F1 = p.F + 0.01 * np.abs(p.F).max() * np.sin(2 * np.pi * ii) * np.cos(np.pi * jj)
+    known = p.phi < 0
+    res = {}
+    for name, start, warm in (("cold", F1, 0), ("warm", np.where(known, F1, prev), 1)):
+        src = torch.from_numpy(np.ascontiguousarray(start)).to(F.device)
+        ow = bhx.default_opts(warm_start=warm)
+        times, its = [], []
+        for _ in range(reps + 1):
+            F.copy_(src)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s, st = bhx.extend_ex(handle, phi, F, bc=p.bc, h=p.h, tol=p.tol, opts=ow,
+                                  stream=stream)
+            times.append(time.perf_counter() - t0)
+            its.append(st.iterations)
+            if s != bhx.OK:
+                raise SystemExit(f"time-step solve failed: {bhx.status_string(s)}")
+        res[name] = {"iterations": its[-1], "ms": round(1e3 * statistics.median(times[1:]), 3),
+                     "true_rel_residual": st.true_rel_residual}
+    F.copy_(torch.from_numpy(np.ascontiguousarray(p.F)).to(F.device))   # the workload's F again
+    torch.cuda.synchronize()
+    log(f"time step: cold {res['cold']}, warm {res['warm']}")
+    res["speedup"] = round(res["cold"]["ms"] / res["warm"]["ms"], 3)
+    res["change"] = "known values + 1% of range x sin(2 pi x) cos(pi y); warm = previous extension"
+    return res
+
+
+def bench_example2(handle, bhx, log, n=256, reps=3):
+    """Example 2 of the paper at its largest grid (256^3, periodic, tol 1e-6):
+    one whole solve per step, inputs resident in HBM."""
+    import torch
+    from paper_1704_08897_amd import workloads as W
+    p = W.peanut3d_problem(n)
+    dev = torch.device("cuda:0")
+    phi = torch.from_numpy(p.phi).to(dev)
+    F = torch.from_numpy(p.F.copy()).to(dev)
+    o = bhx.default_opts()
+    times = []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, st = bhx.extend3d(handle, phi, F, h=p.h, bc=p.bc, tol=p.tol, opts=o)
+        times.append(time.perf_counter() - t0)
+        if s != bhx.OK:
+            raise SystemExit(f"3-D solve failed: {bhx.status_string(s)} {st.as_dict()}")
+    sec = statistics.median(times[1:])
+    log(f"example 2 {n}^3: {st.iterations} iterations, {sec:.3f} s")
+    res = {"grid": f"{n}^3", "bc": "periodic^3", "tol": p.tol, "iterations": st.iterations,
+           "seconds": round(sec, 4), "solves_per_s": round(1.0 / sec, 3),
+           "ms_per_iteration": round(1e3 * sec / max(1, st.iterations), 4),
+           "true_rel_residual": st.true_rel_residual,
+           "paper": "Table 3: 276 iterations, 733.9 s (MATLAB, CPU)"}
+    del phi, F
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,6 +372,8 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cg", action="store_true", help="skip the unpreconditioned CG comparison")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the warm-start time step and the three-dimensional Example 2")
     ap.add_argument("--requests", type=int, default=300, help="serve: requests in the stream")
     ap.add_argument("--pool", type=int, default=24, help="serve: distinct materialised inputs")
     ap.add_argument("--slots", type=int, default=64, help="serve: engine slots")
@@ -323,6 +393,12 @@ def main():
 
     if args.workload == "serve":
         print(json.dumps(bench_serve(args, log)), flush=True)
+        return
+    if args.workload == "example2_256":
+        handle = bhx.Handle(0)
+        res = bench_example2(handle, bhx, log, reps=max(1, args.steps))
+        handle.close()
+        print(json.dumps({"workload": "example2_256", **res}), flush=True)
         return
     if args.workload == "batch256":
         handle = bhx.Handle(0)
@@ -459,6 +535,13 @@ def main():
                                       "solves_per_s": round(1.0 / tc, 4),
                                       "true_rel_residual": stc.true_rel_residual}
         log(f"unpreconditioned CG: {stc.iterations} iterations, {tc:.3f} s")
+        solve()                                  # leave F holding the PCG result
+        torch.cuda.synchronize()
+        got = F.cpu().numpy()
+
+    if not args.no_extra and args.workload == "star_inward_1024":
+        out["warm_start_time_step"] = bench_time_step(p, phi, F, handle, stream, bhx, log)
+        out["example2_3d"] = bench_example2(handle, bhx, log)
         solve()                                  # leave F holding the PCG result
         torch.cuda.synchronize()
         got = F.cpu().numpy()

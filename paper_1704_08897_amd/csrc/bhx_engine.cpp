@@ -204,7 +204,9 @@ Grids engine_grids(bhx_engine* E, const std::vector<Req*>& reqs) {
   g.c = cu * 2;
   const int csize = E->R.precision == 0 ? 16 : 8;
   int buf_r = 0, tab_r = 0, buf_c = 0, tab_c = 0;
+  g.count = (int)reqs.size();
   for (Req* q : reqs) {
+    g.reduce |= q->inst.reduce;
     const AxisPlan& PX = E->hd->plans.plan(q->inst.planx);
     const AxisPlan& PY = E->hd->plans.plan(q->inst.plany);
     buf_r = std::max(buf_r, (q->inst.G / 2) * row_slots(PX.m));
@@ -251,6 +253,7 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
     I.maxit = E->R.maxit_user > 0 ? E->R.maxit_user : 50 * std::max(S.nx, S.ny);
     I.flexible = E->R.flexible;
     I.warm = E->R.warm;
+    I.reduce = L.n_items[kPassS] + 3 * L.n_items[kPassR] > kReduceMin;
     I.phi = (decltype(I.phi))S.phi;
     I.F = (decltype(I.F))S.F;
     char* b = E->arena_base + q->off;

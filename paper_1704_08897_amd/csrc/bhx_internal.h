@@ -35,6 +35,9 @@ constexpr int kLdsDynMax = 152 * 1024; // dynamic LDS cap of a transform launch
 constexpr int kMaxPairs = 8;           // (k, n-k) pairs held in registers per thread
 constexpr int kMaxGc = 16;             // columns per column-pass item (2 x rows cap)
 constexpr int kTargetItems = 512;      // row/column items one instance should supply
+// Partial-sum arrays longer than this (tiles + 3 x row groups) are reduced
+// once per pass by a one-block launch instead of in every consumer block.
+constexpr int kReduceMin = 4096;
 
 enum Bc { kNeumann = 0, kPeriodic = 1, kDirichlet = 2 };
 
@@ -108,6 +111,9 @@ struct Ctl {
   double n_unknown;
   int accurate;
   int max_restarts;
+  // scalars of an instance with Inst::reduce, summed by k_reduce from the
+  // partials of the pass before: p.q, ||r||^2, r.z and r.z_old by parity
+  double red_pq, red_rr, red_rz[2], red_rzo[2];
   double pad[2];
 };
 
@@ -124,6 +130,7 @@ struct Inst {
   int maxit;
   int flexible;
   int warm;             // 1: F's values at U on input are the first iterate x0
+  int reduce;           // 1: scalars come from Ctl::red_* (k_reduce), not the partials
   BHX_GLOBAL const double* phi;
   BHX_GLOBAL double* F;
   BHX_GLOBAL uint8_t* mask;   // 1 = unknown, 0 = known
@@ -197,6 +204,10 @@ hipError_t launch_setup_rows(const Batch* B, int grid, hipStream_t st);
 hipError_t launch_identity(const Batch* B, int grid, int lpar, hipStream_t st,
                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_finalize(const Batch* B, int count, int mode, hipStream_t st);
+// k_reduce after the pass that wrote the partials: p.q (stencil), ||r||^2
+// (row forward) or r.z (row inverse / identity, launched with parity lpar).
+enum RedWhich { kRedPQ = 0, kRedRR = 1, kRedRZ = 2 };
+hipError_t launch_reduce(const Batch* B, int count, int which, int lpar, hipStream_t st);
 hipError_t launch_restart(const Batch* B, int count, hipStream_t st);
 hipError_t launch_bump(const Batch* B, int count, hipStream_t st);
 hipError_t launch_zero_unknown(const Batch* B, int dim, const int* flag, int grid,

@@ -751,9 +751,19 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
     BHX_GLOBAL double* pnew = par ? I.p[0] : I.p[1];
     BHX_GLOBAL const double* arrs[4] = {I.part + PL.rz(par), I.part + PL.rr(),
                                         I.part + PL.rz(par ^ 1), I.part + PL.rzo(par)};
-    const int lens[4] = {PL.nR, PL.nR, PL.nR, PL.nR};
+    // an instance with reduced scalars reads them from the control block;
+    // its partial loads shrink to one element (no branch before the loads)
+    const int nRs = I.reduce ? 1 : PL.nR;
+    const int lens[4] = {nRs, nRs, nRs, nRs};
     Partials<4> PS;
     if (MODE == kModeIter) sums_issue<4>(arrs, lens, PS);
+    double rsc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (MODE == kModeIter) {
+      rsc[0] = ctl->red_rz[par];
+      rsc[1] = ctl->red_rr;
+      rsc[2] = ctl->red_rz[par ^ 1];
+      rsc[3] = ctl->red_rzo[par];
+    }
     const int ld_done = ctl->done;
     const int c_iter = ctl->iter, c_rit = ctl->restart_iter;
     const double c_thresh = ctl->thresh;
@@ -772,9 +782,10 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
     // 2. the halo tile (z and p_old, or F, and the mask) and the output masks
     const int k = c_iter;
     const bool first = (k == c_rit);       // beta = 0: p = z
-    const int ns[4] = {MODE == kModeIter ? PL.nR : 0, (MODE == kModeIter && !first) ? PL.nR : 0,
-                       (MODE == kModeIter && !first) ? PL.nR : 0,
-                       (MODE == kModeIter && !first && I.flexible) ? PL.nR : 0};
+    const int nRn = I.reduce ? 0 : PL.nR;
+    const int ns[4] = {MODE == kModeIter ? nRn : 0, (MODE == kModeIter && !first) ? nRn : 0,
+                       (MODE == kModeIter && !first) ? nRn : 0,
+                       (MODE == kModeIter && !first && I.flexible) ? nRn : 0};
     int i0, j0, k0;
     G::origin(I, tile, i0, j0, k0);
     int oo[kPL];
@@ -829,6 +840,10 @@ __global__ void __launch_bounds__(kThreads) k_stencil(const Batch* __restrict__ 
     if (MODE == kModeIter) {
       double sums[4];
       sums_finish<4>(arrs, ns, PS, sums, red);
+      if (I.reduce) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sums[k] = rsc[k];
+      }
       const double rz = sums[0];
       if (!first) {
         const double rr = sums[1];
@@ -1068,10 +1083,11 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
     //    per thread (rows j0 .. j0+G-1 are contiguous); `done` and the counts
     //    do not change during the pass
     BHX_GLOBAL const double* arrs[2] = {I.part + PL.rz(lpar), I.part + PL.pq()};
-    const int lens[2] = {PL.nR, PL.nS};
-    const int ns[2] = {update ? PL.nR : 0, update ? PL.nS : 0};
+    const int lens[2] = {I.reduce ? 1 : PL.nR, I.reduce ? 1 : PL.nS};
+    const int ns[2] = {update && !I.reduce ? PL.nR : 0, update && !I.reduce ? PL.nS : 0};
     Partials<2> PS;
     sums_issue<2>(arrs, lens, PS);             // unconditional: no branch before the loads
+    const double rsc[2] = {ctl->red_rz[lpar], ctl->red_pq};
     int m0[kPre];
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
@@ -1108,7 +1124,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
     if (update) {
       double sums[2];
       sums_finish<2>(arrs, ns, PS, sums, red);
-      alpha = sums[0] / sums[1];
+      alpha = I.reduce ? rsc[0] / rsc[1] : sums[0] / sums[1];
     }
     const int rows = G >> 1;
     const int st = X.stride();
@@ -1712,6 +1728,36 @@ __global__ void k_bump(const Batch* __restrict__ Bp) {
 }
 
 // Instances whose true residual misses the target restart from it.
+// Scalars of instances with long partial-sum arrays (Inst::reduce): one
+// block per instance sums the partials of the pass just run in a fixed order
+// into the control block, which the next pass reads instead of reducing the
+// partials again in each of its blocks.
+__global__ void __launch_bounds__(kThreads) k_reduce(const Batch* __restrict__ Bp, int which,
+                                                     int lpar) {
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
+  __shared__ double red[4];
+  const Inst I = B.inst[blockIdx.x];
+  if (!I.reduce) return;
+  BHX_GLOBAL Ctl* ctl = I.ctl;
+  if (ctl->done) return;             // no writer of `done` runs during this launch
+  const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
+  if (which == kRedPQ) {
+    const double v = block_sum_array(I.part + PL.pq(), PL.nS, red);
+    if (threadIdx.x == 0) ctl->red_pq = v;
+  } else if (which == kRedRR) {
+    const double v = block_sum_array(I.part + PL.rr(), PL.nR, red);
+    if (threadIdx.x == 0) ctl->red_rr = v;
+  } else {
+    const int par = lpar ^ 1;        // the parity the row-inverse pass wrote
+    const double v = block_sum_array(I.part + PL.rz(par), PL.nR, red);
+    const double w = I.flexible ? block_sum_array(I.part + PL.rzo(par), PL.nR, red) : 0.0;
+    if (threadIdx.x == 0) {
+      ctl->red_rz[par] = v;
+      ctl->red_rzo[par] = w;
+    }
+  }
+}
+
 __global__ void k_restart(const Batch* __restrict__ Bp) {
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   const int inst = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1849,6 +1895,10 @@ hipError_t launch_identity(const Batch* B, int grid, int lpar, hipStream_t st, h
 }
 hipError_t launch_finalize(const Batch* B, int count, int mode, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(count), dim3(kThreads), 0, st, B, mode);
+  return hipGetLastError();
+}
+hipError_t launch_reduce(const Batch* B, int count, int which, int lpar, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(count), dim3(kThreads), 0, st, B, which, lpar);
   return hipGetLastError();
 }
 hipError_t launch_restart(const Batch* B, int count, hipStream_t st) {

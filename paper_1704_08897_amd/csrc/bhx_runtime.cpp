@@ -449,14 +449,24 @@ hipError_t launch_columns(const Batch* B, const Resolved& R, const Grids& g, int
   return hipSuccess;
 }
 
+// k_reduce after a pass, when some instance of the batch reduces its scalars once.
+static hipError_t maybe_reduce(const Batch* B, const Grids& g, int which, int lpar,
+                               hipStream_t st) {
+  return g.reduce ? launch_reduce(B, g.count, which, lpar, st) : hipSuccess;
+}
+
 hipError_t launch_precond(const Batch* B, const Resolved& R, const Grids& g, hipStream_t st) {
   hipError_t e;
   // parity 1: the r.z partials it writes are the ones the first iteration
   // (parity 0) reads
-  if (!R.precond) return launch_identity(B, g.r, 1, st);
+  if (!R.precond) {
+    if ((e = launch_identity(B, g.r, 1, st)) != hipSuccess) return e;
+    return maybe_reduce(B, g, kRedRZ, 1, st);
+  }
   if ((e = launch_rowfwd(B, R.precision, 0, g.r, g.lds_r, g.tw_r, 1, st)) != hipSuccess) return e;
   if ((e = launch_columns(B, R, g, 0, st, nullptr, nullptr)) != hipSuccess) return e;
-  return launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, 1, st);
+  if ((e = launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, 1, st)) != hipSuccess) return e;
+  return maybe_reduce(B, g, kRedRZ, 1, st);
 }
 
 namespace {
@@ -480,18 +490,22 @@ hipError_t launch_iterations(const Batch* B, int n_inst, const Resolved& R, cons
   for (int c = 0; c < count; ++c) {
     const int par = c & 1;               // count is even: every chunk starts at 0
     BHX_TRY(launch_stencil(B, g.dim, kModeIter, g.s, par, st, e0(0, c), e1(0, c)));
+    BHX_TRY(maybe_reduce(B, g, kRedPQ, par, st));
     if (R.precond) {
       BHX_TRY(launch_rowfwd(B, R.precision, 1, g.r, g.lds_r, g.tw_r, par, st, e0(1, c),
                             e1(1, c)));
+      BHX_TRY(maybe_reduce(B, g, kRedRR, par, st));
       BHX_TRY(launch_columns(B, R, g, 1, st, e0(2, c), e1(2, c)));
       BHX_TRY(launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, par, st, e0(3, c), e1(3, c)));
     } else {
       // plain CG: update-only row pass, iteration count, z = r
       BHX_TRY(launch_rowfwd(B, R.precision, 2, g.r, g.lds_r, g.tw_r, par, st, e0(1, c),
                             e1(1, c)));
+      BHX_TRY(maybe_reduce(B, g, kRedRR, par, st));
       BHX_TRY(launch_bump(B, n_inst, st));
       BHX_TRY(launch_identity(B, g.r, par, st, e0(3, c), e1(3, c)));
     }
+    BHX_TRY(maybe_reduce(B, g, kRedRZ, par, st));
   }
 #undef BHX_TRY
   return hipSuccess;
@@ -522,7 +536,8 @@ hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved&
   // launched directly with events around the selected passes.
   const bool graph = use_graphs() && R.profile == 0;
   for (auto& gr : hd->graphs) {
-    if (gr.stream == st && gr.batch == B && gr.count == (R.precond ? 0 : n_inst) &&
+    if (gr.stream == st && gr.batch == B &&
+        gr.count == ((R.precond && !g.reduce) ? 0 : n_inst) && gr.reduce == g.reduce &&
         gr.prec == R.precision && gr.chunk == R.chunk &&
         gr.precond == R.precond && gr.gs == g.s && gr.gr == g.r && gr.gc == g.c &&
         gr.lds_r == g.lds_r && gr.tw_r == g.tw_r && gr.lds_c == g.lds_c && gr.tw_c == g.tw_c &&
@@ -535,7 +550,8 @@ hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved&
   }
   Graph G;
   G.stream = st; G.prec = R.precision; G.chunk = R.chunk; G.precond = R.precond;
-  G.batch = B; G.count = R.precond ? 0 : n_inst;
+  G.batch = B; G.count = (R.precond && !g.reduce) ? 0 : n_inst;
+  G.reduce = g.reduce;
   G.gs = g.s; G.gr = g.r; G.gc = g.c; G.profile = R.profile;
   G.lds_r = g.lds_r; G.tw_r = g.tw_r; G.lds_c = g.lds_c; G.tw_c = g.tw_c;
   G.dim = g.dim; G.gz = g.z; G.lds_z = g.lds_z; G.tw_z = g.tw_z;
@@ -649,6 +665,7 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
     I.maxit = R.maxit_user > 0 ? R.maxit_user : 50 * std::max(std::max(S.nx, S.ny), nz);
     I.flexible = R.flexible;
     I.warm = R.warm;
+    I.reduce = L.n_items[kPassS] + 3 * L.n_items[kPassR] > kReduceMin;
     I.phi = (decltype(I.phi))S.phi;
     I.F = (decltype(I.F))S.F;
     const size_t Np = vec_stride(S.nx, S.ny * nz);
@@ -727,6 +744,8 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
 
   Grids g;
   g.dim = dim;
+  g.count = n;
+  for (int i = 0; i < n; ++i) g.reduce |= inst[i].reduce;
   g.s = std::max(1, std::min(Bh.n_items[kPassS], hd->num_cu * R.sched.occ_s));
   g.r = std::max(1, std::min(Bh.n_items[kPassR], hd->num_cu * R.sched.occ_r));
   g.c = std::max(1, std::min(Bh.n_items[kPassC], hd->num_cu * R.sched.occ_c));

@@ -96,6 +96,8 @@ struct Grids {
   int lds_c, tw_c;         // column (y) passes
   int dim = 2;             // 3: column passes along y, z, y
   int z = 0, lds_z = 0, tw_z = 0;   // z pass (three dimensions)
+  int count = 0;           // instances of the batch
+  int reduce = 0;          // 1: some instance has Inst::reduce (k_reduce launches)
 };
 
 struct Graph {
@@ -105,7 +107,7 @@ struct Graph {
   int count = 0;
   int prec = -1, chunk = 0, precond = -1, gs = 0, gr = 0, gc = 0, profile = 0;
   int lds_r = 0, tw_r = 0, lds_c = 0, tw_c = 0;
-  int dim = 2, gz = 0, lds_z = 0, tw_z = 0;
+  int dim = 2, gz = 0, lds_z = 0, tw_z = 0, reduce = 0;
   std::vector<hipEvent_t> ev;   // [pass][iteration][start, end] when profiling
 };
 
