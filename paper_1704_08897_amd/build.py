@@ -12,6 +12,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep packed FP32 instructions out of the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # kernel arguments arrive preloaded in SGPRs (gfx950): the batch pointer
+    # is there at wave start, one round trip less before the first load
+    "-mllvm", "-amdgpu-kernarg-preload-count=8",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

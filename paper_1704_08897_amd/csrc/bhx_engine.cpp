@@ -210,9 +210,9 @@ Grids engine_grids(bhx_engine* E, const std::vector<Req*>& reqs) {
     const AxisPlan& PX = E->hd->plans.plan(q->inst.planx);
     const AxisPlan& PY = E->hd->plans.plan(q->inst.plany);
     buf_r = std::max(buf_r, (q->inst.G / 2) * row_slots(PX.m));
-    tab_r = std::max(tab_r, table_slots(PX.n, PX.m));
+    tab_r = std::max(tab_r, table_slots(PX.n, PX.m, PX.bc, false));
     buf_c = std::max(buf_c, (q->inst.Gc / 2) * row_slots(PY.m));
-    tab_c = std::max(tab_c, table_slots(PY.n, PY.m));
+    tab_c = std::max(tab_c, table_slots(PY.n, PY.m, PY.bc, true));
   }
   // round the LDS up to 16 KiB steps so graphs are reused across batches
   auto up = [](int b) { return (b + 16383) / 16384 * 16384; };

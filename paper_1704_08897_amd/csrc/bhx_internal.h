@@ -53,6 +53,19 @@ __host__ __device__ inline int stage_twiddles(int logm) {
 }
 // Work lists: stencil tiles, row groups (x rows), column groups (y pencils of
 // the transposed buffer) and, in three dimensions, z-pencil groups.
+// Spectral pairs (k, partner k) of a transform of n nodes: (k, n-k) mod n
+// for k <= n/2; DST-I (k, n-1-k) for k < (n+1)/2.
+__host__ __device__ inline int plan_pairs(int n, int bc) {
+  return bc == 2 ? (n + 1) >> 1 : (n >> 1) + 1;
+}
+// Complex LDS slots of a plan's staged tables: the per-stage twiddles, the
+// DCT post-twiddles of the pairs' first members (Neumann only: the partner's
+// follows by symmetry) and, for passes that scale by the eigenvalues, those
+// of the first members (two reals per slot).  m: the core length.
+__host__ __device__ inline int table_slots(int n, int m, int bc, bool lam) {
+  const int np = plan_pairs(n, bc);
+  return stage_twiddles(31 - __builtin_clz(m)) + (bc == 0 ? np : 0) + (lam ? (np + 1) / 2 : 0);
+}
 enum Pass { kPassS = 0, kPassR = 1, kPassC = 2, kPassZ = 3, kNumPass = 4 };
 
 // Kinds of column-transform launch.  Two dimensions: one launch transforms

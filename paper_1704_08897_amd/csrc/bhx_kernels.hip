@@ -288,17 +288,20 @@ struct XPlan {
   BHX_GLOBAL const C* bhat;
   BHX_GLOBAL const C* post;
   BHX_GLOBAL const R* lam;
-  const C* postl;             // post-twiddles in LDS once staged
-  const R* laml;              // eigenvalues in LDS once staged
-  // Copy the plan's twiddles, DCT post-twiddles and eigenvalues into LDS at
-  // `lds` unless plan `idx` is staged there already; every thread of the
-  // block must call this at the same point.  The twiddles are laid out per
-  // radix-4 stage of span h: W_4h^k for k < h (stage_twiddles), so each
-  // stage reads them at unit stride; the stage squares them for W_2h^k.
-  __device__ void stage(C* lds, int idx, int& staged) {
+  const C* postl;             // post-twiddles of the pairs' first members, in LDS
+  const R* laml;              // eigenvalues of the pairs' first members, in LDS
+  // Copy the plan's twiddles, the DCT post-twiddles and (with `with_lam`,
+  // for passes that scale) the eigenvalues of the pairs' first members into
+  // LDS at `lds` (table_slots(n, m, bc, with_lam) complex slots) unless plan
+  // `idx` is staged there already; every thread of the block must call this
+  // at the same point.  The twiddles are laid out per radix-4 stage of span
+  // h: W_4h^k for k < h (stage_twiddles), so each stage reads them at unit
+  // stride; the stage squares them for W_2h^k.
+  __device__ void stage(C* lds, int idx, int& staged, bool with_lam) {
+    const int np = pairs();
     C* tw_l = lds;
     C* post_l = lds + stage_twiddles(logm);
-    R* lam_l = (R*)(post_l + n);
+    R* lam_l = (R*)(post_l + (bc == kNeumann ? np : 0));
     if (idx != staged) {
       int off = 0;
       for (int h = (logm & 1) ? 2 : 1; h < m; h <<= 2) {
@@ -307,8 +310,9 @@ struct XPlan {
         off += h;
       }
       if (bc == kNeumann)
-        for (int k = threadIdx.x; k < n; k += kThreads) post_l[k] = post[k];
-      for (int k = threadIdx.x; k < n; k += kThreads) lam_l[k] = lam[k];
+        for (int k = threadIdx.x; k < np; k += kThreads) post_l[k] = post[k];
+      if (with_lam)
+        for (int k = threadIdx.x; k < np; k += kThreads) lam_l[k] = lam[k];
       __syncthreads();
       staged = idx;
     }
@@ -343,8 +347,18 @@ struct XPlan {
   }
   // Spectral indices are handled in pairs (k, partner(k)): k < pairs().
   // DCT / Hartley: (k, n - k) mod n, k <= n/2; DST-I: (k, n - 1 - k).
-  __device__ __forceinline__ int pairs() const {
-    return bc == kDirichlet ? (n + 1) >> 1 : (n >> 1) + 1;
+  __device__ __forceinline__ int pairs() const { return plan_pairs(n, bc); }
+  // DCT-II post-twiddles of the pair: t[k] = exp(-i pi k / 2n) staged, and
+  // t[n-k] = -i conj(t[k])
+  __device__ __forceinline__ void post_pair(int k, int kk, C& tk, C& tkk) const {
+    tk = postl[k];
+    tkk = kk == k ? tk : mk<C>(-tk.y, -tk.x);
+  }
+  // eigenvalues of the pair: lambda[partner] = lambda[k] for the periodic
+  // axis, 4 - lambda[k] for the DCT and DST-I ones (4 sin^2 -> 4 cos^2)
+  __device__ __forceinline__ void lam_pair(int k, int kk, R& lk, R& lkk) const {
+    lk = laml[k];
+    lkk = kk == k ? lk : (bc == kPeriodic ? lk : (R)4 - lk);
   }
   __device__ __forceinline__ int partner(int k) const {
     return bc == kDirichlet ? n - 1 - k : (k == 0 ? 0 : n - k);
@@ -532,11 +546,11 @@ __device__ __forceinline__ void fwd_post_pair(const XPlan<R>& X, typename V2<R>:
     const C va = mk<C>((Ck.x + Dk.x) * (R)0.5, (Ck.y - Dk.y) * (R)0.5);
     // (C - conj D)/(2i) = ((Ci + Di) - i (Cr - Dr)) / 2
     const C vb = mk<C>((Ck.y + Dk.y) * (R)0.5, -(Ck.x - Dk.x) * (R)0.5);
-    const C tk = X.postl[k];
+    C tk, tkk;
+    X.post_pair(k, kk, tk, tkk);
     xa_k = (k == 0 ? X.s0 : X.s1) * (tk.x * va.x - tk.y * va.y);
     xb_k = (k == 0 ? X.s0 : X.s1) * (tk.x * vb.x - tk.y * vb.y);
     // V[kk] = conj(V[k])
-    const C tkk = X.postl[kk];
     xa_kk = (kk == 0 ? X.s0 : X.s1) * (tkk.x * va.x + tkk.y * va.y);
     xb_kk = (kk == 0 ? X.s0 : X.s1) * (tkk.x * vb.x + tkk.y * vb.y);
   } else if (X.bc == kDirichlet) {
@@ -573,8 +587,10 @@ __device__ __forceinline__ void inv_pre_pair(const XPlan<R>& X, R ya_k, R yb_k, 
       in_kk = in_k;
       return;
     }
-    const C tk = cconj(X.postl[k]);        // exp(+i pi k / 2n)
-    const C tkk = cconj(X.postl[kk]);
+    C tk, tkk;
+    X.post_pair(k, kk, tk, tkk);
+    tk = cconj(tk);                        // exp(+i pi k / 2n)
+    tkk = cconj(tkk);
     const C Wk = cmul(tk, csub(Pk, cmul_pi(Pkk)));    // P[k] - i P[n-k]
     const C Wkk = cmul(tkk, csub(Pkk, cmul_pi(Pk)));
     in_k = cconj(Wk);
@@ -1119,7 +1135,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
       xv0[u] = update ? Fb[ea] : 0.0;
     }
     XPlan<R> X(B, I.planx);
-    if (update != 2) X.stage(twl, I.planx, staged);
+    if (update != 2) X.stage(twl, I.planx, staged, false);
     double alpha = 0.0;
     if (update) {
       double sums[2];
@@ -1311,7 +1327,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
     }
     if (ctl->done) continue;
     XPlan<R> X(B, plan);
-    X.stage(twl, plan, staged);
+    X.stage(twl, plan, staged, kScale);
     const int rows = Gp >> 1;
     const int st = X.stride();
     const int np = X.pairs();
@@ -1359,7 +1375,8 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
             // 3. scale by the inverse squared eigenvalue sums, inverse inputs
             const R la = s_lam[2 * rr];
             const R lb = s_lam[2 * rr + 1];
-            const R lk = X.laml[k], lkk = X.laml[kk];
+            R lk, lkk;
+            X.lam_pair(k, kk, lk, lkk);
             xa *= inv_sq<R>(la + lk);
             xb *= inv_sq<R>(lb + lk);
             xak *= inv_sq<R>(la + lkk);
@@ -1550,7 +1567,7 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
       zo0[u] = flex ? zb[ea] : 0.0;
     }
     XPlan<R> X(B, I.planx);
-    X.stage(twl, I.planx, staged);
+    X.stage(twl, I.planx, staged, false);
     const int rows = G >> 1;
     const int st = X.stride();
 #pragma unroll

@@ -87,9 +87,6 @@ int core_length(int n) {
 // kernels' rpos(m, shift)).
 int row_slots(int m) { return m + (m >> 3) + (m >> rpos_shift(ilog2(m))); }
 
-// Complex elements of the plan tables staged in LDS: per-stage twiddles,
-// DCT post-twiddles (n) and eigenvalues (n reals = n/2 complex slots).
-int table_slots(int n, int m) { return stage_twiddles(ilog2(m)) + n + (n + 1) / 2; }
 
 // Length of the DFT behind the 1-D transform of an axis of n nodes.
 int fft_length(int n, int bc) { return bc == kDirichlet ? 2 * (n + 1) : n; }
@@ -99,7 +96,7 @@ bool length_supported(int n, int bc, int prec) {
   const int csize = prec == 0 ? 16 : 8;
   const int m = core_length(fft_length(n, bc));
   if ((long)row_slots(m) * csize > kLdsBytes) return false;        // one packed row must fit
-  if ((long)(row_slots(m) + table_slots(n, m)) * csize > kLdsDynMax) return false;
+  if ((long)(row_slots(m) + table_slots(n, m, bc, true)) * csize > kLdsDynMax) return false;
   if ((n / 2 + 1) > kThreads * kMaxPairs) return false;
   return true;
 }
@@ -758,13 +755,13 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
       const AxisPlan& PX = hd->plans.plan(px[i]);
       const AxisPlan& PY = hd->plans.plan(py[i]);
       buf_r = std::max(buf_r, (lay[i].G / 2) * row_slots(PX.m));
-      tab_r = std::max(tab_r, table_slots(PX.n, PX.m));
+      tab_r = std::max(tab_r, table_slots(PX.n, PX.m, PX.bc, false));
       buf_c = std::max(buf_c, (lay[i].Gc / 2) * row_slots(PY.m));
-      tab_c = std::max(tab_c, table_slots(PY.n, PY.m));
+      tab_c = std::max(tab_c, table_slots(PY.n, PY.m, PY.bc, dim == 2));
       if (dim == 3) {
         const AxisPlan& PZ = hd->plans.plan(pz[i]);
         buf_z = std::max(buf_z, (lay[i].Gz / 2) * row_slots(PZ.m));
-        tab_z = std::max(tab_z, table_slots(PZ.n, PZ.m));
+        tab_z = std::max(tab_z, table_slots(PZ.n, PZ.m, PZ.bc, true));
       }
     }
     g.tw_r = buf_r;

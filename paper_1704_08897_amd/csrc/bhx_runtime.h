@@ -153,7 +153,6 @@ size_t instance_bytes3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int pr
 const char* last_error();
 void set_last_error(const char* what, int line, hipError_t e);
 int row_slots(int m);
-int table_slots(int n, int m);
 hipError_t launch_precond(const Batch* B, const Resolved& R, const Grids& g, hipStream_t st);
 hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved& R,
                      const Grids& g, hipStream_t st, Graph** used);
