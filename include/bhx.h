@@ -125,6 +125,17 @@ typedef struct {
                          that already meets it returns with 0 iterations and F
                          unchanged; a non-finite start gives BHX_ERR_NONFINITE.
                          0 = x0 = 0 (Algorithm 1), input values at U are ignored    */
+  int solver;       /* 0 = preconditioned conjugate gradients (Algorithm 1);
+                         1 = sparse direct (Sec. 2.2): banded Cholesky of A_UU on the
+                         GPU with the unknowns numbered row by row, then refinement
+                         with the compensated residual until ||b - A u|| <= tol ||b||
+                         (bhx_stats.iterations = refinement solves).  Two dimensions,
+                         FP64, y axis Neumann or Dirichlet (a periodic y axis couples
+                         the first and last rows: BHX_ERR_ARG); band storage is about
+                         8 (64 + w) bytes per unknown, w the band width (about twice
+                         the unknowns per grid row).  Fields sharing phi in one
+                         bhx_extend_fields call share one factorisation.  Not for
+                         the serving engine or three dimensions (BHX_ERR_ARG).       */
 } bhx_opts;
 
 typedef struct {

@@ -52,7 +52,8 @@ class Opts(ctypes.Structure):
                 ("tol_inner", ctypes.c_double), ("flexible", ctypes.c_int),
                 ("chunk", ctypes.c_int), ("rows", ctypes.c_int), ("occupancy", ctypes.c_int),
                 ("autotune", ctypes.c_int),
-                ("profile", ctypes.c_int), ("warm_start", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("warm_start", ctypes.c_int),
+                ("solver", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

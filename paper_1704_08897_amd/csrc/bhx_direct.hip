@@ -1,0 +1,556 @@
+// Direct solve of the masked biharmonic system on the GPU (two dimensions):
+// banded Cholesky factorisation of A_UU, the direct route of Sec. 2.2.
+//
+// The unknowns are numbered row by row (x fastest), so a 13-point row of
+// A_UU reaches back at most about two grid rows of unknowns: the lower band
+// width w is the largest distance, in that numbering, from an unknown to the
+// first unknown its stencil couples to (computed exactly from the stencil and
+// the ghost rules).  A periodic y axis couples the first and last grid rows
+// and would make the band span the whole grid; it is rejected.
+//
+// Storage: panels of kNb columns.  Panel k holds columns [k*kNb, (k+1)*kNb)
+// of the lower band, rows [k*kNb, k*kNb + H) with H = kNb + W (W = w rounded
+// up to kNb), column-major: P[(k*kNb + c)*H + r] = A[k*kNb + r][k*kNb + c].
+// Rows beyond the last unknown are an identity pad.
+//
+// Factorisation (right-looking, one step per panel): the diagonal block is
+// factored by one wave, the panel below it solved against it (TRSM), and
+// the trailing band updated by tile products of the panel with itself.
+// Solves: forward and backward substitution, one step per panel, each step
+// updating the right-hand side blocks it reaches (no cross-block sums).
+// Every sum runs in a fixed order, so results are deterministic.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "bhx_runtime.h"
+
+namespace bhx {
+namespace {
+
+constexpr int kNb = 64;          // panel width (block size)
+constexpr int kLd = kNb + 1;     // LDS stride of a 64 x 64 tile
+
+struct Band {
+  double* p;     // panels
+  int n;         // unknowns
+  int npad;      // n rounded up to kNb
+  int nblk;      // panels
+  int H;         // panel height kNb + W
+  int Q;         // W / kNb: tiles below the diagonal block
+};
+
+__device__ __forceinline__ size_t band_at(const Band& B, int k, int r, int c) {
+  return ((size_t)k * kNb + c) * B.H + r;
+}
+
+__device__ double block_sum_d(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  const double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
+// Unknown nodes per grid row (one block per row).
+__global__ void __launch_bounds__(kThreads) k_dir_rowcount(const uint8_t* __restrict__ mask,
+                                                           int nx, int* __restrict__ cnt) {
+  __shared__ double red[4];
+  const int y = blockIdx.x;
+  double c = 0;
+  for (int x = threadIdx.x; x < nx; x += kThreads) c += mask[(size_t)y * nx + x];
+  c = block_sum_d(c, red);
+  if (threadIdx.x == 0) cnt[y] = (int)c;
+}
+
+// Position of each unknown in the row-by-row numbering (-1 at known nodes):
+// row offset plus the exclusive prefix count within the row (block scan).
+__global__ void __launch_bounds__(kThreads) k_dir_index(const uint8_t* __restrict__ mask, int nx,
+                                                        const int* __restrict__ row_off,
+                                                        int* __restrict__ uidx) {
+  __shared__ int wsum[4];
+  __shared__ int carry;
+  const int y = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry = row_off[y];
+  __syncthreads();
+  for (int x0 = 0; x0 < nx; x0 += kThreads) {
+    const int x = x0 + threadIdx.x;
+    const int u = x < nx ? mask[(size_t)y * nx + x] : 0;
+    // inclusive scan within the wave
+    int v = u;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(v, o, 64);
+      if (lane >= o) v += t;
+    }
+    if (lane == 63) wsum[w] = v;
+    __syncthreads();
+    int before = carry;
+    for (int i = 0; i < w; ++i) before += wsum[i];
+    if (x < nx) uidx[(size_t)y * nx + x] = u ? before + v - 1 : -1;
+    __syncthreads();
+    if (threadIdx.x == kThreads - 1) carry = before + v;
+    __syncthreads();
+  }
+}
+
+// The row of A_UU of unknown node (x, y): A = L L with L the 5-point
+// negative Laplacian applied to the ghost-padded field, so each of the 25
+// (first, second) stencil pairs contributes cL(d1) cL(d2) s to the node the
+// padded position maps to (s: the ghost sign).  Calls f(target node, coef).
+template <typename Fn>
+__device__ __forceinline__ void row_of_a(int x, int y, int nx, int ny, int bcx, int bcy, Fn f) {
+  const int dx[5] = {0, -1, 1, 0, 0}, dy[5] = {0, 0, 0, -1, 1};
+  const double cl[5] = {4.0, -1.0, -1.0, -1.0, -1.0};
+#pragma unroll
+  for (int a = 0; a < 5; ++a)
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      double sx, sy;
+      const int mx = map_axis(x + dx[a] + dx[b], nx, bcx, sx);
+      const int my = map_axis(y + dy[a] + dy[b], ny, bcy, sy);
+      const double s = sx * sy;
+      if (s != 0.0) f(my * nx + mx, cl[a] * cl[b] * s);
+    }
+}
+
+// Lower band width: max over unknowns of (own index - smallest coupled index).
+__global__ void __launch_bounds__(kThreads) k_dir_width(const uint8_t* __restrict__ mask,
+                                                        const int* __restrict__ uidx, int nx,
+                                                        int ny, int bcx, int bcy,
+                                                        int* __restrict__ wmax) {
+  const int node = blockIdx.x * kThreads + threadIdx.x;
+  if (node >= nx * ny || !mask[node]) return;
+  const int gi = uidx[node];
+  int w = 0;
+  row_of_a(node % nx, node / nx, nx, ny, bcx, bcy, [&](int t, double) {
+    if (mask[t]) w = max(w, gi - uidx[t]);
+  });
+  atomicMax(wmax, w);
+}
+
+// Assemble the lower band: each unknown adds its row's entries at columns
+// not after it (the band is zeroed first; a row is written by its own
+// thread only).
+__global__ void __launch_bounds__(kThreads) k_dir_assemble(const uint8_t* __restrict__ mask,
+                                                           const int* __restrict__ uidx, int nx,
+                                                           int ny, int bcx, int bcy, Band B) {
+  const int node = blockIdx.x * kThreads + threadIdx.x;
+  if (node >= nx * ny || !mask[node]) return;
+  const int gi = uidx[node];
+  row_of_a(node % nx, node / nx, nx, ny, bcx, bcy, [&](int t, double c) {
+    if (!mask[t]) return;
+    const int gt = uidx[t];
+    if (gt > gi) return;
+    const int k = gt / kNb;
+    B.p[band_at(B, k, gi - k * kNb, gt - k * kNb)] += c;
+  });
+}
+
+// Identity on the padded diagonal entries (indices n .. npad-1).
+__global__ void k_dir_pad(Band B) {
+  const int g = B.n + blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= B.npad) return;
+  const int k = g / kNb;
+  B.p[band_at(B, k, g - k * kNb, g - k * kNb)] = 1.0;
+}
+
+// Load the lower triangle of panel k's diagonal block into LDS and factor it
+// in place by one wave (left-looking, lane i owns row i); waves 1-3 idle.
+__device__ void potrf_diag(const Band& B, int k, double (*D)[kLd]) {
+  for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
+    const int c = e / kNb, r = e - c * kNb;
+    D[r][c] = r >= c ? B.p[band_at(B, k, r, c)] : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int i = threadIdx.x;
+    for (int j = 0; j < kNb; ++j) {
+      double s = D[i][j];
+      for (int t = 0; t < j; ++t) s -= D[i][t] * D[j][t];
+      const double d = sqrt(__shfl(s, j, 64));
+      if (i == j) D[i][j] = d;
+      else if (i > j) D[i][j] = s / d;
+      __threadfence_block();             // the column is read by every lane next
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+}
+
+// Step k, part 1: block 0 factors and stores the diagonal block; block b >= 1
+// factors it too (cheaper than another launch) and solves tile b of the
+// panel below it, X <- X L^-T (lane r of wave 0: forward substitution of
+// row r).
+__global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k) {
+  __shared__ double D[kNb][kLd];
+  __shared__ double T[kNb][kLd];
+  potrf_diag(B, k, D);
+  const int b = blockIdx.x;
+  if (b == 0) {
+    for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
+      const int c = e / kNb, r = e - c * kNb;
+      if (r >= c) B.p[band_at(B, k, r, c)] = D[r][c];
+    }
+    return;
+  }
+  const int r0 = b * kNb;
+  for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
+    const int c = e / kNb, r = e - c * kNb;
+    T[r][c] = B.p[band_at(B, k, r0 + r, c)];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int r = threadIdx.x;
+    for (int j = 0; j < kNb; ++j) {
+      double s = T[r][j];
+      for (int t = 0; t < j; ++t) s -= T[r][t] * D[j][t];
+      T[r][j] = s / D[j][j];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
+    const int c = e / kNb, r = e - c * kNb;
+    B.p[band_at(B, k, r0 + r, c)] = T[r][c];
+  }
+}
+
+// Step k, part 2: trailing update of the band by panel k.  Tile (q, rt):
+// rows rt*kNb.. of panel k+q -= (panel k rows (rt+q)*kNb..) (panel k rows
+// q*kNb..)^T, 64 x 64 x 64 in LDS, 4 x 4 outputs per thread.
+__global__ void __launch_bounds__(kThreads) k_dir_update(Band B, int k) {
+  __shared__ double sA[kNb][kNb];   // [t][r]
+  __shared__ double sB[kNb][kNb];   // [t][c]
+  const int q = 1 + blockIdx.x / (B.Q + 1), rt = blockIdx.x % (B.Q + 1);
+  const int j = k + q;
+  if (rt > B.Q - q || j + rt >= B.nblk) return;       // no such tile, or past the pad
+  const int ra = (rt + q) * kNb, rb = q * kNb;
+  for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
+    const int t = e / kNb, r = e - t * kNb;
+    sA[t][r] = B.p[band_at(B, k, ra + r, t)];
+    sB[t][r] = B.p[band_at(B, k, rb + r, t)];
+  }
+  __syncthreads();
+  const int r0 = 4 * (threadIdx.x & 15), c0 = 4 * (threadIdx.x >> 4);
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int t = 0; t < kNb; ++t) {
+    double a[4], bb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = sA[t][r0 + u];
+      bb[u] = sB[t][c0 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * bb[v];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) B.p[band_at(B, j, rt * kNb + r0 + u, c0 + v)] -= acc[u][v];
+}
+
+// Forward substitution step k on y (length npad): every block solves the
+// diagonal block L_kk y_k = y_k (one wave: lane t holds y_t, each y_j is a
+// wave sum); block 0 stores y_k, block b >= 1 updates y_(k+b) -= L_(k+b,k) y_k.
+__global__ void __launch_bounds__(kThreads) k_dir_fwd(Band B, int k, double* __restrict__ y) {
+  __shared__ double D[kNb][kLd];
+  __shared__ double yk[kNb];
+  __shared__ double part[4][kNb];
+  for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
+    const int c = e / kNb, r = e - c * kNb;
+    D[r][c] = r >= c ? B.p[band_at(B, k, r, c)] : 0.0;
+  }
+  if (threadIdx.x < kNb) yk[threadIdx.x] = y[k * kNb + threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int t = threadIdx.x;
+    double yt = yk[t];
+    for (int jj = 0; jj < kNb; ++jj) {
+      double p = t < jj ? D[jj][t] * yt : 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+      const double yj = (__shfl(yt, jj, 64) - p) / D[jj][jj];
+      if (t == jj) yt = yj;
+    }
+    yk[t] = yt;
+  }
+  __syncthreads();
+  const int b = blockIdx.x;
+  if (b == 0) {
+    if (threadIdx.x < kNb) y[k * kNb + threadIdx.x] = yk[threadIdx.x];
+    return;
+  }
+  // rows b*kNb.. of panel k: r = tid % 64, columns in four strips of 16
+  const int r = threadIdx.x & 63, cs = threadIdx.x >> 6;
+  double s = 0.0;
+  for (int c = cs * 16; c < cs * 16 + 16; ++c) s += B.p[band_at(B, k, b * kNb + r, c)] * yk[c];
+  part[cs][r] = s;
+  __syncthreads();
+  if (threadIdx.x < kNb)
+    y[(k + b) * kNb + threadIdx.x] -=
+        (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
+}
+
+// Backward substitution step k (k descending): every block solves
+// L_kk^T x_k = y_k; block 0 stores x_k, block b >= 1 updates
+// y_(k-b) -= L_(k,k-b)^T x_k (rows b*kNb.. of panel k-b).
+__global__ void __launch_bounds__(kThreads) k_dir_bwd(Band B, int k, double* __restrict__ y) {
+  __shared__ double D[kNb][kLd];
+  __shared__ double xk[kNb];
+  __shared__ double part[4][kNb];
+  for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
+    const int c = e / kNb, r = e - c * kNb;
+    D[r][c] = r >= c ? B.p[band_at(B, k, r, c)] : 0.0;
+  }
+  if (threadIdx.x < kNb) xk[threadIdx.x] = y[k * kNb + threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int t = threadIdx.x;
+    double xt = xk[t];
+    for (int jj = kNb - 1; jj >= 0; --jj) {
+      double p = t > jj ? D[t][jj] * xt : 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+      const double xj = (__shfl(xt, jj, 64) - p) / D[jj][jj];
+      if (t == jj) xt = xj;
+    }
+    xk[t] = xt;
+  }
+  __syncthreads();
+  const int b = blockIdx.x;
+  if (b == 0) {
+    if (threadIdx.x < kNb) y[k * kNb + threadIdx.x] = xk[threadIdx.x];
+    return;
+  }
+  // y_(k-b)[c] -= sum_r P_(k-b)[c][b*kNb + r] x_k[r]: c = tid % 64, r strips
+  const int kb = k - b;
+  const int c = threadIdx.x & 63, rs = threadIdx.x >> 6;
+  double s = 0.0;
+  for (int r = rs * 16; r < rs * 16 + 16; ++r) s += B.p[band_at(B, kb, b * kNb + r, c)] * xk[r];
+  part[rs][c] = s;
+  __syncthreads();
+  if (threadIdx.x < kNb)
+    y[kb * kNb + threadIdx.x] -=
+        (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
+}
+
+// y[uidx] = r at unknown nodes; the pad is zeroed.
+__global__ void k_dir_gather(const uint8_t* __restrict__ mask, const int* __restrict__ uidx,
+                             const double* __restrict__ r, int N, int n, int npad,
+                             double* __restrict__ y) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  if (node < N && mask[node]) y[uidx[node]] = r[node];
+  const int g = n + node;
+  if (g < npad) y[g] = 0.0;
+}
+
+// F = y (first solve) or F += y (refinement) at unknown nodes.
+__global__ void k_dir_scatter(const uint8_t* __restrict__ mask, const int* __restrict__ uidx,
+                              const double* __restrict__ y, int N, int add,
+                              double* __restrict__ F) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N || !mask[node]) return;
+  const double v = y[uidx[node]];
+  F[node] = add ? F[node] + v : v;
+}
+
+#define DIR_CHECK(x)                                                      \
+  do {                                                                    \
+    hipError_t _e = (x);                                                  \
+    if (_e != hipSuccess) {                                               \
+      set_last_error(#x, __LINE__, _e);                                   \
+      return _e == hipErrorOutOfMemory ? BHX_ERR_NOMEM : BHX_ERR_HIP;     \
+    }                                                                     \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Device addresses of instance 0 of the handle's current batch.
+struct InstPtrs {
+  uint8_t* mask;
+  double* r;
+  Ctl* ctl;
+};
+InstPtrs instance0(bhx_handle* hd, const InstSpec& S, const Resolved& R) {
+  Layout L;
+  make_layout(S.nx, S.ny, R.precision, core_length(fft_length(S.nx, S.bcx)),
+              core_length(fft_length(S.ny, S.bcy)), R.sched.rows_cap, &L);
+  char* base = (char*)hd->ws + align256(sizeof(Ctl));
+  return {(uint8_t*)(base + L.off_mask), (double*)(base + L.off_vec), (Ctl*)hd->ws};
+}
+
+}  // namespace
+
+bool direct_supported(int bcy) { return bcy != kPeriodic; }
+
+// Banded Cholesky solve of a group of fields sharing phi (specs[0..n) have
+// the same phi, sizes and rules): factor once, then per field: right-hand
+// side, solve, and refinement with the compensated residual until
+// ||b - A u|| <= tol ||b|| (at most 4 refinement solves).
+int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R0,
+                 hipStream_t stream, bhx_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = stream ? stream : hd->own_stream;
+  Resolved R = R0;
+  R.warm = 0;
+  const InstSpec& S0 = specs[0];
+  const int nx = S0.nx, ny = S0.ny, N = nx * ny;
+  if (S0.dim != 2 || !direct_supported(S0.bcy)) return BHX_ERR_ARG;
+  int ret = BHX_OK;
+  bool factored = false;
+  Band B{};
+  int* uidx = nullptr;
+  double* y = nullptr;
+  for (int f = 0; f < n; ++f) {
+    const InstSpec& S = specs[f];
+    Grids g;
+    int rc = prepare_batch(hd, 1, &S, R, st, &g);
+    if (rc != BHX_OK) return rc;
+    const InstPtrs P = instance0(hd, S, R);
+    DIR_CHECK(launch_setup(hd->batch_d, 2, g.s, st));
+    DIR_CHECK(launch_setup_rows(hd->batch_d, g.r, st));
+    DIR_CHECK(launch_stencil(hd->batch_d, 2, kModeRhs, g.s, 0, st));
+    DIR_CHECK(launch_finalize(hd->batch_d, 1, kFinSetupH, st));
+    Ctl* ch = hd->ctl_h;
+    DIR_CHECK(hipMemcpyAsync(ch, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    DIR_CHECK(hipStreamSynchronize(st));
+    int s = BHX_OK, refines = 0;
+    bool preset = true;
+    if (ch->n_unknown == 0) {
+    } else if (ch->n_unknown == N && S.bcx != kDirichlet && S.bcy != kDirichlet) {
+      s = BHX_ERR_SINGULAR;
+    } else if (!std::isfinite(ch->bb)) {
+      s = BHX_ERR_NONFINITE;
+    } else {
+      preset = false;
+    }
+    if (!preset && !factored) {
+      // ordering, band width, storage
+      std::vector<int> cnt(ny), off(ny + 1, 0);
+      const size_t need = align256((size_t)N * sizeof(int)) + align256((ny + 2) * sizeof(int));
+      if (need > hd->dws_cap) {
+        if (hd->dws) DIR_CHECK(hipFree(hd->dws));
+        hd->dws = nullptr;
+        hd->dws_cap = 0;
+        DIR_CHECK(hipMalloc(&hd->dws, need));
+        hd->dws_cap = need;
+      }
+      uidx = (int*)hd->dws;
+      int* cnt_d = (int*)((char*)hd->dws + align256((size_t)N * sizeof(int)));
+      hipLaunchKernelGGL(k_dir_rowcount, dim3(ny), dim3(kThreads), 0, st, P.mask, nx, cnt_d);
+      DIR_CHECK(hipGetLastError());
+      DIR_CHECK(hipMemcpyAsync(cnt.data(), cnt_d, ny * sizeof(int), hipMemcpyDeviceToHost, st));
+      DIR_CHECK(hipStreamSynchronize(st));
+      for (int j = 0; j < ny; ++j) off[j + 1] = off[j] + cnt[j];
+      const int nu = off[ny];
+      {
+        const Upload u{cnt_d, off.data(), (ny + 1) * sizeof(int)};
+        DIR_CHECK(upload_ordered(hd, st, &u, 1));
+      }
+      hipLaunchKernelGGL(k_dir_index, dim3(ny), dim3(kThreads), 0, st, P.mask, nx, cnt_d, uidx);
+      DIR_CHECK(hipGetLastError());
+      int* w_d = cnt_d + ny + 1;
+      DIR_CHECK(hipMemsetAsync(w_d, 0, sizeof(int), st));
+      hipLaunchKernelGGL(k_dir_width, dim3((N + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
+                         P.mask, uidx, nx, ny, S.bcx, S.bcy, w_d);
+      DIR_CHECK(hipGetLastError());
+      int w = 0;
+      DIR_CHECK(hipMemcpyAsync(&w, w_d, sizeof(int), hipMemcpyDeviceToHost, st));
+      DIR_CHECK(hipStreamSynchronize(st));
+      B.n = nu;
+      B.nblk = (nu + kNb - 1) / kNb;
+      B.npad = B.nblk * kNb;
+      B.Q = (w + kNb - 1) / kNb;
+      B.H = kNb + B.Q * kNb;
+      const size_t pbytes = (size_t)B.nblk * kNb * B.H * sizeof(double);
+      const size_t ybytes = (size_t)B.npad * sizeof(double);
+      if (pbytes > ((size_t)200 << 30)) return BHX_ERR_NOMEM;
+      if (pbytes + ybytes > hd->band_cap) {
+        if (hd->band) DIR_CHECK(hipFree(hd->band));
+        hd->band = nullptr;
+        hd->band_cap = 0;
+        DIR_CHECK(hipMalloc(&hd->band, pbytes + ybytes));
+        hd->band_cap = pbytes + ybytes;
+      }
+      B.p = (double*)hd->band;
+      y = (double*)((char*)hd->band + pbytes);
+      // assemble and factor
+      DIR_CHECK(hipMemsetAsync(B.p, 0, pbytes, st));
+      hipLaunchKernelGGL(k_dir_assemble, dim3((N + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                         st, P.mask, uidx, nx, ny, S.bcx, S.bcy, B);
+      DIR_CHECK(hipGetLastError());
+      if (B.npad > B.n) {
+        hipLaunchKernelGGL(k_dir_pad, dim3(1), dim3(kNb), 0, st, B);
+        DIR_CHECK(hipGetLastError());
+      }
+      for (int k = 0; k < B.nblk; ++k) {
+        const int below = std::min(B.Q, B.nblk - 1 - k);
+        hipLaunchKernelGGL(k_dir_potrf_trsm, dim3(1 + below), dim3(kThreads), 0, st, B, k);
+        if (below > 0)
+          hipLaunchKernelGGL(k_dir_update, dim3(below * (B.Q + 1)), dim3(kThreads), 0, st, B, k);
+      }
+      DIR_CHECK(hipGetLastError());
+      factored = true;
+    }
+    if (!preset) {
+      const int grid = (std::max(N, B.npad) + 255) / 256;
+      for (int it = 0; it < 5; ++it) {
+        // y = residual at U (the right-hand side on the first pass)
+        hipLaunchKernelGGL(k_dir_gather, dim3(grid), dim3(256), 0, st, P.mask, uidx, P.r, N, B.n,
+                           B.npad, y);
+        for (int k = 0; k < B.nblk; ++k)
+          hipLaunchKernelGGL(k_dir_fwd, dim3(1 + std::min(B.Q, B.nblk - 1 - k)), dim3(kThreads),
+                             0, st, B, k, y);
+        for (int k = B.nblk - 1; k >= 0; --k)
+          hipLaunchKernelGGL(k_dir_bwd, dim3(1 + std::min(B.Q, k)), dim3(kThreads), 0, st, B, k,
+                             y);
+        hipLaunchKernelGGL(k_dir_scatter, dim3((N + 255) / 256), dim3(256), 0, st, P.mask, uidx,
+                           y, N, it > 0 ? 1 : 0, S.F);
+        DIR_CHECK(hipGetLastError());
+        refines = it + 1;
+        // compensated true residual of F (k_resid runs on converged instances)
+        ch->done = kConverged;
+        DIR_CHECK(hipMemcpyAsync(P.ctl, ch, sizeof(Ctl), hipMemcpyHostToDevice, st));
+        DIR_CHECK(launch_resid(hd->batch_d, 2, g.s, st));
+        DIR_CHECK(launch_finalize(hd->batch_d, 1, kFinResidH, st));
+        DIR_CHECK(hipMemcpyAsync(ch, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        DIR_CHECK(hipStreamSynchronize(st));
+        if (!std::isfinite(ch->true_rr)) {
+          s = BHX_ERR_BREAKDOWN;
+          break;
+        }
+        if (ch->true_rr <= ch->accept) break;
+      }
+      if (s == BHX_OK && !(ch->true_rr <= ch->accept)) s = BHX_NOT_CONVERGED;
+    }
+    if (s < 0 && ret >= 0) ret = s;
+    else if (s > 0 && ret == BHX_OK) ret = s;
+    if (stats) {
+      bhx_stats& o = stats[f];
+      std::memset(&o, 0, sizeof(o));
+      o.status = s;
+      o.iterations = refines;
+      o.n_unknown = (int)ch->n_unknown;
+      const double bb0 = ch->bb0;
+      o.rel_residual = (!preset && bb0 > 0) ? std::sqrt(ch->true_rr / bb0) : 0.0;
+      o.true_rel_residual = o.rel_residual;
+      o.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+  }
+  return ret;
+}
+
+}  // namespace bhx

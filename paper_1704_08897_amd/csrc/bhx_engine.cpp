@@ -473,7 +473,8 @@ int bhx_engine_create(bhx_engine** out, int device, size_t hbm_budget, int max_s
     return BHX_ERR_ARG;
   bhx::Resolved R = bhx::resolve_opts(o);
   static const double dummy = 0;
-  if (bhx::validate(&dummy, (double*)&dummy, 8, 8, 1.0, 0, 0.5, R) != BHX_OK) return BHX_ERR_ARG;
+  if (bhx::validate(&dummy, (double*)&dummy, 8, 8, 1.0, 0, 0.5, R) != BHX_OK || R.solver != 0)
+    return BHX_ERR_ARG;
   bhx_engine* E = new (std::nothrow) bhx_engine();
   if (!E) return BHX_ERR_NOMEM;
   int s = bhx_create(&E->hd, device);

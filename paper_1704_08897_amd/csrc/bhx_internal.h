@@ -66,6 +66,19 @@ __host__ __device__ inline int table_slots(int n, int m, int bc, bool lam) {
   const int np = plan_pairs(n, bc);
   return stage_twiddles(31 - __builtin_clz(m)) + (bc == 0 ? np : 0) + (lam ? (np + 1) / 2 : 0);
 }
+// Ghost-node rule of one axis: global index g in [-2, n+1] -> stored index,
+// with sign s (Dirichlet odd reflection of Algorithm 1: g[-1] = 0,
+// g[-2] = -f[0]); Neumann half-sample even reflection; periodic wrap.
+__device__ __forceinline__ int map_axis(int g, int n, int bc, double& s) {
+  s = 1.0;
+  if (g >= 0 && g < n) return g;
+  if (bc == kNeumann) return g < 0 ? -g - 1 : 2 * n - 1 - g;
+  if (bc == kPeriodic) return g < 0 ? g + n : g - n;
+  if (g == -1 || g == n) { s = 0.0; return 0; }
+  s = -1.0;
+  return g < 0 ? 0 : n - 1;
+}
+
 enum Pass { kPassS = 0, kPassR = 1, kPassC = 2, kPassZ = 3, kNumPass = 4 };
 
 // Kinds of column-transform launch.  Two dimensions: one launch transforms

@@ -217,18 +217,6 @@ __device__ double block_sum(double v, double* red) {
   return t;
 }
 
-// Ghost-node rule of one axis: global index g in [-2, n+1] -> stored index,
-// with sign s (Dirichlet odd reflection of Algorithm 1: g[-1] = 0,
-// g[-2] = -f[0]); Neumann half-sample even reflection; periodic wrap.
-__device__ __forceinline__ int map_axis(int g, int n, int bc, double& s) {
-  s = 1.0;
-  if (g >= 0 && g < n) return g;
-  if (bc == kNeumann) return g < 0 ? -g - 1 : 2 * n - 1 - g;
-  if (bc == kPeriodic) return g < 0 ? g + n : g - n;
-  if (g == -1 || g == n) { s = 0.0; return 0; }
-  s = -1.0;
-  return g < 0 ? 0 : n - 1;
-}
 
 // Branch-free form of map_axis for g in [-2, n+1] (selects only); any other
 // g maps to index 0 with sign 0.

@@ -188,6 +188,7 @@ Resolved resolve_opts(const bhx_opts* o) {
   R.profile = o->profile;
   R.autotune = o->autotune;
   R.warm = o->warm_start;
+  R.solver = o->solver;
   R.rows_opt = o->rows;
   R.occ_opt = o->occupancy;
   if (o->rows > 0) R.sched.rows_cap = o->rows;
@@ -332,6 +333,8 @@ int validate(const double* phi, const double* F, int nx, int ny, double h, int b
   if (R.profile < 0 || R.profile > 15) return BHX_ERR_ARG;
   if (R.autotune != 0 && R.autotune != 1) return BHX_ERR_ARG;
   if (R.warm != 0 && R.warm != 1) return BHX_ERR_ARG;
+  if (R.solver != 0 && R.solver != 1) return BHX_ERR_ARG;
+  if (R.solver == 1 && (R.precision != BHX_PREC_FP64 || by == BHX_PERIODIC)) return BHX_ERR_ARG;
   if (R.rows_opt < 0 || R.rows_opt > 8 || R.occ_opt < 0 || R.occ_opt > 8) return BHX_ERR_ARG;
   if (!length_supported(nx, bx, R.precision) || !length_supported(ny, by, R.precision))
     return BHX_ERR_ARG;
@@ -343,7 +346,7 @@ int validate3(const double* phi, const double* F, int nx, int ny, int nz, double
               double tol, const Resolved& R) {
   if (bc < 0 || (bc >> 12) != 0) return BHX_ERR_ARG;
   const int bz = (bc >> 8) & 15;
-  if (bz > BHX_DIRICHLET || nz < 4) return BHX_ERR_ARG;
+  if (bz > BHX_DIRICHLET || nz < 4 || R.solver != 0) return BHX_ERR_ARG;
   const int v = validate(phi, F, nx, ny, h, bc & 0xff, tol, R);
   if (v != BHX_OK) return v;
   if (!length_supported(nz, bz, R.precision)) return BHX_ERR_ARG;
@@ -414,6 +417,8 @@ void free_handle(bhx_handle* hd) {
   if (hd->flag_d) (void)hipFree(hd->flag_d);
   if (hd->ctl_h) (void)hipHostFree(hd->ctl_h);
   if (hd->stage_h) (void)hipHostFree(hd->stage_h);
+  if (hd->dws) (void)hipFree(hd->dws);
+  if (hd->band) (void)hipFree(hd->band);
   if (hd->own_stream) (void)hipStreamDestroy(hd->own_stream);
 }
 
@@ -1082,6 +1087,24 @@ static int autotune_keeping_fields(bhx_handle* hd, int n, const InstSpec* specs,
 
 int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R0,
                 hipStream_t stream, bhx_stats* stats) {
+  if (R0.solver == 1) {
+    // banded Cholesky: consecutive instances sharing phi, size and rules
+    // (the fields of one level set) share one factorisation
+    int ret = BHX_OK;
+    for (int i = 0; i < n;) {
+      int j = i + 1;
+      while (j < n && specs[j].phi == specs[i].phi && specs[j].nx == specs[i].nx &&
+             specs[j].ny == specs[i].ny && specs[j].bcx == specs[i].bcx &&
+             specs[j].bcy == specs[i].bcy && specs[j].dim == specs[i].dim)
+        ++j;
+      const int s = solve_direct(hd, j - i, specs + i, R0, stream, stats ? stats + i : nullptr);
+      if (s < 0 && ret >= 0) ret = s;
+      else if (s > 0 && ret == BHX_OK) ret = s;
+      if (s == BHX_ERR_HIP || s == BHX_ERR_NOMEM || s == BHX_ERR_ARG) return s;
+      i = j;
+    }
+    return ret;
+  }
   Resolved R = R0;
   if (R.autotune && R.rows_opt == 0 && R.occ_opt == 0) {
     const unsigned long long sig = batch_signature(n, specs, R);

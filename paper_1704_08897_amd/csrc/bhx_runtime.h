@@ -84,6 +84,7 @@ struct Schedule {
 
 struct Resolved {           // options after defaults
   int precision, maxit_user, precond, accurate, flexible, chunk, profile, autotune, warm;
+  int solver;               // 0 PCG, 1 banded Cholesky (two dimensions)
   int rows_opt = 0, occ_opt = 0;
   double tol_inner;
   Schedule sched;
@@ -134,6 +135,10 @@ struct bhx_handle {
   size_t stage_cap = 0;
   std::vector<bhx::Graph> graphs;
   std::map<unsigned long long, bhx::Schedule> tuned;   // autotuner results per batch shape
+  void* dws = nullptr;         // direct solver: ordering (grow-only)
+  size_t dws_cap = 0;
+  void* band = nullptr;        // direct solver: band panels and solve vector (grow-only)
+  size_t band_cap = 0;
   std::mutex mu;
 };
 
@@ -161,6 +166,15 @@ hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved&
 int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, double* out, int nx,
                 int ny, int nz, int bcx, int bcy, int bcz, int precision, hipStream_t stream);
 int init_handle(bhx_handle* hd, int device);
+// Descriptors, layouts, plans and launch grids of a batch (the solve's first step).
+int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
+                  hipStream_t st, Grids* gout);
+int fft_length(int n, int bc);
+// Banded Cholesky solve of fields sharing one phi (all specs: same phi, size
+// and rules; two dimensions, y axis not periodic).
+int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
+                 hipStream_t stream, bhx_stats* stats);
+bool direct_supported(int bcy);
 // One host array to copy to device memory.
 struct Upload {
   void* dst;

@@ -135,3 +135,18 @@ def test_three_dimensional_arguments():
     assert s == bhx.ERR_ARG
     assert bhx.debug_apply3d(FAKE, 2, FAKE, FAKE, FAKE, 8, 8, 8) == bhx.ERR_ARG
     assert bhx.debug_apply3d(FAKE, 0, FAKE, FAKE, FAKE, 8, 8, 2) == bhx.ERR_ARG
+
+
+def test_direct_solver_option_checks():
+    """solver = 1 (banded Cholesky): FP64, y axis not periodic, two
+    dimensions, not the engine; anything else is rejected on the host."""
+    assert bhx.default_opts().solver == 0
+    for kw, bc in (({"solver": 2}, 0), ({"solver": 1}, bhx.BC(0, 1)),
+                   ({"solver": 1, "precision": 1}, 0)):
+        s, _ = bhx.extend_ex(FAKE, FAKE, FAKE, 8, 8, 1.0, bc, 1e-8, opts=bhx.default_opts(**kw))
+        assert s == bhx.ERR_ARG, kw
+    s, _ = bhx.extend3d(FAKE, FAKE, FAKE, 8, 8, 8, opts=bhx.default_opts(solver=1))
+    assert s == bhx.ERR_ARG
+    e = ctypes.c_void_p()
+    assert bhx._lib.bhx_engine_create(ctypes.byref(e), 0, 1 << 30, 4,
+                                      ctypes.byref(bhx.default_opts(solver=1))) == bhx.ERR_ARG
