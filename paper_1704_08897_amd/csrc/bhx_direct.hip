@@ -14,7 +14,8 @@
 // Rows beyond the last unknown are an identity pad.
 //
 // Factorisation (right-looking, one step per panel): the diagonal block is
-// factored by one wave, the panel below it solved against it (TRSM), and
+// factored in the registers of a wave (one row per lane, pivots and columns
+// exchanged by readlane), the panel below it solved against it (TRSM), and
 // the trailing band updated by tile products of the panel with itself.
 // Solves: forward and backward substitution, one step per panel, each step
 // updating the right-hand side blocks it reaches (no cross-block sums).
@@ -31,7 +32,6 @@ namespace bhx {
 namespace {
 
 constexpr int kNb = 64;          // panel width (block size)
-constexpr int kLd = kNb + 1;     // LDS stride of a 64 x 64 tile
 
 struct Band {
   double* p;     // panels
@@ -162,64 +162,64 @@ __global__ void k_dir_pad(Band B) {
   B.p[band_at(B, k, g - k * kNb, g - k * kNb)] = 1.0;
 }
 
-// Load the lower triangle of panel k's diagonal block into LDS and factor it
-// in place by one wave (left-looking, lane i owns row i); waves 1-3 idle.
-__device__ void potrf_diag(const Band& B, int k, double (*D)[kLd]) {
-  for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
-    const int c = e / kNb, r = e - c * kNb;
-    D[r][c] = r >= c ? B.p[band_at(B, k, r, c)] : 0.0;
-  }
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const int i = threadIdx.x;
-    for (int j = 0; j < kNb; ++j) {
-      double s = D[i][j];
-      for (int t = 0; t < j; ++t) s -= D[i][t] * D[j][t];
-      const double d = sqrt(__shfl(s, j, 64));
-      if (i == j) D[i][j] = d;
-      else if (i > j) D[i][j] = s / d;
-      __threadfence_block();             // the column is read by every lane next
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  __syncthreads();
+// Value of v in lane `lane` of the wave (uniform result, no memory access).
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Step k, part 1: block 0 factors and stores the diagonal block; block b >= 1
-// factors it too (cheaper than another launch) and solves tile b of the
-// panel below it, X <- X L^-T (lane r of wave 0: forward substitution of
-// row r).
-__global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k) {
-  __shared__ double D[kNb][kLd];
-  __shared__ double T[kNb][kLd];
-  potrf_diag(B, k, D);
-  const int b = blockIdx.x;
-  if (b == 0) {
-    for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
-      const int c = e / kNb, r = e - c * kNb;
-      if (r >= c) B.p[band_at(B, k, r, c)] = D[r][c];
-    }
+// Row `lane` of panel k's diagonal block (lower part; zeros above).
+__device__ __forceinline__ void load_diag_row(const Band& B, int k, int lane, double (&a)[kNb]) {
+#pragma unroll
+  for (int c = 0; c < kNb; ++c) a[c] = c <= lane ? B.p[band_at(B, k, lane, c)] : 0.0;
+}
+
+// Cholesky of the 64 x 64 block held one row per lane (right-looking): on
+// return lane i holds row i of L (lower part).  Column j: the pivot from
+// lane j, the column entries scaled, then the trailing rows updated with
+// L[k][j] read from lane k.
+__device__ __forceinline__ void potrf_wave(int lane, double (&a)[kNb]) {
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) {
+    const double d = sqrt(lane_value(a[j], j));
+    const double l = lane > j ? a[j] / d : (lane == j ? d : 0.0);
+    a[j] = l;
+#pragma unroll
+    for (int k = j + 1; k < kNb; ++k) a[k] -= l * lane_value(l, k);
+  }
+}
+
+// Step k, part 1: wave w of block b takes tile t = 4 b + w of panel k.
+// Every wave factors the diagonal block in its registers (cheaper than a
+// second launch); tile 0 stores L, tile t >= 1 (rows 64 t..) solves
+// X <- X L^-T in registers (lane r: row r, right-looking over columns).
+__global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int tiles) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= tiles) return;                // whole waves: no barrier in this kernel
+  double a[kNb];
+  load_diag_row(B, k, lane, a);
+  potrf_wave(lane, a);
+  if (t == 0) {
+#pragma unroll
+    for (int c = 0; c < kNb; ++c)
+      if (c <= lane) B.p[band_at(B, k, lane, c)] = a[c];
     return;
   }
-  const int r0 = b * kNb;
-  for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
-    const int c = e / kNb, r = e - c * kNb;
-    T[r][c] = B.p[band_at(B, k, r0 + r, c)];
+  const int r0 = t * kNb;
+  double x[kNb];
+#pragma unroll
+  for (int c = 0; c < kNb; ++c) x[c] = B.p[band_at(B, k, r0 + lane, c)];
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) {
+    x[j] /= lane_value(a[j], j);         // L[j][j]
+#pragma unroll
+    for (int c = j + 1; c < kNb; ++c) x[c] -= x[j] * lane_value(a[j], c);   // L[c][j]
   }
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const int r = threadIdx.x;
-    for (int j = 0; j < kNb; ++j) {
-      double s = T[r][j];
-      for (int t = 0; t < j; ++t) s -= T[r][t] * D[j][t];
-      T[r][j] = s / D[j][j];
-    }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
-    const int c = e / kNb, r = e - c * kNb;
-    B.p[band_at(B, k, r0 + r, c)] = T[r][c];
-  }
+#pragma unroll
+  for (int c = 0; c < kNb; ++c) B.p[band_at(B, k, r0 + lane, c)] = x[c];
 }
 
 // Step k, part 2: trailing update of the band by panel k.  Tile (q, rt):
@@ -262,30 +262,24 @@ __global__ void __launch_bounds__(kThreads) k_dir_update(Band B, int k) {
     for (int u = 0; u < 4; ++u) B.p[band_at(B, j, rt * kNb + r0 + u, c0 + v)] -= acc[u][v];
 }
 
-// Forward substitution step k on y (length npad): every block solves the
-// diagonal block L_kk y_k = y_k (one wave: lane t holds y_t, each y_j is a
-// wave sum); block 0 stores y_k, block b >= 1 updates y_(k+b) -= L_(k+b,k) y_k.
+// Forward substitution step k on y (length npad): wave 0 of every block
+// solves L_kk y_k = y_k (lane t: y_t and row t of L_kk in registers);
+// block 0 stores y_k, block b >= 1 updates y_(k+b) -= L_(k+b,k) y_k.
 __global__ void __launch_bounds__(kThreads) k_dir_fwd(Band B, int k, double* __restrict__ y) {
-  __shared__ double D[kNb][kLd];
   __shared__ double yk[kNb];
   __shared__ double part[4][kNb];
-  for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
-    const int c = e / kNb, r = e - c * kNb;
-    D[r][c] = r >= c ? B.p[band_at(B, k, r, c)] : 0.0;
-  }
-  if (threadIdx.x < kNb) yk[threadIdx.x] = y[k * kNb + threadIdx.x];
-  __syncthreads();
   if (threadIdx.x < 64) {
-    const int t = threadIdx.x;
-    double yt = yk[t];
-    for (int jj = 0; jj < kNb; ++jj) {
-      double p = t < jj ? D[jj][t] * yt : 0.0;
+    const int lane = threadIdx.x;
+    double a[kNb];
+    load_diag_row(B, k, lane, a);
+    double v = y[k * kNb + lane];
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
-      const double yj = (__shfl(yt, jj, 64) - p) / D[jj][jj];
-      if (t == jj) yt = yj;
+    for (int j = 0; j < kNb; ++j) {
+      const double yj = lane_value(v, j) / lane_value(a[j], j);
+      if (lane == j) v = yj;
+      else if (lane > j) v -= a[j] * yj;
     }
-    yk[t] = yt;
+    yk[lane] = v;
   }
   __syncthreads();
   const int b = blockIdx.x;
@@ -304,30 +298,26 @@ __global__ void __launch_bounds__(kThreads) k_dir_fwd(Band B, int k, double* __r
         (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
 }
 
-// Backward substitution step k (k descending): every block solves
-// L_kk^T x_k = y_k; block 0 stores x_k, block b >= 1 updates
-// y_(k-b) -= L_(k,k-b)^T x_k (rows b*kNb.. of panel k-b).
+// Backward substitution step k (k descending): wave 0 of every block solves
+// L_kk^T x_k = y_k (lane t: y_t and column t of L_kk in registers); block 0
+// stores x_k, block b >= 1 updates y_(k-b) -= L_(k,k-b)^T x_k (rows b*kNb..
+// of panel k-b).
 __global__ void __launch_bounds__(kThreads) k_dir_bwd(Band B, int k, double* __restrict__ y) {
-  __shared__ double D[kNb][kLd];
   __shared__ double xk[kNb];
   __shared__ double part[4][kNb];
-  for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
-    const int c = e / kNb, r = e - c * kNb;
-    D[r][c] = r >= c ? B.p[band_at(B, k, r, c)] : 0.0;
-  }
-  if (threadIdx.x < kNb) xk[threadIdx.x] = y[k * kNb + threadIdx.x];
-  __syncthreads();
   if (threadIdx.x < 64) {
-    const int t = threadIdx.x;
-    double xt = xk[t];
-    for (int jj = kNb - 1; jj >= 0; --jj) {
-      double p = t > jj ? D[t][jj] * xt : 0.0;
+    const int lane = threadIdx.x;
+    double col[kNb];                     // col[j] = L[j][lane]
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
-      const double xj = (__shfl(xt, jj, 64) - p) / D[jj][jj];
-      if (t == jj) xt = xj;
+    for (int j = 0; j < kNb; ++j) col[j] = j >= lane ? B.p[band_at(B, k, j, lane)] : 0.0;
+    double v = y[k * kNb + lane];
+#pragma unroll
+    for (int j = kNb - 1; j >= 0; --j) {
+      const double xj = lane_value(v, j) / lane_value(col[j], j);
+      if (lane == j) v = xj;
+      else if (lane < j) v -= col[j] * xj;
     }
-    xk[t] = xt;
+    xk[lane] = v;
   }
   __syncthreads();
   const int b = blockIdx.x;
@@ -498,7 +488,8 @@ int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R
       }
       for (int k = 0; k < B.nblk; ++k) {
         const int below = std::min(B.Q, B.nblk - 1 - k);
-        hipLaunchKernelGGL(k_dir_potrf_trsm, dim3(1 + below), dim3(kThreads), 0, st, B, k);
+        hipLaunchKernelGGL(k_dir_potrf_trsm, dim3((1 + below + 3) / 4), dim3(kThreads), 0, st, B,
+                           k, 1 + below);
         if (below > 0)
           hipLaunchKernelGGL(k_dir_update, dim3(below * (B.Q + 1)), dim3(kThreads), 0, st, B, k);
       }
