@@ -28,7 +28,7 @@ constexpr int kTileX = 64;             // stencil tile (nodes), two dimensions
 constexpr int kTileY = 32;
 constexpr int kTileX3 = 16;            // stencil tile (nodes), three dimensions
 constexpr int kTileY3 = 8;
-constexpr int kTileZ3 = 8;
+constexpr int kTileZ3 = 4;
 constexpr int kLdsBytes = 80 * 1024;   // LDS for the packed rows of one transform item
 constexpr int kLdsMax = 160 * 1024;    // LDS of a CU (gfx950)
 constexpr int kLdsDynMax = 152 * 1024; // dynamic LDS cap of a transform launch

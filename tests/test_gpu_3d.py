@@ -1,7 +1,7 @@
 """GPU parity in three dimensions (Sec. 3, Example 2): the HIP library through
 the C interface against the three-dimensional CPU oracle.
 
-Sizes span several stencil tiles (16 x 8 x 8) with ragged tails, power-of-two
+Sizes span several stencil tiles (16 x 8 x 4) with ragged tails, power-of-two
 and Bluestein transform lengths and all three boundary rules.  Tolerances:
 * masked 25-point operator: integer coefficients, only the summation order
   differs: |diff| <= 64 eps max|x| per node (times the coefficient sum 98);
@@ -230,7 +230,7 @@ def test_3d_deterministic(handle):
 
 
 def test_reduced_scalars_mode(handle):
-    """96^3 (6 x 12 x 12 tiles, 1152 row groups): long enough partial-sum
+    """96^3 (6 x 12 x 24 tiles, 1152 row groups): long enough partial-sum
     arrays that the scalars are summed once per pass by k_reduce.  Standard
     FP64 PCG follows the oracle's iteration count; the flexible FP32 form
     (which also reduces r.z_old) and plain CG (identity preconditioner)
