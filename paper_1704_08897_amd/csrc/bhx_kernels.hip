@@ -265,6 +265,8 @@ __device__ __forceinline__ int inv_index(int j, int n) {
   return (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
 }
 
+constexpr int kStageRound = 4;    // plan-table entries per thread per staging round
+
 template <typename R>
 struct XPlan {
   using C = typename V2<R>::T;
@@ -284,23 +286,47 @@ struct XPlan {
   // `idx` is staged there already; every thread of the block must call this
   // at the same point.  The twiddles are laid out per radix-4 stage of span
   // h: W_4h^k for k < h (stage_twiddles), so each stage reads them at unit
-  // stride; the stage squares them for W_2h^k.
+  // stride; the stage squares them for W_2h^k.  The tables are copied as one
+  // flat index space in rounds of kStageRound entries per thread, all loads of
+  // a round issued before its LDS writes: one or two memory round trips per
+  // launch instead of one per table.
   __device__ void stage(C* lds, int idx, int& staged, bool with_lam) {
     const int np = pairs();
+    const int ntw = stage_twiddles(logm);
     C* tw_l = lds;
-    C* post_l = lds + stage_twiddles(logm);
+    C* post_l = lds + ntw;
     R* lam_l = (R*)(post_l + (bc == kNeumann ? np : 0));
     if (idx != staged) {
-      int off = 0;
-      for (int h = (logm & 1) ? 2 : 1; h < m; h <<= 2) {
-        const int ls = logm - 2 - (31 - __clz(h));     // W_4h^k = twg[k << ls]
-        for (int k = threadIdx.x; k < h; k += kThreads) tw_l[off + k] = twg[k << ls];
-        off += h;
+      const int nc = ntw + (bc == kNeumann ? np : 0);   // complex entries
+      const int nl = with_lam ? np : 0;                  // real entries
+      const int h0 = (logm & 1) ? 2 : 1;
+      for (int base = 0; base < max(nc, nl); base += kStageRound * kThreads) {
+        R vr[kStageRound], vi[kStageRound], vl[kStageRound];   // real arrays stay in VGPRs
+#pragma unroll
+        for (int u = 0; u < kStageRound; ++u) {
+          const int e = base + (int)threadIdx.x + u * kThreads;
+          C v = mk<C>(0, 0);
+          if (e < ntw) {
+            // the table of span h = h0 4^j starts at (h - h0) / 3: entry e
+            // lies in table j where h0 4^j <= 3e + h0 < h0 4^(j+1)
+            const int j = ((31 - __clz(3 * e + h0)) - (h0 - 1)) >> 1;
+            const int h = h0 << (2 * j);
+            const int ls = logm - 2 - (31 - __clz(h));   // W_4h^k = twg[k << ls]
+            v = twg[(e - (h - h0) / 3) << ls];
+          } else if (e < nc) {
+            v = post[e - ntw];
+          }
+          vr[u] = v.x;
+          vi[u] = v.y;
+          vl[u] = e < nl ? lam[e] : (R)0;
+        }
+#pragma unroll
+        for (int u = 0; u < kStageRound; ++u) {
+          const int e = base + (int)threadIdx.x + u * kThreads;
+          if (e < nc) tw_l[e] = mk<C>(vr[u], vi[u]);
+          if (e < nl) lam_l[e] = vl[u];
+        }
       }
-      if (bc == kNeumann)
-        for (int k = threadIdx.x; k < np; k += kThreads) post_l[k] = post[k];
-      if (with_lam)
-        for (int k = threadIdx.x; k < np; k += kThreads) lam_l[k] = lam[k];
       __syncthreads();
       staged = idx;
     }
