@@ -218,14 +218,21 @@ hipError_t launch_stencil(const Batch* B, int dim, int mode, int grid, int lpar,
 hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st);
 // Transform launches: `lds` dynamic LDS bytes, `twoff` complex-element offset
 // of the twiddle table staged in LDS (after the largest packed-row buffer).
-hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, int lds, int twoff,
+// `shape`: 0 = kernels that read every shape from the plan table; otherwise
+// (L << 2) | bc of the pass's axis (2^L nodes, L = 9..11, Neumann or periodic,
+// FP64, one instance, one packed row per work item; launch_col: kCol2D only),
+// whose compile-time instance runs instead; shape_key() decides.
+int shape_key(int n_inst, int dim, int prec, int n, int m, int logm, int bluestein, int bc,
+              int rows_g);
+hipError_t launch_rowfwd(const Batch* B, int prec, int shape, int update, int grid, int lds,
+                         int twoff, int lpar, hipStream_t st, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
+hipError_t launch_col(const Batch* B, int prec, int shape, int kind, int count_iter, int grid,
+                      int lds, int twoff, hipStream_t st, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr);
+hipError_t launch_rowinv(const Batch* B, int prec, int shape, int grid, int lds, int twoff,
                          int lpar, hipStream_t st, hipEvent_t e0 = nullptr,
                          hipEvent_t e1 = nullptr);
-hipError_t launch_col(const Batch* B, int prec, int kind, int count_iter, int grid, int lds,
-                      int twoff, hipStream_t st, hipEvent_t e0 = nullptr,
-                      hipEvent_t e1 = nullptr);
-hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, int lpar,
-                         hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_setup_rows(const Batch* B, int grid, hipStream_t st);
 hipError_t launch_identity(const Batch* B, int grid, int lpar, hipStream_t st,
                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

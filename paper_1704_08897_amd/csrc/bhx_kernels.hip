@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 #include <stdint.h>
+#include <cstdlib>
 
 #include "bhx_internal.h"
 
@@ -267,7 +268,11 @@ __device__ __forceinline__ int inv_index(int j, int n) {
 
 constexpr int kStageRound = 4;    // plan-table entries per thread per staging round
 
-template <typename R>
+// A transform plan as the kernels use it.  SP = 0 reads the shape from the
+// plan table; SP = (L << 2) | bc fixes it at compile time (a power-of-two
+// axis of 2^L nodes with the Neumann or periodic rule, no Bluestein), so that
+// the index arithmetic of every stage folds to constants.
+template <typename R, int SP = 0>
 struct XPlan {
   using C = typename V2<R>::T;
   int n, nf, m, logm, blue, bc, sh;
@@ -336,7 +341,14 @@ struct XPlan {
   }
   __device__ XPlan(const Batch& B, int idx) {
     const AxisPlan P = B.plans[idx];
-    n = P.n; nf = P.nf; m = P.m; logm = P.logm; blue = P.bluestein; bc = P.bc;
+    if constexpr (SP != 0) {
+      logm = SP >> 2;
+      n = nf = m = 1 << logm;
+      blue = 0;
+      bc = SP & 3;
+    } else {
+      n = P.n; nf = P.nf; m = P.m; logm = P.logm; blue = P.bluestein; bc = P.bc;
+    }
     sh = rpos_shift(logm);
     s0 = (R)P.s0; s1 = (R)P.s1; g0 = (R)P.g0; g1 = (R)P.g1; hs = (R)P.hs;
     const int pi = sizeof(R) == 8 ? 0 : 1;
@@ -516,8 +528,8 @@ __device__ void fft_dif_inv(typename V2<R>::T* buf, int rows, int st, int m, int
 
 // After inputs are placed at pos(k) (k < n): Bluestein multiplies by the
 // chirp and zero-fills k in [n, m); then the core forward DFT of length n.
-template <typename R>
-__device__ void dft_core(const XPlan<R>& X, typename V2<R>::T* buf, int rows) {
+template <typename R, int SP>
+__device__ void dft_core(const XPlan<R, SP>& X, typename V2<R>::T* buf, int rows) {
   using C = typename V2<R>::T;
   const int st = X.stride();
   if (X.blue) {
@@ -551,8 +563,8 @@ __device__ void dft_core(const XPlan<R>& X, typename V2<R>::T* buf, int rows) {
 //   DST-I (orthonormal; C = out(k+1), D = out(kk+1)): the odd extensions'
 //     spectra are imaginary, so X_a[k] = -Im(C) hs, X_b[k] = Re(C) hs with
 //     hs = sqrt(2/(n+1)) / 2.
-template <typename R>
-__device__ __forceinline__ void fwd_post_pair(const XPlan<R>& X, typename V2<R>::T Ck,
+template <typename R, int SP>
+__device__ __forceinline__ void fwd_post_pair(const XPlan<R, SP>& X, typename V2<R>::T Ck,
                                               typename V2<R>::T Dk, int k, int kk, R& xa_k,
                                               R& xb_k, R& xa_kk, R& xb_kk) {
   using C = typename V2<R>::T;
@@ -587,8 +599,8 @@ __device__ __forceinline__ void fwd_post_pair(const XPlan<R>& X, typename V2<R>:
 // unnormalised inverse DFT is taken as conj(DFT(conj W)), so conj(W) is
 // returned.  Hartley and DST-I: the forward transform again (both are their
 // own inverses), inputs Y_a + i Y_b.
-template <typename R>
-__device__ __forceinline__ void inv_pre_pair(const XPlan<R>& X, R ya_k, R yb_k, R ya_kk,
+template <typename R, int SP>
+__device__ __forceinline__ void inv_pre_pair(const XPlan<R, SP>& X, R ya_k, R yb_k, R ya_kk,
                                              R yb_kk, int k, int kk, typename V2<R>::T& in_k,
                                              typename V2<R>::T& in_kk) {
   using C = typename V2<R>::T;
@@ -1085,8 +1097,9 @@ __global__ void __launch_bounds__(kThreads) k_resid(const Batch* __restrict__ Bp
 // ---------------------------------------------------------------------------
 
 // `lpar`: buffer parity of the iteration (as in k_stencil): p_new = p[lpar ^ 1],
-// current r.z partials rz(lpar).
-template <typename R>
+// current r.z partials rz(lpar).  SP: compile-time shape of the x axis (see
+// XPlan; then one packed row per item, G = 2), 0 for any shape.
+template <typename R, int SP>
 __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ Bp, int update,
                                                      int twoff, int lpar) {
   using C = typename V2<R>::T;
@@ -1103,7 +1116,8 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
     const int g = code & kItemMask;
     BHX_GLOBAL Ctl* ctl = I.ctl;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
-    const int nx = I.nx, ny = I.nrows, G = I.G, j0 = g * G;   // ny: rows of the pass
+    // ny: rows of the pass
+    const int nx = SP ? 1 << (SP >> 2) : I.nx, ny = I.nrows, G = SP ? 2 : I.G, j0 = g * G;
     const int E = min(G, ny - j0) * nx;          // valid elements of this row group
     const size_t base = (size_t)j0 * nx;
     BHX_GLOBAL const uint8_t* __restrict__ mk = I.mask + base;
@@ -1151,7 +1165,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
       qv0[u] = update ? qb[ea] : 0.0;
       xv0[u] = update ? Fb[ea] : 0.0;
     }
-    XPlan<R> X(B, I.planx);
+    XPlan<R, SP> X(B, I.planx);
     if (update != 2) X.stage(twl, I.planx, staged, false);
     double alpha = 0.0;
     if (update) {
@@ -1261,12 +1275,14 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
 //   kColZ     forward along z, scale by 1/(lambda_x + lambda_y + lambda_z)^2,
 //             inverse along z;
 //   kColYInv  inverse along y.
-// All in place on t.
+// All in place on t.  SP: compile-time shape of the y axis for kCol2D (see
+// XPlan; then one packed row per item, Gc = 2), 0 for any shape.
 // ---------------------------------------------------------------------------
 
-template <typename R, int KIND>
+template <typename R, int KIND, int SP>
 __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, int count_iter,
                                                   int twoff) {
+  static_assert(SP == 0 || KIND == kCol2D, "compile-time shapes: two-dimensional pass only");
   using C = typename V2<R>::T;
   constexpr int kPass = KIND == kColZ ? kPassZ : kPassC;
   constexpr bool kStrided = KIND == kColZ;       // z pencils: stride ny
@@ -1300,8 +1316,8 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
       ps = 1;
       js = I.ny;
     } else {
-      n = I.ny;
-      Gp = I.Gc;
+      n = SP ? 1 << (SP >> 2) : I.ny;
+      Gp = SP ? 2 : I.Gc;
       plan = I.plany;
       c0 = c * Gp;
       cnt = min(Gp, I.nx * I.nz - c0);    // pencils (kx, z); nz = 1 in two dimensions
@@ -1343,7 +1359,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
       lam = Xx.lam[kx] + Xy.lam[min(ky0 + min((int)threadIdx.x, kMaxGc - 1), I.ny - 1)];
     }
     if (ctl->done) continue;
-    XPlan<R> X(B, plan);
+    XPlan<R, SP> X(B, plan);
     X.stage(twl, plan, staged, kScale);
     const int rows = Gp >> 1;
     const int st = X.stride();
@@ -1520,9 +1536,10 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
 // transform along x, restrict to U -> z; partial r.z and r.z_old.
 // ---------------------------------------------------------------------------
 
-template <typename R>
 // `lpar`: buffer parity of the iteration; the r.z partials written here are
-// the next iteration's current ones, rz(lpar ^ 1) (and rzo(lpar ^ 1)).
+// the next iteration's current ones, rz(lpar ^ 1) (and rzo(lpar ^ 1)).  SP as
+// in k_rowfwd.
+template <typename R, int SP>
 __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ Bp, int twoff,
                                                      int lpar) {
   using C = typename V2<R>::T;
@@ -1540,7 +1557,8 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
     BHX_GLOBAL Ctl* ctl = I.ctl;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
     const int par = lpar ^ 1;
-    const int nx = I.nx, ny = I.nrows, G = I.G, j0 = g * G;   // ny: rows of the pass
+    // ny: rows of the pass
+    const int nx = SP ? 1 << (SP >> 2) : I.nx, ny = I.nrows, G = SP ? 2 : I.G, j0 = g * G;
     BHX_GLOBAL const R* t = (BHX_GLOBAL const R*)I.t;
     // 1. issue together: `done` and the row group's unknown count (both
     //    unchanged during the pass), the first kPre transposed loads of the
@@ -1583,7 +1601,7 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
       rv0[u] = rb[ea];
       zo0[u] = flex ? zb[ea] : 0.0;
     }
-    XPlan<R> X(B, I.planx);
+    XPlan<R, SP> X(B, I.planx);
     X.stage(twl, I.planx, staged, false);
     const int rows = G >> 1;
     const int st = X.stride();
@@ -1885,37 +1903,88 @@ hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st) {
     hipLaunchKernelGGL(k_resid<2>, dim3(grid), dim3(kThreads), 0, st, B);
   return hipGetLastError();
 }
-hipError_t launch_rowfwd(const Batch* B, int prec, int update, int grid, int lds, int twoff,
-                         int lpar, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  if (prec == 0)
-    BHX_LAUNCH(k_rowfwd<double>, grid, lds, st, e0, e1, B, update, twoff, lpar);
-  else
-    BHX_LAUNCH(k_rowfwd<float>, grid, lds, st, e0, e1, B, update, twoff, lpar);
+// Compile-time shapes instantiated for the transform passes: 2^L nodes,
+// L = 9, 10, 11, Neumann (0) or periodic (1); FP64.
+#define BHX_SHAPES(X) X(9, 0) X(9, 1) X(10, 0) X(10, 1) X(11, 0) X(11, 1)
+
+// The environment variable BHX_SHAPE_KERNELS=0 keeps every launch on the
+// plan-table kernels (for comparing the two).
+int shape_key(int n_inst, int dim, int prec, int n, int m, int logm, int bluestein, int bc,
+              int rows_g) {
+  if (n_inst != 1 || dim != 2 || prec != 0 || rows_g != 2) return 0;
+  if (bluestein || n != m || (bc != kNeumann && bc != kPeriodic)) return 0;
+  if (logm < 9 || logm > 11) return 0;
+  const char* v = std::getenv("BHX_SHAPE_KERNELS");
+  if (v && v[0] == '0') return 0;
+  return (logm << 2) | bc;
+}
+
+hipError_t launch_rowfwd(const Batch* B, int prec, int shape, int update, int grid, int lds,
+                         int twoff, int lpar, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (prec != 0) {
+    BHX_LAUNCH((k_rowfwd<float, 0>), grid, lds, st, e0, e1, B, update, twoff, lpar);
+    return hipGetLastError();
+  }
+  switch (shape) {
+#define BHX_CASE(L, bc)                                                                    \
+  case (L << 2) | bc:                                                                      \
+    BHX_LAUNCH((k_rowfwd<double, (L << 2) | bc>), grid, lds, st, e0, e1, B, update, twoff, \
+               lpar);                                                                      \
+    break;
+    BHX_SHAPES(BHX_CASE)
+#undef BHX_CASE
+    case 0: BHX_LAUNCH((k_rowfwd<double, 0>), grid, lds, st, e0, e1, B, update, twoff, lpar); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 template <typename R>
 static hipError_t launch_col_prec(const Batch* B, int kind, int count_iter, int grid, int lds,
                                   int twoff, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   switch (kind) {
-    case kCol2D: BHX_LAUNCH((k_col<R, kCol2D>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
-    case kColYFwd: BHX_LAUNCH((k_col<R, kColYFwd>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
-    case kColZ: BHX_LAUNCH((k_col<R, kColZ>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
-    case kColYInv: BHX_LAUNCH((k_col<R, kColYInv>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
+    case kCol2D: BHX_LAUNCH((k_col<R, kCol2D, 0>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
+    case kColYFwd: BHX_LAUNCH((k_col<R, kColYFwd, 0>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
+    case kColZ: BHX_LAUNCH((k_col<R, kColZ, 0>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
+    case kColYInv: BHX_LAUNCH((k_col<R, kColYInv, 0>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
-hipError_t launch_col(const Batch* B, int prec, int kind, int count_iter, int grid, int lds,
-                      int twoff, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_col(const Batch* B, int prec, int shape, int kind, int count_iter, int grid,
+                      int lds, int twoff, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (shape != 0) {
+    if (prec != 0 || kind != kCol2D) return hipErrorInvalidValue;
+    switch (shape) {
+#define BHX_CASE(L, bc)                                                                    \
+  case (L << 2) | bc:                                                                      \
+    BHX_LAUNCH((k_col<double, kCol2D, (L << 2) | bc>), grid, lds, st, e0, e1, B, count_iter, \
+               twoff);                                                                     \
+    break;
+      BHX_SHAPES(BHX_CASE)
+#undef BHX_CASE
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   return prec == 0 ? launch_col_prec<double>(B, kind, count_iter, grid, lds, twoff, st, e0, e1)
                    : launch_col_prec<float>(B, kind, count_iter, grid, lds, twoff, st, e0, e1);
 }
-hipError_t launch_rowinv(const Batch* B, int prec, int grid, int lds, int twoff, int lpar,
-                         hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  if (prec == 0)
-    BHX_LAUNCH(k_rowinv<double>, grid, lds, st, e0, e1, B, twoff, lpar);
-  else
-    BHX_LAUNCH(k_rowinv<float>, grid, lds, st, e0, e1, B, twoff, lpar);
+hipError_t launch_rowinv(const Batch* B, int prec, int shape, int grid, int lds, int twoff,
+                         int lpar, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (prec != 0) {
+    BHX_LAUNCH((k_rowinv<float, 0>), grid, lds, st, e0, e1, B, twoff, lpar);
+    return hipGetLastError();
+  }
+  switch (shape) {
+#define BHX_CASE(L, bc)                                                                   \
+  case (L << 2) | bc:                                                                     \
+    BHX_LAUNCH((k_rowinv<double, (L << 2) | bc>), grid, lds, st, e0, e1, B, twoff, lpar); \
+    break;
+    BHX_SHAPES(BHX_CASE)
+#undef BHX_CASE
+    case 0: BHX_LAUNCH((k_rowinv<double, 0>), grid, lds, st, e0, e1, B, twoff, lpar); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 hipError_t launch_setup_rows(const Batch* B, int grid, hipStream_t st) {
@@ -1959,18 +2028,24 @@ hipError_t set_kernel_attributes() {
                                        kLdsDynMax);
     if (x != hipSuccess) e = x;
   };
-  set((const void*)k_rowfwd<double>);
-  set((const void*)k_rowfwd<float>);
-  set((const void*)k_col<double, kCol2D>);
-  set((const void*)k_col<float, kCol2D>);
-  set((const void*)k_col<double, kColYFwd>);
-  set((const void*)k_col<float, kColYFwd>);
-  set((const void*)k_col<double, kColZ>);
-  set((const void*)k_col<float, kColZ>);
-  set((const void*)k_col<double, kColYInv>);
-  set((const void*)k_col<float, kColYInv>);
-  set((const void*)k_rowinv<double>);
-  set((const void*)k_rowinv<float>);
+  set((const void*)k_rowfwd<double, 0>);
+  set((const void*)k_rowfwd<float, 0>);
+  set((const void*)k_col<double, kCol2D, 0>);
+  set((const void*)k_col<float, kCol2D, 0>);
+  set((const void*)k_col<double, kColYFwd, 0>);
+  set((const void*)k_col<float, kColYFwd, 0>);
+  set((const void*)k_col<double, kColZ, 0>);
+  set((const void*)k_col<float, kColZ, 0>);
+  set((const void*)k_col<double, kColYInv, 0>);
+  set((const void*)k_col<float, kColYInv, 0>);
+  set((const void*)k_rowinv<double, 0>);
+  set((const void*)k_rowinv<float, 0>);
+#define BHX_SET(L, bc)                                             \
+  set((const void*)k_rowfwd<double, (L << 2) | bc>);               \
+  set((const void*)k_col<double, kCol2D, (L << 2) | bc>);          \
+  set((const void*)k_rowinv<double, (L << 2) | bc>);
+  BHX_SHAPES(BHX_SET)
+#undef BHX_SET
   return e;
 }
 

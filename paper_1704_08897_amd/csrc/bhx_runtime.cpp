@@ -437,15 +437,16 @@ namespace {
 hipError_t launch_columns(const Batch* B, const Resolved& R, const Grids& g, int count_iter,
                           hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (g.dim == 2)
-    return launch_col(B, R.precision, kCol2D, count_iter, g.c, g.lds_c, g.tw_c, st, e0, e1);
+    return launch_col(B, R.precision, g.shape_c, kCol2D, count_iter, g.c, g.lds_c, g.tw_c, st,
+                      e0, e1);
   hipError_t e;
   if (e0 && (e = hipEventRecord(e0, st)) != hipSuccess) return e;
-  if ((e = launch_col(B, R.precision, kColYFwd, 0, g.c, g.lds_c, g.tw_c, st)) != hipSuccess)
+  if ((e = launch_col(B, R.precision, 0, kColYFwd, 0, g.c, g.lds_c, g.tw_c, st)) != hipSuccess)
     return e;
-  if ((e = launch_col(B, R.precision, kColZ, count_iter, g.z, g.lds_z, g.tw_z, st)) !=
+  if ((e = launch_col(B, R.precision, 0, kColZ, count_iter, g.z, g.lds_z, g.tw_z, st)) !=
       hipSuccess)
     return e;
-  if ((e = launch_col(B, R.precision, kColYInv, 0, g.c, g.lds_c, g.tw_c, st)) != hipSuccess)
+  if ((e = launch_col(B, R.precision, 0, kColYInv, 0, g.c, g.lds_c, g.tw_c, st)) != hipSuccess)
     return e;
   if (e1) return hipEventRecord(e1, st);
   return hipSuccess;
@@ -465,9 +466,12 @@ hipError_t launch_precond(const Batch* B, const Resolved& R, const Grids& g, hip
     if ((e = launch_identity(B, g.r, 1, st)) != hipSuccess) return e;
     return maybe_reduce(B, g, kRedRZ, 1, st);
   }
-  if ((e = launch_rowfwd(B, R.precision, 0, g.r, g.lds_r, g.tw_r, 1, st)) != hipSuccess) return e;
+  if ((e = launch_rowfwd(B, R.precision, g.shape_r, 0, g.r, g.lds_r, g.tw_r, 1, st)) !=
+      hipSuccess)
+    return e;
   if ((e = launch_columns(B, R, g, 0, st, nullptr, nullptr)) != hipSuccess) return e;
-  if ((e = launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, 1, st)) != hipSuccess) return e;
+  if ((e = launch_rowinv(B, R.precision, g.shape_r, g.r, g.lds_r, g.tw_r, 1, st)) != hipSuccess)
+    return e;
   return maybe_reduce(B, g, kRedRZ, 1, st);
 }
 
@@ -494,15 +498,16 @@ hipError_t launch_iterations(const Batch* B, int n_inst, const Resolved& R, cons
     BHX_TRY(launch_stencil(B, g.dim, kModeIter, g.s, par, st, e0(0, c), e1(0, c)));
     BHX_TRY(maybe_reduce(B, g, kRedPQ, par, st));
     if (R.precond) {
-      BHX_TRY(launch_rowfwd(B, R.precision, 1, g.r, g.lds_r, g.tw_r, par, st, e0(1, c),
-                            e1(1, c)));
+      BHX_TRY(launch_rowfwd(B, R.precision, g.shape_r, 1, g.r, g.lds_r, g.tw_r, par, st,
+                            e0(1, c), e1(1, c)));
       BHX_TRY(maybe_reduce(B, g, kRedRR, par, st));
       BHX_TRY(launch_columns(B, R, g, 1, st, e0(2, c), e1(2, c)));
-      BHX_TRY(launch_rowinv(B, R.precision, g.r, g.lds_r, g.tw_r, par, st, e0(3, c), e1(3, c)));
+      BHX_TRY(launch_rowinv(B, R.precision, g.shape_r, g.r, g.lds_r, g.tw_r, par, st, e0(3, c),
+                            e1(3, c)));
     } else {
       // plain CG: update-only row pass, iteration count, z = r
-      BHX_TRY(launch_rowfwd(B, R.precision, 2, g.r, g.lds_r, g.tw_r, par, st, e0(1, c),
-                            e1(1, c)));
+      BHX_TRY(launch_rowfwd(B, R.precision, g.shape_r, 2, g.r, g.lds_r, g.tw_r, par, st,
+                            e0(1, c), e1(1, c)));
       BHX_TRY(maybe_reduce(B, g, kRedRR, par, st));
       BHX_TRY(launch_bump(B, n_inst, st));
       BHX_TRY(launch_identity(B, g.r, par, st, e0(3, c), e1(3, c)));
@@ -544,6 +549,7 @@ hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved&
         gr.precond == R.precond && gr.gs == g.s && gr.gr == g.r && gr.gc == g.c &&
         gr.lds_r == g.lds_r && gr.tw_r == g.tw_r && gr.lds_c == g.lds_c && gr.tw_c == g.tw_c &&
         gr.dim == g.dim && gr.gz == g.z && gr.lds_z == g.lds_z && gr.tw_z == g.tw_z &&
+        gr.shape_r == g.shape_r && gr.shape_c == g.shape_c &&
         gr.profile == R.profile && (gr.exec != nullptr) == graph) {
       *used = &gr;
       if (gr.exec) return hipGraphLaunch(gr.exec, st);
@@ -557,6 +563,7 @@ hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved&
   G.gs = g.s; G.gr = g.r; G.gc = g.c; G.profile = R.profile;
   G.lds_r = g.lds_r; G.tw_r = g.tw_r; G.lds_c = g.lds_c; G.tw_c = g.tw_c;
   G.dim = g.dim; G.gz = g.z; G.lds_z = g.lds_z; G.tw_z = g.tw_z;
+  G.shape_r = g.shape_r; G.shape_c = g.shape_c;
   hipError_t e;
   if (R.profile && (e = make_events(&G.ev, R.chunk)) != hipSuccess) {
     free_graph(G);
@@ -776,6 +783,14 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
     g.tw_z = buf_z;
     g.lds_z = (buf_z + tab_z) * csize;
     if (g.lds_r > kLdsDynMax || g.lds_c > kLdsDynMax || g.lds_z > kLdsDynMax) return BHX_ERR_ARG;
+  }
+  {
+    const AxisPlan& PX = hd->plans.plan(px[0]);
+    const AxisPlan& PY = hd->plans.plan(py[0]);
+    g.shape_r = shape_key(n, dim, R.precision, PX.n, PX.m, PX.logm, PX.bluestein, PX.bc,
+                          lay[0].G);
+    g.shape_c = shape_key(n, dim, R.precision, PY.n, PY.m, PY.logm, PY.bluestein, PY.bc,
+                          lay[0].Gc);
   }
   *gout = g;
   return BHX_OK;

@@ -1,0 +1,109 @@
+"""GPU parity of the compile-time-shape transform kernels: one FP64 instance
+whose x or y axis has 512, 1024 or 2048 nodes with the Neumann or periodic
+rule runs instances of the row and column passes with that shape fixed at
+compile time.  Checked against the oracle's spectral preconditioner and sparse
+direct extension, and against the same launches with the shape kernels
+switched off (BHX_SHAPE_KERNELS=0, read at every call).
+
+Bounds: the preconditioner within relative L2 1e-11 of the oracle, as in the
+generic parity tests; the two kernel families perform the same operations in
+the same order (only constant folding and contraction differ), so their
+preconditioner outputs agree within 1e-13.  Solved fields at tol 1e-12 within
+1e-9 of the oracle (the star's conditioning, as in the full-size tests)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1704_08897_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1704_08897_amd import bhx  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def handle():
+    h = bhx.Handle(0)
+    yield h
+    h.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def apply_precond(handle, phi, r, bx, by):
+    out = dev(np.zeros_like(r))
+    assert bhx.debug_apply(handle, 1, dev(phi), dev(r), out, bc=bhx.BC(bx, by)) == bhx.OK
+    return host(out)
+
+
+# (nx, ny, bcx, bcy): both axes shaped; one shaped and one generic (Bluestein
+# length, Dirichlet rule); a length just outside the instantiated set
+CASES = [(512, 512, 0, 0), (1024, 512, 1, 0), (512, 2048, 0, 1), (2048, 1024, 1, 1),
+         (1024, 1000, 0, 0), (1000, 1024, 1, 0), (1024, 1023, 0, 2), (256, 1024, 0, 1)]
+
+
+@pytest.mark.parametrize("nx,ny,bx,by", CASES)
+def test_preconditioner_shapes(handle, monkeypatch, nx, ny, bx, by):
+    rng = np.random.default_rng(nx + 3 * ny + bx + by)
+    phi = -(rng.random((ny, nx)) - 0.3)
+    r = rng.normal(size=(ny, nx))
+    known = O.known_mask(phi)
+    ref = O.spectral_preconditioner(r, known, bx, by)
+    got = apply_precond(handle, phi, r, bx, by)
+    assert np.array_equal(got[known], np.zeros(known.sum()))
+    assert O.relative_l2(got, ref) <= 1e-11
+    monkeypatch.setenv("BHX_SHAPE_KERNELS", "0")
+    generic = apply_precond(handle, phi, r, bx, by)
+    assert O.relative_l2(got, generic) <= 1e-13
+
+
+def test_star1024_solve_shapes(handle, monkeypatch):
+    """The benchmark star through the shape kernels (both axes 1024, Neumann)
+    and through the generic ones: both meet the tolerance and the oracle."""
+    p = W.star_inward_problem(1024, tol=1e-12)
+    Fo, _ = O.extend_direct(p.phi, p.F, p.bcx, p.bcy)
+    K = O.known_mask(p.phi)
+    res = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BHX_SHAPE_KERNELS", flag)
+        G = dev(p.F)
+        s, st = bhx.extend_ex(handle, dev(p.phi), G, bc=p.bc, h=p.h, tol=p.tol)
+        assert s == bhx.OK, st.as_dict()
+        got = host(G)
+        assert np.array_equal(got[K], p.F[K])
+        assert O.true_relative_residual(K, p.F, got, p.bcx, p.bcy) <= p.tol * 1.001
+        assert O.relative_l2(got, Fo) <= 1e-9
+        res[flag] = (got, st.iterations)
+    # same Krylov method on operators equal to rounding: iteration counts close
+    assert abs(res["1"][1] - res["0"][1]) <= 0.05 * res["0"][1]
+
+
+@pytest.mark.parametrize("make", [lambda: W.peanut_problem(512, 1, 0, tol=1e-12),
+                                  lambda: W.annulus_problem(512, 0, 1, tol=1e-12)],
+                         ids=["peanut512_periodic_neumann", "annulus512_neumann_periodic"])
+def test_paper_masks_solve_shapes(handle, make):
+    """Examples 1 and 3's masks on shaped axes of both rules, against the
+    oracle's sparse direct extension."""
+    p = make()
+    Fo, _ = O.extend_direct(p.phi, p.F, p.bcx, p.bcy)
+    K = O.known_mask(p.phi)
+    G = dev(p.F)
+    s, st = bhx.extend_ex(handle, dev(p.phi), G, bc=p.bc, h=p.h, tol=p.tol)
+    assert s == bhx.OK, st.as_dict()
+    got = host(G)
+    assert np.array_equal(got[K], p.F[K])
+    assert O.true_relative_residual(K, p.F, got, p.bcx, p.bcy) <= p.tol * 1.001
+    assert O.relative_l2(got, Fo) <= 1e-9
