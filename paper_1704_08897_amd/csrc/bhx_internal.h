@@ -220,10 +220,11 @@ hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st);
 // of the twiddle table staged in LDS (after the largest packed-row buffer).
 // `shape`: 0 = kernels that read every shape from the plan table; otherwise
 // (L << 2) | bc of the pass's axis (2^L nodes, L = 9..11, Neumann or periodic,
-// FP64, one instance, one packed row per work item; launch_col: kCol2D only),
-// whose compile-time instance runs instead; shape_key() decides.
-int shape_key(int n_inst, int dim, int prec, int n, int m, int logm, int bluestein, int bc,
-              int rows_g);
+// FP64, two dimensions, one packed row per work item; launch_col: kCol2D
+// only), whose compile-time instance runs instead.  shape_key() gives it for
+// one instance's axis; a batch uses it when every instance has that axis plan
+// and row grouping.
+int shape_key(int dim, int prec, int n, int m, int logm, int bluestein, int bc, int rows_g);
 hipError_t launch_rowfwd(const Batch* B, int prec, int shape, int update, int grid, int lds,
                          int twoff, int lpar, hipStream_t st, hipEvent_t e0 = nullptr,
                          hipEvent_t e1 = nullptr);

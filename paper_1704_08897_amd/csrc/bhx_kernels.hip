@@ -1909,9 +1909,8 @@ hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st) {
 
 // The environment variable BHX_SHAPE_KERNELS=0 keeps every launch on the
 // plan-table kernels (for comparing the two).
-int shape_key(int n_inst, int dim, int prec, int n, int m, int logm, int bluestein, int bc,
-              int rows_g) {
-  if (n_inst != 1 || dim != 2 || prec != 0 || rows_g != 2) return 0;
+int shape_key(int dim, int prec, int n, int m, int logm, int bluestein, int bc, int rows_g) {
+  if (dim != 2 || prec != 0 || rows_g != 2) return 0;
   if (bluestein || n != m || (bc != kNeumann && bc != kPeriodic)) return 0;
   if (logm < 9 || logm > 11) return 0;
   const char* v = std::getenv("BHX_SHAPE_KERNELS");

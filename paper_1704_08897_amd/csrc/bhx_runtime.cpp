@@ -785,12 +785,17 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
     if (g.lds_r > kLdsDynMax || g.lds_c > kLdsDynMax || g.lds_z > kLdsDynMax) return BHX_ERR_ARG;
   }
   {
+    // compile-time-shape kernels when every instance shares the axis plan and
+    // the row grouping of instance 0
     const AxisPlan& PX = hd->plans.plan(px[0]);
     const AxisPlan& PY = hd->plans.plan(py[0]);
-    g.shape_r = shape_key(n, dim, R.precision, PX.n, PX.m, PX.logm, PX.bluestein, PX.bc,
-                          lay[0].G);
-    g.shape_c = shape_key(n, dim, R.precision, PY.n, PY.m, PY.logm, PY.bluestein, PY.bc,
-                          lay[0].Gc);
+    g.shape_r = shape_key(dim, R.precision, PX.n, PX.m, PX.logm, PX.bluestein, PX.bc, lay[0].G);
+    g.shape_c =
+        shape_key(dim, R.precision, PY.n, PY.m, PY.logm, PY.bluestein, PY.bc, lay[0].Gc);
+    for (int i = 1; i < n; ++i) {
+      if (px[i] != px[0] || lay[i].G != lay[0].G) g.shape_r = 0;
+      if (py[i] != py[0] || lay[i].Gc != lay[0].Gc) g.shape_c = 0;
+    }
   }
   *gout = g;
   return BHX_OK;

@@ -107,3 +107,36 @@ def test_paper_masks_solve_shapes(handle, make):
     assert np.array_equal(got[K], p.F[K])
     assert O.true_relative_residual(K, p.F, got, p.bcx, p.bcy) <= p.tol * 1.001
     assert O.relative_l2(got, Fo) <= 1e-9
+
+
+def test_fields_and_same_shape_batch(handle):
+    """Several fields on one phi, and a batch of two instances of one shape
+    (512 x 512, periodic x Neumann), run the shape kernels as a batch: each
+    result equals its own one-instance solve bit for bit (per-instance
+    reductions in a fixed order) and meets the oracle."""
+    p = W.peanut_problem(512, 1, 0, tol=1e-10)
+    ny, nx = p.F.shape
+    X, Y = np.meshgrid(np.arange(nx) / nx, np.arange(ny) / ny)
+    fields = [p.F, np.where(O.known_mask(p.phi), X**3 - Y, 0.0)]
+    Fs = [dev(f) for f in fields]
+    s, sts = bhx.extend_fields(handle, dev(p.phi), Fs, h=p.h, bc=p.bc, tol=p.tol)
+    assert s == bhx.OK
+    for f, G in zip(fields, Fs):
+        A = dev(f)
+        s1, _ = bhx.extend_ex(handle, dev(p.phi), A, bc=p.bc, h=p.h, tol=p.tol)
+        assert s1 == bhx.OK
+        assert np.array_equal(host(G), host(A))
+    q = W.annulus_problem(512, 1, 0, tol=1e-10)
+    batch = [p, q]
+    Bs = [dev(b.F) for b in batch]
+    s, sts = bhx.extend_batched(handle, [dev(b.phi) for b in batch], Bs, [b.h for b in batch],
+                                [b.bc for b in batch], [b.tol for b in batch])
+    assert s == bhx.OK
+    for b, G in zip(batch, Bs):
+        A = dev(b.F)
+        s1, _ = bhx.extend_ex(handle, dev(b.phi), A, bc=b.bc, h=b.h, tol=b.tol)
+        assert s1 == bhx.OK
+        got = host(G)
+        assert np.array_equal(got, host(A))
+        K = O.known_mask(b.phi)
+        assert O.true_relative_residual(K, b.F, got, b.bcx, b.bcy) <= b.tol * 1.001
