@@ -219,12 +219,13 @@ hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st);
 // Transform launches: `lds` dynamic LDS bytes, `twoff` complex-element offset
 // of the twiddle table staged in LDS (after the largest packed-row buffer).
 // `shape`: 0 = kernels that read every shape from the plan table; otherwise
-// (L << 2) | bc of the pass's axis (2^L nodes, L = 9..11, Neumann or periodic,
-// FP64, two dimensions, one packed row per work item; launch_col: kCol2D
-// only), whose compile-time instance runs instead.  shape_key() gives it for
-// one instance's axis; a batch uses it when every instance has that axis plan
-// and row grouping.
-int shape_key(int dim, int prec, int n, int m, int logm, int bluestein, int bc, int rows_g);
+// (G << 8) | (L << 2) | bc of the pass's axis and line group (2^L nodes,
+// Neumann or periodic, FP64, G lines per work item), whose compile-time
+// instance runs instead.  shape_key() gives it for one instance's axis of
+// pass family `pass` (ShapePass), or 0 when that shape is not instantiated; a
+// batch uses it when every instance has that axis plan and grouping.
+enum ShapePass { kShapeRow = 0, kShapeCol2D = 1, kShapeColY = 2, kShapeColZ = 3 };
+int shape_key(int pass, int prec, int n, int m, int logm, int bluestein, int bc, int group);
 hipError_t launch_rowfwd(const Batch* B, int prec, int shape, int update, int grid, int lds,
                          int twoff, int lpar, hipStream_t st, hipEvent_t e0 = nullptr,
                          hipEvent_t e1 = nullptr);

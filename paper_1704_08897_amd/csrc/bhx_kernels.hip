@@ -269,9 +269,10 @@ __device__ __forceinline__ int inv_index(int j, int n) {
 constexpr int kStageRound = 4;    // plan-table entries per thread per staging round
 
 // A transform plan as the kernels use it.  SP = 0 reads the shape from the
-// plan table; SP = (L << 2) | bc fixes it at compile time (a power-of-two
-// axis of 2^L nodes with the Neumann or periodic rule, no Bluestein), so that
-// the index arithmetic of every stage folds to constants.
+// plan table; SP = (G << 8) | (L << 2) | bc fixes it at compile time (a
+// power-of-two axis of 2^L nodes with the Neumann or periodic rule, no
+// Bluestein, G lines per work item), so that the index arithmetic of every
+// stage folds to constants.
 template <typename R, int SP = 0>
 struct XPlan {
   using C = typename V2<R>::T;
@@ -342,7 +343,7 @@ struct XPlan {
   __device__ XPlan(const Batch& B, int idx) {
     const AxisPlan P = B.plans[idx];
     if constexpr (SP != 0) {
-      logm = SP >> 2;
+      logm = (SP >> 2) & 63;
       n = nf = m = 1 << logm;
       blue = 0;
       bc = SP & 3;
@@ -1097,8 +1098,8 @@ __global__ void __launch_bounds__(kThreads) k_resid(const Batch* __restrict__ Bp
 // ---------------------------------------------------------------------------
 
 // `lpar`: buffer parity of the iteration (as in k_stencil): p_new = p[lpar ^ 1],
-// current r.z partials rz(lpar).  SP: compile-time shape of the x axis (see
-// XPlan; then one packed row per item, G = 2), 0 for any shape.
+// current r.z partials rz(lpar).  SP: compile-time shape of the x axis and
+// row group (see XPlan), 0 for any shape.
 template <typename R, int SP>
 __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ Bp, int update,
                                                      int twoff, int lpar) {
@@ -1117,7 +1118,8 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
     BHX_GLOBAL Ctl* ctl = I.ctl;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
     // ny: rows of the pass
-    const int nx = SP ? 1 << (SP >> 2) : I.nx, ny = I.nrows, G = SP ? 2 : I.G, j0 = g * G;
+    const int nx = SP ? 1 << ((SP >> 2) & 63) : I.nx, ny = I.nrows, G = SP ? SP >> 8 : I.G,
+              j0 = g * G;
     const int E = min(G, ny - j0) * nx;          // valid elements of this row group
     const size_t base = (size_t)j0 * nx;
     BHX_GLOBAL const uint8_t* __restrict__ mk = I.mask + base;
@@ -1275,14 +1277,13 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
 //   kColZ     forward along z, scale by 1/(lambda_x + lambda_y + lambda_z)^2,
 //             inverse along z;
 //   kColYInv  inverse along y.
-// All in place on t.  SP: compile-time shape of the y axis for kCol2D (see
-// XPlan; then one packed row per item, Gc = 2), 0 for any shape.
+// All in place on t.  SP: compile-time shape of the pass's axis and pencil
+// group (see XPlan), 0 for any shape.
 // ---------------------------------------------------------------------------
 
 template <typename R, int KIND, int SP>
 __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, int count_iter,
                                                   int twoff) {
-  static_assert(SP == 0 || KIND == kCol2D, "compile-time shapes: two-dimensional pass only");
   using C = typename V2<R>::T;
   constexpr int kPass = KIND == kColZ ? kPassZ : kPassC;
   constexpr bool kStrided = KIND == kColZ;       // z pencils: stride ny
@@ -1305,8 +1306,8 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
     int n, Gp, cnt, ps, js, plan, c0 = 0, kx = 0, ky0 = 0;
     size_t pb;
     if constexpr (kStrided) {
-      n = I.nz;
-      Gp = I.Gz;
+      n = SP ? 1 << ((SP >> 2) & 63) : I.nz;
+      Gp = SP ? SP >> 8 : I.Gz;
       plan = I.planz;
       const int ngy = (I.ny + Gp - 1) / Gp;
       kx = c / ngy;
@@ -1316,8 +1317,8 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
       ps = 1;
       js = I.ny;
     } else {
-      n = SP ? 1 << (SP >> 2) : I.ny;
-      Gp = SP ? 2 : I.Gc;
+      n = SP ? 1 << ((SP >> 2) & 63) : I.ny;
+      Gp = SP ? SP >> 8 : I.Gc;
       plan = I.plany;
       c0 = c * Gp;
       cnt = min(Gp, I.nx * I.nz - c0);    // pencils (kx, z); nz = 1 in two dimensions
@@ -1558,7 +1559,8 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
     const int par = lpar ^ 1;
     // ny: rows of the pass
-    const int nx = SP ? 1 << (SP >> 2) : I.nx, ny = I.nrows, G = SP ? 2 : I.G, j0 = g * G;
+    const int nx = SP ? 1 << ((SP >> 2) & 63) : I.nx, ny = I.nrows, G = SP ? SP >> 8 : I.G,
+              j0 = g * G;
     BHX_GLOBAL const R* t = (BHX_GLOBAL const R*)I.t;
     // 1. issue together: `done` and the row group's unknown count (both
     //    unchanged during the pass), the first kPre transposed loads of the
@@ -1903,19 +1905,38 @@ hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st) {
     hipLaunchKernelGGL(k_resid<2>, dim3(grid), dim3(kThreads), 0, st, B);
   return hipGetLastError();
 }
-// Compile-time shapes instantiated for the transform passes: 2^L nodes,
-// L = 9, 10, 11, Neumann (0) or periodic (1); FP64.
-#define BHX_SHAPES(X) X(9, 0) X(9, 1) X(10, 0) X(10, 1) X(11, 0) X(11, 1)
+// Compile-time shapes instantiated per pass family, as (G, L, bc): G lines
+// per work item, 2^L nodes, Neumann (0) or periodic (1); FP64.  Two
+// dimensions: 512-2048 nodes, one packed row per item; three dimensions:
+// 256 nodes, the groups the layout gives 256^3 (rows and y pencils 8, z 16).
+#define BHX_ROW_SHAPES(X) \
+  X(2, 9, 0) X(2, 9, 1) X(2, 10, 0) X(2, 10, 1) X(2, 11, 0) X(2, 11, 1) X(8, 8, 0) X(8, 8, 1)
+#define BHX_COL2D_SHAPES(X) \
+  X(2, 9, 0) X(2, 9, 1) X(2, 10, 0) X(2, 10, 1) X(2, 11, 0) X(2, 11, 1)
+#define BHX_COLY_SHAPES(X) X(8, 8, 0) X(8, 8, 1)
+#define BHX_COLZ_SHAPES(X) X(16, 8, 0) X(16, 8, 1)
+#define BHX_KEY(G, L, bc) (((G) << 8) | ((L) << 2) | (bc))
 
 // The environment variable BHX_SHAPE_KERNELS=0 keeps every launch on the
 // plan-table kernels (for comparing the two).
-int shape_key(int dim, int prec, int n, int m, int logm, int bluestein, int bc, int rows_g) {
-  if (dim != 2 || prec != 0 || rows_g != 2) return 0;
-  if (bluestein || n != m || (bc != kNeumann && bc != kPeriodic)) return 0;
-  if (logm < 9 || logm > 11) return 0;
+int shape_key(int pass, int prec, int n, int m, int logm, int bluestein, int bc, int group) {
+  if (prec != 0 || bluestein || n != m || (bc != kNeumann && bc != kPeriodic)) return 0;
+  if (logm < 1 || logm > 15 || group < 2 || group > 64) return 0;
+  const int key = BHX_KEY(group, logm, bc);
+  bool listed = false;
+#define BHX_IS(G, L, b) listed = listed || key == BHX_KEY(G, L, b);
+  switch (pass) {
+    case kShapeRow: BHX_ROW_SHAPES(BHX_IS) break;
+    case kShapeCol2D: BHX_COL2D_SHAPES(BHX_IS) break;
+    case kShapeColY: BHX_COLY_SHAPES(BHX_IS) break;
+    case kShapeColZ: BHX_COLZ_SHAPES(BHX_IS) break;
+    default: break;
+  }
+#undef BHX_IS
+  if (!listed) return 0;
   const char* v = std::getenv("BHX_SHAPE_KERNELS");
   if (v && v[0] == '0') return 0;
-  return (logm << 2) | bc;
+  return key;
 }
 
 hipError_t launch_rowfwd(const Batch* B, int prec, int shape, int update, int grid, int lds,
@@ -1925,12 +1946,12 @@ hipError_t launch_rowfwd(const Batch* B, int prec, int shape, int update, int gr
     return hipGetLastError();
   }
   switch (shape) {
-#define BHX_CASE(L, bc)                                                                    \
-  case (L << 2) | bc:                                                                      \
-    BHX_LAUNCH((k_rowfwd<double, (L << 2) | bc>), grid, lds, st, e0, e1, B, update, twoff, \
-               lpar);                                                                      \
+#define BHX_CASE(G, L, bc)                                                              \
+  case BHX_KEY(G, L, bc):                                                               \
+    BHX_LAUNCH((k_rowfwd<double, BHX_KEY(G, L, bc)>), grid, lds, st, e0, e1, B, update, \
+               twoff, lpar);                                                            \
     break;
-    BHX_SHAPES(BHX_CASE)
+    BHX_ROW_SHAPES(BHX_CASE)
 #undef BHX_CASE
     case 0: BHX_LAUNCH((k_rowfwd<double, 0>), grid, lds, st, e0, e1, B, update, twoff, lpar); break;
     default: return hipErrorInvalidValue;
@@ -1952,17 +1973,36 @@ static hipError_t launch_col_prec(const Batch* B, int kind, int count_iter, int 
 hipError_t launch_col(const Batch* B, int prec, int shape, int kind, int count_iter, int grid,
                       int lds, int twoff, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (shape != 0) {
-    if (prec != 0 || kind != kCol2D) return hipErrorInvalidValue;
-    switch (shape) {
-#define BHX_CASE(L, bc)                                                                    \
-  case (L << 2) | bc:                                                                      \
-    BHX_LAUNCH((k_col<double, kCol2D, (L << 2) | bc>), grid, lds, st, e0, e1, B, count_iter, \
-               twoff);                                                                     \
+    if (prec != 0) return hipErrorInvalidValue;
+#define BHX_CASE_K(K, G, L, bc)                                                          \
+  case BHX_KEY(G, L, bc):                                                                \
+    BHX_LAUNCH((k_col<double, K, BHX_KEY(G, L, bc)>), grid, lds, st, e0, e1, B, count_iter, \
+               twoff);                                                                   \
     break;
-      BHX_SHAPES(BHX_CASE)
-#undef BHX_CASE
+#define BHX_CASE_2D(G, L, bc) BHX_CASE_K(kCol2D, G, L, bc)
+#define BHX_CASE_YF(G, L, bc) BHX_CASE_K(kColYFwd, G, L, bc)
+#define BHX_CASE_YI(G, L, bc) BHX_CASE_K(kColYInv, G, L, bc)
+#define BHX_CASE_Z(G, L, bc) BHX_CASE_K(kColZ, G, L, bc)
+    switch (kind) {
+      case kCol2D:
+        switch (shape) { BHX_COL2D_SHAPES(BHX_CASE_2D) default: return hipErrorInvalidValue; }
+        break;
+      case kColYFwd:
+        switch (shape) { BHX_COLY_SHAPES(BHX_CASE_YF) default: return hipErrorInvalidValue; }
+        break;
+      case kColYInv:
+        switch (shape) { BHX_COLY_SHAPES(BHX_CASE_YI) default: return hipErrorInvalidValue; }
+        break;
+      case kColZ:
+        switch (shape) { BHX_COLZ_SHAPES(BHX_CASE_Z) default: return hipErrorInvalidValue; }
+        break;
       default: return hipErrorInvalidValue;
     }
+#undef BHX_CASE_2D
+#undef BHX_CASE_YF
+#undef BHX_CASE_YI
+#undef BHX_CASE_Z
+#undef BHX_CASE_K
     return hipGetLastError();
   }
   return prec == 0 ? launch_col_prec<double>(B, kind, count_iter, grid, lds, twoff, st, e0, e1)
@@ -1975,11 +2015,11 @@ hipError_t launch_rowinv(const Batch* B, int prec, int shape, int grid, int lds,
     return hipGetLastError();
   }
   switch (shape) {
-#define BHX_CASE(L, bc)                                                                   \
-  case (L << 2) | bc:                                                                     \
-    BHX_LAUNCH((k_rowinv<double, (L << 2) | bc>), grid, lds, st, e0, e1, B, twoff, lpar); \
+#define BHX_CASE(G, L, bc)                                                                 \
+  case BHX_KEY(G, L, bc):                                                                  \
+    BHX_LAUNCH((k_rowinv<double, BHX_KEY(G, L, bc)>), grid, lds, st, e0, e1, B, twoff, lpar); \
     break;
-    BHX_SHAPES(BHX_CASE)
+    BHX_ROW_SHAPES(BHX_CASE)
 #undef BHX_CASE
     case 0: BHX_LAUNCH((k_rowinv<double, 0>), grid, lds, st, e0, e1, B, twoff, lpar); break;
     default: return hipErrorInvalidValue;
@@ -2039,12 +2079,22 @@ hipError_t set_kernel_attributes() {
   set((const void*)k_col<float, kColYInv, 0>);
   set((const void*)k_rowinv<double, 0>);
   set((const void*)k_rowinv<float, 0>);
-#define BHX_SET(L, bc)                                             \
-  set((const void*)k_rowfwd<double, (L << 2) | bc>);               \
-  set((const void*)k_col<double, kCol2D, (L << 2) | bc>);          \
-  set((const void*)k_rowinv<double, (L << 2) | bc>);
-  BHX_SHAPES(BHX_SET)
-#undef BHX_SET
+#define BHX_SET_ROW(G, L, bc)                                        \
+  set((const void*)k_rowfwd<double, BHX_KEY(G, L, bc)>);             \
+  set((const void*)k_rowinv<double, BHX_KEY(G, L, bc)>);
+#define BHX_SET_2D(G, L, bc) set((const void*)k_col<double, kCol2D, BHX_KEY(G, L, bc)>);
+#define BHX_SET_Y(G, L, bc)                                          \
+  set((const void*)k_col<double, kColYFwd, BHX_KEY(G, L, bc)>);      \
+  set((const void*)k_col<double, kColYInv, BHX_KEY(G, L, bc)>);
+#define BHX_SET_Z(G, L, bc) set((const void*)k_col<double, kColZ, BHX_KEY(G, L, bc)>);
+  BHX_ROW_SHAPES(BHX_SET_ROW)
+  BHX_COL2D_SHAPES(BHX_SET_2D)
+  BHX_COLY_SHAPES(BHX_SET_Y)
+  BHX_COLZ_SHAPES(BHX_SET_Z)
+#undef BHX_SET_ROW
+#undef BHX_SET_2D
+#undef BHX_SET_Y
+#undef BHX_SET_Z
   return e;
 }
 

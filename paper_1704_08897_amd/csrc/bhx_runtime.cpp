@@ -441,12 +441,14 @@ hipError_t launch_columns(const Batch* B, const Resolved& R, const Grids& g, int
                       e0, e1);
   hipError_t e;
   if (e0 && (e = hipEventRecord(e0, st)) != hipSuccess) return e;
-  if ((e = launch_col(B, R.precision, 0, kColYFwd, 0, g.c, g.lds_c, g.tw_c, st)) != hipSuccess)
-    return e;
-  if ((e = launch_col(B, R.precision, 0, kColZ, count_iter, g.z, g.lds_z, g.tw_z, st)) !=
+  if ((e = launch_col(B, R.precision, g.shape_c, kColYFwd, 0, g.c, g.lds_c, g.tw_c, st)) !=
       hipSuccess)
     return e;
-  if ((e = launch_col(B, R.precision, 0, kColYInv, 0, g.c, g.lds_c, g.tw_c, st)) != hipSuccess)
+  if ((e = launch_col(B, R.precision, g.shape_z, kColZ, count_iter, g.z, g.lds_z, g.tw_z, st)) !=
+      hipSuccess)
+    return e;
+  if ((e = launch_col(B, R.precision, g.shape_c, kColYInv, 0, g.c, g.lds_c, g.tw_c, st)) !=
+      hipSuccess)
     return e;
   if (e1) return hipEventRecord(e1, st);
   return hipSuccess;
@@ -549,7 +551,7 @@ hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved&
         gr.precond == R.precond && gr.gs == g.s && gr.gr == g.r && gr.gc == g.c &&
         gr.lds_r == g.lds_r && gr.tw_r == g.tw_r && gr.lds_c == g.lds_c && gr.tw_c == g.tw_c &&
         gr.dim == g.dim && gr.gz == g.z && gr.lds_z == g.lds_z && gr.tw_z == g.tw_z &&
-        gr.shape_r == g.shape_r && gr.shape_c == g.shape_c &&
+        gr.shape_r == g.shape_r && gr.shape_c == g.shape_c && gr.shape_z == g.shape_z &&
         gr.profile == R.profile && (gr.exec != nullptr) == graph) {
       *used = &gr;
       if (gr.exec) return hipGraphLaunch(gr.exec, st);
@@ -563,7 +565,7 @@ hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved&
   G.gs = g.s; G.gr = g.r; G.gc = g.c; G.profile = R.profile;
   G.lds_r = g.lds_r; G.tw_r = g.tw_r; G.lds_c = g.lds_c; G.tw_c = g.tw_c;
   G.dim = g.dim; G.gz = g.z; G.lds_z = g.lds_z; G.tw_z = g.tw_z;
-  G.shape_r = g.shape_r; G.shape_c = g.shape_c;
+  G.shape_r = g.shape_r; G.shape_c = g.shape_c; G.shape_z = g.shape_z;
   hipError_t e;
   if (R.profile && (e = make_events(&G.ev, R.chunk)) != hipSuccess) {
     free_graph(G);
@@ -786,14 +788,16 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
   }
   {
     // compile-time-shape kernels when every instance shares the axis plan and
-    // the row grouping of instance 0
-    const AxisPlan& PX = hd->plans.plan(px[0]);
-    const AxisPlan& PY = hd->plans.plan(py[0]);
-    g.shape_r = shape_key(dim, R.precision, PX.n, PX.m, PX.logm, PX.bluestein, PX.bc, lay[0].G);
-    g.shape_c =
-        shape_key(dim, R.precision, PY.n, PY.m, PY.logm, PY.bluestein, PY.bc, lay[0].Gc);
+    // the line grouping of instance 0
+    auto key = [&](int pass, const AxisPlan& P, int group) {
+      return shape_key(pass, R.precision, P.n, P.m, P.logm, P.bluestein, P.bc, group);
+    };
+    g.shape_r = key(kShapeRow, hd->plans.plan(px[0]), lay[0].G);
+    g.shape_c = key(dim == 3 ? kShapeColY : kShapeCol2D, hd->plans.plan(py[0]), lay[0].Gc);
+    g.shape_z = dim == 3 ? key(kShapeColZ, hd->plans.plan(pz[0]), lay[0].Gz) : 0;
     for (int i = 1; i < n; ++i) {
       if (px[i] != px[0] || lay[i].G != lay[0].G) g.shape_r = 0;
+      if (pz[i] != pz[0] || lay[i].Gz != lay[0].Gz) g.shape_z = 0;
       if (py[i] != py[0] || lay[i].Gc != lay[0].Gc) g.shape_c = 0;
     }
   }

@@ -99,7 +99,7 @@ struct Grids {
   int z = 0, lds_z = 0, tw_z = 0;   // z pass (three dimensions)
   int count = 0;           // instances of the batch
   int reduce = 0;          // 1: some instance has Inst::reduce (k_reduce launches)
-  int shape_r = 0, shape_c = 0;   // compile-time shapes of the x and y passes (shape_key)
+  int shape_r = 0, shape_c = 0, shape_z = 0;   // compile-time shapes of the passes (shape_key)
 };
 
 struct Graph {
@@ -109,7 +109,7 @@ struct Graph {
   int count = 0;
   int prec = -1, chunk = 0, precond = -1, gs = 0, gr = 0, gc = 0, profile = 0;
   int lds_r = 0, tw_r = 0, lds_c = 0, tw_c = 0;
-  int dim = 2, gz = 0, lds_z = 0, tw_z = 0, reduce = 0, shape_r = 0, shape_c = 0;
+  int dim = 2, gz = 0, lds_z = 0, tw_z = 0, reduce = 0, shape_r = 0, shape_c = 0, shape_z = 0;
   std::vector<hipEvent_t> ev;   // [pass][iteration][start, end] when profiling
 };
 

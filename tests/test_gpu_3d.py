@@ -248,3 +248,50 @@ def test_reduced_scalars_mode(handle):
         assert np.array_equal(got2[K], p.F[K])
         assert O.true_relative_residual_3d(K, p.F, got2, p.bcx, p.bcy, p.bcz) <= 1e-6 * 1.001
     assert st2.iterations > 5 * st.iterations          # plain CG needs far more
+
+
+# Compile-time-shape instances in three dimensions (256-node Neumann or
+# periodic axes with the groups the layout gives: rows and y pencils 8, z
+# pencils 16).  256 x 256 x 64 runs the row and y shapes with a plan-table z
+# pass; 128 x 64 x 256 the z shape alone.  Bounds as above against the oracle;
+# against the plan-table kernels (BHX_SHAPE_KERNELS=0) 1e-13, since both
+# perform the same operations in the same order.
+@pytest.mark.parametrize("nx,ny,nz,bx,by,bz", [(256, 256, 64, 1, 1, 1), (256, 256, 64, 0, 0, 0),
+                                              (128, 64, 256, 0, 1, 1)])
+def test_preconditioner_3d_shapes(handle, monkeypatch, nx, ny, nz, bx, by, bz):
+    rng = np.random.default_rng(nx + ny + nz + bx)
+    phi = random_phi3(rng, nx, ny, nz, 0.3)
+    r = rng.normal(size=(nz, ny, nx))
+    known = O.known_mask(phi)
+    ref = O.spectral_preconditioner_3d(r, known, bx, by, bz)
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BHX_SHAPE_KERNELS", flag)
+        out = dev(np.zeros((nz, ny, nx)))
+        assert bhx.debug_apply3d(handle, 1, dev(phi), dev(r), out, bc=bhx.BC3(bx, by, bz)) == bhx.OK
+        outs.append(host(out))
+    assert np.array_equal(outs[0][known], np.zeros(known.sum()))
+    assert O.relative_l2(outs[0], ref) <= 1e-11
+    assert O.relative_l2(outs[0], outs[1]) <= 1e-13
+
+
+def test_example2_256_shapes(handle, monkeypatch):
+    """Example 2 at 256^3 (16.8 M nodes) through the shape kernels and the
+    plan-table kernels: Table 3's 276 iterations within 8 %, the residual
+    recomputed on the CPU meets tol, known values bit-exact, the near error
+    within 15 % of the table's 2.84e-3; the two runs' iteration counts within
+    2 %."""
+    p = W.peanut3d_problem(256)
+    K = O.known_mask(p.phi)
+    its = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BHX_SHAPE_KERNELS", flag)
+        s, st, got = solve3(handle, p)
+        assert s == bhx.OK, st.as_dict()
+        assert abs(st.iterations - 276) <= 0.08 * 276, st.iterations
+        assert np.array_equal(got[K], p.F[K])
+        res = O.true_relative_residual_3d(K, p.F, got, p.bcx, p.bcy, p.bcz)
+        assert res <= 1e-6 * 1.001
+        assert abs(_near_error(p, got) - 2.84e-3) <= 0.15 * 2.84e-3
+        its.append(st.iterations)
+    assert abs(its[0] - its[1]) <= 0.02 * its[1]
