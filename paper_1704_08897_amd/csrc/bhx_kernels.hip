@@ -837,11 +837,23 @@ __global__ void __launch_bounds__(kThreads, DIM == 3 ? 3 : 2)
     int oo[kPL];
     double sg[kPL], va[kPL], vb[kPL];
     uint8_t vm[kPL], mo[kOut];
+    // a tile whose halo lies inside the grid on every axis needs no ghost
+    // rule: the offsets are affine in the box coordinates (most tiles of a
+    // large grid; the same values as the general path)
+    const bool interior = i0 >= 2 && i0 + G::PX - 2 <= nx && j0 >= 2 && j0 + G::PY - 2 <= ny &&
+                          (DIM == 2 || (k0 >= 2 && k0 + G::PZ - 2 <= nz));
+    const int base = DIM == 2 ? (j0 - 2) * nx + (i0 - 2)
+                              : ((k0 - 2) * ny + (j0 - 2)) * nx + (i0 - 2);
 #pragma unroll
     for (int s = 0; s < kPL; ++s) {
       const int e = min((int)threadIdx.x + s * kThreads, kPN - 1);
       int ii, jj, kk;
       G::template coords<G::PX, G::PY>(e, ii, jj, kk);
+      if (interior) {
+        sg[s] = 1.0;
+        oo[s] = base + (kk * ny + jj) * nx + ii;
+        continue;
+      }
       double sx, sy;
       const int mi = map_axis_sel(i0 + ii - 2, nx, I.bcx, sx);
       const int mj = map_axis_sel(j0 + jj - 2, ny, I.bcy, sy);
