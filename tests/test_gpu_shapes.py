@@ -50,9 +50,12 @@ def apply_precond(handle, phi, r, bx, by):
 
 
 # (nx, ny, bcx, bcy): both axes shaped; one shaped and one generic (Bluestein
-# length, Dirichlet rule); a length just outside the instantiated set
+# length, Dirichlet rule); a length just outside the instantiated set; ragged
+# last groups on a shaped axis (an odd row count under the x shape, an odd
+# column count under the y shape)
 CASES = [(512, 512, 0, 0), (1024, 512, 1, 0), (512, 2048, 0, 1), (2048, 1024, 1, 1),
-         (1024, 1000, 0, 0), (1000, 1024, 1, 0), (1024, 1023, 0, 2), (256, 1024, 0, 1)]
+         (1024, 1000, 0, 0), (1000, 1024, 1, 0), (1024, 1023, 0, 2), (256, 1024, 0, 1),
+         (1024, 333, 1, 0), (257, 1024, 0, 1), (2048, 77, 0, 0)]
 
 
 @pytest.mark.parametrize("nx,ny,bx,by", CASES)
