@@ -26,7 +26,10 @@
 // Scalars never cross blocks inside a kernel: a producer writes one partial
 // sum per work item; every consumer item reduces the partial array itself in
 // a fixed order, so each block computes bit-identical alpha/beta and the
-// result does not depend on scheduling or on the batch composition.
+// result does not depend on scheduling or on the batch composition (within
+// one kernel family: the compile-time-shape instances run only when every
+// instance of a launch shares the shape, and agree with the plan-table ones
+// to rounding).
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 #include <stdint.h>

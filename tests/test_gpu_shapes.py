@@ -143,3 +143,26 @@ def test_fields_and_same_shape_batch(handle):
         assert np.array_equal(got, host(A))
         K = O.known_mask(b.phi)
         assert O.true_relative_residual(K, b.F, got, b.bcx, b.bcy) <= b.tol * 1.001
+
+
+def test_mixed_batch_runs_plan_table_family(handle):
+    """A shaped instance (512 x 512, periodic x Neumann) batched with a
+    differently shaped one runs the plan-table kernels: it meets the residual
+    bar and agrees with its solo (shape-kernel) solve to the solves' accuracy,
+    not bit for bit (a batch of equal shapes does reproduce the solo solve bit
+    for bit, test_fields_and_same_shape_batch)."""
+    p = W.peanut_problem(512, 1, 0, tol=1e-12)
+    q = W.circle_problem(64, tol=1e-12)
+    Bs = [dev(p.F), dev(q.F)]
+    s, sts = bhx.extend_batched(handle, [dev(p.phi), dev(q.phi)], Bs, [p.h, q.h], [p.bc, q.bc],
+                                [p.tol, q.tol])
+    assert s == bhx.OK
+    got = host(Bs[0])
+    A = dev(p.F)
+    s1, _ = bhx.extend_ex(handle, dev(p.phi), A, bc=p.bc, h=p.h, tol=p.tol)
+    assert s1 == bhx.OK
+    solo = host(A)
+    K = O.known_mask(p.phi)
+    assert np.array_equal(got[K], p.F[K])
+    assert O.true_relative_residual(K, p.F, got, p.bcx, p.bcy) <= p.tol * 1.001
+    assert O.relative_l2(got, solo) <= 1e-9
