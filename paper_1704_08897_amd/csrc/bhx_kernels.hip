@@ -1921,9 +1921,10 @@ hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 // Compile-time shapes instantiated per pass family, as (G, L, bc): G lines
-// per work item, 2^L nodes, Neumann (0) or periodic (1); FP64.  Two
-// dimensions: 512-2048 nodes, one packed row per item; three dimensions:
-// 256 nodes, the groups the layout gives 256^3 (rows and y pencils 8, z 16).
+// per work item, 2^L nodes, Neumann (0) or periodic (1).  Two dimensions:
+// 512-2048 nodes, one packed row per item, FP64 and FP32 transforms; three
+// dimensions (FP64): 256 nodes, the groups the layout gives 256^3 (rows and y
+// pencils 8, z 16).
 #define BHX_ROW_SHAPES(X) \
   X(2, 9, 0) X(2, 9, 1) X(2, 10, 0) X(2, 10, 1) X(2, 11, 0) X(2, 11, 1) X(8, 8, 0) X(8, 8, 1)
 #define BHX_COL2D_SHAPES(X) \
@@ -1935,7 +1936,8 @@ hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st) {
 // The environment variable BHX_SHAPE_KERNELS=0 keeps every launch on the
 // plan-table kernels (for comparing the two).
 int shape_key(int pass, int prec, int n, int m, int logm, int bluestein, int bc, int group) {
-  if (prec != 0 || bluestein || n != m || (bc != kNeumann && bc != kPeriodic)) return 0;
+  if (bluestein || n != m || (bc != kNeumann && bc != kPeriodic)) return 0;
+  if (prec != 0 && (group != 2 || (pass != kShapeRow && pass != kShapeCol2D))) return 0;
   if (logm < 1 || logm > 15 || group < 2 || group > 64) return 0;
   const int key = BHX_KEY(group, logm, bc);
   bool listed = false;
@@ -1957,7 +1959,17 @@ int shape_key(int pass, int prec, int n, int m, int logm, int bluestein, int bc,
 hipError_t launch_rowfwd(const Batch* B, int prec, int shape, int update, int grid, int lds,
                          int twoff, int lpar, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (prec != 0) {
-    BHX_LAUNCH((k_rowfwd<float, 0>), grid, lds, st, e0, e1, B, update, twoff, lpar);
+    switch (shape) {
+#define BHX_CASE(G, L, bc)                                                             \
+  case BHX_KEY(G, L, bc):                                                              \
+    BHX_LAUNCH((k_rowfwd<float, BHX_KEY(G, L, bc)>), grid, lds, st, e0, e1, B, update, \
+               twoff, lpar);                                                           \
+    break;
+      BHX_COL2D_SHAPES(BHX_CASE)
+#undef BHX_CASE
+      case 0: BHX_LAUNCH((k_rowfwd<float, 0>), grid, lds, st, e0, e1, B, update, twoff, lpar); break;
+      default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
   switch (shape) {
@@ -1987,8 +1999,21 @@ static hipError_t launch_col_prec(const Batch* B, int kind, int count_iter, int 
 }
 hipError_t launch_col(const Batch* B, int prec, int shape, int kind, int count_iter, int grid,
                       int lds, int twoff, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (shape != 0 && prec != 0) {
+    if (kind != kCol2D) return hipErrorInvalidValue;
+    switch (shape) {
+#define BHX_CASE_F(G, L, bc)                                                               \
+  case BHX_KEY(G, L, bc):                                                                  \
+    BHX_LAUNCH((k_col<float, kCol2D, BHX_KEY(G, L, bc)>), grid, lds, st, e0, e1, B,        \
+               count_iter, twoff);                                                         \
+    break;
+      BHX_COL2D_SHAPES(BHX_CASE_F)
+#undef BHX_CASE_F
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   if (shape != 0) {
-    if (prec != 0) return hipErrorInvalidValue;
 #define BHX_CASE_K(K, G, L, bc)                                                          \
   case BHX_KEY(G, L, bc):                                                                \
     BHX_LAUNCH((k_col<double, K, BHX_KEY(G, L, bc)>), grid, lds, st, e0, e1, B, count_iter, \
@@ -2026,7 +2051,16 @@ hipError_t launch_col(const Batch* B, int prec, int shape, int kind, int count_i
 hipError_t launch_rowinv(const Batch* B, int prec, int shape, int grid, int lds, int twoff,
                          int lpar, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (prec != 0) {
-    BHX_LAUNCH((k_rowinv<float, 0>), grid, lds, st, e0, e1, B, twoff, lpar);
+    switch (shape) {
+#define BHX_CASE(G, L, bc)                                                                \
+  case BHX_KEY(G, L, bc):                                                                 \
+    BHX_LAUNCH((k_rowinv<float, BHX_KEY(G, L, bc)>), grid, lds, st, e0, e1, B, twoff, lpar); \
+    break;
+      BHX_COL2D_SHAPES(BHX_CASE)
+#undef BHX_CASE
+      case 0: BHX_LAUNCH((k_rowinv<float, 0>), grid, lds, st, e0, e1, B, twoff, lpar); break;
+      default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
   switch (shape) {
@@ -2097,7 +2131,11 @@ hipError_t set_kernel_attributes() {
 #define BHX_SET_ROW(G, L, bc)                                        \
   set((const void*)k_rowfwd<double, BHX_KEY(G, L, bc)>);             \
   set((const void*)k_rowinv<double, BHX_KEY(G, L, bc)>);
-#define BHX_SET_2D(G, L, bc) set((const void*)k_col<double, kCol2D, BHX_KEY(G, L, bc)>);
+#define BHX_SET_2D(G, L, bc)                                         \
+  set((const void*)k_col<double, kCol2D, BHX_KEY(G, L, bc)>);        \
+  set((const void*)k_col<float, kCol2D, BHX_KEY(G, L, bc)>);         \
+  set((const void*)k_rowfwd<float, BHX_KEY(G, L, bc)>);              \
+  set((const void*)k_rowinv<float, BHX_KEY(G, L, bc)>);
 #define BHX_SET_Y(G, L, bc)                                          \
   set((const void*)k_col<double, kColYFwd, BHX_KEY(G, L, bc)>);      \
   set((const void*)k_col<double, kColYInv, BHX_KEY(G, L, bc)>);

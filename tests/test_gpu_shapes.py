@@ -166,3 +166,48 @@ def test_mixed_batch_runs_plan_table_family(handle):
     assert np.array_equal(got[K], p.F[K])
     assert O.true_relative_residual(K, p.F, got, p.bcx, p.bcy) <= p.tol * 1.001
     assert O.relative_l2(got, solo) <= 1e-9
+
+
+@pytest.mark.parametrize("nx,ny,bx,by", [(1024, 512, 0, 1), (2048, 333, 1, 0)])
+def test_preconditioner_shapes_fp32(handle, monkeypatch, nx, ny, bx, by):
+    """FP32 transforms through the shape instances: within the FP32 bound of
+    the generic tests (2e-4) of the oracle, and within 1e-5 of the plan-table
+    FP32 kernels (the same operations; contraction differs, at FP32
+    rounding amplified by the 1/Lambda^2 spread)."""
+    rng = np.random.default_rng(nx + ny)
+    phi = -(rng.random((ny, nx)) - 0.3)
+    r = rng.normal(size=(ny, nx))
+    known = O.known_mask(phi)
+    ref = O.spectral_preconditioner(r, known, bx, by)
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BHX_SHAPE_KERNELS", flag)
+        out = dev(np.zeros_like(r))
+        assert bhx.debug_apply(handle, 1, dev(phi), dev(r), out, bc=bhx.BC(bx, by),
+                               precision=1) == bhx.OK
+        outs.append(host(out))
+    assert np.array_equal(outs[0][known], np.zeros(known.sum()))
+    assert O.relative_l2(outs[0], ref) <= 2e-4
+    assert O.relative_l2(outs[0], outs[1]) <= 1e-5
+
+
+def test_star1024_fp32_solve_shapes(handle, monkeypatch):
+    """The star with the FP32 preconditioner (standard PCG) through both
+    kernel families: both meet tol 1e-8 with the true residual.  Iteration
+    counts within 15 %: FP32 rounding of the preconditioner (about 1e-7
+    relative, amplified by the 1/Lambda^2 spread) moves the Krylov path far
+    more than FP64 rounding does (measured 3,823 against 4,098)."""
+    p = W.star_inward_problem(1024, tol=1e-8)
+    K = O.known_mask(p.phi)
+    its = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BHX_SHAPE_KERNELS", flag)
+        G = dev(p.F)
+        s, st = bhx.extend_ex(handle, dev(p.phi), G, bc=p.bc, h=p.h, tol=p.tol,
+                              opts=bhx.default_opts(precision=1))
+        assert s == bhx.OK, st.as_dict()
+        got = host(G)
+        assert np.array_equal(got[K], p.F[K])
+        assert O.true_relative_residual(K, p.F, got, p.bcx, p.bcy) <= p.tol * 1.001
+        its.append(st.iterations)
+    assert abs(its[0] - its[1]) <= 0.15 * its[1]
