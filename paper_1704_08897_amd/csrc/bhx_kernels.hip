@@ -271,11 +271,18 @@ __device__ __forceinline__ int inv_index(int j, int n) {
 
 constexpr int kStageRound = 4;    // plan-table entries per thread per staging round
 
+// Nodes of an axis of compile-time shape SP: 2^L for the Neumann and periodic
+// rules; 2^(L-1) - 1 for the Dirichlet rule, whose DST-I runs through the
+// 2(n + 1) = 2^L point odd extension.
+__host__ __device__ constexpr int sp_nodes(int sp) {
+  return (sp & 3) == kDirichlet ? (1 << (((sp >> 2) & 63) - 1)) - 1 : 1 << ((sp >> 2) & 63);
+}
+
 // A transform plan as the kernels use it.  SP = 0 reads the shape from the
-// plan table; SP = (G << 8) | (L << 2) | bc fixes it at compile time (a
-// power-of-two axis of 2^L nodes with the Neumann or periodic rule, no
-// Bluestein, G lines per work item), so that the index arithmetic of every
-// stage folds to constants.
+// plan table; SP = (G << 8) | (L << 2) | bc fixes it at compile time (an axis
+// whose core FFT has 2^L points without Bluestein: sp_nodes(SP) nodes, G
+// lines per work item), so that the index arithmetic of every stage folds to
+// constants.
 template <typename R, int SP = 0>
 struct XPlan {
   using C = typename V2<R>::T;
@@ -347,7 +354,8 @@ struct XPlan {
     const AxisPlan P = B.plans[idx];
     if constexpr (SP != 0) {
       logm = (SP >> 2) & 63;
-      n = nf = m = 1 << logm;
+      nf = m = 1 << logm;
+      n = sp_nodes(SP);
       blue = 0;
       bc = SP & 3;
     } else {
@@ -1133,7 +1141,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
     BHX_GLOBAL Ctl* ctl = I.ctl;
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
     // ny: rows of the pass
-    const int nx = SP ? 1 << ((SP >> 2) & 63) : I.nx, ny = I.nrows, G = SP ? SP >> 8 : I.G,
+    const int nx = SP ? sp_nodes(SP) : I.nx, ny = I.nrows, G = SP ? SP >> 8 : I.G,
               j0 = g * G;
     const int E = min(G, ny - j0) * nx;          // valid elements of this row group
     const size_t base = (size_t)j0 * nx;
@@ -1321,7 +1329,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
     int n, Gp, cnt, ps, js, plan, c0 = 0, kx = 0, ky0 = 0;
     size_t pb;
     if constexpr (kStrided) {
-      n = SP ? 1 << ((SP >> 2) & 63) : I.nz;
+      n = SP ? sp_nodes(SP) : I.nz;
       Gp = SP ? SP >> 8 : I.Gz;
       plan = I.planz;
       const int ngy = (I.ny + Gp - 1) / Gp;
@@ -1332,7 +1340,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
       ps = 1;
       js = I.ny;
     } else {
-      n = SP ? 1 << ((SP >> 2) & 63) : I.ny;
+      n = SP ? sp_nodes(SP) : I.ny;
       Gp = SP ? SP >> 8 : I.Gc;
       plan = I.plany;
       c0 = c * Gp;
@@ -1574,7 +1582,7 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
     const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
     const int par = lpar ^ 1;
     // ny: rows of the pass
-    const int nx = SP ? 1 << ((SP >> 2) & 63) : I.nx, ny = I.nrows, G = SP ? SP >> 8 : I.G,
+    const int nx = SP ? sp_nodes(SP) : I.nx, ny = I.nrows, G = SP ? SP >> 8 : I.G,
               j0 = g * G;
     BHX_GLOBAL const R* t = (BHX_GLOBAL const R*)I.t;
     // 1. issue together: `done` and the row group's unknown count (both
@@ -1921,14 +1929,17 @@ hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 // Compile-time shapes instantiated per pass family, as (G, L, bc): G lines
-// per work item, 2^L nodes, Neumann (0) or periodic (1).  Two dimensions:
-// 512-2048 nodes, one packed row per item, FP64 and FP32 transforms; three
+// per work item, a 2^L-point core, Neumann (0), periodic (1) or Dirichlet (2).
+// Two dimensions: 512-2048 nodes (Neumann, periodic) and 511 or 1023 nodes
+// (Dirichlet), one packed row per item, FP64 and FP32 transforms; three
 // dimensions (FP64): 256 nodes, the groups the layout gives 256^3 (rows and y
 // pencils 8, z 16).
-#define BHX_ROW_SHAPES(X) \
-  X(2, 9, 0) X(2, 9, 1) X(2, 10, 0) X(2, 10, 1) X(2, 11, 0) X(2, 11, 1) X(8, 8, 0) X(8, 8, 1)
-#define BHX_COL2D_SHAPES(X) \
-  X(2, 9, 0) X(2, 9, 1) X(2, 10, 0) X(2, 10, 1) X(2, 11, 0) X(2, 11, 1)
+#define BHX_ROW_SHAPES(X)                                                               \
+  X(2, 9, 0) X(2, 9, 1) X(2, 10, 0) X(2, 10, 1) X(2, 11, 0) X(2, 11, 1) X(2, 10, 2) \
+  X(2, 11, 2) X(8, 8, 0) X(8, 8, 1)
+#define BHX_COL2D_SHAPES(X)                                                             \
+  X(2, 9, 0) X(2, 9, 1) X(2, 10, 0) X(2, 10, 1) X(2, 11, 0) X(2, 11, 1) X(2, 10, 2) \
+  X(2, 11, 2)
 #define BHX_COLY_SHAPES(X) X(8, 8, 0) X(8, 8, 1)
 #define BHX_COLZ_SHAPES(X) X(16, 8, 0) X(16, 8, 1)
 #define BHX_KEY(G, L, bc) (((G) << 8) | ((L) << 2) | (bc))
@@ -1936,7 +1947,7 @@ hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st) {
 // The environment variable BHX_SHAPE_KERNELS=0 keeps every launch on the
 // plan-table kernels (for comparing the two).
 int shape_key(int pass, int prec, int n, int m, int logm, int bluestein, int bc, int group) {
-  if (bluestein || n != m || (bc != kNeumann && bc != kPeriodic)) return 0;
+  if (bluestein || m != (bc == kDirichlet ? 2 * (n + 1) : n)) return 0;
   if (prec != 0 && (group != 2 || (pass != kShapeRow && pass != kShapeCol2D))) return 0;
   if (logm < 1 || logm > 15 || group < 2 || group > 64) return 0;
   const int key = BHX_KEY(group, logm, bc);

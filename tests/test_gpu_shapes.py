@@ -50,12 +50,14 @@ def apply_precond(handle, phi, r, bx, by):
 
 
 # (nx, ny, bcx, bcy): both axes shaped; one shaped and one generic (Bluestein
-# length, Dirichlet rule); a length just outside the instantiated set; ragged
-# last groups on a shaped axis (an odd row count under the x shape, an odd
-# column count under the y shape)
+# length, Dirichlet rule on a non-shaped length); a length just outside the
+# instantiated set; ragged last groups on a shaped axis (an odd row count under
+# the x shape, an odd column count under the y shape); Dirichlet axes of 1023
+# and 511 nodes (DST-I through 2048- and 1024-point cores)
 CASES = [(512, 512, 0, 0), (1024, 512, 1, 0), (512, 2048, 0, 1), (2048, 1024, 1, 1),
          (1024, 1000, 0, 0), (1000, 1024, 1, 0), (1024, 1023, 0, 2), (256, 1024, 0, 1),
-         (1024, 333, 1, 0), (257, 1024, 0, 1), (2048, 77, 0, 0)]
+         (1024, 333, 1, 0), (257, 1024, 0, 1), (2048, 77, 0, 0),
+         (1023, 511, 2, 2), (1023, 1024, 2, 0), (511, 1023, 1, 2), (1023, 100, 2, 1)]
 
 
 @pytest.mark.parametrize("nx,ny,bx,by", CASES)
@@ -168,7 +170,7 @@ def test_mixed_batch_runs_plan_table_family(handle):
     assert O.relative_l2(got, solo) <= 1e-9
 
 
-@pytest.mark.parametrize("nx,ny,bx,by", [(1024, 512, 0, 1), (2048, 333, 1, 0)])
+@pytest.mark.parametrize("nx,ny,bx,by", [(1024, 512, 0, 1), (2048, 333, 1, 0), (1023, 511, 2, 2)])
 def test_preconditioner_shapes_fp32(handle, monkeypatch, nx, ny, bx, by):
     """FP32 transforms through the shape instances: within the FP32 bound of
     the generic tests (2e-4) of the oracle, and within 1e-5 of the plan-table
@@ -211,3 +213,26 @@ def test_star1024_fp32_solve_shapes(handle, monkeypatch):
         assert O.true_relative_residual(K, p.F, got, p.bcx, p.bcy) <= p.tol * 1.001
         its.append(st.iterations)
     assert abs(its[0] - its[1]) <= 0.15 * its[1]
+
+
+def test_dirichlet_star1023_solve_shapes(handle, monkeypatch):
+    """The star on 1023 x 1023 with Dirichlet rules on both axes (shape
+    instances with the DST-I through 2048-point cores) and through the
+    plan-table kernels: both meet tol with the true residual and agree with
+    the oracle's sparse direct extension within 1e-9 at tol 1e-12."""
+    s0 = W.star_inward_problem(1023, tol=1e-12)
+    bc = bhx.BC(2, 2)
+    Fo, _ = O.extend_direct(s0.phi, s0.F, 2, 2)
+    K = O.known_mask(s0.phi)
+    its = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("BHX_SHAPE_KERNELS", flag)
+        G = dev(s0.F)
+        s, st = bhx.extend_ex(handle, dev(s0.phi), G, bc=bc, h=s0.h, tol=1e-12)
+        assert s == bhx.OK, st.as_dict()
+        got = host(G)
+        assert np.array_equal(got[K], s0.F[K])
+        assert O.true_relative_residual(K, s0.F, got, 2, 2) <= 1e-12 * 1.001
+        assert O.relative_l2(got, Fo) <= 1e-9
+        its.append(st.iterations)
+    assert abs(its[0] - its[1]) <= 0.05 * its[1]
