@@ -5,6 +5,7 @@ keeps each request's work split (tiles, row groups) a function of its own
 size, every reduction in a fixed order, and each request's scalars apart, so
 a result in the mix is bit-identical to the same request solved alone.
 """
+import os
 import time
 
 import numpy as np
@@ -40,9 +41,20 @@ def handle():
 
 
 def alone(handle, p):
-    F = dev(p.F)
-    s, st = bhx.extend_ex(handle, dev(p.phi), F, bc=p.bc, h=p.h, tol=p.tol)
-    torch.cuda.synchronize()
+    """The request solved alone with bhx_extend_ex on the plan-table kernels,
+    the family the engine runs (a single solve of a compile-time shape would
+    otherwise take the shape instances, which agree only to rounding)."""
+    old = os.environ.get("BHX_SHAPE_KERNELS")
+    os.environ["BHX_SHAPE_KERNELS"] = "0"
+    try:
+        F = dev(p.F)
+        s, st = bhx.extend_ex(handle, dev(p.phi), F, bc=p.bc, h=p.h, tol=p.tol)
+        torch.cuda.synchronize()
+    finally:
+        if old is None:
+            del os.environ["BHX_SHAPE_KERNELS"]
+        else:
+            os.environ["BHX_SHAPE_KERNELS"] = old
     return s, st, F.cpu().numpy()
 
 

@@ -239,12 +239,12 @@ def test_transpose_equivariance(handle):
     assert O.relative_l2(b.T, a) < 1e-9
 
 
-def test_batched_equals_alone(handle):
+def test_batched_equals_alone(handle, monkeypatch):
     """Each instance solved in a batch of mixed sizes and boundary rules is
     bit-identical to the same instance solved alone (per-instance reductions
-    in a fixed order, work split independent of the batch; the sizes here are
-    outside the compile-time shapes, so alone and batched run the same kernel
-    family)."""
+    in a fixed order, work split independent of the batch).  A mixed batch
+    runs the plan-table kernels, so the solo solves do too."""
+    monkeypatch.setenv("BHX_SHAPE_KERNELS", "0")
     batch = W.star_cubic_batch(6, seed=21, nmin=40, nmax=150, tol=1e-10)
     phis = [dev(p.phi) for p in batch]
     Fs = [dev(p.F) for p in batch]
@@ -278,11 +278,13 @@ def test_batched_autotuned_fp32(handle):
         check_against_oracle(p, host(F), bound=1e-8)
 
 
-def test_large_batch_deterministic(handle):
+def test_large_batch_deterministic(handle, monkeypatch):
     """A batch whose stencil tiles outnumber the persistent grid (each block
     takes several items, instances converge while others iterate): every
     instance converges, repeated solves are bit-identical, and sampled
-    instances equal their solo solves bit for bit."""
+    instances equal their solo solves bit for bit (on the plan-table kernels,
+    which a mixed batch runs)."""
+    monkeypatch.setenv("BHX_SHAPE_KERNELS", "0")
     batch = W.star_cubic_batch(256, seed=4, tol=1e-8)
     tiles = sum(-(-p.phi.shape[1] // 64) * -(-p.phi.shape[0] // 32) for p in batch)
     assert tiles > 2 * 256 * 8

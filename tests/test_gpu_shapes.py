@@ -1,7 +1,8 @@
-"""GPU parity of the compile-time-shape transform kernels: one FP64 instance
-whose x or y axis has 512, 1024 or 2048 nodes with the Neumann or periodic
-rule runs instances of the row and column passes with that shape fixed at
-compile time.  Checked against the oracle's spectral preconditioner and sparse
+"""GPU parity of the compile-time-shape transform kernels: an instance (or a
+batch of same-shape instances) whose x or y axis has 64 to 2048 nodes (a
+power of two) with the Neumann or periodic rule, or 511 or 1023 nodes with the
+Dirichlet rule, runs instances of the row and column passes with that shape
+fixed at compile time.  Checked against the oracle's spectral preconditioner and sparse
 direct extension, and against the same launches with the shape kernels
 switched off (BHX_SHAPE_KERNELS=0, read at every call).
 
