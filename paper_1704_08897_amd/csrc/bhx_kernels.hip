@@ -1930,13 +1930,15 @@ hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st) {
 }
 // Compile-time shapes instantiated per pass family, as (G, L, bc): G lines
 // per work item, a 2^L-point core, Neumann (0), periodic (1) or Dirichlet (2).
-// Two dimensions: 64-2048 nodes (Neumann, periodic) and 511 or 1023 nodes
-// (Dirichlet), one packed row per item, FP64 and FP32 transforms; three
+// Two dimensions: 64-2048 nodes (Neumann, periodic) and 63-2047 nodes with
+// n + 1 a power of two (Dirichlet), one packed row per item, FP64 and FP32
+// transforms; three
 // dimensions (FP64): 256 nodes, the groups the layout gives 256^3 (rows and y
 // pencils 8, z 16).
 #define BHX_COL2D_SHAPES(X)                                                             \
   X(2, 6, 0) X(2, 6, 1) X(2, 7, 0) X(2, 7, 1) X(2, 8, 0) X(2, 8, 1) X(2, 9, 0) X(2, 9, 1) \
-  X(2, 10, 0) X(2, 10, 1) X(2, 11, 0) X(2, 11, 1) X(2, 10, 2) X(2, 11, 2)
+  X(2, 10, 0) X(2, 10, 1) X(2, 11, 0) X(2, 11, 1) X(2, 7, 2) X(2, 8, 2) X(2, 9, 2)         \
+  X(2, 10, 2) X(2, 11, 2) X(2, 12, 2)
 #define BHX_ROW_SHAPES(X) BHX_COL2D_SHAPES(X) X(8, 8, 0) X(8, 8, 1)
 #define BHX_COLY_SHAPES(X) X(8, 8, 0) X(8, 8, 1)
 #define BHX_COLZ_SHAPES(X) X(16, 8, 0) X(16, 8, 1)

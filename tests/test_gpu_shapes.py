@@ -1,7 +1,7 @@
 """GPU parity of the compile-time-shape transform kernels: an instance (or a
 batch of same-shape instances) whose x or y axis has 64 to 2048 nodes (a
-power of two) with the Neumann or periodic rule, or 511 or 1023 nodes with the
-Dirichlet rule, runs instances of the row and column passes with that shape
+power of two) with the Neumann or periodic rule, or 63 to 2047 nodes (n + 1 a
+power of two) with the Dirichlet rule, runs instances of the row and column passes with that shape
 fixed at compile time.  Checked against the oracle's spectral preconditioner and sparse
 direct extension, and against the same launches with the shape kernels
 switched off (BHX_SHAPE_KERNELS=0, read at every call).
@@ -53,12 +53,13 @@ def apply_precond(handle, phi, r, bx, by):
 # (nx, ny, bcx, bcy): both axes shaped; one shaped and one generic (Bluestein
 # length, Dirichlet rule on a non-shaped length); a length just outside the
 # instantiated set; ragged last groups on a shaped axis (an odd row count under
-# the x shape, an odd column count under the y shape); Dirichlet axes of 1023
-# and 511 nodes (DST-I through 2048- and 1024-point cores)
+# the x shape, an odd column count under the y shape); Dirichlet axes of 63 to
+# 2047 nodes (DST-I through 128- to 4096-point cores)
 CASES = [(512, 512, 0, 0), (1024, 512, 1, 0), (512, 2048, 0, 1), (2048, 1024, 1, 1),
          (1024, 1000, 0, 0), (1000, 1024, 1, 0), (1024, 1023, 0, 2), (256, 1024, 0, 1),
          (1024, 333, 1, 0), (257, 1024, 0, 1), (2048, 77, 0, 0),
-         (1023, 511, 2, 2), (1023, 1024, 2, 0), (511, 1023, 1, 2), (1023, 100, 2, 1)]
+         (1023, 511, 2, 2), (1023, 1024, 2, 0), (511, 1023, 1, 2), (1023, 100, 2, 1),
+         (255, 127, 2, 2), (63, 255, 2, 0), (2047, 64, 2, 1)]
 
 
 @pytest.mark.parametrize("nx,ny,bx,by", CASES)
