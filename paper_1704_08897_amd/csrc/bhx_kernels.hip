@@ -1932,16 +1932,15 @@ hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st) {
 // per work item, a 2^L-point core, Neumann (0), periodic (1) or Dirichlet (2).
 // Two dimensions: 64-2048 nodes (Neumann, periodic) and 63-2047 nodes with
 // n + 1 a power of two (Dirichlet), one packed row per item, FP64 and FP32
-// transforms; three
-// dimensions (FP64): 256 nodes, the groups the layout gives 256^3 (rows and y
-// pencils 8, z 16).
+// transforms; three dimensions (FP64): 128 and 256 nodes with the groups the
+// layout gives 128^3 and 256^3 (rows and y pencils 8, z pencils 16).
 #define BHX_COL2D_SHAPES(X)                                                             \
   X(2, 6, 0) X(2, 6, 1) X(2, 7, 0) X(2, 7, 1) X(2, 8, 0) X(2, 8, 1) X(2, 9, 0) X(2, 9, 1) \
   X(2, 10, 0) X(2, 10, 1) X(2, 11, 0) X(2, 11, 1) X(2, 7, 2) X(2, 8, 2) X(2, 9, 2)         \
   X(2, 10, 2) X(2, 11, 2) X(2, 12, 2)
-#define BHX_ROW_SHAPES(X) BHX_COL2D_SHAPES(X) X(8, 8, 0) X(8, 8, 1)
-#define BHX_COLY_SHAPES(X) X(8, 8, 0) X(8, 8, 1)
-#define BHX_COLZ_SHAPES(X) X(16, 8, 0) X(16, 8, 1)
+#define BHX_ROW_SHAPES(X) BHX_COL2D_SHAPES(X) X(8, 7, 0) X(8, 7, 1) X(8, 8, 0) X(8, 8, 1)
+#define BHX_COLY_SHAPES(X) X(8, 7, 0) X(8, 7, 1) X(8, 8, 0) X(8, 8, 1)
+#define BHX_COLZ_SHAPES(X) X(16, 7, 0) X(16, 7, 1) X(16, 8, 0) X(16, 8, 1)
 #define BHX_KEY(G, L, bc) (((G) << 8) | ((L) << 2) | (bc))
 
 // The environment variable BHX_SHAPE_KERNELS=0 keeps every launch on the

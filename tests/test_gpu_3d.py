@@ -250,17 +250,19 @@ def test_reduced_scalars_mode(handle):
     assert st2.iterations > 5 * st.iterations          # plain CG needs far more
 
 
-# Compile-time-shape instances in three dimensions (256-node Neumann or
-# periodic axes with the groups the layout gives: rows and y pencils 8, z
+# Compile-time-shape instances in three dimensions (128- and 256-node Neumann
+# or periodic axes with the groups the layout gives: rows and y pencils 8, z
 # pencils 16).  256 x 256 x 64 runs the row and y shapes with a plan-table z
 # pass; 128 x 64 x 256 the z shape alone; the last three leave a ragged last
 # group under the row, y and z shapes (4100 rows in groups of 8, 4100 y
 # pencils in groups of 8, 72 z pencils per x in groups of 16).  Bounds as above
 # against the oracle; against the plan-table kernels (BHX_SHAPE_KERNELS=0)
-# 1e-13, since both perform the same operations in the same order.
+# 1e-13, since both perform the same operations in the same order.  128^3 runs
+# all three 128-node shapes.
 @pytest.mark.parametrize("nx,ny,nz,bx,by,bz", [(256, 256, 64, 1, 1, 1), (256, 256, 64, 0, 0, 0),
                                               (128, 64, 256, 0, 1, 1), (256, 100, 41, 1, 0, 2),
-                                              (100, 256, 41, 0, 1, 2), (128, 72, 256, 2, 0, 1)])
+                                              (100, 256, 41, 0, 1, 2), (128, 72, 256, 2, 0, 1),
+                                              (128, 128, 128, 0, 1, 1)])
 def test_preconditioner_3d_shapes(handle, monkeypatch, nx, ny, nz, bx, by, bz):
     rng = np.random.default_rng(nx + ny + nz + bx)
     phi = random_phi3(rng, nx, ny, nz, 0.3)
