@@ -14,9 +14,10 @@
 // Rows beyond the last unknown are an identity pad.
 //
 // Factorisation (right-looking, one step per panel): the diagonal block is
-// factored in the registers of a wave (one row per lane, pivots and columns
-// exchanged by readlane), the panel below it solved against it (TRSM), and
-// the trailing band updated by tile products of the panel with itself.
+// factored in LDS in steps of 16 columns (each 16 x 16 diagonal in one wave's
+// registers, pivots exchanged by readlane), the panel below it solved against
+// it (TRSM, L read from LDS), and the trailing band updated by tile products
+// of the panel with itself.
 // Solves: forward and backward substitution, one step per panel, each step
 // updating the right-hand side blocks it reaches (no cross-block sums).
 // Every sum runs in a fixed order, so results are deterministic.
@@ -176,47 +177,92 @@ __device__ __forceinline__ void load_diag_row(const Band& B, int k, int lane, do
   for (int c = 0; c < kNb; ++c) a[c] = c <= lane ? B.p[band_at(B, k, lane, c)] : 0.0;
 }
 
-// Cholesky of the 64 x 64 block held one row per lane (right-looking): on
-// return lane i holds row i of L (lower part).  Column j: the pivot from
-// lane j, the column entries scaled, then the trailing rows updated with
-// L[k][j] read from lane k.
-__device__ __forceinline__ void potrf_wave(int lane, double (&a)[kNb]) {
-#pragma unroll
-  for (int j = 0; j < kNb; ++j) {
-    const double d = sqrt(lane_value(a[j], j));
-    const double l = lane > j ? a[j] / d : (lane == j ? d : 0.0);
-    a[j] = l;
-#pragma unroll
-    for (int k = j + 1; k < kNb; ++k) a[k] -= l * lane_value(l, k);
-  }
-}
-
-// Step k, part 1: wave w of block b takes tile t = 4 b + w of panel k.
-// Every wave factors the diagonal block in its registers (cheaper than a
-// second launch); tile 0 stores L, tile t >= 1 (rows 64 t..) solves
-// X <- X L^-T in registers (lane r: row r, right-looking over columns).
+// Step k, part 1: every block factors panel k's diagonal block in LDS (held
+// column-major, M[c][r] = A[r][c], lower part), right-looking in four steps of
+// 16 columns: wave 0 factors the 16 x 16 diagonal in its registers (one row
+// per lane, pivots exchanged by readlane), threads solve the rows below it,
+// and all threads update the trailing block.  Block 0 then stores L; wave w
+// of block b solves tile t = 4 b + w >= 1 of the panel (rows 64 t..): lane r
+// holds row r in registers and runs right-looking over the columns, reading
+// column j of L from LDS (the same address in every lane).
 __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int tiles) {
-  const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= tiles) return;                // whole waves: no barrier in this kernel
-  double a[kNb];
-  load_diag_row(B, k, lane, a);
-  potrf_wave(lane, a);
-  if (t == 0) {
-#pragma unroll
-    for (int c = 0; c < kNb; ++c)
-      if (c <= lane) B.p[band_at(B, k, lane, c)] = a[c];
-    return;
+  __shared__ __align__(16) double M[kNb][kNb + 2];
+  __shared__ double rinv[kNb];                 // 1 / L[j][j]
+  constexpr int kStep = 16;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < kNb * kNb; e += kThreads) {
+    const int c = e >> 6, r = e & 63;
+    M[c][r] = r >= c ? B.p[band_at(B, k, r, c)] : 0.0;
   }
+  __syncthreads();
+  for (int c0 = 0; c0 < kNb; c0 += kStep) {
+    if (w == 0) {
+      // diagonal kStep x kStep block: lane l < kStep holds row c0 + l
+      double a[kStep];
+#pragma unroll
+      for (int d = 0; d < kStep; ++d) a[d] = lane < kStep ? M[c0 + d][c0 + lane] : 0.0;
+#pragma unroll
+      for (int j = 0; j < kStep; ++j) {
+        const double dj = sqrt(lane_value(a[j], j));
+        const double l = lane > j ? a[j] / dj : (lane == j ? dj : 0.0);
+        a[j] = l;
+#pragma unroll
+        for (int m = j + 1; m < kStep; ++m) a[m] -= l * lane_value(l, m);
+      }
+      if (lane < kStep) {
+#pragma unroll
+        for (int d = 0; d < kStep; ++d)
+          if (d <= lane) M[c0 + d][c0 + lane] = a[d];
+        rinv[c0 + lane] = 1.0 / a[lane];
+      }
+    }
+    __syncthreads();
+    const int rb = c0 + kStep, nt = kNb - rb;
+    if (tid < nt) {
+      // row i below the diagonal block: L[i][c0..] = A[i][c0..] L_d^-T
+      const int i = rb + tid;
+      double x[kStep];
+#pragma unroll
+      for (int c = 0; c < kStep; ++c) x[c] = M[c0 + c][i];
+#pragma unroll
+      for (int c = 0; c < kStep; ++c) {
+#pragma unroll
+        for (int d = 0; d < c; ++d) x[c] -= x[d] * M[c0 + d][c0 + c];
+        x[c] *= rinv[c0 + c];
+      }
+#pragma unroll
+      for (int c = 0; c < kStep; ++c) M[c0 + c][i] = x[c];
+    }
+    __syncthreads();
+    // trailing block: A[i][j] -= sum_d L[i][c0 + d] L[j][c0 + d], i >= j >= rb
+    for (int e = tid; e < nt * nt; e += kThreads) {
+      const int jj = e / nt, ii = e - jj * nt;
+      if (ii >= jj) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int d = 0; d < kStep; ++d) sacc += M[c0 + d][rb + ii] * M[c0 + d][rb + jj];
+        M[rb + jj][rb + ii] -= sacc;
+      }
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0) {
+    for (int e = tid; e < kNb * kNb; e += kThreads) {
+      const int c = e >> 6, r = e & 63;
+      if (r >= c) B.p[band_at(B, k, r, c)] = M[c][r];
+    }
+  }
+  const int t = blockIdx.x * 4 + w;
+  if (t == 0 || t >= tiles) return;      // no barrier below
   const int r0 = t * kNb;
   double x[kNb];
 #pragma unroll
   for (int c = 0; c < kNb; ++c) x[c] = B.p[band_at(B, k, r0 + lane, c)];
 #pragma unroll
   for (int j = 0; j < kNb; ++j) {
-    x[j] /= lane_value(a[j], j);         // L[j][j]
+    x[j] *= rinv[j];                     // X <- X L^-T, column j
 #pragma unroll
-    for (int c = j + 1; c < kNb; ++c) x[c] -= x[j] * lane_value(a[j], c);   // L[c][j]
+    for (int c = j + 1; c < kNb; ++c) x[c] -= x[j] * M[j][c];   // L[c][j]
   }
 #pragma unroll
   for (int c = 0; c < kNb; ++c) B.p[band_at(B, k, r0 + lane, c)] = x[c];
