@@ -177,6 +177,8 @@ __device__ __forceinline__ void load_diag_row(const Band& B, int k, int lane, do
   for (int c = 0; c < kNb; ++c) a[c] = c <= lane ? B.p[band_at(B, k, lane, c)] : 0.0;
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 // Step k, part 1: every block factors panel k's diagonal block in LDS (held
 // column-major, M[c][r] = A[r][c], lower part), right-looking in four steps of
 // 16 columns: wave 0 factors the 16 x 16 diagonal in its registers (one row
@@ -246,6 +248,23 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
     }
     __syncthreads();
   }
+  // inverses of the four 16 x 16 diagonal blocks: thread (db, j) solves
+  // L_dd y = e_j for column j of L_dd^-1
+  __shared__ double Li[kNb / kStep][kStep][kStep + 1];   // Li[d][i][j] = (L_dd^-1)[i][j]
+  if (tid < kNb) {
+    const int d = tid / kStep, jc = tid % kStep, o = d * kStep;
+    double y[kStep];
+#pragma unroll
+    for (int i = 0; i < kStep; ++i) {
+      double v = i == jc ? 1.0 : 0.0;
+#pragma unroll
+      for (int m = 0; m < i; ++m) v -= M[o + m][o + i] * (m >= jc ? y[m] : 0.0);   // L[o+i][o+m]
+      y[i] = i >= jc ? v * rinv[o + i] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kStep; ++i) Li[d][i][jc] = y[i];
+  }
+  __syncthreads();
   if (blockIdx.x == 0) {
     for (int e = tid; e < kNb * kNb; e += kThreads) {
       const int c = e >> 6, r = e & 63;
@@ -254,23 +273,63 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
   }
   const int t = blockIdx.x * 4 + w;
   if (t == 0 || t >= tiles) return;      // no barrier below
-  const int r0 = t * kNb;
-  double x[kNb];
+  // Tile t solves X L^T = T (rows 64 t.. of the panel), as L Z = T^T with
+  // Z = X^T, by 16-row blocks on the matrix cores:
+  //   Z_d = L_dd^-1 (W_d - sum_{a<d} L_da Z_a),  W = T^T.
+  // Z is held as 4 x 4 tiles of 16 x 16 in the v_mfma_f64_16x16x4 output
+  // layout (lane l, element v: row 4 v + l / 16, column l % 16 of the tile),
+  // in which element s of a tile is exactly the B operand of k-step s, so the
+  // products chain without leaving registers.
+  const int r0 = t * kNb, li = lane & 15, lk = lane >> 4;
+  v4d Z[4][4];
 #pragma unroll
-  for (int c = 0; c < kNb; ++c) x[c] = B.p[band_at(B, k, r0 + lane, c)];
+  for (int d = 0; d < 4; ++d)
 #pragma unroll
-  for (int j = 0; j < kNb; ++j) {
-    x[j] *= rinv[j];                     // X <- X L^-T, column j
+    for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
-    for (int c = j + 1; c < kNb; ++c) x[c] -= x[j] * M[j][c];   // L[c][j]
+      for (int v = 0; v < 4; ++v)
+        Z[d][jt][v] = B.p[band_at(B, k, r0 + kStep * jt + li, kStep * d + 4 * v + lk)];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+#pragma unroll
+    for (int a2 = 0; a2 < d; ++a2)
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        // A operand -L[16 d + i][16 a2 + 4 s4 + kk], i = l % 16, kk = l / 16
+        const double aop = -M[kStep * a2 + 4 * s4 + lk][kStep * d + li];
+#pragma unroll
+        for (int jt = 0; jt < 4; ++jt)
+          Z[d][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, Z[a2][jt][s4], Z[d][jt], 0, 0, 0);
+      }
+    v4d T[4];
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) T[jt] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const double aop = Li[d][li][4 * s4 + lk];
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt)
+        T[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, Z[d][jt][s4], T[jt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) Z[d][jt] = T[jt];
   }
 #pragma unroll
-  for (int c = 0; c < kNb; ++c) B.p[band_at(B, k, r0 + lane, c)] = x[c];
+  for (int d = 0; d < 4; ++d)
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        B.p[band_at(B, k, r0 + kStep * jt + li, kStep * d + 4 * v + lk)] = Z[d][jt][v];
 }
 
 // Step k, part 2: trailing update of the band by panel k.  Tile (q, rt):
 // rows rt*kNb.. of panel k+q -= (panel k rows (rt+q)*kNb..) (panel k rows
-// q*kNb..)^T, 64 x 64 x 64 in LDS, 4 x 4 outputs per thread.
+// q*kNb..)^T, a 64 x 64 x 64 FP64 product on the matrix cores: the operands
+// are staged in LDS, wave w computes the 32 x 32 quadrant (w >> 1, w & 1) as
+// 2 x 2 tiles of v_mfma_f64_16x16x4 over k in steps of 4.  Lane layout of that
+// instruction: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
+// receives D[4 v + l / 16][l % 16] in accumulator element v.
 __global__ void __launch_bounds__(kThreads) k_dir_update(Band B, int k) {
   __shared__ double sA[kNb][kNb];   // [t][r]
   __shared__ double sB[kNb][kNb];   // [t][c]
@@ -284,28 +343,36 @@ __global__ void __launch_bounds__(kThreads) k_dir_update(Band B, int k) {
     sB[t][r] = B.p[band_at(B, k, rb + r, t)];
   }
   __syncthreads();
-  const int r0 = 4 * (threadIdx.x & 15), c0 = 4 * (threadIdx.x >> 4);
-  double acc[4][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int qr = (w >> 1) * 32, qc = (w & 1) * 32;      // the wave's quadrant
+  const int li = lane & 15, lk = lane >> 4;
+  v4d acc[2][2];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  for (int t = 0; t < kNb; ++t) {
-    double a[4], bb[4];
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int t0 = 0; t0 < kNb; t0 += 4) {
+    double av[2], bv[2];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = sA[t][r0 + u];
-      bb[u] = sB[t][c0 + u];
-    }
+    for (int a = 0; a < 2; ++a) av[a] = sA[t0 + lk][qr + 16 * a + li];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int b = 0; b < 2; ++b) bv[b] = sB[t0 + lk][qc + 16 * b + li];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * bb[v];
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) B.p[band_at(B, j, rt * kNb + r0 + u, c0 + v)] -= acc[u][v];
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = qr + 16 * a + 4 * v + lk, c = qc + 16 * b + li;
+        B.p[band_at(B, j, rt * kNb + r, c)] -= acc[a][b][v];
+      }
 }
 
 // Forward substitution step k on y (length npad): wave 0 of every block
