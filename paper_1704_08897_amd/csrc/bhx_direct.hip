@@ -191,18 +191,23 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
   __shared__ __align__(16) double M[kNb][kNb + 2];
   __shared__ double rinv[kNb];                 // 1 / L[j][j]
   constexpr int kStep = 16;
+  __shared__ double Li[kNb / kStep][kStep][kStep + 1];   // Li[d][i][j] = (L_dd^-1)[i][j]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   for (int e = tid; e < kNb * kNb; e += kThreads) {
     const int c = e >> 6, r = e & 63;
     M[c][r] = r >= c ? B.p[band_at(B, k, r, c)] : 0.0;
   }
   __syncthreads();
-  for (int c0 = 0; c0 < kNb; c0 += kStep) {
+  // Only the lower part of M is read from here on: the products below also
+  // write the strictly upper half of diagonal 16 x 16 tiles, which no step
+  // reads.
+  for (int c0 = 0, d = 0; c0 < kNb; c0 += kStep, ++d) {
     if (w == 0) {
       // diagonal kStep x kStep block: lane l < kStep holds row c0 + l
       double a[kStep];
 #pragma unroll
-      for (int d = 0; d < kStep; ++d) a[d] = lane < kStep ? M[c0 + d][c0 + lane] : 0.0;
+      for (int dd = 0; dd < kStep; ++dd) a[dd] = lane < kStep ? M[c0 + dd][c0 + lane] : 0.0;
 #pragma unroll
       for (int j = 0; j < kStep; ++j) {
         const double dj = sqrt(lane_value(a[j], j));
@@ -213,58 +218,65 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
       }
       if (lane < kStep) {
 #pragma unroll
-        for (int d = 0; d < kStep; ++d)
-          if (d <= lane) M[c0 + d][c0 + lane] = a[d];
+        for (int dd = 0; dd < kStep; ++dd)
+          if (dd <= lane) M[c0 + dd][c0 + lane] = a[dd];
         rinv[c0 + lane] = 1.0 / a[lane];
       }
     }
     __syncthreads();
-    const int rb = c0 + kStep, nt = kNb - rb;
-    if (tid < nt) {
-      // row i below the diagonal block: L[i][c0..] = A[i][c0..] L_d^-T
-      const int i = rb + tid;
-      double x[kStep];
+    if (tid < kStep) {
+      // column tid of L_dd^-1: solve L_dd y = e_tid
+      const int jc = tid;
+      double y[kStep];
 #pragma unroll
-      for (int c = 0; c < kStep; ++c) x[c] = M[c0 + c][i];
+      for (int i = 0; i < kStep; ++i) {
+        double v = i == jc ? 1.0 : 0.0;
 #pragma unroll
-      for (int c = 0; c < kStep; ++c) {
-#pragma unroll
-        for (int d = 0; d < c; ++d) x[c] -= x[d] * M[c0 + d][c0 + c];
-        x[c] *= rinv[c0 + c];
+        for (int m = 0; m < i; ++m) v -= M[c0 + m][c0 + i] * (m >= jc ? y[m] : 0.0);
+        y[i] = i >= jc ? v * rinv[c0 + i] : 0.0;
       }
 #pragma unroll
-      for (int c = 0; c < kStep; ++c) M[c0 + c][i] = x[c];
+      for (int i = 0; i < kStep; ++i) Li[d][i][jc] = y[i];
     }
     __syncthreads();
-    // trailing block: A[i][j] -= sum_d L[i][c0 + d] L[j][c0 + d], i >= j >= rb
-    for (int e = tid; e < nt * nt; e += kThreads) {
-      const int jj = e / nt, ii = e - jj * nt;
-      if (ii >= jj) {
-        double sacc = 0.0;
+    const int rb = c0 + kStep, nt = (kNb - rb) / kStep;   // 16-row tiles below
+    // rows below: X = A_below L_dd^-T on the matrix cores, wave w takes tile w
+    // (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of each k-step
+    // and holds D[4 v + l / 16][l % 16] in accumulator element v)
+    if (w < nt) {
+      const int rw = rb + kStep * w;
+      v4d acc = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int d = 0; d < kStep; ++d) sacc += M[c0 + d][rb + ii] * M[c0 + d][rb + jj];
-        M[rb + jj][rb + ii] -= sacc;
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const double aop = M[c0 + 4 * s4 + lk][rw + li];   // A[rw + i][c0 + kk]
+        const double bop = Li[d][li][4 * s4 + lk];          // L_dd^-T[kk][j] = Linv[j][kk]
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, acc, 0, 0, 0);
       }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) M[c0 + li][rw + 4 * v + lk] = acc[v];   // L[rw+i][c0+j]
+    }
+    __syncthreads();
+    // trailing block: C -= X X^T over the lower 16 x 16 tiles (ti >= tj)
+    const int ntl = nt * (nt + 1) / 2;
+    for (int tt = w; tt < ntl; tt += 4) {
+      int ti = 0;
+      while ((ti + 1) * (ti + 2) / 2 <= tt) ++ti;
+      const int tj = tt - ti * (ti + 1) / 2;
+      const int ri = rb + kStep * ti, rj = rb + kStep * tj;
+      v4d acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = M[rj + li][ri + 4 * v + lk];   // C[ri + 4v + kk][rj + j]
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const double aop = -M[c0 + 4 * s4 + lk][ri + li];   // -X[ri + i][kk]
+        const double bop = M[c0 + 4 * s4 + lk][rj + li];    // X^T[kk][rj + j]
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) M[rj + li][ri + 4 * v + lk] = acc[v];
     }
     __syncthreads();
   }
-  // inverses of the four 16 x 16 diagonal blocks: thread (db, j) solves
-  // L_dd y = e_j for column j of L_dd^-1
-  __shared__ double Li[kNb / kStep][kStep][kStep + 1];   // Li[d][i][j] = (L_dd^-1)[i][j]
-  if (tid < kNb) {
-    const int d = tid / kStep, jc = tid % kStep, o = d * kStep;
-    double y[kStep];
-#pragma unroll
-    for (int i = 0; i < kStep; ++i) {
-      double v = i == jc ? 1.0 : 0.0;
-#pragma unroll
-      for (int m = 0; m < i; ++m) v -= M[o + m][o + i] * (m >= jc ? y[m] : 0.0);   // L[o+i][o+m]
-      y[i] = i >= jc ? v * rinv[o + i] : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < kStep; ++i) Li[d][i][jc] = y[i];
-  }
-  __syncthreads();
   if (blockIdx.x == 0) {
     for (int e = tid; e < kNb * kNb; e += kThreads) {
       const int c = e >> 6, r = e & 63;
@@ -280,7 +292,7 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
   // layout (lane l, element v: row 4 v + l / 16, column l % 16 of the tile),
   // in which element s of a tile is exactly the B operand of k-step s, so the
   // products chain without leaving registers.
-  const int r0 = t * kNb, li = lane & 15, lk = lane >> 4;
+  const int r0 = t * kNb;
   v4d Z[4][4];
 #pragma unroll
   for (int d = 0; d < 4; ++d)
