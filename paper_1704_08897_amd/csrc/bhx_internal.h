@@ -226,8 +226,14 @@ hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st);
 // batch uses it when every instance has that axis plan and grouping.
 enum ShapePass { kShapeRow = 0, kShapeCol2D = 1, kShapeColY = 2, kShapeColZ = 3 };
 int shape_key(int pass, int prec, int n, int m, int logm, int bluestein, int bc, int group);
-hipError_t launch_rowfwd(const Batch* B, int prec, int shape, int update, int grid, int lds,
-                         int twoff, int lpar, hipStream_t st, hipEvent_t e0 = nullptr,
+// `stream_t` != 0: the row-forward pass writes t with non-temporal stores.
+// Its transposed store writes G-element pieces of many lines.  While the
+// launch's whole t is small the pass is latency-bound, and streaming those
+// pieces past the L2 shortens the write-back at the kernel's end; on a large
+// t the unmerged pieces cost HBM bandwidth instead.  The runtime sets it when
+// the launch's t arrays total at most kStreamTMax bytes.
+hipError_t launch_rowfwd(const Batch* B, int prec, int shape, int update, int stream_t, int grid,
+                         int lds, int twoff, int lpar, hipStream_t st, hipEvent_t e0 = nullptr,
                          hipEvent_t e1 = nullptr);
 hipError_t launch_col(const Batch* B, int prec, int shape, int kind, int count_iter, int grid,
                       int lds, int twoff, hipStream_t st, hipEvent_t e0 = nullptr,

@@ -1120,13 +1120,17 @@ __global__ void __launch_bounds__(kThreads) k_resid(const Batch* __restrict__ Bp
 // j = y in two dimensions, j = z * ny + y in three (nrows = ny * nz).
 // ---------------------------------------------------------------------------
 
-// `lpar`: buffer parity of the iteration (as in k_stencil): p_new = p[lpar ^ 1],
+// `mode`: bits 0-1 the update (0 none, 1 PCG update then transform, 2 plain
+// CG update only), bit 2 set: store t with non-temporal stores.  `lpar`:
+// buffer parity of the iteration (as in k_stencil): p_new = p[lpar ^ 1],
 // current r.z partials rz(lpar).  SP: compile-time shape of the x axis and
 // row group (see XPlan), 0 for any shape.
 template <typename R, int SP>
-__global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ Bp, int update,
+__global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ Bp, int mode,
                                                      int twoff, int lpar) {
   using C = typename V2<R>::T;
+  const int update = mode & 3;
+  const bool stream_t = (mode & 4) != 0;
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   extern __shared__ __align__(16) unsigned char smem[];
   C* buf = (C*)smem;
@@ -1280,12 +1284,19 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
       }
     }
     __syncthreads();
-    // 5. coalesced transposed store
+    // 5. coalesced transposed store (one loop per store kind: a store kind
+    //    chosen inside the loop body is merged away by the compiler)
     BHX_GLOBAL R* t = (BHX_GLOBAL R*)I.t;
-    for (int e = threadIdx.x; e < nx * G; e += kThreads) {
-      const int k = e / G, jr = e - k * G;
-      const int j = j0 + jr;
-      if (j < ny) t[(size_t)k * ny + j] = stg[e];
+    if (stream_t) {
+      for (int e = threadIdx.x; e < nx * G; e += kThreads) {
+        const int k = e / G, j = j0 + e - k * G;
+        if (j < ny) __builtin_nontemporal_store(stg[e], &t[(size_t)k * ny + j]);
+      }
+    } else {
+      for (int e = threadIdx.x; e < nx * G; e += kThreads) {
+        const int k = e / G, j = j0 + e - k * G;
+        if (j < ny) t[(size_t)k * ny + j] = stg[e];
+      }
     }
     __syncthreads();
   }
@@ -1966,8 +1977,10 @@ int shape_key(int pass, int prec, int n, int m, int logm, int bluestein, int bc,
   return key;
 }
 
-hipError_t launch_rowfwd(const Batch* B, int prec, int shape, int update, int grid, int lds,
-                         int twoff, int lpar, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_rowfwd(const Batch* B, int prec, int shape, int update, int stream_t, int grid,
+                         int lds, int twoff, int lpar, hipStream_t st, hipEvent_t e0,
+                         hipEvent_t e1) {
+  update |= stream_t ? 4 : 0;
   if (prec != 0) {
     switch (shape) {
 #define BHX_CASE(G, L, bc)                                                             \

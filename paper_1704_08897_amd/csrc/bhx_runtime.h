@@ -100,7 +100,12 @@ struct Grids {
   int count = 0;           // instances of the batch
   int reduce = 0;          // 1: some instance has Inst::reduce (k_reduce launches)
   int shape_r = 0, shape_c = 0, shape_z = 0;   // compile-time shapes of the passes (shape_key)
+  int stream_t = 0;        // 1: the row-forward pass stores t non-temporally
 };
+
+// Largest total of a launch's t arrays (bytes) whose row-forward stores go
+// non-temporal: one 1024 x 1024 FP64 instance.
+constexpr size_t kStreamTMax = (size_t)8 << 20;
 
 struct Graph {
   hipGraphExec_t exec = nullptr;
@@ -110,6 +115,7 @@ struct Graph {
   int prec = -1, chunk = 0, precond = -1, gs = 0, gr = 0, gc = 0, profile = 0;
   int lds_r = 0, tw_r = 0, lds_c = 0, tw_c = 0;
   int dim = 2, gz = 0, lds_z = 0, tw_z = 0, reduce = 0, shape_r = 0, shape_c = 0, shape_z = 0;
+  int stream_t = 0;
   std::vector<hipEvent_t> ev;   // [pass][iteration][start, end] when profiling
 };
 
