@@ -388,34 +388,47 @@ __global__ void __launch_bounds__(kThreads) k_dir_update(Band B, int k) {
 }
 
 // Forward substitution step k on y (length npad): wave 0 of every block
-// solves L_kk y_k = y_k (lane t: y_t and row t of L_kk in registers);
+// solves L_kk y_k = y_k (lane t: y_t and row t of L_kk in registers, and
+// 1 / L_tt, so that the serial chain multiplies instead of dividing);
 // block 0 stores y_k, block b >= 1 updates y_(k+b) -= L_(k+b,k) y_k.
 __global__ void __launch_bounds__(kThreads) k_dir_fwd(Band B, int k, double* __restrict__ y) {
   __shared__ double yk[kNb];
   __shared__ double part[4][kNb];
+  // the update's part of L_(k+b,k) (row r, columns 16 cs..), loaded before
+  // the triangular solve so that its latency overlaps the serial chain
+  const int b = blockIdx.x;
+  const int r = threadIdx.x & 63, cs = threadIdx.x >> 6;
+  double lv[16];
+  if (b > 0) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) lv[u] = B.p[band_at(B, k, b * kNb + r, cs * 16 + u)];
+  }
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     double a[kNb];
     load_diag_row(B, k, lane, a);
     double v = y[k * kNb + lane];
+    double dg = 1.0;
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) dg = lane == j ? a[j] : dg;
+    const double rd = 1.0 / dg;
 #pragma unroll
     for (int j = 0; j < kNb; ++j) {
-      const double yj = lane_value(v, j) / lane_value(a[j], j);
+      const double yj = lane_value(v, j) * lane_value(rd, j);
       if (lane == j) v = yj;
       else if (lane > j) v -= a[j] * yj;
     }
     yk[lane] = v;
   }
   __syncthreads();
-  const int b = blockIdx.x;
   if (b == 0) {
     if (threadIdx.x < kNb) y[k * kNb + threadIdx.x] = yk[threadIdx.x];
     return;
   }
   // rows b*kNb.. of panel k: r = tid % 64, columns in four strips of 16
-  const int r = threadIdx.x & 63, cs = threadIdx.x >> 6;
   double s = 0.0;
-  for (int c = cs * 16; c < cs * 16 + 16; ++c) s += B.p[band_at(B, k, b * kNb + r, c)] * yk[c];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) s += lv[u] * yk[cs * 16 + u];
   part[cs][r] = s;
   __syncthreads();
   if (threadIdx.x < kNb)
@@ -424,37 +437,48 @@ __global__ void __launch_bounds__(kThreads) k_dir_fwd(Band B, int k, double* __r
 }
 
 // Backward substitution step k (k descending): wave 0 of every block solves
-// L_kk^T x_k = y_k (lane t: y_t and column t of L_kk in registers); block 0
+// L_kk^T x_k = y_k (lane t: y_t, column t of L_kk and 1 / L_tt in registers); block 0
 // stores x_k, block b >= 1 updates y_(k-b) -= L_(k,k-b)^T x_k (rows b*kNb..
 // of panel k-b).
 __global__ void __launch_bounds__(kThreads) k_dir_bwd(Band B, int k, double* __restrict__ y) {
   __shared__ double xk[kNb];
   __shared__ double part[4][kNb];
+  // the update's part of panel k-b (column c, rows b*kNb + 16 rs..), loaded
+  // before the triangular solve so that its latency overlaps the serial chain
+  const int b = blockIdx.x, kb = k - b;
+  const int c = threadIdx.x & 63, rs = threadIdx.x >> 6;
+  double lv[16];
+  if (b > 0) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) lv[u] = B.p[band_at(B, kb, b * kNb + rs * 16 + u, c)];
+  }
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     double col[kNb];                     // col[j] = L[j][lane]
 #pragma unroll
     for (int j = 0; j < kNb; ++j) col[j] = j >= lane ? B.p[band_at(B, k, j, lane)] : 0.0;
     double v = y[k * kNb + lane];
+    double dg = 1.0;
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) dg = lane == j ? col[j] : dg;
+    const double rd = 1.0 / dg;
 #pragma unroll
     for (int j = kNb - 1; j >= 0; --j) {
-      const double xj = lane_value(v, j) / lane_value(col[j], j);
+      const double xj = lane_value(v, j) * lane_value(rd, j);
       if (lane == j) v = xj;
       else if (lane < j) v -= col[j] * xj;
     }
     xk[lane] = v;
   }
   __syncthreads();
-  const int b = blockIdx.x;
   if (b == 0) {
     if (threadIdx.x < kNb) y[k * kNb + threadIdx.x] = xk[threadIdx.x];
     return;
   }
   // y_(k-b)[c] -= sum_r P_(k-b)[c][b*kNb + r] x_k[r]: c = tid % 64, r strips
-  const int kb = k - b;
-  const int c = threadIdx.x & 63, rs = threadIdx.x >> 6;
   double s = 0.0;
-  for (int r = rs * 16; r < rs * 16 + 16; ++r) s += B.p[band_at(B, kb, b * kNb + r, c)] * xk[r];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) s += lv[u] * xk[rs * 16 + u];
   part[rs][c] = s;
   __syncthreads();
   if (threadIdx.x < kNb)
