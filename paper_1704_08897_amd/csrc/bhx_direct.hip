@@ -184,9 +184,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // 16 columns: wave 0 factors the 16 x 16 diagonal in its registers (one row
 // per lane, pivots exchanged by readlane), threads solve the rows below it,
 // and all threads update the trailing block.  Block 0 then stores L; wave w
-// of block b solves tile t = 4 b + w >= 1 of the panel (rows 64 t..): lane r
-// holds row r in registers and runs right-looking over the columns, reading
-// column j of L from LDS (the same address in every lane).
+// of block b solves tile t = 4 b + w >= 1 of the panel (rows 64 t..) against
+// L on the matrix cores, with L read from LDS.
 __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int tiles) {
   __shared__ __align__(16) double M[kNb][kNb + 2];
   __shared__ double rinv[kNb];                 // 1 / L[j][j]
