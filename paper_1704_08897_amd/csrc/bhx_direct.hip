@@ -193,9 +193,21 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
   __shared__ double Li[kNb / kStep][kStep][kStep + 1];   // Li[d][i][j] = (L_dd^-1)[i][j]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  for (int e = tid; e < kNb * kNb; e += kThreads) {
-    const int c = e >> 6, r = e & 63;
-    M[c][r] = r >= c ? B.p[band_at(B, k, r, c)] : 0.0;
+  {
+    // all of a thread's loads issued before its first LDS write (rows r < c
+    // of the block lie inside the band's storage too: H >= 64)
+    constexpr int kPer = kNb * kNb / kThreads;
+    double mv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + u * kThreads, c = e >> 6, r = e & 63;
+      mv[u] = B.p[band_at(B, k, r, c)];
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + u * kThreads, c = e >> 6, r = e & 63;
+      M[c][r] = r >= c ? mv[u] : 0.0;
+    }
   }
   __syncthreads();
   // Only the lower part of M is read from here on: the products below also
@@ -348,15 +360,37 @@ __global__ void __launch_bounds__(kThreads) k_dir_update(Band B, int k) {
   const int j = k + q;
   if (rt > B.Q - q || j + rt >= B.nblk) return;       // no such tile, or past the pad
   const int ra = (rt + q) * kNb, rb = q * kNb;
-  for (int e = threadIdx.x; e < kNb * kNb; e += kThreads) {
-    const int t = e / kNb, r = e - t * kNb;
-    sA[t][r] = B.p[band_at(B, k, ra + r, t)];
-    sB[t][r] = B.p[band_at(B, k, rb + r, t)];
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int qr = (w >> 1) * 32, qc = (w & 1) * 32;      // the wave's quadrant
   const int li = lane & 15, lk = lane >> 4;
+  // every load of the block is issued before the first wait: the thread's
+  // part of the output tile (which only this block reads or writes), then
+  // the two operand tiles
+  double cv[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        cv[a][b][v] = B.p[band_at(B, j, rt * kNb + qr + 16 * a + 4 * v + lk, qc + 16 * b + li)];
+  {
+    constexpr int kPer = kNb * kNb / kThreads;
+    double va[kPer], vb[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + u * kThreads, t = e / kNb, r = e - t * kNb;
+      va[u] = B.p[band_at(B, k, ra + r, t)];
+      vb[u] = B.p[band_at(B, k, rb + r, t)];
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + u * kThreads, t = e / kNb, r = e - t * kNb;
+      sA[t][r] = va[u];
+      sB[t][r] = vb[u];
+    }
+  }
+  __syncthreads();
   v4d acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -382,7 +416,7 @@ __global__ void __launch_bounds__(kThreads) k_dir_update(Band B, int k) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = qr + 16 * a + 4 * v + lk, c = qc + 16 * b + li;
-        B.p[band_at(B, j, rt * kNb + r, c)] -= acc[a][b][v];
+        B.p[band_at(B, j, rt * kNb + r, c)] = cv[a][b][v] - acc[a][b][v];
       }
 }
 
