@@ -172,9 +172,14 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
 }
 
 // Row `lane` of panel k's diagonal block (lower part; zeros above).
+// (loads of the upper part too, which lies inside the band's storage,
+// H >= 64, so that no load waits behind a branch; those values are dropped)
 __device__ __forceinline__ void load_diag_row(const Band& B, int k, int lane, double (&a)[kNb]) {
 #pragma unroll
-  for (int c = 0; c < kNb; ++c) a[c] = c <= lane ? B.p[band_at(B, k, lane, c)] : 0.0;
+  for (int c = 0; c < kNb; ++c) {
+    const double x = B.p[band_at(B, k, lane, c)];
+    a[c] = c <= lane ? x : 0.0;
+  }
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -489,7 +494,10 @@ __global__ void __launch_bounds__(kThreads) k_dir_bwd(Band B, int k, double* __r
     const int lane = threadIdx.x;
     double col[kNb];                     // col[j] = L[j][lane]
 #pragma unroll
-    for (int j = 0; j < kNb; ++j) col[j] = j >= lane ? B.p[band_at(B, k, j, lane)] : 0.0;
+    for (int j = 0; j < kNb; ++j) {
+      const double x = B.p[band_at(B, k, j, lane)];   // as in load_diag_row
+      col[j] = j >= lane ? x : 0.0;
+    }
     double v = y[k * kNb + lane];
     double dg = 1.0;
 #pragma unroll
