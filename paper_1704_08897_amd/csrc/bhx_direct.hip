@@ -221,13 +221,18 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
   for (int c0 = 0, d = 0; c0 < kNb; c0 += kStep, ++d) {
     if (w == 0) {
       // diagonal kStep x kStep block: lane l < kStep holds row c0 + l
+      // one reciprocal square root per pivot p on the serial chain:
+      // L_jj = p / sqrt(p), the column below it a / sqrt(p)
       double a[kStep];
+      double rl = 1.0;                           // 1 / L[c0 + lane][c0 + lane]
 #pragma unroll
       for (int dd = 0; dd < kStep; ++dd) a[dd] = lane < kStep ? M[c0 + dd][c0 + lane] : 0.0;
 #pragma unroll
       for (int j = 0; j < kStep; ++j) {
-        const double dj = sqrt(lane_value(a[j], j));
-        const double l = lane > j ? a[j] / dj : (lane == j ? dj : 0.0);
+        const double pj = lane_value(a[j], j);
+        const double rj = rsqrt(pj);
+        const double l = lane > j ? a[j] * rj : (lane == j ? pj * rj : 0.0);
+        rl = lane == j ? rj : rl;
         a[j] = l;
 #pragma unroll
         for (int m = j + 1; m < kStep; ++m) a[m] -= l * lane_value(l, m);
@@ -236,7 +241,7 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
 #pragma unroll
         for (int dd = 0; dd < kStep; ++dd)
           if (dd <= lane) M[c0 + dd][c0 + lane] = a[dd];
-        rinv[c0 + lane] = 1.0 / a[lane];
+        rinv[c0 + lane] = rl;
       }
     }
     __syncthreads();
