@@ -246,15 +246,19 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
     }
     __syncthreads();
     if (tid < kStep) {
-      // column tid of L_dd^-1: solve L_dd y = e_tid
+      // column tid of L_dd^-1: solve L_dd y = e_tid, column-oriented so that
+      // each step's updates are independent (every entry still subtracts
+      // its terms in ascending order)
       const int jc = tid;
       double y[kStep];
 #pragma unroll
-      for (int i = 0; i < kStep; ++i) {
-        double v = i == jc ? 1.0 : 0.0;
+      for (int i = 0; i < kStep; ++i) y[i] = i == jc ? 1.0 : 0.0;
 #pragma unroll
-        for (int m = 0; m < i; ++m) v -= M[c0 + m][c0 + i] * (m >= jc ? y[m] : 0.0);
-        y[i] = i >= jc ? v * rinv[c0 + i] : 0.0;
+      for (int i = 0; i < kStep; ++i) {
+        const double yi = i >= jc ? y[i] * rinv[c0 + i] : 0.0;
+        y[i] = yi;
+#pragma unroll
+        for (int m = i + 1; m < kStep; ++m) y[m] -= M[c0 + i][c0 + m] * yi;
       }
 #pragma unroll
       for (int i = 0; i < kStep; ++i) Li[d][i][jc] = y[i];
