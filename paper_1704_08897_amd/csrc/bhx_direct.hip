@@ -36,6 +36,8 @@ constexpr int kNb = 64;          // panel width (block size)
 
 struct Band {
   double* p;     // panels
+  double* d;     // factored diagonal blocks L_kk, two 64 x 64 copies per panel:
+                 // column-major (forward substitution), row-major (backward)
   int n;         // unknowns
   int npad;      // n rounded up to kNb
   int nblk;      // panels
@@ -45,6 +47,13 @@ struct Band {
 
 __device__ __forceinline__ size_t band_at(const Band& B, int k, int r, int c) {
   return ((size_t)k * kNb + c) * B.H + r;
+}
+// L_kk[r][c] in the column-major and the row-major copy
+__device__ __forceinline__ size_t diag_col(int k, int r, int c) {
+  return ((size_t)k * 2 * kNb + c) * kNb + r;
+}
+__device__ __forceinline__ size_t diag_row(int k, int r, int c) {
+  return ((size_t)k * 2 * kNb + kNb + r) * kNb + c;
 }
 
 __device__ double block_sum_d(double v, double* red) {
@@ -171,15 +180,10 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Row `lane` of panel k's diagonal block (lower part; zeros above).
-// (loads of the upper part too, which lies inside the band's storage,
-// H >= 64, so that no load waits behind a branch; those values are dropped)
+// Row `lane` of L_kk (zeros above the diagonal), from the column-major copy.
 __device__ __forceinline__ void load_diag_row(const Band& B, int k, int lane, double (&a)[kNb]) {
 #pragma unroll
-  for (int c = 0; c < kNb; ++c) {
-    const double x = B.p[band_at(B, k, lane, c)];
-    a[c] = c <= lane ? x : 0.0;
-  }
+  for (int c = 0; c < kNb; ++c) a[c] = B.d[diag_col(k, lane, c)];
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -302,10 +306,14 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
     }
     __syncthreads();
   }
+  // Block 0 stores L_kk outside the band: the other blocks of this launch
+  // read the band's diagonal block (A_kk) when they start, at any time.
   if (blockIdx.x == 0) {
     for (int e = tid; e < kNb * kNb; e += kThreads) {
       const int c = e >> 6, r = e & 63;
-      if (r >= c) B.p[band_at(B, k, r, c)] = M[c][r];
+      B.d[diag_col(k, r, c)] = r >= c ? M[c][r] : 0.0;
+      const int r2 = e >> 6, c2 = e & 63;
+      B.d[diag_row(k, r2, c2)] = r2 >= c2 ? M[c2][r2] : 0.0;
     }
   }
   const int t = blockIdx.x * 4 + w;
@@ -434,11 +442,13 @@ __global__ void __launch_bounds__(kThreads) k_dir_update(Band B, int k) {
       }
 }
 
-// Forward substitution step k on y (length npad): wave 0 of every block
-// solves L_kk y_k = y_k (lane t: y_t and row t of L_kk in registers, and
-// 1 / L_tt, so that the serial chain multiplies instead of dividing);
-// block 0 stores y_k, block b >= 1 updates y_(k+b) -= L_(k+b,k) y_k.
-__global__ void __launch_bounds__(kThreads) k_dir_fwd(Band B, int k, double* __restrict__ y) {
+// Forward substitution step k: wave 0 of every block solves L_kk z_k = y_k
+// (lane t: y_t and row t of L_kk in registers, and 1 / L_tt, so that the
+// serial chain multiplies instead of dividing); block 0 stores z_k, block
+// b >= 1 updates y_(k+b) -= L_(k+b,k) z_k.  z_k goes to its own vector: the
+// other blocks read y_k when they start, at any time.
+__global__ void __launch_bounds__(kThreads) k_dir_fwd(Band B, int k, double* __restrict__ y,
+                                                      double* __restrict__ z) {
   __shared__ double yk[kNb];
   __shared__ double part[4][kNb];
   // the update's part of L_(k+b,k) (row r, columns 16 cs..), loaded before
@@ -469,7 +479,7 @@ __global__ void __launch_bounds__(kThreads) k_dir_fwd(Band B, int k, double* __r
   }
   __syncthreads();
   if (b == 0) {
-    if (threadIdx.x < kNb) y[k * kNb + threadIdx.x] = yk[threadIdx.x];
+    if (threadIdx.x < kNb) z[k * kNb + threadIdx.x] = yk[threadIdx.x];
     return;
   }
   // rows b*kNb.. of panel k: r = tid % 64, columns in four strips of 16
@@ -484,10 +494,11 @@ __global__ void __launch_bounds__(kThreads) k_dir_fwd(Band B, int k, double* __r
 }
 
 // Backward substitution step k (k descending): wave 0 of every block solves
-// L_kk^T x_k = y_k (lane t: y_t, column t of L_kk and 1 / L_tt in registers); block 0
-// stores x_k, block b >= 1 updates y_(k-b) -= L_(k,k-b)^T x_k (rows b*kNb..
-// of panel k-b).
-__global__ void __launch_bounds__(kThreads) k_dir_bwd(Band B, int k, double* __restrict__ y) {
+// L_kk^T x_k = z_k (lane t: z_t, column t of L_kk and 1 / L_tt in
+// registers); block 0 stores x_k into x, block b >= 1 updates
+// z_(k-b) -= L_(k,k-b)^T x_k (rows b*kNb.. of panel k-b).
+__global__ void __launch_bounds__(kThreads) k_dir_bwd(Band B, int k, double* __restrict__ z,
+                                                      double* __restrict__ x) {
   __shared__ double xk[kNb];
   __shared__ double part[4][kNb];
   // the update's part of panel k-b (column c, rows b*kNb + 16 rs..), loaded
@@ -503,11 +514,8 @@ __global__ void __launch_bounds__(kThreads) k_dir_bwd(Band B, int k, double* __r
     const int lane = threadIdx.x;
     double col[kNb];                     // col[j] = L[j][lane]
 #pragma unroll
-    for (int j = 0; j < kNb; ++j) {
-      const double x = B.p[band_at(B, k, j, lane)];   // as in load_diag_row
-      col[j] = j >= lane ? x : 0.0;
-    }
-    double v = y[k * kNb + lane];
+    for (int j = 0; j < kNb; ++j) col[j] = B.d[diag_row(k, j, lane)];
+    double v = z[k * kNb + lane];
     double dg = 1.0;
 #pragma unroll
     for (int j = 0; j < kNb; ++j) dg = lane == j ? col[j] : dg;
@@ -522,7 +530,7 @@ __global__ void __launch_bounds__(kThreads) k_dir_bwd(Band B, int k, double* __r
   }
   __syncthreads();
   if (b == 0) {
-    if (threadIdx.x < kNb) y[k * kNb + threadIdx.x] = xk[threadIdx.x];
+    if (threadIdx.x < kNb) x[k * kNb + threadIdx.x] = xk[threadIdx.x];
     return;
   }
   // y_(k-b)[c] -= sum_r P_(k-b)[c][b*kNb + r] x_k[r]: c = tid % 64, r strips
@@ -532,7 +540,7 @@ __global__ void __launch_bounds__(kThreads) k_dir_bwd(Band B, int k, double* __r
   part[rs][c] = s;
   __syncthreads();
   if (threadIdx.x < kNb)
-    y[kb * kNb + threadIdx.x] -=
+    z[kb * kNb + threadIdx.x] -=
         (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
 }
 
@@ -602,7 +610,8 @@ int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R
   bool factored = false;
   Band B{};
   int* uidx = nullptr;
-  double* y = nullptr;
+  double* y = nullptr;   // right-hand side, then the solution
+  double* z = nullptr;   // forward substitution's result
   for (int f = 0; f < n; ++f) {
     const InstSpec& S = specs[f];
     Grids g;
@@ -665,17 +674,21 @@ int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R
       B.Q = (w + kNb - 1) / kNb;
       B.H = kNb + B.Q * kNb;
       const size_t pbytes = (size_t)B.nblk * kNb * B.H * sizeof(double);
+      const size_t dbytes = (size_t)B.nblk * 2 * kNb * kNb * sizeof(double);
       const size_t ybytes = (size_t)B.npad * sizeof(double);
+      const size_t bytes = pbytes + dbytes + 2 * ybytes;
       if (pbytes > ((size_t)200 << 30)) return BHX_ERR_NOMEM;
-      if (pbytes + ybytes > hd->band_cap) {
+      if (bytes > hd->band_cap) {
         if (hd->band) DIR_CHECK(hipFree(hd->band));
         hd->band = nullptr;
         hd->band_cap = 0;
-        DIR_CHECK(hipMalloc(&hd->band, pbytes + ybytes));
-        hd->band_cap = pbytes + ybytes;
+        DIR_CHECK(hipMalloc(&hd->band, bytes));
+        hd->band_cap = bytes;
       }
       B.p = (double*)hd->band;
-      y = (double*)((char*)hd->band + pbytes);
+      B.d = (double*)((char*)hd->band + pbytes);
+      y = (double*)((char*)hd->band + pbytes + dbytes);
+      z = y + B.npad;
       // assemble and factor
       DIR_CHECK(hipMemsetAsync(B.p, 0, pbytes, st));
       hipLaunchKernelGGL(k_dir_assemble, dim3((N + kThreads - 1) / kThreads), dim3(kThreads), 0,
@@ -703,10 +716,10 @@ int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R
                            B.npad, y);
         for (int k = 0; k < B.nblk; ++k)
           hipLaunchKernelGGL(k_dir_fwd, dim3(1 + std::min(B.Q, B.nblk - 1 - k)), dim3(kThreads),
-                             0, st, B, k, y);
+                             0, st, B, k, y, z);
         for (int k = B.nblk - 1; k >= 0; --k)
           hipLaunchKernelGGL(k_dir_bwd, dim3(1 + std::min(B.Q, k)), dim3(kThreads), 0, st, B, k,
-                             y);
+                             z, y);
         hipLaunchKernelGGL(k_dir_scatter, dim3((N + 255) / 256), dim3(256), 0, st, P.mask, uidx,
                            y, N, it > 0 ? 1 : 0, S.F);
         DIR_CHECK(hipGetLastError());
