@@ -88,6 +88,28 @@ def test_star1024_direct(handle):
         assert O.relative_l2(got, Fo) <= bound, (tol, O.relative_l2(got, Fo))
 
 
+def test_repeated_solves_identical(handle):
+    """Solves of one problem are bit-identical, whether F starts from the
+    given values or holds the previous extension, and take one pass.  In
+    each launch of the factorisation and the substitutions, the blocks read
+    data that no block of the same launch writes, so block start order
+    cannot change a result."""
+    p = W.star_inward_problem(256, tol=1e-8)
+    phi = dev(p.phi)
+    o = bhx.default_opts(solver=1)
+    outs, its = [], []
+    G = dev(p.F)
+    for fresh in (True, False, False, True):
+        if fresh:
+            G = dev(p.F)
+        s, st = bhx.extend_ex(handle, phi, G, bc=p.bc, h=p.h, tol=p.tol, opts=o)
+        assert s == bhx.OK, st.as_dict()
+        outs.append(host(G))
+        its.append(st.iterations)
+    assert all(np.array_equal(outs[0], x) for x in outs[1:])
+    assert its == [its[0]] * len(its) and its[0] == 1, its
+
+
 def test_fields_share_one_factorisation(handle):
     """Several fields on one phi: each equals its own direct solve bit for
     bit (one factorisation serves all)."""
