@@ -495,8 +495,9 @@ __global__ void __launch_bounds__(kThreads) k_dir_fwd(Band B, int k, double* __r
 
 // Backward substitution step k (k descending): wave 0 of every block solves
 // L_kk^T x_k = z_k (lane t: z_t, column t of L_kk and 1 / L_tt in
-// registers); block 0 stores x_k into x, block b >= 1 updates
-// z_(k-b) -= L_(k,k-b)^T x_k (rows b*kNb.. of panel k-b).
+// registers); block 0 stores x_k into x (its own vector, as in the forward
+// step), block b >= 1 updates z_(k-b) -= L_(k,k-b)^T x_k (rows b*kNb.. of
+// panel k-b).
 __global__ void __launch_bounds__(kThreads) k_dir_bwd(Band B, int k, double* __restrict__ z,
                                                       double* __restrict__ x) {
   __shared__ double xk[kNb];
@@ -533,7 +534,7 @@ __global__ void __launch_bounds__(kThreads) k_dir_bwd(Band B, int k, double* __r
     if (threadIdx.x < kNb) x[k * kNb + threadIdx.x] = xk[threadIdx.x];
     return;
   }
-  // y_(k-b)[c] -= sum_r P_(k-b)[c][b*kNb + r] x_k[r]: c = tid % 64, r strips
+  // z_(k-b)[c] -= sum_r P_(k-b)[c][b*kNb + r] x_k[r]: c = tid % 64, r strips
   double s = 0.0;
 #pragma unroll
   for (int u = 0; u < 16; ++u) s += lv[u] * xk[rs * 16 + u];
