@@ -257,12 +257,26 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
       double y[kStep];
 #pragma unroll
       for (int i = 0; i < kStep; ++i) y[i] = i == jc ? 1.0 : 0.0;
+      // step i's column of L and 1 / L_ii are read one step ahead, so the
+      // chain does not wait for LDS
+      double lc[kStep], ln[kStep];
+      double rc = rinv[c0], rn = 0.0;
+#pragma unroll
+      for (int m = 1; m < kStep; ++m) lc[m] = M[c0][c0 + m];
 #pragma unroll
       for (int i = 0; i < kStep; ++i) {
-        const double yi = i >= jc ? y[i] * rinv[c0 + i] : 0.0;
+        if (i + 1 < kStep) {
+#pragma unroll
+          for (int m = i + 2; m < kStep; ++m) ln[m] = M[c0 + i + 1][c0 + m];
+          rn = rinv[c0 + i + 1];
+        }
+        const double yi = i >= jc ? y[i] * rc : 0.0;
         y[i] = yi;
 #pragma unroll
-        for (int m = i + 1; m < kStep; ++m) y[m] -= M[c0 + i][c0 + m] * yi;
+        for (int m = i + 1; m < kStep; ++m) y[m] -= lc[m] * yi;
+#pragma unroll
+        for (int m = i + 2; m < kStep; ++m) lc[m] = ln[m];
+        rc = rn;
       }
 #pragma unroll
       for (int i = 0; i < kStep; ++i) Li[d][i][jc] = y[i];
