@@ -111,15 +111,19 @@ def _fourier_field(X, Y, rng, modes=8, kmax=6, period=1.0):
     return F
 
 
-def _circles_phi(X, Y, rng, count, rmin=0.05, rmax=0.15, period=1.0):
+def _circles_phi(X, Y, rng, count, rmin=0.05, rmax=0.15, periodic=True):
+    """min over ``count`` circles of (distance - radius); centres uniform on
+    the unit square the grids cover, radii U[rmin, rmax].  ``periodic``: the
+    distance is the minimum-image one on the unit torus; otherwise plain."""
     phi = np.full(X.shape, np.inf)
     for _ in range(count):
-        cx, cy = rng.uniform(0, period, size=2)
+        cx, cy = rng.uniform(0, 1, size=2)
         r = rng.uniform(rmin, rmax)
         dx = X - cx
         dy = Y - cy
-        dx -= period * np.round(dx / period)        # minimum image
-        dy -= period * np.round(dy / period)
+        if periodic:
+            dx -= np.round(dx)                     # minimum image, period 1
+            dy -= np.round(dy)
         phi = np.minimum(phi, np.sqrt(dx * dx + dy * dy) - r)
     return phi
 
@@ -200,19 +204,79 @@ class RequestSpec:
     kind: str                # "circles" or "star"
     tol: float = 1e-8
 
-    def materialise(self) -> Problem:
+    def params(self) -> dict:
+        """The request's random parameters, drawn from its seed in a fixed
+        order: the interface (circle centres and radii, or the star's
+        amplitudes and phases), then the 8 Fourier modes of F."""
         rng = np.random.default_rng(self.seed)
+        out = {"kind": self.kind}
+        if self.kind == "circles":
+            circ = []
+            for _ in range(int(rng.integers(1, 21))):
+                cx, cy = rng.uniform(0, 1, size=2)
+                circ.append((cx, cy, rng.uniform(0.05, 0.15)))
+            out["circles"] = circ
+        else:
+            out["star_a"] = rng.uniform(0, 0.05, size=8)
+            out["star_psi"] = rng.uniform(0, 2 * np.pi, size=8)
+        modes = []
+        for _ in range(8):
+            while True:
+                k = rng.integers(-6, 7, size=2)
+                if k[0] != 0 or k[1] != 0:
+                    break
+            modes.append((int(k[0]), int(k[1]), rng.normal(), rng.uniform(0, 2 * np.pi)))
+        out["modes"] = modes
+        return out
+
+    def materialise(self) -> Problem:
+        """numpy arrays on the host."""
         n, bc = self.n, self.bc
         X, Y = _mesh(n, n, ((0, 1), (0, 1)), bc, bc)
-        if self.kind == "circles":
-            phi = _circles_phi(X, Y, rng, int(rng.integers(1, 21)),
-                               period=1.0 if bc == PERIODIC else 1e9)
-        else:
-            phi = _star_phi(X - 0.5, Y - 0.5, rng, r0=0.25)
-        F = _fourier_field(X, Y, rng)
+        phi, F = _request_fields(self.params(), X, Y, bc == PERIODIC, np)
         if not (phi < 0).any():          # guarantee a known node
             phi.flat[0] = -1.0
         return Problem(phi, F, bc, bc, 1.0 / n, self.tol, f"req{self.seed}")
+
+    def materialise_torch(self, device):
+        """The same fields evaluated by torch on ``device`` (float64), for
+        streams too long to build on the host; the values agree with
+        ``materialise`` to rounding.  Returns (phi, F) tensors."""
+        import torch
+        n, bc = self.n, self.bc
+        x = torch.as_tensor(axis_nodes(n, 0.0, 1.0, bc), device=device)
+        Y, X = torch.meshgrid(x, x, indexing="ij")          # X[j, i] = x_i
+        phi, F = _request_fields(self.params(), X, Y, bc == PERIODIC, torch)
+        if not bool((phi < 0).any()):
+            phi.view(-1)[0] = -1.0
+        return phi.contiguous(), F.contiguous()
+
+
+def _request_fields(prm, X, Y, periodic, xp):
+    """phi and F of a serving request from its parameters, with array module
+    ``xp`` (numpy or torch): the multi-circle or star interface, known
+    inside, and the sum of Fourier modes."""
+    if prm["kind"] == "circles":
+        phi = None
+        for cx, cy, r in prm["circles"]:
+            dx = X - cx
+            dy = Y - cy
+            if periodic:
+                dx = dx - xp.round(dx)                     # minimum image, period 1
+                dy = dy - xp.round(dy)
+            d = xp.sqrt(dx * dx + dy * dy) - r
+            phi = d if phi is None else xp.minimum(phi, d)
+    else:
+        Xc, Yc = X - 0.5, Y - 0.5
+        th = xp.arctan2(Yc, Xc)
+        rr = xp.ones_like(th)
+        for k in range(8):
+            rr = rr + prm["star_a"][k] * xp.cos((k + 1) * th + prm["star_psi"][k])
+        phi = xp.sqrt(Xc * Xc + Yc * Yc) - 0.25 * rr
+    F = xp.zeros_like(X)
+    for kx, ky, a, psi in prm["modes"]:
+        F = F + a * xp.cos(2 * np.pi * (kx * X + ky * Y) + psi)
+    return phi, F
 
 
 def request_stream(count: int = 10000, seed: int = 5, nmin=128, nmax=2048,

@@ -56,7 +56,10 @@ def random_phi(rng, nx, ny, frac=0.4):
 # n+1 a power of two use a plain FFT of length 2(n+1), others Bluestein.
 CASES_OP = [(64, 64, 0, 0), (100, 75, 0, 1), (96, 128, 1, 1), (4, 4, 0, 0), (5, 7, 1, 0),
             (130, 33, 1, 0), (256, 48, 0, 0), (63, 31, 2, 2), (100, 75, 2, 0), (96, 130, 1, 2),
-            (5, 7, 2, 1), (4, 4, 2, 2)]
+            (5, 7, 2, 1), (4, 4, 2, 2),
+            # 64 x 32 tiles whose 2-node halo lies inside the grid on every side
+            # take the interior fast path of the stencil (no ghost rule)
+            (256, 256, 0, 0), (300, 260, 1, 2)]
 
 
 @pytest.mark.parametrize("nx,ny,bx,by", CASES_OP)
@@ -245,7 +248,7 @@ def test_batched_equals_alone(handle, monkeypatch):
     in a fixed order, work split independent of the batch).  A mixed batch
     runs the plan-table kernels, so the solo solves do too."""
     monkeypatch.setenv("BHX_SHAPE_KERNELS", "0")
-    batch = W.star_cubic_batch(6, seed=21, nmin=40, nmax=150, tol=1e-10)
+    batch = W.star_cubic_batch(6, seed=21, nmin=40, nmax=150, tol=1e-12)
     phis = [dev(p.phi) for p in batch]
     Fs = [dev(p.F) for p in batch]
     s, sts = bhx.extend_batched(handle, phis, Fs, [p.h for p in batch], [p.bc for p in batch],
@@ -256,7 +259,7 @@ def test_batched_equals_alone(handle, monkeypatch):
         got = host(F)
         assert np.array_equal(got, alone)
         assert st1.iterations == st.iterations
-        check_against_oracle(p, got, bound=1e-7)
+        check_against_oracle(p, got, bound=1e-9)
 
 
 def test_batched_autotuned_fp32(handle):
@@ -327,3 +330,21 @@ def test_paper_examples_iterations_and_errors(handle, golden_dir):
         assert abs(it - iters) <= 0.08 * iters, (key, it, iters)
         e = _near_error(p, got, kind)
         assert abs(e - err) <= 0.15 * err, (key, kind, e, err)
+
+
+def test_known_set_tie_break_on_gpu(handle):
+    """Nodes with phi exactly 0 or NaN are unknown on the GPU path too (the
+    strict inequality of the region definitions of Sec. 3): the extension
+    replaces their sentinel values and matches the oracle element by element;
+    the values at phi < 0 come back bit for bit."""
+    from test_oracle_pins import tie_break_problem
+    phi, F, known, ties = tie_break_problem()
+    p = W.Problem(phi, F, 0, 0, 1.0, 1e-12)
+    s, st, got = solve(handle, p)
+    assert s == bhx.OK, st.as_dict()
+    assert st.n_unknown == int((~known).sum())
+    assert np.all(got[ties] != 1e3)
+    ref, _ = O.extend_direct(phi, F, 0, 0)
+    assert np.array_equal(got[known], F[known])
+    assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
+    assert O.relative_l2(got, ref) <= 1e-9

@@ -262,6 +262,55 @@ def test_enclosed_interior_independent_of_bc():
     assert np.abs(Fn[outer] - Fd[outer]).max() > 1e-3
 
 
+def tie_break_problem():
+    """A disc known inside on a 24 x 20 Neumann grid, with some nodes where
+    phi is exactly 0 or NaN, half of them inside the disc.  F holds a sentinel
+    (1e3) at those nodes.  Returns (phi, F, hand-built known mask, the nodes
+    with phi == 0 or NaN)."""
+    nx, ny = 24, 20
+    jj, ii = np.mgrid[0:ny, 0:nx]
+    d2 = (ii - 11.37) ** 2 + (jj - 9.61) ** 2
+    inside = d2 < 6.5 ** 2                     # the disc, from squared distances
+    phi = np.sqrt(d2) - 6.5
+    ties = np.zeros((ny, nx), bool)
+    for (j, i) in ((9, 11), (8, 14), (12, 9), (3, 3), (15, 20)):
+        phi[j, i] = 0.0
+        ties[j, i] = True
+    for (j, i) in ((10, 8), (6, 12), (1, 22)):
+        phi[j, i] = np.nan
+        ties[j, i] = True
+    F = np.cos(0.3 * ii) + 0.1 * jj
+    F[ties] = 1e3
+    known = inside & ~ties                     # strict reading: phi == 0 and NaN unknown
+    return phi, F, known, ties
+
+
+def test_known_set_is_strict_at_zero_and_nan():
+    """The region definitions of Sec. 3 use a strict inequality: a node with
+    phi == 0 is unknown, and so is a node with phi NaN (it is not < 0).  The
+    mask is compared with one built from squared distances by hand; the
+    extension treats those nodes as unknown (their sentinel value is replaced
+    by a value satisfying eq. (12) there), and the non-strict reading gives a
+    different field."""
+    phi, F, known, ties = tie_break_problem()
+    assert np.array_equal(ties, (phi == 0) | np.isnan(phi))
+    inside = known | (ties & (np.hypot(*(np.mgrid[0:20, 0:24] - np.array([[[9.61]], [[11.37]]])))
+                              < 6.5))
+    assert (ties & inside).sum() == 5 and (ties & ~inside).sum() == 3
+    assert np.array_equal(O.known_mask(phi), known)
+    Fo, info = O.extend_direct(phi, F, O.NEUMANN, O.NEUMANN)
+    assert info["n_unknown"] == (~known).sum()
+    assert np.all(Fo[ties] != 1e3) and np.all(np.abs(Fo[ties]) < 10)
+    assert np.array_equal(Fo[known], F[known])
+    # eq. (12) holds at every unknown node, the tie nodes included
+    res = O.stencil_padded(Fo, O.NEUMANN, O.NEUMANN)
+    assert np.abs(res[~known]).max() < 1e-9 * np.abs(Fo).max()
+    # the non-strict reading (phi <= 0 known) keeps the sentinels and moves u
+    Fle, _ = O.extend_direct(None, F, O.NEUMANN, O.NEUMANN, known=known | (phi == 0))
+    assert np.all(Fle[phi == 0] == 1e3)
+    assert np.abs(Fle - Fo)[~known & ~ties].max() > 1.0
+
+
 def test_singular_and_trivial_cases():
     F = np.ones((6, 6))
     with pytest.raises(O.biharmonic.SingularProblem):

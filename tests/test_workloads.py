@@ -1,0 +1,77 @@
+"""CPU checks of the seeded input generators (no GPU, no oracle).
+
+The serving mix must be what its description says: every request has a
+genuine interface, with a known region of the size its circles or star give
+(a single circle of the smallest radius, 0.05, covers 0.79% of the unit
+square; the star of mean radius 0.25 about 20%), never a lone known node.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1704_08897_amd import workloads as W
+
+
+def interface_nodes(known):
+    """Known nodes with an unknown axis neighbour (edges not wrapped)."""
+    k = known
+    u = ~k
+    nb = np.zeros_like(k)
+    nb[1:, :] |= u[:-1, :]
+    nb[:-1, :] |= u[1:, :]
+    nb[:, 1:] |= u[:, :-1]
+    nb[:, :-1] |= u[:, 1:]
+    return int((k & nb).sum())
+
+
+def test_request_mix_has_real_interfaces():
+    """The first 300 requests of the serving stream, materialised at a side of
+    at most 128 (the geometry is drawn from the seed independently of the
+    side): known fraction in [0.5%, 99%] and at least 8 interface nodes, for
+    both boundary rules and both interface kinds."""
+    specs = W.request_stream(300, seed=5)
+    seen = set()
+    for s in specs:
+        small = W.RequestSpec(s.seed, min(s.n, 128), s.bc, s.kind, s.tol)
+        p = small.materialise()
+        known = p.phi < 0
+        frac = known.mean()
+        assert 0.005 <= frac <= 0.99, (s, frac)
+        assert interface_nodes(known) >= 8, s
+        seen.add((s.kind, s.bc))
+    assert seen == {("circles", 0), ("circles", 1), ("star", 0), ("star", 1)}
+
+
+def test_request_mix_full_size_sample():
+    """A few requests at their own sizes: the fractions agree with the
+    reduced-size ones, and Neumann circle centres lie on the grid."""
+    specs = [s for s in W.request_stream(60, seed=5) if s.n <= 700]
+    neumann_circles = [s for s in specs if s.kind == "circles" and s.bc == W.NEUMANN][:3]
+    assert neumann_circles
+    for s in neumann_circles + [s for s in specs if s.kind == "star"][:1]:
+        p = s.materialise()
+        q = W.RequestSpec(s.seed, 128, s.bc, s.kind, s.tol).materialise()
+        f, g = (p.phi < 0).mean(), (q.phi < 0).mean()
+        assert 0.005 <= f <= 0.99
+        assert abs(f - g) <= 0.02 + 0.1 * g, (s, f, g)
+
+
+def test_request_stream_distribution():
+    specs = W.request_stream(2000, seed=5)
+    n = np.array([s.n for s in specs])
+    assert n.min() >= 128 and n.max() <= 2048
+    # log-uniform: the median side is near sqrt(128 * 2048) = 512
+    assert 420 <= np.median(n) <= 620
+    assert 0.45 <= np.mean([s.bc == W.PERIODIC for s in specs]) <= 0.55
+    assert 0.45 <= np.mean([s.kind == "star" for s in specs]) <= 0.55
+    assert len({s.seed for s in specs}) == len(specs)
+
+
+def test_generators_are_deterministic():
+    a = W.request_stream(5, seed=9)[3].materialise()
+    b = W.request_stream(5, seed=9)[3].materialise()
+    assert np.array_equal(a.phi, b.phi) and np.array_equal(a.F, b.F)
+    c = W.star_cubic_batch(3, seed=4)
+    d = W.star_cubic_batch(3, seed=4)
+    assert all(np.array_equal(x.phi, y.phi) for x, y in zip(c, d))
