@@ -1,15 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the biharmonic-extension solve on one MI355X.
 
-One step = one complete extension solve (mask, right-hand side,
-preconditioned CG to the relative-residual tolerance, true-residual check)
-of the default workload: a 1024 x 1024 grid on [-1, 1]^2 with Neumann
-boundaries, the star interface r(theta) = 0.4 (1 + 0.1 cos 5 theta),
-F = exp(x) cos(3y) known outside the star and extended inward, float64 PCG
-with the DCT fast Poisson preconditioner, tolerance 1e-8.  phi and F are
-resident in device memory before the timed region; every solve overwrites
-the unknown values of F (the solver ignores them on input, so each step
-solves the same system).
+Default workload: the serving stream.  Extension requests arrive as a Poisson
+process and are served by the continuous-batching engine (FP64
+preconditioner, tol 1e-8): square grids with sides log-uniform in
+[128, 2048], Neumann or periodic, multi-circle or star interfaces, F a sum
+of 8 Fourier modes, each request distinct and built from its own seed.  The
+arrival rate is 0.8 x the saturated rate, measured first on other requests
+of the same stream submitted all at once.  The value is completed solves
+per second over the timed stream, with p50/p99 latency from arrival to
+completion.  Inputs are materialised in device memory before a stream
+starts (not counted in latency).  A "step" of this workload is one request:
+the timed stream holds max(--steps, --requests) requests.
+
+Beside it (unless --no-extra): the same stream served with the FP32
+preconditioner; the 1024^2 star (one solve per step, FP64 at tol 1e-8 and in
+accurate mode at tol 1e-13); the 256-instance batch (FP64 and FP32 batched
+against one call per instance); the 2048^2 periodic multi-circle case with
+the FP32 and FP64 preconditioners; and the CPU oracle timed on a bounded
+sample of the stream.
+
+Other workloads (--workload): star_inward_1024, circle_64,
+periodic_circles_2048(_fp64), batch256, example2_256.
 
 Prints ONE JSON line (last line of stdout).  Progress goes to stderr.
 """
@@ -17,6 +29,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import statistics
 import sys
 import time
@@ -47,23 +60,27 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def pass_bytes(p, n_unknown, N, prec):
-    """Algorithmic HBM bytes of one launch of pass p for one instance: each
-    vector read or written once, values only at unknown nodes for the CG
-    vectors (loads and stores are predicated on the mask), the 1-byte mask
-    where a pass reads it, the transform buffer over the whole grid
-    (8 B float64 or 4 B float32 per node)."""
-    U = n_unknown
+def pass_coeffs(p, prec):
+    """Algorithmic HBM bytes of one launch of pass p for one instance, as
+    (bytes per unknown node, bytes per node): each vector read or written
+    once, values only at unknown nodes for the CG vectors (loads and stores
+    are predicated on the mask), the 1-byte mask where a pass reads it, the
+    transform buffer over the whole grid (8 B float64 or 4 B float32)."""
     tb = 8 if prec == 0 else 4
     if p == 0:      # z, p_old read; p_new, q written; mask
-        return 32 * U + N
+        return 32, 1
     if p == 1:      # F, p, q, r read; F, r written; mask; t written
-        return 48 * U + N + tb * N
+        return 48, 1 + tb
     if p == 2:      # t read and written
-        return 2 * tb * N
+        return 0, 2 * tb
     if p == 3:      # t read, r read, z written, mask
-        return 16 * U + N + tb * N
+        return 16, 1 + tb
     raise ValueError(p)
+
+
+def pass_bytes(p, n_unknown, N, prec):
+    cu, cn = pass_coeffs(p, prec)
+    return cu * n_unknown + cn * N
 
 
 def kernel_source_hash():
@@ -91,23 +108,309 @@ def load_traffic(kernel, wl):
         return None
 
 
-def cpu_baseline(p, samples):
+def host_info():
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def percentiles(lat):
     import numpy as np
-    import oracle as O
-    times = []
-    ref = None
-    for _ in range(samples):
+    a = np.asarray(lat)
+    return {"p50": round(1e3 * float(np.median(a)), 2),
+            "p99": round(1e3 * float(np.percentile(a, 99)), 2),
+            "max": round(1e3 * float(a.max()), 2)}
+
+
+# ---------------------------------------------------------------------------
+# serving stream (default)
+# ---------------------------------------------------------------------------
+
+def bench_serve(args):
+    """FP64 serving: warm-up, saturated rate, timed Poisson stream; FP32
+    served the same way; one profiled stream for the roofline."""
+    import numpy as np
+    import torch
+    from paper_1704_08897_amd import bhx, workloads as W
+    from paper_1704_08897_amd.server import Request, Server, serve_stream
+    dev = torch.device("cuda:0")
+    specs = W.request_stream(10000, seed=5)
+    n_timed = max(args.steps, args.requests)
+    n_warm = min(8, max(1, args.warmup) * 4)
+    a0, a1 = n_warm, n_warm + args.sat_requests
+    sets = {"warm": specs[:a0], "sat": specs[a0:a1], "timed": specs[a1:a1 + n_timed]}
+
+    def materialise(ss):
+        out = [s.materialise_torch(dev) for s in ss]
+        torch.cuda.synchronize()
+        return out
+
+    def requests(ss, fields, arrivals):
+        return [Request(phi, F, W.bc_code(s.bc, s.bc), 1.0 / s.n, s.tol, arrival=a, tag=s)
+                for s, (phi, F), a in zip(ss, fields, arrivals)]
+
+    def progress(tag):
+        count = [0]
+        t_start = time.perf_counter()
+
+        def on_done(r):
+            count[0] += 1
+            if count[0] % 20 == 0:
+                log(f"{tag}: {count[0]} done, {time.perf_counter() - t_start:.1f} s")
+        return on_done
+
+    def run(srv, ss, fields, arrivals, tag):
+        reqs = requests(ss, fields, arrivals)
         t0 = time.perf_counter()
-        ref, _ = O.extend_direct(p.phi, p.F, p.bcx, p.bcy)
-        times.append(time.perf_counter() - t0)
-    return ref, times
+        res = serve_stream(srv, reqs, on_done=progress(tag))
+        span = max(r.t_done for r in res) - t0
+        ok = [r for r in res if r.stats["status"] == bhx.OK]
+        return res, ok, span
+
+    def serve(precision, profile=0, timed=True, n_sat=None, n_timed=None):
+        srv = Server(0, hbm_budget=args.budget_gb << 30, max_slots=args.slots,
+                     precision=precision, profile=profile)
+        out = {}
+        ns = n_sat or len(sets["sat"])
+        nt = n_timed or len(sets["timed"])
+        try:
+            run(srv, sets["warm"], fields["warm"], [0.0] * len(sets["warm"]), "warm-up")
+            res, ok, span = run(srv, sets["sat"][:ns], fields["sat"][:ns], [0.0] * ns,
+                                f"saturated fp{64 if precision == 0 else 32}")
+            sat = len(ok) / span
+            out["saturated_solves_per_s"] = round(sat, 3)
+            log(f"saturated (prec {precision}): {sat:.3f} solves/s over {len(res)} requests")
+            if profile:
+                out["profile"] = bhx.engine_profile(srv.engine)
+                return out
+            if timed:
+                rate = 0.8 * sat
+                arr = W.poisson_arrivals(nt, rate, seed=6)
+                res, ok, span = run(srv, sets["timed"][:nt], fields["timed"][:nt],
+                                    list(arr - arr[0]), f"poisson fp{64 if precision == 0 else 32}")
+                lat = [r.latency for r in res]
+                its = [r.stats["iterations"] for r in res]
+                out.update({"solves_per_s": round(len(ok) / span, 3), "requests": len(res),
+                            "span_s": round(span, 3), "rate_per_s": round(rate, 3),
+                            "latency_ms": percentiles(lat),
+                            "iterations": {"mean": round(float(np.mean(its)), 1),
+                                           "max": int(max(its))},
+                            "not_converged": len(res) - len(ok),
+                            "saturation_requests": ns,
+                            "sides": [min(s.n for s in sets["timed"][:nt]),
+                                      max(s.n for s in sets["timed"][:nt])]})
+                log(f"poisson (prec {precision}): {out['solves_per_s']} solves/s, "
+                    f"p50 {out['latency_ms']['p50']} ms, p99 {out['latency_ms']['p99']} ms, "
+                    f"not converged {out['not_converged']}")
+        finally:
+            srv.close()
+        return out
+
+    t0 = time.perf_counter()
+    fields = {k: materialise(v) for k, v in sets.items()}
+    log(f"serve: {sum(len(v) for v in sets.values())} distinct requests materialised on the "
+        f"device in {time.perf_counter() - t0:.1f} s")
+    fp64 = serve(0)
+    fp32 = serve(1, n_sat=24, n_timed=48) if not args.no_extra else None
+    # roofline: the first requests of the saturated phase again, with
+    # dispatch events on every pass
+    n_prof = min(20, len(sets["sat"]))
+    prof = serve(0, profile=15, timed=False, n_sat=n_prof)["profile"]
+    tot = [prof["ms"][p] for p in range(4)]
+    dom = int(np.argmax(tot))
+    cu, cn = pass_coeffs(dom, 0)
+    launches = prof["launches"][dom]
+    alg_total = cu * prof["unknown_nodes"][dom] + cn * prof["nodes"][dom]
+    avg_ms = prof["ms"][dom] / max(1, launches)
+    alg = alg_total / max(1, launches)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": load_traffic(PASS_KERNELS[dom], "serve"),
+                "kernel": PASS_KERNELS[dom], "avg_launch_ms": round(avg_ms, 5),
+                "launches": launches, "alg_bytes_per_launch": round(alg),
+                "pass_ms_per_launch": {PASS_NAMES[p]: round(prof["ms"][p] /
+                                                            max(1, prof["launches"][p]), 5)
+                                       for p in range(4)},
+                "timed_with": "dispatch start/stop events (hipExtLaunchKernelGGL) on every "
+                              "launch of the engine's chunks while it serves the first "
+                              f"{n_prof} requests of the saturated phase again; bytes per "
+                              "launch summed over the requests each launch worked on"}
+    log(f"roofline: {PASS_KERNELS[dom]} {achieved:.1f} GB/s ({achieved / HBM_PEAK_GBS:.3f})")
+    out = {
+        "metric": METRIC, "value": fp64["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": fp64["requests"], "warmup": len(sets["warm"]),
+        "ms_per_step": round(1e3 * fp64["span_s"] / fp64["requests"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic: seeded serving requests built on the device from their seeds",
+        "config": {"workload": "serve_stream", "requests": fp64["requests"],
+                   "stream": f"request_stream(seed=5) entries {a1}..{a1 + n_timed - 1}",
+                   "side_range": [128, 2048], "bc": "neumann or periodic (1/2 each)",
+                   "interfaces": "1-20 circles or star (1/2 each), known inside",
+                   "tol": 1e-8, "arrivals": "poisson (seed 6)",
+                   "rate_per_s": fp64["rate_per_s"],
+                   "saturated_solves_per_s": fp64["saturated_solves_per_s"],
+                   "saturation_requests": len(sets["sat"]),
+                   "slots": args.slots, "hbm_budget_gb": args.budget_gb,
+                   "preconditioner": "fp64", "parallelism": "single_gpu",
+                   "latency": "arrival to completion (host monotonic clock); inputs "
+                              "materialised in HBM before the stream starts"},
+        "latency_ms": fp64["latency_ms"],
+        "iterations": fp64["iterations"],
+        "not_converged": fp64["not_converged"],
+        "roofline": roofline,
+    }
+    if fp32:
+        out["fp32_preconditioner_served"] = fp32
+    return out, sets
 
 
-def bench_batch(args, handle, log):
+def cpu_baseline_serve(sets, budget_s):
+    """The oracle on the first requests of the timed stream with side <= 384,
+    in stream order, until `budget_s` seconds of CPU time (a bounded sample:
+    one 2048^2 request takes the oracle many minutes)."""
+    import oracle as O
+    t_cpu, n, sides = 0.0, 0, []
+    for s in sets["timed"]:
+        if s.n > 384:
+            continue
+        p = s.materialise()
+        t0 = time.perf_counter()
+        O.extend_direct(p.phi, p.F, p.bcx, p.bcy)
+        t_cpu += time.perf_counter() - t0
+        n += 1
+        sides.append(s.n)
+        if t_cpu >= budget_s:
+            break
+    return {"value": round(n / t_cpu, 3), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {n} requests of the timed stream with side <= 384 (sides "
+                      f"{min(sides)}-{max(sides)}), one SuperLU factorisation (single-threaded) "
+                      "+ 2 long-double refinement steps each; larger requests cost the oracle "
+                      "roughly n^3 more", **host_info()}
+
+
+# ---------------------------------------------------------------------------
+# single instance
+# ---------------------------------------------------------------------------
+
+def bench_single(p, prec, args, handle, wl, extra=True):
+    """Graph-launched solves of one instance; per-pass event timing; the
+    dominant kernel's roofline."""
+    import numpy as np
+    import torch
+    from paper_1704_08897_amd import bhx
+    N = p.nx * p.ny
+    dev = torch.device("cuda:0")
+    phi = torch.from_numpy(p.phi).to(dev)
+    F = torch.from_numpy(p.F.copy()).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def solve(profile=0, tol=None, **kw):
+        o = bhx.default_opts(precision=prec, profile=profile, **kw)
+        s, st = bhx.extend_ex(handle, phi, F, bc=p.bc, h=p.h, tol=tol or p.tol, opts=o,
+                              stream=stream)
+        if s != bhx.OK:
+            raise SystemExit(f"solve failed: {bhx.status_string(s)} {bhx.last_error()} "
+                             f"{st.as_dict()}")
+        return st
+
+    for _ in range(args.warmup):
+        solve()
+    br = solve(profile=15)
+    per_pass = [br.pass_ms[k] / max(1, br.pass_launches[k]) for k in range(4)]
+    dom = int(np.argmax([br.pass_ms[k] for k in range(4)]))
+    log(f"{wl}: pass breakdown (ms/launch): " +
+        ", ".join(f"{PASS_NAMES[k]}={per_pass[k]:.4f}" for k in range(4)) +
+        f"; iterations={br.iterations}")
+    steps = args.steps
+    lat, iters = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        st = solve()
+        lat.append(time.perf_counter() - ts)
+        iters.append(st.iterations)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = steps / elapsed
+    log(f"{wl}: {steps} solves in {elapsed:.3f} s -> {value:.2f} solves/s")
+    dom_ms, dom_launches = 0.0, 0
+    tp0 = time.perf_counter()
+    for _ in range(steps):
+        stp = solve(profile=1 << dom)
+        dom_ms += stp.pass_ms[dom]
+        dom_launches += stp.pass_launches[dom]
+    torch.cuda.synchronize()
+    prof_rate = steps / (time.perf_counter() - tp0)
+    avg_ms = dom_ms / max(1, dom_launches)
+    alg = pass_bytes(dom, st.n_unknown, N, prec)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    iter_bytes = sum(pass_bytes(k, st.n_unknown, N, prec) for k in range(4))
+    iter_ms = sum(per_pass)
+    res = {
+        "solves_per_s": round(value, 3), "steps": steps,
+        "ms_per_solve": round(1e3 * elapsed / steps, 3),
+        "latency_ms": {"p50": round(1e3 * statistics.median(lat), 3),
+                       "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
+        "config": {"nx": p.nx, "ny": p.ny,
+                   "bc": ["neumann", "periodic", "dirichlet"][p.bcx] + "x" +
+                         ["neumann", "periodic", "dirichlet"][p.bcy],
+                   "tol": p.tol, "preconditioner": "fp32" if prec else "fp64",
+                   "n_unknown": st.n_unknown},
+        "iterations": iters[0], "true_rel_residual": st.true_rel_residual,
+        "pass_ms_per_launch": {PASS_NAMES[k]: round(per_pass[k], 5) for k in range(4)},
+        "iteration_hbm_gbs": round(iter_bytes / (iter_ms * 1e-3) / 1e9, 1) if iter_ms else None,
+        "working_set_mb": round((5 * 8 * st.n_unknown + N * (1 + (8 if prec == 0 else 4)))
+                                / 1e6, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic(PASS_KERNELS[dom], wl),
+                     "kernel": PASS_KERNELS[dom], "avg_launch_ms": round(avg_ms, 5),
+                     "launches": dom_launches, "alg_bytes_per_launch": alg,
+                     "timed_with": "dispatch start/stop events (hipExtLaunchKernelGGL) on "
+                                   f"every launch over {steps} solves (direct launches, "
+                                   f"{prof_rate:.2f} solves/s)"},
+    }
+    if extra and wl == "star_inward_1024":
+        # accurate mode at the FP64 bar (tol 1e-13), unpreconditioned CG, direct
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            sta = solve(tol=1e-13, accurate=1, tol_inner=1e-8)
+            times.append(time.perf_counter() - ts)
+        res["accurate_mode_tol_1e-13"] = {
+            "ms_per_solve": round(1e3 * statistics.median(times), 3),
+            "iterations": sta.iterations, "restarts": sta.restarts,
+            "true_rel_residual": sta.true_rel_residual}
+        res["accurate_field"] = F.cpu().numpy()
+        ts = time.perf_counter()
+        o = bhx.default_opts(precision=0, precond=0, maxit=400000)
+        s, stc = bhx.extend_ex(handle, phi, F, bc=p.bc, h=p.h, tol=p.tol, opts=o, stream=stream)
+        tc = time.perf_counter() - ts
+        res["unpreconditioned_cg"] = {"status": s, "iterations": stc.iterations,
+                                      "seconds": round(tc, 3),
+                                      "true_rel_residual": stc.true_rel_residual}
+        res["direct"] = bench_direct(p, phi, F, handle, stream, bhx)
+        res["warm_start_time_step"] = bench_time_step(p, phi, F, handle, stream, bhx)
+    solve()                                     # leave F holding the PCG result
+    torch.cuda.synchronize()
+    res["field"] = F.cpu().numpy()
+    del phi, F
+    return res
+
+
+def bench_batch(args, handle, steps):
     """256 uneven instances per step (one batched call, autotuned schedule).
-    The headline is the FP64 batched solve; the FP32-preconditioner form
-    (standard PCG) and the plain FP64 PCG solving the same instances one call
-    each are measured beside it."""
+    FP64 batched, the FP32-preconditioner form (standard PCG) and the plain
+    FP64 PCG solving the same instances one call each."""
     import numpy as np
     import torch
     from paper_1704_08897_amd import bhx, workloads as W
@@ -120,59 +423,38 @@ def bench_batch(args, handle, log):
     tols = [p.tol for p in probs]
     Ntot = sum(p.nx * p.ny for p in probs)
     stream = torch.cuda.current_stream()
-    log(f"batch: {len(probs)} instances, {Ntot} nodes")
 
     def run(prec, profile=0, autotune=1):
         o = bhx.default_opts(precision=prec, autotune=autotune, profile=profile)
         s, sts = bhx.extend_batched(handle, phis, Fs, hs, bcs, tols, opts=o, stream=stream)
         if s < 0:
             raise SystemExit(f"batched solve failed: {bhx.status_string(s)} {bhx.last_error()}")
-        if s != bhx.OK:
-            bad = [(i, probs[i].nx, probs[i].ny, st.status, st.iterations, st.restarts,
-                    st.rel_residual, st.true_rel_residual) for i, st in enumerate(sts)
-                   if st.status != bhx.OK]
-            log(f"warning: {len(bad)} instances not converged: {bad[:8]}")
         return sts
 
-    def timed(prec, steps):
-        lat = []
+    def timed(prec, k):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            ts = time.perf_counter()
+        for _ in range(k):
             sts = run(prec)
-            lat.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, lat, sts
+        return time.perf_counter() - t0, sts
 
     t0 = time.perf_counter()
-    run(0)                                     # autotune + first solve
-    log(f"autotune + first FP64 batched solve: {time.perf_counter() - t0:.3f} s")
-    for _ in range(args.warmup):
-        run(0)
-    el, lat, sts = timed(0, args.steps)
-    value = len(probs) * args.steps / el
+    run(0)
+    log(f"batch256: autotune + first FP64 batched solve {time.perf_counter() - t0:.2f} s")
+    el, sts = timed(0, steps)
+    value = len(probs) * steps / el
     iters = [s.iterations for s in sts]
-    log(f"batched FP64: {value:.1f} solves/s; iterations {min(iters)}..{max(iters)}")
-    # roofline: events around the dominant pass (direct launches)
     br = run(0, profile=15)
     per_pass = [br[0].pass_ms[k] / max(1, br[0].pass_launches[k]) for k in range(4)]
-    dom = int(np.argmax(per_pass))
-    stp = run(0, profile=1 << dom)
-    dom_ms = stp[0].pass_ms[dom]
-    dom_n = stp[0].pass_launches[dom]
-    alg = sum(pass_bytes(dom, s.n_unknown, p.nx * p.ny, 0) for s, p in zip(stp, probs))
-    avg_ms = dom_ms / max(1, dom_n)
+    dom = int(np.argmax([br[0].pass_ms[k] for k in range(4)]))
+    alg = sum(pass_bytes(dom, s.n_unknown, p.nx * p.ny, 0) for s, p in zip(br, probs))
+    avg_ms = per_pass[dom]
     achieved = alg / (avg_ms * 1e-3) / 1e9
-    # FP32 preconditioner (standard PCG, the default), batched
     run(1)
-    el32, _, st32 = timed(1, max(1, args.steps // 5))
-    v32 = len(probs) * max(1, args.steps // 5) / el32
-    log(f"batched FP32-preconditioner: {v32:.1f} solves/s")
-    # the plain FP64 one-instance-per-call baseline
+    el32, st32 = timed(1, 1)
+    v32 = len(probs) / el32
     o = bhx.default_opts(precision=0)
-    for i in range(4):
-        bhx.extend_ex(handle, phis[i], Fs[i], bc=bcs[i], h=hs[i], tol=tols[i], opts=o, stream=stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     it64 = []
@@ -182,22 +464,18 @@ def bench_batch(args, handle, log):
         it64.append(st.iterations)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    log(f"plain FP64 one call per instance: {len(probs) / t_plain:.1f} solves/s")
-    run(0)                                     # leave F holding the batched result
-    out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(1e3 * el / args.steps, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "batch256_star_cubic", "instances": len(probs), "nodes": Ntot,
-                   "side_range": [64, 512], "bc": "mixed neumann/periodic per axis",
-                   "tol": 1e-8, "preconditioner": "fp64", "autotune": 1,
-                   "parallelism": "single_gpu"},
-        "latency_ms": {"p50": round(1e3 * statistics.median(lat), 3),
-                       "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
+    log(f"batch256: FP64 batched {value:.1f}, FP32 batched {v32:.1f}, plain FP64 per instance "
+        f"{len(probs) / t_plain:.1f} solves/s")
+    return {
+        "solves_per_s": round(value, 2), "steps": steps, "instances": len(probs), "nodes": Ntot,
+        "ms_per_batch": round(1e3 * el / steps, 3),
+        "config": {"side_range": [64, 512], "bc": "mixed neumann/periodic per axis",
+                   "tol": 1e-8, "preconditioner": "fp64", "autotune": 1},
         "iterations": {"min": min(iters), "max": max(iters), "mean": float(np.mean(iters))},
         "max_true_rel_residual": max(s.true_rel_residual for s in sts),
         "not_converged": sum(1 for s in sts if s.status != 0),
+        "pass_ms_per_launch_first_iterations": {PASS_NAMES[k]: round(per_pass[k], 5)
+                                                for k in range(4)},
         "fp32_preconditioner_batched": {
             "solves_per_s": round(v32, 2),
             "mean_iterations": float(np.mean([s.iterations for s in st32])),
@@ -205,97 +483,15 @@ def bench_batch(args, handle, log):
         "plain_fp64_per_instance": {"solves_per_s": round(len(probs) / t_plain, 2),
                                     "mean_iterations": float(np.mean(it64))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "kernel": PASS_KERNELS[dom], "avg_launch_ms": round(avg_ms, 5),
-                     "launches": dom_n, "alg_bytes_per_launch": alg},
+                     "alg_bytes_per_launch": alg,
+                     "note": "average over the launches of one profiled batched solve, as "
+                             "instances retire"},
     }
-    return out, probs, Fs
 
 
-def bench_serve(args, log):
-    """Continuous batching of a request stream: square grids with sides
-    log-uniform in [128, 2048], Neumann or periodic, multi-circle or star
-    interfaces, Fourier-mode fields, tol 1e-8.  Phase 1 submits every request
-    at t = 0 (saturated throughput); phase 2 plays Poisson arrivals at 0.8 x
-    that rate and reports p50/p99 latency (arrival to completion)."""
-    import numpy as np
-    import torch
-    from paper_1704_08897_amd import workloads as W
-    from paper_1704_08897_amd.server import Request, Server, serve_stream
-    specs = W.request_stream(10000, seed=5)[:args.requests]
-    pool_n = min(args.pool, len(specs))
-    t0 = time.perf_counter()
-    pool = [specs[i].materialise() for i in range(pool_n)]
-    log(f"serve: {len(specs)} requests over a pool of {pool_n} materialised inputs "
-        f"({time.perf_counter() - t0:.1f} s to build)")
-    dev = torch.device("cuda:0")
-    phis = [torch.from_numpy(p.phi).to(dev) for p in pool]
-    base = [torch.from_numpy(p.F).to(dev) for p in pool]
-
-    def make(arrivals):
-        reqs = []
-        for i, a in enumerate(arrivals):
-            k = i % pool_n
-            p = pool[k]
-            reqs.append(Request(phis[k], base[k].clone(), p.bc, p.h, p.tol, arrival=a, tag=k))
-        torch.cuda.synchronize()
-        return reqs
-
-    srv = Server(0, hbm_budget=args.budget_gb << 30, max_slots=args.slots,
-                 precision=args.serve_precision)
-
-    def progress(tag):
-        count = [0]
-        t_start = time.perf_counter()
-
-        def on_done(r):
-            count[0] += 1
-            if count[0] % 25 == 0:
-                log(f"{tag}: {count[0]} done, {time.perf_counter() - t_start:.1f} s")
-        return on_done
-
-    try:
-        serve_stream(srv, make([0.0] * min(8, len(specs))), on_done=progress("warm-up"))
-        reqs = make([0.0] * len(specs))
-        t0 = time.perf_counter()
-        res = serve_stream(srv, reqs, on_done=progress("saturated"))
-        sat = len(res) / (time.perf_counter() - t0)
-        log(f"saturated: {sat:.2f} solves/s")
-        rate = 0.8 * sat
-        arr = W.poisson_arrivals(len(specs), rate, seed=6)
-        reqs = make(list(arr - arr[0]))
-        t0 = time.perf_counter()
-        res = serve_stream(srv, reqs, on_done=progress("poisson"))
-        span = max(r.t_done for r in res) - t0
-    finally:
-        srv.close()
-    lat = np.array([r.latency for r in res])
-    bad = sum(1 for r in res if r.stats["status"] != 0)
-    its = [r.stats["iterations"] for r in res]
-    log(f"poisson: {len(res) / span:.2f} solves/s, p50 {1e3 * np.median(lat):.1f} ms, "
-        f"p99 {1e3 * np.percentile(lat, 99):.1f} ms, not converged {bad}")
-    out = {
-        "metric": METRIC, "value": round(len(res) / span, 3), "unit": "solves/s", "n_gpus": 1,
-        "steps": len(res), "warmup": 8, "ms_per_step": round(1e3 * span / len(res), 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.serve_precision == 0 else "f64+f32", "data": "synthetic",
-        "config": {"workload": "serve_stream", "requests": len(res), "input_pool": pool_n,
-                   "side_range": [128, 2048], "bc": "neumann or periodic (1/2 each)",
-                   "tol": 1e-8, "arrivals": "poisson", "rate_per_s": round(rate, 3),
-                   "slots": args.slots, "hbm_budget_gb": args.budget_gb,
-                   "preconditioner": "fp64" if args.serve_precision == 0 else "fp32",
-                   "parallelism": "single_gpu"},
-        "saturated_solves_per_s": round(sat, 3),
-        "latency_ms": {"p50": round(1e3 * float(np.median(lat)), 2),
-                       "p99": round(1e3 * float(np.percentile(lat, 99)), 2),
-                       "max": round(1e3 * float(lat.max()), 2)},
-        "iterations": {"mean": float(np.mean(its)), "max": int(max(its))},
-        "not_converged": bad,
-    }
-    return out
-
-
-def bench_direct(p, phi, F, handle, stream, bhx, log, reps=3):
+def bench_direct(p, phi, F, handle, stream, bhx, reps=3):
     """The same solve by the sparse direct path (banded Cholesky of A_UU on
     the GPU, refined to the same tolerance), and three fields on the same
     phi sharing one factorisation."""
@@ -315,24 +511,21 @@ def bench_direct(p, phi, F, handle, stream, bhx, log, reps=3):
     t0 = time.perf_counter()
     s, sts = bhx.extend_fields(handle, phi, G, h=p.h, bc=p.bc, tol=p.tol, opts=o, stream=stream)
     tf = time.perf_counter() - t0
-    log(f"direct: {sec * 1e3:.1f} ms per solve ({st.iterations} refinement solves); "
-        f"3 fields {tf * 1e3:.1f} ms")
-    return {"ms_per_solve": round(1e3 * sec, 3), "solves_per_s": round(1.0 / sec, 3),
-            "refinement_solves": st.iterations, "true_rel_residual": st.true_rel_residual,
-            "three_fields_ms": round(1e3 * tf, 3),
+    log(f"direct: {sec * 1e3:.1f} ms per solve; 3 fields {tf * 1e3:.1f} ms")
+    return {"ms_per_solve": round(1e3 * sec, 3), "refinement_solves": st.iterations,
+            "true_rel_residual": st.true_rel_residual, "three_fields_ms": round(1e3 * tf, 3),
             "method": "banded Cholesky of A_UU (unknowns row by row), FP64, refined with the "
-                      "compensated residual",
-            "paper": "Table 2: direct 12.4 s vs iterative 131.0 s at 1024^2 (MATLAB, CPU, tol 1e-6)"}
+                      "compensated residual"}
 
 
-def bench_time_step(p, phi, F, handle, stream, bhx, log, reps=5):
+def bench_time_step(p, phi, F, handle, stream, bhx, reps=3):
     """A level-set time step: the known values move by a smooth 1 % of their
     range; the new extension is solved from zero and from the previous
     extension (warm start), same tolerance."""
     import numpy as np
     import torch
     o = bhx.default_opts()
-    s, st = bhx.extend_ex(handle, phi, F, bc=p.bc, h=p.h, tol=p.tol, opts=o, stream=stream)
+    bhx.extend_ex(handle, phi, F, bc=p.bc, h=p.h, tol=p.tol, opts=o, stream=stream)
     torch.cuda.synchronize()
     prev = F.cpu().numpy()
     jj, ii = np.meshgrid(np.arange(p.ny) / p.ny, np.arange(p.nx) / p.nx, indexing="ij")
@@ -351,244 +544,162 @@ def bench_time_step(p, phi, F, handle, stream, bhx, log, reps=5):
                                   stream=stream)
             times.append(time.perf_counter() - t0)
             its.append(st.iterations)
-            if s != bhx.OK:
-                raise SystemExit(f"time-step solve failed: {bhx.status_string(s)}")
-        res[name] = {"iterations": its[-1], "ms": round(1e3 * statistics.median(times[1:]), 3),
-                     "true_rel_residual": st.true_rel_residual}
-    F.copy_(torch.from_numpy(np.ascontiguousarray(p.F)).to(F.device))   # the workload's F again
+        res[name] = {"iterations": its[-1], "ms": round(1e3 * statistics.median(times[1:]), 3)}
+    F.copy_(torch.from_numpy(np.ascontiguousarray(p.F)).to(F.device))
     torch.cuda.synchronize()
-    log(f"time step: cold {res['cold']}, warm {res['warm']}")
     res["speedup"] = round(res["cold"]["ms"] / res["warm"]["ms"], 3)
-    res["change"] = "known values + 1% of range x sin(2 pi x) cos(pi y); warm = previous extension"
     return res
 
 
-def bench_example2(handle, bhx, log, n=256, reps=3):
-    """Example 2 of the paper at its largest grid (256^3, periodic, tol 1e-6):
-    one whole solve per step, inputs resident in HBM."""
+def bench_periodic(handle, reps=1):
+    """The 2048^2 periodic multi-circle case, one solve each with the FP32
+    preconditioner (its stated precision) and the FP64 one, tol 1e-8."""
+    import torch
+    from paper_1704_08897_amd import bhx, workloads as W
+    p = W.periodic_circles_problem(2048, tol=1e-8)
+    dev = torch.device("cuda:0")
+    phi = torch.from_numpy(p.phi).to(dev)
+    F = torch.from_numpy(p.F.copy()).to(dev)
+    out = {"nx": 2048, "ny": 2048, "bc": "periodic x periodic", "tol": 1e-8,
+           "n_unknown": int((p.phi >= 0).sum())}
+    for name, prec in (("fp32_preconditioner", 1), ("fp64_preconditioner", 0)):
+        o = bhx.default_opts(precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, st = bhx.extend_ex(handle, phi, F, bc=p.bc, h=p.h, tol=p.tol, opts=o)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[name] = {"status": s, "seconds": round(sec, 3), "solves_per_s": round(1 / sec, 4),
+                     "iterations": st.iterations, "true_rel_residual": st.true_rel_residual}
+        log(f"periodic 2048 prec {prec}: {st.iterations} iterations, {sec:.2f} s")
+    del phi, F
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_example2(handle, bhx, n=256, reps=3):
+    """Example 2 of the paper at its largest grid (256^3, periodic, tol 1e-6)."""
     import torch
     from paper_1704_08897_amd import workloads as W
     p = W.peanut3d_problem(n)
     dev = torch.device("cuda:0")
     phi = torch.from_numpy(p.phi).to(dev)
     F = torch.from_numpy(p.F.copy()).to(dev)
-    o = bhx.default_opts()
     times = []
     for _ in range(reps + 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s, st = bhx.extend3d(handle, phi, F, h=p.h, bc=p.bc, tol=p.tol, opts=o)
+        s, st = bhx.extend3d(handle, phi, F, h=p.h, bc=p.bc, tol=p.tol)
         times.append(time.perf_counter() - t0)
         if s != bhx.OK:
             raise SystemExit(f"3-D solve failed: {bhx.status_string(s)} {st.as_dict()}")
     sec = statistics.median(times[1:])
     log(f"example 2 {n}^3: {st.iterations} iterations, {sec:.3f} s")
-    res = {"grid": f"{n}^3", "bc": "periodic^3", "tol": p.tol, "iterations": st.iterations,
-           "seconds": round(sec, 4), "solves_per_s": round(1.0 / sec, 3),
-           "ms_per_iteration": round(1e3 * sec / max(1, st.iterations), 4),
-           "true_rel_residual": st.true_rel_residual,
-           "paper": "Table 3: 276 iterations, 733.9 s (MATLAB, CPU)"}
     del phi, F
     torch.cuda.empty_cache()
-    return res
+    return {"grid": f"{n}^3", "bc": "periodic^3", "tol": p.tol, "iterations": st.iterations,
+            "seconds": round(sec, 4), "true_rel_residual": st.true_rel_residual}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="star_inward_1024")
-    ap.add_argument("--cpu-samples", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-cg", action="store_true", help="skip the unpreconditioned CG comparison")
-    ap.add_argument("--no-extra", action="store_true",
-                    help="skip the warm-start time step and the three-dimensional Example 2")
-    ap.add_argument("--requests", type=int, default=300, help="serve: requests in the stream")
-    ap.add_argument("--pool", type=int, default=24, help="serve: distinct materialised inputs")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="serve")
+    ap.add_argument("--requests", type=int, default=100,
+                    help="serve: requests in the timed stream (at least --steps)")
+    ap.add_argument("--sat-requests", type=int, default=40,
+                    help="serve: requests of the saturated phase that sets the arrival rate")
     ap.add_argument("--slots", type=int, default=64, help="serve: engine slots")
     ap.add_argument("--budget-gb", type=int, default=64, help="serve: engine HBM budget")
-    ap.add_argument("--serve-precision", type=int, default=0, help="serve: 0 fp64, 1 fp32")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="CPU time budget of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the workload itself (no FP32 serving, no other configurations)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+              "how the path would shard is described in the design notes, not built.",
+              file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1704_08897_amd import bhx
 
-    if args.workload == "serve":
-        print(json.dumps(bench_serve(args, log)), flush=True)
-        return
-    if args.workload == "example2_256":
-        handle = bhx.Handle(0)
-        res = bench_example2(handle, bhx, log, reps=max(1, args.steps))
-        handle.close()
-        print(json.dumps({"workload": "example2_256", **res}), flush=True)
-        return
-    if args.workload == "batch256":
-        handle = bhx.Handle(0)
-        out, probs, Fs = bench_batch(args, handle, log)
-        if not args.no_cpu_baseline:
-            import oracle as O
-            errs = []
-            t_cpu = 0.0
-            nsamp = min(args.cpu_samples * 4, len(probs))
-            for i in range(nsamp):
-                p = probs[i]
-                t0 = time.perf_counter()
-                ref, _ = O.extend_direct(p.phi, p.F, p.bcx, p.bcy)
-                t_cpu += time.perf_counter() - t0
-                errs.append(O.relative_l2(Fs[i].cpu().numpy(), ref))
-            out["cpu_baseline"] = {"value": round(nsamp / t_cpu, 3), "unit": "solves/s",
-                                   "cores": 1, "kind": "oracle",
-                                   "sample": f"first {nsamp} instances of the batch, one "
-                                             "SuperLU solve + 2 refinement steps each"}
-            out["max_rel_l2_vs_oracle_sample"] = max(errs)
-        handle.close()
-        print(json.dumps(out), flush=True)
-        return
-
-    p, prec = workload(args.workload)
-    N = p.nx * p.ny
-    log(f"workload {args.workload}: {p.nx}x{p.ny} bc=({p.bcx},{p.bcy}) tol={p.tol} prec={prec}")
-    dev = torch.device("cuda:0")
-    phi = torch.from_numpy(p.phi).to(dev)
-    F = torch.from_numpy(p.F.copy()).to(dev)
-    stream = torch.cuda.current_stream()
-    handle = bhx.Handle(0)
-
     if args.calib_copy_mb > 0:
         nb = args.calib_copy_mb * (1 << 20)
-        a = torch.empty(nb // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        a = torch.empty(nb // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
         log(f"calibration copy: {args.calib_copy_mb} MiB read + written")
 
-    def solve(profile=0, **kw):
-        o = bhx.default_opts(precision=prec, profile=profile, **kw)
-        s, st = bhx.extend_ex(handle, phi, F, bc=p.bc, h=p.h, tol=p.tol, opts=o, stream=stream)
-        if s != bhx.OK:
-            raise SystemExit(f"solve failed: {bhx.status_string(s)} {bhx.last_error()} "
-                             f"{st.as_dict()}")
-        return st
-
-    for _ in range(args.warmup):
-        solve()
-    # per-pass breakdown (events around every pass) to pick the dominant kernel
-    br = solve(profile=15)
-    per_pass = [br.pass_ms[k] / max(1, br.pass_launches[k]) for k in range(4)]
-    dom = int(np.argmax([br.pass_ms[k] for k in range(4)]))
-    log("pass breakdown (ms/launch): " +
-        ", ".join(f"{PASS_NAMES[k]}={per_pass[k]:.4f}" for k in range(4)) +
-        f"; iterations={br.iterations}")
-
-    # timed region: graph-launched solves, no profiling
-    lat = []
-    iters = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        st = solve()
-        lat.append(time.perf_counter() - ts)
-        iters.append(st.iterations)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    value = args.steps / elapsed
-    log(f"timed: {args.steps} solves in {elapsed:.3f} s -> {value:.2f} solves/s; "
-        f"iterations {iters[0]}")
-    torch.cuda.synchronize()
-    got = F.cpu().numpy()
-
-    # roofline region: the same solves, every launch of the dominant kernel
-    # carrying a start/stop event pair that its dispatch records (kernel
-    # execution time, on the solve's stream; direct launches, since events
-    # recorded inside a captured graph cannot be timed)
-    dom_ms = 0.0
-    dom_launches = 0
-    tp0 = time.perf_counter()
-    for _ in range(args.steps):
-        stp = solve(profile=1 << dom)
-        dom_ms += stp.pass_ms[dom]
-        dom_launches += stp.pass_launches[dom]
-    torch.cuda.synchronize()
-    prof_rate = args.steps / (time.perf_counter() - tp0)
-
-    n_unknown = st.n_unknown
-    avg_ms = dom_ms / max(1, dom_launches)
-    alg = pass_bytes(dom, n_unknown, N, prec)
-    achieved = alg / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(PASS_KERNELS[dom], args.workload)
-    iter_bytes = sum(pass_bytes(k, n_unknown, N, prec) for k in range(4))
-    iter_ms = sum(per_pass)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": PASS_KERNELS[dom],
-                "avg_launch_ms": round(avg_ms, 5), "launches": dom_launches,
-                "alg_bytes_per_launch": alg,
-                "timed_with": f"dispatch start/stop events (hipExtLaunchKernelGGL) on every "
-                              f"launch over {args.steps} solves (direct launches, "
-                              f"{prof_rate:.2f} solves/s)"}
-
-    out = {
-        "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": args.workload, "nx": p.nx, "ny": p.ny,
-                   "bc": ["neumann", "periodic"][p.bcx] + "x" + ["neumann", "periodic"][p.bcy],
-                   "tol": p.tol, "preconditioner": "fp32" if prec else "fp64",
-                   "n_unknown": n_unknown, "parallelism": "single_gpu"},
-        "latency_ms": {"p50": round(1e3 * statistics.median(lat), 3),
-                       "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
-        "iterations": iters[0],
-        "true_rel_residual": st.true_rel_residual,
-        "pass_ms_per_launch": {PASS_NAMES[k]: round(per_pass[k], 5) for k in range(4)},
-        "iteration_hbm_gbs": round(iter_bytes / (iter_ms * 1e-3) / 1e9, 1) if iter_ms else None,
-        "roofline": roofline,
-    }
-
-    if not args.no_cg and args.workload == "star_inward_1024":
-        ts = time.perf_counter()
-        o = bhx.default_opts(precision=0, precond=0, maxit=400000)
-        s, stc = bhx.extend_ex(handle, phi, F, bc=p.bc, h=p.h, tol=p.tol, opts=o, stream=stream)
-        tc = time.perf_counter() - ts
-        out["unpreconditioned_cg"] = {"status": s, "iterations": stc.iterations,
-                                      "seconds": round(tc, 3),
-                                      "solves_per_s": round(1.0 / tc, 4),
-                                      "true_rel_residual": stc.true_rel_residual}
-        log(f"unpreconditioned CG: {stc.iterations} iterations, {tc:.3f} s")
-        solve()                                  # leave F holding the PCG result
-        torch.cuda.synchronize()
-        got = F.cpu().numpy()
-
-    if not args.no_extra and args.workload == "star_inward_1024":
-        out["direct"] = bench_direct(p, phi, F, handle, stream, bhx, log)
-        out["warm_start_time_step"] = bench_time_step(p, phi, F, handle, stream, bhx, log)
-        out["example2_3d"] = bench_example2(handle, bhx, log)
-        solve()                                  # leave F holding the PCG result
-        torch.cuda.synchronize()
-        got = F.cpu().numpy()
-
-    if not args.no_cpu_baseline:
-        import oracle as O
-        log(f"cpu baseline: {args.cpu_samples} oracle solves ...")
-        ref, times = cpu_baseline(p, args.cpu_samples)
-        out["cpu_baseline"] = {"value": round(len(times) / sum(times), 4), "unit": "solves/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": f"{len(times)} complete oracle solves of this workload "
-                                         "(SuperLU factorisation, single-threaded, + 2 "
-                                         "long-double refinement steps)"}
-        out["rel_l2_vs_oracle"] = O.relative_l2(got, ref)
-        log(f"cpu: {times}; rel L2 vs oracle {out['rel_l2_vs_oracle']:.3e}")
-    handle.close()
+    handle = bhx.Handle(0)
+    try:
+        if args.workload == "serve":
+            out, sets = bench_serve(args)
+            if not args.no_extra:
+                p, _ = workload("star_inward_1024")
+                star = bench_single(p, 0, argparse.Namespace(steps=min(args.steps, 10),
+                                                             warmup=1), handle,
+                                    "star_inward_1024")
+                star_field = star.pop("field")
+                acc_field = star.pop("accurate_field")
+                out["star_inward_1024"] = star
+                out["batch256"] = bench_batch(args, handle, steps=2)
+                out["periodic_circles_2048"] = bench_periodic(handle)
+                out["example2_3d"] = bench_example2(handle, bhx)
+            if not args.no_cpu_baseline:
+                import oracle as O
+                out["cpu_baseline"] = cpu_baseline_serve(sets, args.cpu_seconds)
+                log(f"cpu baseline: {out['cpu_baseline']}")
+                if not args.no_extra:
+                    # the 1024^2 star's results against the oracle (FP64 bar)
+                    t0 = time.perf_counter()
+                    ref, _ = O.extend_direct(p.phi, p.F, p.bcx, p.bcy)
+                    out["star_inward_1024"]["rel_l2_vs_oracle"] = O.relative_l2(star_field, ref)
+                    out["star_inward_1024"]["accurate_mode_tol_1e-13"]["rel_l2_vs_oracle"] = \
+                        O.relative_l2(acc_field, ref)
+                    out["star_inward_1024"]["cpu_oracle_seconds"] = round(
+                        time.perf_counter() - t0, 3)
+        elif args.workload == "batch256":
+            out = bench_batch(args, handle, steps=args.steps)
+            out.update({"metric": METRIC, "value": out["solves_per_s"], "unit": "solves/s",
+                        "n_gpus": 1, "warmup": 1, "dtype": "f64", "data": "synthetic",
+                        "higher_is_better": True, "scaling": "weak", "vs_baseline": None})
+        elif args.workload == "example2_256":
+            out = {"workload": "example2_256", **bench_example2(handle, bhx)}
+        else:
+            p, prec = workload(args.workload)
+            res = bench_single(p, prec, args, handle, args.workload, extra=not args.no_extra)
+            field = res.pop("field")
+            res.pop("accurate_field", None)
+            out = {"metric": METRIC, "value": res["solves_per_s"], "unit": "solves/s",
+                   "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                   "ms_per_step": res["ms_per_solve"], "higher_is_better": True,
+                   "scaling": "weak", "vs_baseline": None,
+                   "dtype": "f64" if prec == 0 else "f64+f32", "data": "synthetic",
+                   "config": {"workload": args.workload, **res.pop("config"),
+                              "parallelism": "single_gpu"}, **res}
+            if not args.no_cpu_baseline:
+                import oracle as O
+                t = []
+                for _ in range(2):
+                    t0 = time.perf_counter()
+                    ref, _ = O.extend_direct(p.phi, p.F, p.bcx, p.bcy)
+                    t.append(time.perf_counter() - t0)
+                out["cpu_baseline"] = {"value": round(len(t) / sum(t), 4), "unit": "solves/s",
+                                       "cores": 1, "kind": "oracle",
+                                       "sample": f"{len(t)} complete oracle solves of this "
+                                                 "workload", **host_info()}
+                out["rel_l2_vs_oracle"] = O.relative_l2(field, ref)
+    finally:
+        handle.close()
     print(json.dumps(out), flush=True)
 
 

@@ -237,6 +237,18 @@ int bhx_engine_submit(bhx_engine* e, const double* phi, double* F, int nx, int n
 int bhx_engine_poll(bhx_engine* e, uint64_t* ids, bhx_stats* st, int max, int* n_done);
 /* Number of requests admitted and not yet collected by poll. */
 int bhx_engine_inflight(bhx_engine* e);
+/* Kernel timing of an engine created with bhx_opts.profile != 0 (a bit mask
+ * of iteration passes: bit 0 stencil, 1 row-forward, 2 column, 3
+ * row-inverse; such an engine launches its iteration chunks directly with
+ * dispatch-recorded start/stop events around the selected passes instead of
+ * replaying captured graphs).  For each pass p (arrays of 4, caller-owned
+ * host memory): ms[p] the summed kernel execution time of its launches,
+ * launches[p] their number, unknown_nodes[p] and nodes[p] the sums over those
+ * launches of the unknown and of all nodes of the requests each launch
+ * worked on (a request counts in the launches of the iterations it ran).
+ * reset != 0 zeroes the sums after reading.  Returns BHX_OK or BHX_ERR_ARG. */
+int bhx_engine_profile(bhx_engine* e, double* ms, long long* launches, double* unknown_nodes,
+                       double* nodes, int reset);
 /* Stops the worker after in-flight requests finish and frees everything. */
 void bhx_engine_destroy(bhx_engine* e);
 

@@ -11,9 +11,13 @@ there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import itertools
 import os
 import re
+import sys
+import weakref
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbhx.so")
@@ -96,6 +100,10 @@ _sig = {
     "bhx_engine_poll": (_ci, [_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(Stats), _ci,
                               ctypes.POINTER(_ci)]),
     "bhx_engine_inflight": (_ci, [_vp]),
+    "bhx_engine_profile": (_ci, [_vp, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_longlong),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                 _ci]),
     "bhx_engine_destroy": (None, [_vp]),
     "bhx_status_string": (ctypes.c_char_p, [_ci]),
     "bhx_version": (ctypes.c_char_p, []),
@@ -202,19 +210,60 @@ def destroy(handle: int) -> None:
     _lib.bhx_destroy(handle)
 
 
+# Objects that own library resources (handles, engines) and are still open.
+# They are closed explicitly by an exit hook that runs while the HIP runtime
+# (and a profiler attached to it) is still up: engines first (their worker
+# threads are joined), then handles.  A finaliser that runs during interpreter
+# shutdown releases nothing, since the runtime may already be gone then.
+_open = weakref.WeakValueDictionary()
+_open_seq = itertools.count()
+
+
+def _register(obj) -> int:
+    key = next(_open_seq)
+    _open[key] = obj
+    return key
+
+
+def close_all() -> None:
+    """Close every open engine, then every open handle (idempotent)."""
+    objs = list(_open.values())
+    for o in objs:
+        if getattr(o, "is_engine", False):
+            o.close()
+    for o in objs:
+        o.close()
+
+
+atexit.register(close_all)
+
+
 class Handle:
-    """Owning wrapper of a ``bhx_handle``."""
+    """Owning wrapper of a ``bhx_handle``.  Call ``close()`` when done (or use
+    it as a context manager); open handles are closed at interpreter exit."""
+
+    is_engine = False
 
     def __init__(self, device: int = 0):
         self.device = device
         self.ptr = create(device)
+        self._key = _register(self)
 
     def close(self):
         if self.ptr:
-            destroy(self.ptr)
-            self.ptr = None
+            ptr, self.ptr = self.ptr, None
+            _open.pop(self._key, None)
+            destroy(ptr)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -355,6 +404,18 @@ def engine_poll(engine, max_n: int = 256):
 
 def engine_inflight(engine) -> int:
     return int(_lib.bhx_engine_inflight(engine))
+
+
+def engine_profile(engine, reset: bool = False) -> dict:
+    """``bhx_engine_profile``: per-pass kernel time, launches and node sums."""
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_longlong * 4)()
+    u = (ctypes.c_double * 4)()
+    a = (ctypes.c_double * 4)()
+    s = _lib.bhx_engine_profile(engine, ms, n, u, a, int(reset))
+    if s != OK:
+        raise BhxError(s)
+    return {"ms": list(ms), "launches": list(n), "unknown_nodes": list(u), "nodes": list(a)}
 
 
 def engine_destroy(engine) -> None:

@@ -20,22 +20,38 @@ FLAGS = [
 ]
 
 
-def build(verbose=False, extra=()):
-    """Compile every source into ``libbhx.so``; raises on failure."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *extra, "-I", os.path.join(HERE, "..", "include"), *srcs, "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libbhx.so")
+        raise RuntimeError(f"hipcc failed: {' '.join(cmd[-3:])}")
     if verbose and r.stderr.strip():
         # the host pass does not know the packed-fp32 feature; that warning is harmless
         lines = [l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l]
         if lines:
             print("\n".join(lines))
+
+
+def build(verbose=False, extra=()):
+    """Compile every source to an object (in parallel), then link
+    ``libbhx.so``; raises on failure."""
+    from concurrent.futures import ThreadPoolExecutor
+    inc = ["-I", os.path.join(HERE, "..", "include")]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, src + ".o")
+        jobs.append((obj, [HIPCC, *compile_flags, *extra, *inc, "-c",
+                           os.path.join(CSRC, src), "-o", obj]))
+    workers = min(len(jobs), max(1, int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(lambda j: _run(j[1], verbose), jobs))
+    tmp = LIB + ".tmp"
+    _run([HIPCC, *FLAGS, *extra, *[o for o, _ in jobs], "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -112,6 +112,7 @@ struct bhx_engine {
   bhx::Arena arena;
   bhx::Ctl* ctl_d = nullptr;
   bhx::Ctl* ctl_h = nullptr;
+  int* flag_d = nullptr;            // per-request flags of a setup round [max_slots]
   bhx::DevBatch run, aux;
   std::vector<int> free_slots;
   std::deque<bhx::Req*> incoming;
@@ -125,6 +126,10 @@ struct bhx_engine {
   uint64_t next_id = 1;
   std::thread worker;
   int device = 0;
+  // kernel timing of the iteration passes (engines created with a profile mask)
+  double prof_ms[4] = {0, 0, 0, 0};
+  long long prof_launches[4] = {0, 0, 0, 0};
+  double prof_unknown[4] = {0, 0, 0, 0}, prof_nodes[4] = {0, 0, 0, 0};
 };
 
 namespace bhx {
@@ -317,13 +322,12 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
     }
   }
   if (any_zero) {
-    int* flag_d = nullptr;
-    ENG_CHECK(hipMalloc((void**)&flag_d, n * sizeof(int)));
-    const Upload u{flag_d, zero_flag.data(), n * sizeof(int)};
+    // flag_d holds max_slots entries (allocated with the engine); a setup
+    // round never has more new requests than slots
+    const Upload u{E->flag_d, zero_flag.data(), n * sizeof(int)};
     ENG_CHECK(upload_ordered(E->hd, st, &u, 1));
-    ENG_CHECK(launch_zero_unknown(E->aux.hdr, 2, flag_d, g.s, st));
+    ENG_CHECK(launch_zero_unknown(E->aux.hdr, 2, E->flag_d, g.s, st));
     ENG_CHECK(hipStreamSynchronize(st));
-    ENG_CHECK(hipFree(flag_d));
   }
   if (E->R.warm && !keep.empty()) {
     // warm start: r0 = b - A x0; requests whose start already meets the
@@ -372,11 +376,41 @@ int step_active(bhx_engine* E, hipStream_t st) {
   if (rc != BHX_OK) return rc;
   const Grids g = engine_grids(E, E->active);
   const int n = (int)E->active.size();
+  std::vector<int> iter_before(n);
+  for (int i = 0; i < n; ++i) iter_before[i] = E->ctl_h[E->active[i]->slot].iter;
   Graph* used = nullptr;
   ENG_CHECK(run_chunk(E->hd, E->run.hdr, n, E->R, g, st, &used));
   ENG_CHECK(hipMemcpyAsync(E->ctl_h, E->ctl_d, E->max_slots * sizeof(Ctl), hipMemcpyDeviceToHost,
                            st));
   ENG_CHECK(hipStreamSynchronize(st));
+  if (E->R.profile && used && !used->ev.empty()) {
+    // launch c of a pass worked on the requests that ran more than c
+    // iterations of this chunk; their node counts go with its time
+    int worked = 0;
+    double iu = 0, in = 0;
+    for (int i = 0; i < n; ++i) {
+      const Req* q = E->active[i];
+      const int it = E->ctl_h[q->slot].iter - iter_before[i];
+      worked = std::max(worked, it);
+      iu += (double)it * E->ctl_h[q->slot].n_unknown;
+      in += (double)it * q->spec.nx * q->spec.ny;
+    }
+    for (int p = 0; p < 4; ++p) {
+      if (!(E->R.profile & (1 << p))) continue;
+      double sum = 0;
+      for (int c = 0; c < worked && c < E->R.chunk; ++c) {
+        float ms = 0;
+        ENG_CHECK(hipEventElapsedTime(&ms, used->ev[((size_t)p * E->R.chunk + c) * 2],
+                                      used->ev[((size_t)p * E->R.chunk + c) * 2 + 1]));
+        sum += ms;
+      }
+      std::lock_guard<std::mutex> lk(E->mu);   // read by bhx_engine_profile
+      E->prof_ms[p] += sum;
+      E->prof_launches[p] += std::min(worked, E->R.chunk);
+      E->prof_unknown[p] += iu;
+      E->prof_nodes[p] += in;
+    }
+  }
   bool any_done = false;
   for (Req* q : E->active)
     if (E->ctl_h[q->slot].done != kRunning) any_done = true;
@@ -486,11 +520,14 @@ int bhx_engine_create(bhx_engine** out, int device, size_t hbm_budget, int max_s
   E->R = R;
   E->R.chunk = o && o->chunk > 0 ? o->chunk : 16;   // short chunks: new requests join quickly
   E->R.chunk += E->R.chunk & 1;                       // even (buffer parity restarts each chunk)
-  E->R.profile = 0;
+  // profile mask: the chunks launch directly with dispatch events around the
+  // selected passes (slower than the captured graphs; for measurement runs)
+  E->R.profile = o ? o->profile : 0;
   E->budget = hbm_budget;
   E->max_slots = max_slots;
   if (hipMalloc((void**)&E->arena_base, hbm_budget) != hipSuccess ||
       hipMalloc((void**)&E->ctl_d, max_slots * sizeof(bhx::Ctl)) != hipSuccess ||
+      hipMalloc((void**)&E->flag_d, max_slots * sizeof(int)) != hipSuccess ||
       hipHostMalloc((void**)&E->ctl_h, max_slots * sizeof(bhx::Ctl)) != hipSuccess) {
     bhx_engine_destroy(E);
     return BHX_ERR_NOMEM;
@@ -553,6 +590,24 @@ int bhx_engine_poll(bhx_engine* E, uint64_t* ids, bhx_stats* st, int max, int* n
 
 int bhx_engine_inflight(bhx_engine* E) { return E ? E->inflight.load() : 0; }
 
+int bhx_engine_profile(bhx_engine* E, double* ms, long long* launches, double* unknown_nodes,
+                       double* nodes, int reset) {
+  if (!E || !ms || !launches || !unknown_nodes || !nodes) return BHX_ERR_ARG;
+  std::lock_guard<std::mutex> lk(E->mu);
+  for (int p = 0; p < 4; ++p) {
+    ms[p] = E->prof_ms[p];
+    launches[p] = E->prof_launches[p];
+    unknown_nodes[p] = E->prof_unknown[p];
+    nodes[p] = E->prof_nodes[p];
+    if (reset) {
+      E->prof_ms[p] = 0;
+      E->prof_launches[p] = 0;
+      E->prof_unknown[p] = E->prof_nodes[p] = 0;
+    }
+  }
+  return BHX_OK;
+}
+
 void bhx_engine_destroy(bhx_engine* E) {
   if (!E) return;
   {
@@ -573,6 +628,7 @@ void bhx_engine_destroy(bhx_engine* E) {
   free_db(E->aux);
   if (E->arena_base) (void)hipFree(E->arena_base);
   if (E->ctl_d) (void)hipFree(E->ctl_d);
+  if (E->flag_d) (void)hipFree(E->flag_d);
   if (E->ctl_h) (void)hipHostFree(E->ctl_h);
   if (E->hd) bhx_destroy(E->hd);
   delete E;
