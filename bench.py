@@ -185,6 +185,9 @@ def bench_serve(args):
                                 f"saturated fp{64 if precision == 0 else 32}")
             sat = len(ok) / span
             out["saturated_solves_per_s"] = round(sat, 3)
+            out["saturated_requests"] = ns
+            out["saturated_latency_ms"] = percentiles([r.latency for r in res])
+            out["saturated_not_converged"] = len(res) - len(ok)
             log(f"saturated (prec {precision}): {sat:.3f} solves/s over {len(res)} requests")
             if profile:
                 out["profile"] = bhx.engine_profile(srv.engine)
@@ -217,10 +220,12 @@ def bench_serve(args):
     log(f"serve: {sum(len(v) for v in sets.values())} distinct requests materialised on the "
         f"device in {time.perf_counter() - t0:.1f} s")
     fp64 = serve(0)
-    fp32 = serve(1, n_sat=24, n_timed=48) if not args.no_extra else None
+    # the FP32 preconditioner needs 3-4x the iterations: its saturated rate on
+    # the first requests of the same phase (all arrive at once)
+    fp32 = serve(1, n_sat=8, timed=False) if not args.no_extra else None
     # roofline: the first requests of the saturated phase again, with
     # dispatch events on every pass
-    n_prof = min(20, len(sets["sat"]))
+    n_prof = min(8, len(sets["sat"]))
     prof = serve(0, profile=15, timed=False, n_sat=n_prof)["profile"]
     tot = [prof["ms"][p] for p in range(4)]
     dom = int(np.argmax(tot))
@@ -607,9 +612,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="serve")
-    ap.add_argument("--requests", type=int, default=100,
+    ap.add_argument("--requests", type=int, default=48,
                     help="serve: requests in the timed stream (at least --steps)")
-    ap.add_argument("--sat-requests", type=int, default=40,
+    ap.add_argument("--sat-requests", type=int, default=24,
                     help="serve: requests of the saturated phase that sets the arrival rate")
     ap.add_argument("--slots", type=int, default=64, help="serve: engine slots")
     ap.add_argument("--budget-gb", type=int, default=64, help="serve: engine HBM budget")

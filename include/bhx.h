@@ -136,6 +136,17 @@ typedef struct {
                          the unknowns per grid row).  Fields sharing phi in one
                          bhx_extend_fields call share one factorisation.  Not for
                          the serving engine or three dimensions (BHX_ERR_ARG).       */
+  int transform;    /* form of the preconditioner's 1-D transforms (two dimensions):
+                         1 = FFT family: radix-4/2 cores in LDS, Bluestein's chirp-z for
+                         lengths without one;
+                         2 = dense where both axes have at most 512 nodes: each 1-D
+                         transform a product with its basis matrix on the matrix cores
+                         (v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4), the basis entries
+                         generated from a table in LDS; the FFT family otherwise;
+                         0 = built-in choice: the FFT family (faster at every size
+                         measured); with autotune = 1 the autotuner also times dense-
+                         wherever-possible for the batch and keeps it if faster.  The
+                         two forms' results agree to rounding.                        */
 } bhx_opts;
 
 typedef struct {
@@ -260,7 +271,9 @@ void bhx_engine_destroy(bhx_engine* e);
  *         `in` restricted to the unknown nodes (embed with zeros at K,
  *         transform, divide by (lambda_x + lambda_y)^2 with 0 for a zero
  *         eigenvalue, transform back, restrict), in the given precision.
- * Synchronises with the stream.  Returns a status code. */
+ * `precision`: bits 0-3 the preconditioner's precision (BHX_PREC_*), bits
+ * 4-7 the transform form (bhx_opts.transform).  Synchronises with the
+ * stream.  Returns a status code. */
 int bhx_debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, double* out,
                     int nx, int ny, int bc, int precision, void* stream);
 /* bhx_debug_apply in three dimensions: op 0 the masked 25-point operator,

@@ -57,7 +57,7 @@ class Opts(ctypes.Structure):
                 ("chunk", ctypes.c_int), ("rows", ctypes.c_int), ("occupancy", ctypes.c_int),
                 ("autotune", ctypes.c_int),
                 ("profile", ctypes.c_int), ("warm_start", ctypes.c_int),
-                ("solver", ctypes.c_int)]
+                ("solver", ctypes.c_int), ("transform", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -262,9 +262,9 @@ class Handle:
         self.close()
 
     def __del__(self):
-        if sys.is_finalizing():
-            return
         try:
+            if sys.is_finalizing():
+                return
             self.close()
         except Exception:
             pass
@@ -359,13 +359,15 @@ def workspace_bytes(nx, ny, bc, opts=None) -> int:
                                         ctypes.byref(opts) if opts is not None else None))
 
 
-def debug_apply(handle, op, phi, x, out, nx=None, ny=None, bc=0, precision=0, stream=None):
-    """``bhx_debug_apply``: op 0 masked operator, op 1 preconditioner."""
+def debug_apply(handle, op, phi, x, out, nx=None, ny=None, bc=0, precision=0, stream=None,
+                transform=0):
+    """``bhx_debug_apply``: op 0 masked operator, op 1 preconditioner
+    (``transform`` as bhx_opts.transform)."""
     if nx is None:
         nx, ny = _dims(phi)
     hp = handle.ptr if isinstance(handle, Handle) else handle
     return _lib.bhx_debug_apply(hp, int(op), _ptr(phi), _ptr(x), _ptr(out), nx, ny, int(bc),
-                                int(precision), _stream(stream))
+                                int(precision) | (int(transform) << 4), _stream(stream))
 
 
 # ---------------------------------------------------------------------------

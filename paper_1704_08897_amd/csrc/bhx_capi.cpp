@@ -153,7 +153,9 @@ int bhx_debug_apply3d(bhx_handle* hd, int op, const double* phi, const double* i
   if (!hd || !in || (op != 0 && op != 1)) return BHX_ERR_ARG;
   bhx_opts o;
   bhx_default_opts(&o);
-  o.precision = precision;
+  o.precision = precision & 15;           // bits 4-7: the transform form (three
+  o.transform = (precision >> 4) & 15;    // dimensions always use the FFT family)
+  if (precision < 0 || (precision >> 8) != 0) return BHX_ERR_ARG;
   const Resolved R = bhx::resolve_opts(&o);
   int v = bhx::validate3(phi, out, nx, ny, nz, 1.0, bc, 0.5, R);
   if (v != BHX_OK) return v;
@@ -175,7 +177,9 @@ int bhx_debug_apply(bhx_handle* hd, int op, const double* phi, const double* in,
   if (!hd || !in || (op != 0 && op != 1)) return BHX_ERR_ARG;
   bhx_opts o;
   bhx_default_opts(&o);
-  o.precision = precision;
+  o.precision = precision & 15;           // bits 4-7: the transform form
+  o.transform = (precision >> 4) & 15;
+  if (precision < 0 || (precision >> 8) != 0) return BHX_ERR_ARG;
   const Resolved R = bhx::resolve_opts(&o);
   int v = bhx::validate(phi, out, nx, ny, 1.0, bc, 0.5, R);
   if (v != BHX_OK) return v;

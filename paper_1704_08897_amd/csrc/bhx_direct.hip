@@ -618,6 +618,8 @@ int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R
   hipStream_t st = stream ? stream : hd->own_stream;
   Resolved R = R0;
   R.warm = 0;
+  R.transform = 1;              // the layout instance0() recomputes (FFT row groups)
+  R.sched.transform = -1;
   const InstSpec& S0 = specs[0];
   const int nx = S0.nx, ny = S0.ny, N = nx * ny;
   if (S0.dim != 2 || !direct_supported(S0.bcy)) return BHX_ERR_ARG;

@@ -166,7 +166,7 @@ int upload_batch(bhx_engine* E, DevBatch& db, const std::vector<Req*>& reqs, hip
   for (int i = 0; i < n; ++i) {
     inst[i] = reqs[i]->inst;
     for (int p = 0; p < kNumPass; ++p)
-      for (int k = 0; k < inst[i].n_items[p]; ++k) items[p].push_back((i << kItemShift) | k);
+      for (int k = 0; k < list_items(inst[i], p); ++k) items[p].push_back((i << kItemShift) | k);
   }
   if (!db.hdr) ENG_CHECK(hipMalloc((void**)&db.hdr, sizeof(Batch)));
   ENG_CHECK(ensure(&db.inst, &db.inst_cap, std::max(n, 1)));
@@ -212,6 +212,7 @@ Grids engine_grids(bhx_engine* E, const std::vector<Req*>& reqs) {
   g.count = (int)reqs.size();
   for (Req* q : reqs) {
     g.reduce |= q->inst.reduce;
+    if (q->inst.dense) continue;                 // no FFT pass works on it
     const AxisPlan& PX = E->hd->plans.plan(q->inst.planx);
     const AxisPlan& PY = E->hd->plans.plan(q->inst.plany);
     buf_r = std::max(buf_r, (q->inst.G / 2) * row_slots(PX.m));
@@ -225,6 +226,12 @@ Grids engine_grids(bhx_engine* E, const std::vector<Req*>& reqs) {
   g.lds_r = std::min(kLdsDynMax, up((buf_r + tab_r) * csize));
   g.tw_c = buf_c;
   g.lds_c = std::min(kLdsDynMax, up((buf_c + tab_c) * csize));
+  // both transform families launch every iteration (a family without
+  // requests returns at once), with the dense passes sized for the longest
+  // dense axis, so the captured graphs do not depend on the active set
+  g.fft = 1;
+  g.dense = 1;
+  dense_grids(E->R.precision, kDenseMax, kDenseMax, cu * 2, cu * 2, cu, 2, &g);
   return g;
 }
 
@@ -247,7 +254,9 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
     const InstSpec& S = q->spec;
     const int px = hd->plans.get(S.nx, S.bcx), py = hd->plans.get(S.ny, S.bcy);
     Layout L;
-    make_layout(S.nx, S.ny, E->R.precision, hd->plans.plan(px).m, hd->plans.plan(py).m, 0, &L);
+    const bool dense = use_dense(E->R, hd->plans.plan(px), hd->plans.plan(py));
+    make_layout(S.nx, S.ny, E->R.precision, hd->plans.plan(px).m, hd->plans.plan(py).m, 0, &L,
+                dense);
     Inst& I = q->inst;
     std::memset(&I, 0, sizeof(I));
     I.nx = S.nx; I.ny = S.ny; I.nz = 1; I.nrows = S.ny;
@@ -259,6 +268,7 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
     I.flexible = E->R.flexible;
     I.warm = E->R.warm;
     I.reduce = L.n_items[kPassS] + 3 * L.n_items[kPassR] > kReduceMin;
+    I.dense = dense;
     I.phi = (decltype(I.phi))S.phi;
     I.F = (decltype(I.F))S.F;
     char* b = E->arena_base + q->off;
@@ -289,7 +299,7 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
   const Grids g = engine_grids(E, news);
   const int n = (int)news.size();
   ENG_CHECK(launch_setup(E->aux.hdr, 2, g.s, st));
-  ENG_CHECK(launch_setup_rows(E->aux.hdr, g.r, st));
+  ENG_CHECK(launch_setup_rows(E->aux.hdr, std::max(g.r, g.rd), st));
   ENG_CHECK(launch_stencil(E->aux.hdr, 2, kModeRhs, g.s, 0, st));
   ENG_CHECK(launch_finalize(E->aux.hdr, n, kFinSetupH, st));
   ENG_CHECK(hipMemcpyAsync(E->ctl_h, E->ctl_d, E->max_slots * sizeof(Ctl), hipMemcpyDeviceToHost,

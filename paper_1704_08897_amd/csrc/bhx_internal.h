@@ -79,7 +79,17 @@ __device__ __forceinline__ int map_axis(int g, int n, int bc, double& s) {
   return g < 0 ? 0 : n - 1;
 }
 
-enum Pass { kPassS = 0, kPassR = 1, kPassC = 2, kPassZ = 3, kNumPass = 4 };
+// Work lists: stencil tiles, row groups, column groups, z-pencil groups, and
+// the row and column groups of instances whose preconditioner runs as dense
+// matrix products (kPassRD, kPassCD; those instances are absent from the
+// kPassR and kPassC lists).
+enum Pass { kPassS = 0, kPassR = 1, kPassC = 2, kPassZ = 3, kPassRD = 4, kPassCD = 5,
+            kNumPass = 6 };
+
+// Dense transforms: lines per work item (one 16-wide matrix-core tile) and
+// the longest axis they take.
+constexpr int kDenseG = 16;
+constexpr int kDenseMax = 512;
 
 // Kinds of column-transform launch.  Two dimensions: one launch transforms
 // along y, scales by 1/(lambda_x + lambda_y)^2 and transforms back.  Three
@@ -115,6 +125,17 @@ struct AxisPlan {
   int off_lam;     // eigenvalues lambda_k of T, k < n           (real table)
   int nf;          // length of the DFT computed: n (DCT-II via Makhoul, Hartley);
                    // 2(n+1) for DST-I (odd extension 0, x, 0, -reversed x)
+  // Dense form of the 1-D transform (n <= kDenseMax, else dense_P = 0): the
+  // unnormalised basis T(k, i) = dtab[f(((k + ck) (di i + ci)) mod P)] with
+  // (ck, di, ci, P) = (0, 2, 1, 4n) and dtab[a] = cos(pi a / 2n) (DCT-II),
+  // (0, 1, 0, n) and cos(2 pi a / n) + sin(2 pi a / n) (Hartley), (1, 1, 1,
+  // 2(n+1)) and sin(pi a / (n+1)) (DST-I); f(a) = min(a, P - a) for the
+  // cosine (dense_fold = 1, P/2 + 1 entries), f(a) = a otherwise.  The
+  // orthonormal transform is nk(k) T(k, i) with nk = s_0, s_1 (DCT) or 2 hs.
+  int dense_P;
+  int dense_fold;
+  int off_dtab;    // dense basis table (real table), dense_len entries
+  int dense_len;
   // normalisations: DCT-II s_0 = sqrt(1/n), s_k = sqrt(2/n); its inverse's
   // pre-scale g_0 = 1/sqrt(n), g_k = 1/sqrt(2n); hs: Hartley 1/(2 sqrt(n)),
   // DST-I sqrt(2/(n+1)) / 2
@@ -157,6 +178,9 @@ struct Inst {
   int flexible;
   int warm;             // 1: F's values at U on input are the first iterate x0
   int reduce;           // 1: scalars come from Ctl::red_* (k_reduce), not the partials
+  int dense;            // 1: the preconditioner's transforms are dense matrix
+                        //    products on the matrix cores (k_rowfwd_dense, k_col_dense,
+                        //    k_rowinv_dense; G = Gc = kDenseG)
   BHX_GLOBAL const double* phi;
   BHX_GLOBAL double* F;
   BHX_GLOBAL uint8_t* mask;   // 1 = unknown, 0 = known
@@ -182,6 +206,17 @@ struct PartLayout {
   __host__ __device__ int rowcnt() const { return 3 * nS + 5 * nR; }   // [nR] unknowns per row group
   __host__ __device__ int total() const { return 3 * nS + 6 * nR; }
 };
+
+// Items instance I contributes to the work list of pass p: a dense
+// instance's row and column groups go to the dense lists instead of the FFT
+// ones; I.n_items holds the group counts either way (the partial sums are
+// laid out by them).
+__host__ __device__ inline int list_items(const Inst& I, int p) {
+  if (p == kPassR || p == kPassC) return I.dense ? 0 : I.n_items[p];
+  if (p == kPassRD) return I.dense ? I.n_items[kPassR] : 0;
+  if (p == kPassCD) return I.dense ? I.n_items[kPassC] : 0;
+  return I.n_items[p];
+}
 
 // Flat work list of one pass: items[i] = (instance << 20) | local item.
 constexpr int kItemShift = 20;
@@ -241,7 +276,22 @@ hipError_t launch_col(const Batch* B, int prec, int shape, int kind, int count_i
 hipError_t launch_rowinv(const Batch* B, int prec, int shape, int grid, int lds, int twoff,
                          int lpar, hipStream_t st, hipEvent_t e0 = nullptr,
                          hipEvent_t e1 = nullptr);
+// Unknown counts per row group, over the FFT and the dense row-group lists.
 hipError_t launch_setup_rows(const Batch* B, int grid, hipStream_t st);
+// Dense-transform passes (instances with Inst::dense): `lds` dynamic LDS
+// bytes (dense_lds_bytes of the pass and the longest axis of the launch),
+// `tab_off` the element offset of the basis table in it (dense_tab_off).
+hipError_t launch_rowfwd_dense(const Batch* B, int prec, int update, int grid, int lds,
+                               int tab_off, int lpar, hipStream_t st, hipEvent_t e0 = nullptr,
+                               hipEvent_t e1 = nullptr);
+hipError_t launch_col_dense(const Batch* B, int prec, int count_iter, int grid, int lds,
+                            int tab_off, hipStream_t st, hipEvent_t e0 = nullptr,
+                            hipEvent_t e1 = nullptr);
+hipError_t launch_rowinv_dense(const Batch* B, int prec, int grid, int lds, int tab_off,
+                               int lpar, hipStream_t st, hipEvent_t e0 = nullptr,
+                               hipEvent_t e1 = nullptr);
+int dense_lds_bytes(int pass, int prec, int n_max);
+int dense_tab_off(int n_max);
 hipError_t launch_identity(const Batch* B, int grid, int lpar, hipStream_t st,
                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_finalize(const Batch* B, int count, int mode, hipStream_t st);

@@ -738,11 +738,12 @@ __global__ void __launch_bounds__(kThreads) k_setup(const Batch* __restrict__ Bp
 }
 
 // Unknown nodes per row group (row passes skip groups without any).
-__global__ void __launch_bounds__(kThreads) k_setup_rows(const Batch* __restrict__ Bp) {
+// `pass`: the row-group list, kPassR (FFT instances) or kPassRD (dense ones).
+__global__ void __launch_bounds__(kThreads) k_setup_rows(const Batch* __restrict__ Bp, int pass) {
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   __shared__ double red[4];
-  for (int it = logical_block(); it < B.n_items[kPassR]; it += gridDim.x) {
-    const int code = item_code(B, kPassR, it);
+  for (int it = logical_block(); it < B.n_items[pass]; it += gridDim.x) {
+    const int code = item_code(B, pass, it);
     const Inst I = B.inst[code >> kItemShift];
     const int g = code & kItemMask;
     if (I.ctl->done) continue;
@@ -1762,6 +1763,407 @@ __global__ void __launch_bounds__(kThreads) k_identity(const Batch* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Dense transforms on the matrix cores.  For an axis of at most kDenseMax
+// nodes the 1-D transform is applied as a product with its basis matrix
+// T(k, i), whose entries come from a table in LDS through the index rule of
+// AxisPlan (dense_P, dense_fold): v_mfma_f64_16x16x4 for the FP64
+// preconditioner, v_mfma_f32_16x16x4 for the FP32 one.  A work item is 16
+// lines, one matrix tile wide.  The passes and their results are those of
+// the FFT family (the orthonormal coefficients in t, laid out [kx][y]):
+//   k_rowfwd_dense   CG update of 16 rows, then t[k][j] = nk(k) sum_i T(k, i) r[j][i]
+//   k_col_dense      16 columns of t: forward along y, scale by
+//                    nk(ky)^2 / (lambda_x + lambda_y)^2, inverse along y
+//   k_rowinv_dense   z[j][i] = sum_k T(k, i) nk(k) t[k][j] at unknown nodes; r.z
+// ---------------------------------------------------------------------------
+
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+template <typename R> struct Mfma;
+// Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of a 16 x 4 by
+// 4 x 16 product; accumulator element v of lane l is D[row(v, l)][l % 16].
+template <> struct Mfma<double> {
+  using Acc = v4d_t;
+  static __device__ __forceinline__ Acc mac(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int l) { return 4 * v + (l >> 4); }
+};
+template <> struct Mfma<float> {
+  using Acc = v4f_t;
+  static __device__ __forceinline__ Acc mac(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int l) { return 4 * (l >> 4) + v; }
+};
+
+// Matrix tiles one wave owns at most (tiles w, w + 4, ... of an axis).
+constexpr int kDenseTiles = (kDenseMax / 16 + 3) / 4;
+
+// LDS stride of one line of an item buffer holding K entries: K rounded up
+// to the matrix step (4) plus one, odd, so the 16 lines of a tile fall on
+// different banks.
+__host__ __device__ inline int dense_stride(int K) { return ((K + 3) & ~3) + 1; }
+
+// The dense form of one axis' transform, with its basis table staged in LDS.
+template <typename R>
+struct DPlan {
+  int n, P, fold, ck, di, ci;
+  R nk0, nk1;          // orthonormal factor of coefficient 0 and of the others
+  const R* tab;        // LDS
+  BHX_GLOBAL const R* gtab;
+  BHX_GLOBAL const R* glam;
+  __device__ DPlan(const Batch& B, int idx) {
+    const AxisPlan A = B.plans[idx];
+    n = A.n;
+    P = A.dense_P;
+    fold = A.dense_fold;
+    ck = A.bc == kDirichlet ? 1 : 0;
+    di = A.bc == kNeumann ? 2 : 1;
+    ci = A.bc == kPeriodic ? 0 : 1;
+    nk0 = A.bc == kNeumann ? (R)A.s0 : (R)(2 * A.hs);
+    nk1 = A.bc == kNeumann ? (R)A.s1 : (R)(2 * A.hs);
+    const int pi = sizeof(R) == 8 ? 0 : 1;
+    gtab = (BHX_GLOBAL const R*)B.rtab[pi] + A.off_dtab;
+    glam = (BHX_GLOBAL const R*)B.rtab[pi] + A.off_lam;
+    tab = nullptr;
+  }
+  __device__ __forceinline__ R nk(int k) const { return k == 0 ? nk0 : nk1; }
+  __device__ __forceinline__ int len() const { return fold ? P / 2 + 1 : P; }
+  __device__ __forceinline__ R at(int idx) const { return tab[fold ? min(idx, P - idx) : idx]; }
+  // Copy the basis table (and, given `lam`, the eigenvalues) of plan `idx`
+  // into LDS unless it is there already; every thread calls this at the
+  // same point.
+  __device__ void stage(R* lds, R* lam, int idx, int& staged) {
+    if (idx != staged) {
+      const int L = len();
+      for (int e = threadIdx.x; e < L; e += kThreads) lds[e] = gtab[e];
+      if (lam)
+        for (int e = threadIdx.x; e < n; e += kThreads) lam[e] = glam[e];
+      __syncthreads();
+      staged = idx;
+    }
+    tab = lds;
+  }
+};
+
+// acc[t] = the wave's matrix tile t (axis tile w + 4t) of a product with the
+// basis over K = n entries, from the item buffer dat (16 lines, stride S,
+// zero past K up to a multiple of 4):
+//   TAB_A: D[k][c] = sum_i T(k, i) dat[c][i]   (tiles along k)
+//   TAB_B: D[c][i] = sum_k dat[c][k] T(k, i)   (tiles along i)
+// Each lane walks its basis row or column by the index rule, one modular
+// addition per step.
+template <typename R, bool TAB_A>
+__device__ __forceinline__ void dense_product(const DPlan<R>& X, const R* dat, int S, int K,
+                                              typename Mfma<R>::Acc (&acc)[kDenseTiles]) {
+  using M = Mfma<R>;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lo = l & 15, hi = l >> 4;
+  const int ntiles = (X.n + 15) >> 4;
+  const int nt = (ntiles - w + 3) >> 2;          // this wave's tiles (wave-uniform)
+  int idx[kDenseTiles], inc[kDenseTiles];
+#pragma unroll
+  for (int t = 0; t < kDenseTiles; ++t) {
+    acc[t] = (typename M::Acc){0, 0, 0, 0};
+    const int u = ((w + 4 * t) << 4) + lo;       // the tile's fixed coordinate (k or i)
+    // T(k, i) index ((k + ck)(di i + ci)) mod P; the moving coordinate is
+    // hi, hi + 4, ...
+    const int F = TAB_A ? u + X.ck : X.di * u + X.ci;
+    const int G0 = TAB_A ? X.di * hi + X.ci : hi + X.ck;
+    const int step = TAB_A ? 4 * X.di : 4;
+    idx[t] = (F * G0) % X.P;
+    inc[t] = (F * step) % X.P;
+  }
+  const R* line = dat + lo * S + hi;
+#pragma unroll 2
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const R s = line[k0];
+#pragma unroll
+    for (int t = 0; t < kDenseTiles; ++t) {
+      if (t < nt) {
+        const R tv = X.at(idx[t]);
+        acc[t] = TAB_A ? M::mac(tv, s, acc[t]) : M::mac(s, tv, acc[t]);
+        idx[t] += inc[t];
+        idx[t] -= idx[t] >= X.P ? X.P : 0;
+      }
+    }
+  }
+}
+
+// Row pass, forward, dense: the CG update of 16 rows (as k_rowfwd), the rows
+// staged in LDS, then the x transform as a product with the basis, written
+// transposed to t[k * nrows + j].  `mode` bits 0-1: 0 transform only, 1 PCG
+// update then transform.  `tab_off`: element offset of the basis table in
+// the dynamic LDS (after the largest item buffer of the launch).
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_rowfwd_dense(const Batch* __restrict__ Bp,
+                                                           int mode, int tab_off, int lpar) {
+  using M = Mfma<R>;
+  const int update = mode & 3;
+  const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* dat = (R*)smem;
+  R* tabl = dat + tab_off;
+  __shared__ double red[8];
+  int staged = -1;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int itm = logical_block(); itm < B.n_items[kPassRD]; itm += gridDim.x) {
+    const int code = item_code(B, kPassRD, itm);
+    const Inst I = B.inst[code >> kItemShift];
+    const int g = code & kItemMask;
+    BHX_GLOBAL Ctl* ctl = I.ctl;
+    const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
+    const int nx = I.nx, ny = I.nrows, j0 = g * kDenseG;
+    const int jn = min(kDenseG, ny - j0);
+    const int E = jn * nx;
+    const size_t base = (size_t)j0 * nx;
+    BHX_GLOBAL const uint8_t* __restrict__ mk = I.mask + base;
+    BHX_GLOBAL double* __restrict__ Fb = I.F + base;
+    BHX_GLOBAL double* __restrict__ rb = I.r + base;
+    BHX_GLOBAL const double* __restrict__ pb = (lpar ? I.p[0] : I.p[1]) + base;
+    BHX_GLOBAL const double* __restrict__ qb = I.q + base;
+    BHX_GLOBAL const double* arrs[2] = {I.part + PL.rz(lpar), I.part + PL.pq()};
+    const int lens[2] = {I.reduce ? 1 : PL.nR, I.reduce ? 1 : PL.nS};
+    const int ns[2] = {update && !I.reduce ? PL.nR : 0, update && !I.reduce ? PL.nS : 0};
+    Partials<2> PS;
+    sums_issue<2>(arrs, lens, PS);
+    const double rsc[2] = {ctl->red_rz[lpar], ctl->red_pq};
+    const int c_done = ctl->done, k_it = ctl->iter;
+    const double rowcnt = I.part[PL.rowcnt() + g];
+    if (c_done) continue;
+    BHX_GLOBAL R* t = (BHX_GLOBAL R*)I.t;
+    if (rowcnt == 0.0) {
+      // no unknown node in these rows: r = 0 there, so is its transform
+      for (int e = threadIdx.x; e < nx * kDenseG; e += kThreads) {
+        const int kx = e / kDenseG, j = j0 + (e - kx * kDenseG);
+        if (j < ny) t[(size_t)kx * ny + j] = (R)0;
+      }
+      if (update && threadIdx.x == 0) I.part[PL.rr() + g] = 0.0;
+      continue;
+    }
+    double alpha = 0.0;
+    if (update) {
+      double sums[2];
+      sums_finish<2>(arrs, ns, PS, sums, red);
+      alpha = I.reduce ? rsc[0] / rsc[1] : sums[0] / sums[1];
+    }
+    const bool first = k_it == 0;
+    const int S = dense_stride(nx);
+    double acc_rr = 0.0;
+    for (int e0 = threadIdx.x; e0 < kDenseG * nx; e0 += kUnroll * kThreads) {
+      int m[kUnroll];
+      double rv[kUnroll], pv[kUnroll], qv[kUnroll], xv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int e = e0 + u * kThreads;
+        m[u] = e < E ? mk[min(e, E - 1)] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int ea = m[u] ? e0 + u * kThreads : 0;
+        rv[u] = rb[ea];
+        pv[u] = update ? pb[ea] : 0.0;
+        qv[u] = update ? qb[ea] : 0.0;
+        xv[u] = update ? Fb[ea] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int e = e0 + u * kThreads;
+        if (e >= kDenseG * nx) break;
+        double v = m[u] ? rv[u] : 0.0;
+        if (update && m[u]) {
+          Fb[e] = (first && !I.warm ? 0.0 : xv[u]) + alpha * pv[u];
+          v -= alpha * qv[u];
+          rb[e] = v;
+          acc_rr += v * v;
+        }
+        const int jr = e / nx, i = e - jr * nx;
+        dat[jr * S + i] = (R)v;
+      }
+    }
+    for (int e = threadIdx.x; e < kDenseG * (S - nx); e += kThreads) {
+      const int jr = e / (S - nx);
+      dat[jr * S + nx + (e - jr * (S - nx))] = (R)0;
+    }
+    DPlan<R> X(B, I.planx);
+    X.stage(tabl, nullptr, I.planx, staged);       // synchronises the block
+    __syncthreads();
+    if (update) {
+      acc_rr = block_sum(acc_rr, red);
+      if (threadIdx.x == 0) I.part[PL.rr() + g] = acc_rr;
+    }
+    typename M::Acc acc[kDenseTiles];
+    dense_product<R, true>(X, dat, S, nx, acc);
+    const int nt = (((nx + 15) >> 4) - w + 3) >> 2;
+#pragma unroll
+    for (int tt = 0; tt < kDenseTiles; ++tt) {
+      if (tt < nt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = ((w + 4 * tt) << 4) + M::row(v, l), c = l & 15;
+          if (k < nx && c < jn) t[(size_t)k * ny + j0 + c] = acc[tt][v] * X.nk(k);
+        }
+      }
+    }
+    __syncthreads();          // dat is reused by the block's next item
+  }
+}
+
+// Column pass, dense: 16 columns (kx lines of t, y contiguous) per item:
+// U = T_y t (forward), scaled by nk(ky)^2 / (lambda_x + lambda_y)^2 (0 for a
+// zero sum) - both orthonormal factors of the pair of transforms at once -
+// then t = T_y^T U (inverse), in place.
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_col_dense(const Batch* __restrict__ Bp,
+                                                        int count_iter, int tab_off) {
+  using M = Mfma<R>;
+  const Batch B = *(BHX_CONST const Batch*)Bp;
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* dat = (R*)smem;
+  R* tabl = dat + tab_off;
+  R* laml = tabl + 2 * kDenseMax + 2;       // after the longest table (DST-I: 2(n+1))
+  __shared__ R s_lamx[kDenseG];
+  int staged = -1;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int itm = logical_block(); itm < B.n_items[kPassCD]; itm += gridDim.x) {
+    const int code = item_code(B, kPassCD, itm);
+    const Inst I = B.inst[code >> kItemShift];
+    const int c = code & kItemMask;
+    BHX_GLOBAL Ctl* ctl = I.ctl;
+    if (ctl->done) continue;
+    const int nx = I.nx, ny = I.ny, c0 = c * kDenseG;
+    const int cnt = min(kDenseG, nx - c0);
+    const int S = dense_stride(ny);
+    BHX_GLOBAL R* t = (BHX_GLOBAL R*)I.t;
+    for (int e = threadIdx.x; e < kDenseG * S; e += kThreads) {
+      const int cr = e / S, j = e - cr * S;
+      dat[e] = (cr < cnt && j < ny) ? t[(size_t)(c0 + cr) * ny + j] : (R)0;
+    }
+    if (threadIdx.x < kDenseG) {
+      const DPlan<R> Xx(B, I.planx);
+      s_lamx[threadIdx.x] = Xx.glam[min(c0 + (int)threadIdx.x, nx - 1)];
+    }
+    DPlan<R> X(B, I.plany);
+    X.stage(tabl, laml, I.plany, staged);
+    __syncthreads();
+    typename M::Acc acc[kDenseTiles];
+    dense_product<R, true>(X, dat, S, ny, acc);     // U[ky][cr]
+    const int nt = (((ny + 15) >> 4) - w + 3) >> 2;
+    __syncthreads();                                 // every wave is done reading dat
+#pragma unroll
+    for (int tt = 0; tt < kDenseTiles; ++tt) {
+      if (tt < nt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ky = ((w + 4 * tt) << 4) + M::row(v, l), cr = l & 15;
+          if (ky < ny) {
+            const R f = X.nk(ky);
+            dat[cr * S + ky] = acc[tt][v] * (f * f) * inv_sq<R>(laml[ky] + s_lamx[cr]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    dense_product<R, false>(X, dat, S, ny, acc);    // t[cr][j]
+#pragma unroll
+    for (int tt = 0; tt < kDenseTiles; ++tt) {
+      if (tt < nt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int cr = M::row(v, l), j = ((w + 4 * tt) << 4) + (l & 15);
+          if (cr < cnt && j < ny) t[(size_t)(c0 + cr) * ny + j] = acc[tt][v];
+        }
+      }
+    }
+    if (count_iter && c == 0 && threadIdx.x == 0) ctl->iter = ctl->iter + 1;
+    __syncthreads();
+  }
+}
+
+// Row pass, inverse, dense: 16 rows of spectra read transposed from t,
+// pre-scaled by nk(k), multiplied by the basis; z at the unknown nodes;
+// partial r.z (and r.z_old), as k_rowinv.
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_rowinv_dense(const Batch* __restrict__ Bp,
+                                                           int tab_off, int lpar) {
+  using M = Mfma<R>;
+  const Batch B = *(BHX_CONST const Batch*)Bp;
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* dat = (R*)smem;
+  R* tabl = dat + tab_off;
+  __shared__ double red[4];
+  int staged = -1;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int itm = logical_block(); itm < B.n_items[kPassRD]; itm += gridDim.x) {
+    const int code = item_code(B, kPassRD, itm);
+    const Inst I = B.inst[code >> kItemShift];
+    const int g = code & kItemMask;
+    BHX_GLOBAL Ctl* ctl = I.ctl;
+    const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
+    const int par = lpar ^ 1;
+    const int nx = I.nx, ny = I.nrows, j0 = g * kDenseG;
+    const int jn = min(kDenseG, ny - j0);
+    const int c_done = ctl->done;
+    const double rowcnt = I.part[PL.rowcnt() + g];
+    if (c_done) continue;
+    const bool flex = I.flexible != 0;
+    if (rowcnt == 0.0) {      // z stays 0 on rows without unknowns
+      if (threadIdx.x == 0) {
+        I.part[PL.rz(par) + g] = 0.0;
+        if (flex) I.part[PL.rzo(par) + g] = 0.0;
+      }
+      continue;
+    }
+    DPlan<R> X(B, I.planx);
+    const int S = dense_stride(nx);
+    BHX_GLOBAL const R* t = (BHX_GLOBAL const R*)I.t;
+    // dat[jr][k] = nk(k) t[k][j0 + jr]: 16 consecutive j per k in memory
+    for (int e = threadIdx.x; e < kDenseG * S; e += kThreads) {
+      const int k = e / kDenseG, jr = e - k * kDenseG;
+      if (k < S) dat[jr * S + k] = (jr < jn && k < nx) ? t[(size_t)k * ny + j0 + jr] * X.nk(k)
+                                                        : (R)0;
+    }
+    X.stage(tabl, nullptr, I.planx, staged);
+    __syncthreads();
+    typename M::Acc acc[kDenseTiles];
+    dense_product<R, false>(X, dat, S, nx, acc);
+    const size_t base = (size_t)j0 * nx;
+    BHX_GLOBAL const uint8_t* __restrict__ mk = I.mask + base;
+    BHX_GLOBAL const double* __restrict__ rb = I.r + base;
+    BHX_GLOBAL double* __restrict__ zb = I.z + base;
+    const int nt = (((nx + 15) >> 4) - w + 3) >> 2;
+    double a_rz = 0.0, a_rzo = 0.0;
+#pragma unroll
+    for (int tt = 0; tt < kDenseTiles; ++tt) {
+      if (tt < nt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int jr = M::row(v, l), i = ((w + 4 * tt) << 4) + (l & 15);
+          if (jr < jn && i < nx) {
+            const size_t o = (size_t)jr * nx + i;
+            if (mk[o]) {
+              const double zv = (double)acc[tt][v];
+              const double rv = rb[o];
+              if (flex) a_rzo += rv * zb[o];
+              zb[o] = zv;
+              a_rz += rv * zv;
+            }
+          }
+        }
+      }
+    }
+    a_rz = block_sum(a_rz, red);
+    if (flex) a_rzo = block_sum(a_rzo, red);
+    if (threadIdx.x == 0) {
+      I.part[PL.rz(par) + g] = a_rz;
+      if (flex) I.part[PL.rzo(par) + g] = a_rzo;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Per-instance finalisation (one block per instance) and helpers.
 // ---------------------------------------------------------------------------
 
@@ -1908,7 +2310,7 @@ hipError_t launch_setup(const Batch* B, int dim, int grid, hipStream_t st) {
 // records them at kernel start and end.
 #define BHX_LAUNCH(kernel, grid, lds, st, e0, e1, ...)                                  \
   do {                                                                                \
-    if (e0)                                                                           \
+    if ((e0) || (e1))                                                                 \
       hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), lds, st, e0, e1, 0,   \
                             __VA_ARGS__);                                             \
     else                                                                              \
@@ -2099,9 +2501,41 @@ hipError_t launch_rowinv(const Batch* B, int prec, int shape, int grid, int lds,
   return hipGetLastError();
 }
 hipError_t launch_setup_rows(const Batch* B, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_setup_rows, dim3(grid), dim3(kThreads), 0, st, B);
+  hipLaunchKernelGGL(k_setup_rows, dim3(grid), dim3(kThreads), 0, st, B, (int)kPassR);
+  hipLaunchKernelGGL(k_setup_rows, dim3(grid), dim3(kThreads), 0, st, B, (int)kPassRD);
   return hipGetLastError();
 }
+hipError_t launch_rowfwd_dense(const Batch* B, int prec, int update, int grid, int lds,
+                               int tab_off, int lpar, hipStream_t st, hipEvent_t e0,
+                               hipEvent_t e1) {
+  if (prec != 0)
+    BHX_LAUNCH((k_rowfwd_dense<float>), grid, lds, st, e0, e1, B, update, tab_off, lpar);
+  else
+    BHX_LAUNCH((k_rowfwd_dense<double>), grid, lds, st, e0, e1, B, update, tab_off, lpar);
+  return hipGetLastError();
+}
+hipError_t launch_col_dense(const Batch* B, int prec, int count_iter, int grid, int lds,
+                            int tab_off, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (prec != 0)
+    BHX_LAUNCH((k_col_dense<float>), grid, lds, st, e0, e1, B, count_iter, tab_off);
+  else
+    BHX_LAUNCH((k_col_dense<double>), grid, lds, st, e0, e1, B, count_iter, tab_off);
+  return hipGetLastError();
+}
+hipError_t launch_rowinv_dense(const Batch* B, int prec, int grid, int lds, int tab_off,
+                               int lpar, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (prec != 0)
+    BHX_LAUNCH((k_rowinv_dense<float>), grid, lds, st, e0, e1, B, tab_off, lpar);
+  else
+    BHX_LAUNCH((k_rowinv_dense<double>), grid, lds, st, e0, e1, B, tab_off, lpar);
+  return hipGetLastError();
+}
+int dense_lds_bytes(int pass, int prec, int n_max) {
+  const int sz = prec == 0 ? 8 : 4;
+  const int tab = 2 * kDenseMax + 2;                     // longest basis table
+  return (kDenseG * dense_stride(n_max) + tab + (pass == kPassCD ? n_max : 0)) * sz;
+}
+int dense_tab_off(int n_max) { return kDenseG * dense_stride(n_max); }
 hipError_t launch_identity(const Batch* B, int grid, int lpar, hipStream_t st, hipEvent_t e0,
                            hipEvent_t e1) {
   BHX_LAUNCH(k_identity, grid, 0, st, e0, e1, B, lpar);
@@ -2151,6 +2585,12 @@ hipError_t set_kernel_attributes() {
   set((const void*)k_col<float, kColYInv, 0>);
   set((const void*)k_rowinv<double, 0>);
   set((const void*)k_rowinv<float, 0>);
+  set((const void*)k_rowfwd_dense<double>);
+  set((const void*)k_rowfwd_dense<float>);
+  set((const void*)k_col_dense<double>);
+  set((const void*)k_col_dense<float>);
+  set((const void*)k_rowinv_dense<double>);
+  set((const void*)k_rowinv_dense<float>);
 #define BHX_SET_ROW(G, L, bc)                                        \
   set((const void*)k_rowfwd<double, BHX_KEY(G, L, bc)>);             \
   set((const void*)k_rowinv<double, BHX_KEY(G, L, bc)>);

@@ -102,7 +102,7 @@ bool length_supported(int n, int bc, int prec) {
 }
 
 bool make_layout(int nx, int ny, int nz, int prec, int mx, int my, int mz, int rows_user,
-                 Layout* L) {
+                 Layout* L, bool dense) {
   const bool d3 = mz > 0;
   const int csize = prec == 0 ? 16 : 8;
   const int rows_cap = prec == 0 ? 4 : 8;
@@ -121,8 +121,8 @@ bool make_layout(int nx, int ny, int nz, int prec, int mx, int my, int mz, int r
   // z pencils are strided: wider groups give longer contiguous runs
   const int rz = d3 ? rows_for(nz, mz, (long)nx * ny, kMaxGc / 2) : 1;
   if (rx < 1 || ry < 1 || rz < 1) return false;
-  L->G = 2 * rx;
-  L->Gc = 2 * ry;
+  L->G = dense ? kDenseG : 2 * rx;
+  L->Gc = dense ? kDenseG : 2 * ry;
   L->Gz = d3 ? 2 * rz : 0;
   if (L->Gc > kMaxGc || L->Gz > kMaxGc) return false;
   const int tx = d3 ? kTileX3 : kTileX, ty = d3 ? kTileY3 : kTileY, tz = d3 ? kTileZ3 : 1;
@@ -132,7 +132,7 @@ bool make_layout(int nx, int ny, int nz, int prec, int mx, int my, int mz, int r
   const long items[kNumPass] = {(long)L->tiles_x * L->tiles_y * L->tiles_z,
                                 (nrows + L->G - 1) / L->G,
                                 ((long)nx * nz + L->Gc - 1) / L->Gc,
-                                d3 ? (long)nx * ((ny + L->Gz - 1) / L->Gz) : 0};
+                                d3 ? (long)nx * ((ny + L->Gz - 1) / L->Gz) : 0, 0, 0};
   for (int p = 0; p < kNumPass; ++p) {
     if (items[p] > kItemMask) return false;
     L->n_items[p] = (int)items[p];
@@ -191,6 +191,7 @@ Resolved resolve_opts(const bhx_opts* o) {
   R.solver = o->solver;
   R.rows_opt = o->rows;
   R.occ_opt = o->occupancy;
+  R.transform = o->transform;
   if (o->rows > 0) R.sched.rows_cap = o->rows;
   if (o->occupancy > 0) R.sched.occ_r = R.sched.occ_c = o->occupancy;
   return R;
@@ -264,6 +265,21 @@ int PlanCache::get(int n, int bc) {
     const long double s = sinl(th / 2);
     rtab_.push_back(4 * s * s);
   }
+  if (n <= kDenseMax) {
+    // basis of the dense form (see AxisPlan): DCT-II cos(pi a / 2n) over
+    // a <= 2n (folded), Hartley cas(2 pi a / n), DST-I sin(pi a / (n + 1))
+    P.dense_P = bc == kNeumann ? 4 * n : (bc == kPeriodic ? n : 2 * (n + 1));
+    P.dense_fold = bc == kNeumann;
+    P.dense_len = P.dense_fold ? P.dense_P / 2 + 1 : P.dense_P;
+    P.off_dtab = (int)rtab_.size();
+    for (int a = 0; a < P.dense_len; ++a) {
+      long double v;
+      if (bc == kNeumann) v = cosl(kPi * a / (2.0L * n));
+      else if (bc == kPeriodic) v = cosl(2 * kPi * a / n) + sinl(2 * kPi * a / n);
+      else v = sinl(kPi * a / (n + 1.0L));
+      rtab_.push_back(v);
+    }
+  }
   const int idx = (int)plans_.size();
   plans_.push_back(P);
   index_[key] = idx;
@@ -284,18 +300,11 @@ hipError_t PlanCache::sync_device(hipStream_t st) {
   if ((e = grow(&rtab_d_, &cap_r_, rtab_.size())) != hipSuccess) return e;
   cap_r_ = rc;
   if ((e = grow(&rtab_f_, &cap_r_, rtab_.size())) != hipSuccess) return e;
-  std::vector<double2> cd(ctab_.size());
-  std::vector<float2> cf(ctab_.size());
-  for (size_t i = 0; i < ctab_.size(); ++i) {
-    cd[i] = make_double2((double)ctab_[i].real(), (double)ctab_[i].imag());
-    cf[i] = make_float2((float)ctab_[i].real(), (float)ctab_[i].imag());
-  }
-  std::vector<double> rd(rtab_.size());
-  std::vector<float> rf(rtab_.size());
-  for (size_t i = 0; i < rtab_.size(); ++i) {
-    rd[i] = (double)rtab_[i];
-    rf[i] = (float)rtab_[i];
-  }
+  std::vector<double2> cd;
+  std::vector<float2> cf;
+  std::vector<double> rd;
+  std::vector<float> rf;
+  tables_host(&cd, &cf, &rd, &rf);
   // stream-ordered: launches on st must not read tables still in transit
   const Upload u[5] = {{plans_d_, plans_.data(), plans_.size() * sizeof(AxisPlan)},
                        {ctab_d_, cd.data(), cd.size() * sizeof(double2)},
@@ -309,6 +318,22 @@ hipError_t PlanCache::sync_device(hipStream_t st) {
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
   dirty_ = false;
   return hipSuccess;
+}
+
+void PlanCache::tables_host(std::vector<double2>* cd, std::vector<float2>* cf,
+                            std::vector<double>* rd, std::vector<float>* rf) const {
+  cd->resize(ctab_.size());
+  cf->resize(ctab_.size());
+  for (size_t i = 0; i < ctab_.size(); ++i) {
+    (*cd)[i] = make_double2((double)ctab_[i].real(), (double)ctab_[i].imag());
+    (*cf)[i] = make_float2((float)ctab_[i].real(), (float)ctab_[i].imag());
+  }
+  rd->resize(rtab_.size());
+  rf->resize(rtab_.size());
+  for (size_t i = 0; i < rtab_.size(); ++i) {
+    (*rd)[i] = (double)rtab_[i];
+    (*rf)[i] = (float)rtab_[i];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -336,6 +361,7 @@ int validate(const double* phi, const double* F, int nx, int ny, double h, int b
   if (R.solver != 0 && R.solver != 1) return BHX_ERR_ARG;
   if (R.solver == 1 && (R.precision != BHX_PREC_FP64 || by == BHX_PERIODIC)) return BHX_ERR_ARG;
   if (R.rows_opt < 0 || R.rows_opt > 8 || R.occ_opt < 0 || R.occ_opt > 8) return BHX_ERR_ARG;
+  if (R.transform < 0 || R.transform > 2) return BHX_ERR_ARG;
   if (!length_supported(nx, bx, R.precision) || !length_supported(ny, by, R.precision))
     return BHX_ERR_ARG;
   if ((long long)nx * ny > (1LL << 31)) return BHX_ERR_ARG;
@@ -460,6 +486,45 @@ static hipError_t maybe_reduce(const Batch* B, const Grids& g, int which, int lp
   return g.reduce ? launch_reduce(B, g.count, which, lpar, st) : hipSuccess;
 }
 
+// The three transform passes over both families: the FFT kernels for the
+// instances in the kPassR / kPassC lists, the dense ones for the kPassRD /
+// kPassCD lists.  Given events, the first launch of a pass records e0 at its
+// start and the last e1 at its end.
+static hipError_t launch_rowpass_fwd(const Batch* B, const Resolved& R, const Grids& g,
+                                     int update, int lpar, hipStream_t st, hipEvent_t e0,
+                                     hipEvent_t e1) {
+  hipError_t e;
+  if (g.fft && (e = launch_rowfwd(B, R.precision, g.shape_r, update, g.stream_t, g.r, g.lds_r,
+                                  g.tw_r, lpar, st, e0, g.dense ? nullptr : e1)) != hipSuccess)
+    return e;
+  if (g.dense && (e = launch_rowfwd_dense(B, R.precision, update, g.rd, g.lds_rd, g.tab_rd, lpar,
+                                          st, g.fft ? nullptr : e0, e1)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+static hipError_t launch_colpass(const Batch* B, const Resolved& R, const Grids& g,
+                                 int count_iter, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  hipError_t e;
+  if (g.fft && (e = launch_columns(B, R, g, count_iter, st, e0, g.dense ? nullptr : e1)) !=
+                   hipSuccess)
+    return e;
+  if (g.dense && (e = launch_col_dense(B, R.precision, count_iter, g.cd, g.lds_cd, g.tab_cd, st,
+                                       g.fft ? nullptr : e0, e1)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+static hipError_t launch_rowpass_inv(const Batch* B, const Resolved& R, const Grids& g,
+                                     int lpar, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  hipError_t e;
+  if (g.fft && (e = launch_rowinv(B, R.precision, g.shape_r, g.r, g.lds_r, g.tw_r, lpar, st, e0,
+                                  g.dense ? nullptr : e1)) != hipSuccess)
+    return e;
+  if (g.dense && (e = launch_rowinv_dense(B, R.precision, g.rd, g.lds_rd, g.tab_rd, lpar, st,
+                                          g.fft ? nullptr : e0, e1)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+
 hipError_t launch_precond(const Batch* B, const Resolved& R, const Grids& g, hipStream_t st) {
   hipError_t e;
   // parity 1: the r.z partials it writes are the ones the first iteration
@@ -468,19 +533,15 @@ hipError_t launch_precond(const Batch* B, const Resolved& R, const Grids& g, hip
     if ((e = launch_identity(B, g.r, 1, st)) != hipSuccess) return e;
     return maybe_reduce(B, g, kRedRZ, 1, st);
   }
-  if ((e = launch_rowfwd(B, R.precision, g.shape_r, 0, g.stream_t, g.r, g.lds_r, g.tw_r, 1, st)) !=
-      hipSuccess)
-    return e;
-  if ((e = launch_columns(B, R, g, 0, st, nullptr, nullptr)) != hipSuccess) return e;
-  if ((e = launch_rowinv(B, R.precision, g.shape_r, g.r, g.lds_r, g.tw_r, 1, st)) != hipSuccess)
-    return e;
+  if ((e = launch_rowpass_fwd(B, R, g, 0, 1, st, nullptr, nullptr)) != hipSuccess) return e;
+  if ((e = launch_colpass(B, R, g, 0, st, nullptr, nullptr)) != hipSuccess) return e;
+  if ((e = launch_rowpass_inv(B, R, g, 1, st, nullptr, nullptr)) != hipSuccess) return e;
   return maybe_reduce(B, g, kRedRZ, 1, st);
 }
 
-namespace {
-
 // Event of pass p, iteration c, edge e (0 start, 1 end) in a Graph's array.
-inline hipEvent_t ev_at(const std::vector<hipEvent_t>* ev, int chunk, int p, int c, int e) {
+static inline hipEvent_t ev_at(const std::vector<hipEvent_t>* ev, int chunk, int p, int c,
+                                int e) {
   return (*ev)[((size_t)p * chunk + c) * 2 + e];
 }
 
@@ -500,12 +561,10 @@ hipError_t launch_iterations(const Batch* B, int n_inst, const Resolved& R, cons
     BHX_TRY(launch_stencil(B, g.dim, kModeIter, g.s, par, st, e0(0, c), e1(0, c)));
     BHX_TRY(maybe_reduce(B, g, kRedPQ, par, st));
     if (R.precond) {
-      BHX_TRY(launch_rowfwd(B, R.precision, g.shape_r, 1, g.stream_t, g.r, g.lds_r, g.tw_r, par, st,
-                            e0(1, c), e1(1, c)));
+      BHX_TRY(launch_rowpass_fwd(B, R, g, 1, par, st, e0(1, c), e1(1, c)));
       BHX_TRY(maybe_reduce(B, g, kRedRR, par, st));
-      BHX_TRY(launch_columns(B, R, g, 1, st, e0(2, c), e1(2, c)));
-      BHX_TRY(launch_rowinv(B, R.precision, g.shape_r, g.r, g.lds_r, g.tw_r, par, st, e0(3, c),
-                            e1(3, c)));
+      BHX_TRY(launch_colpass(B, R, g, 1, st, e0(2, c), e1(2, c)));
+      BHX_TRY(launch_rowpass_inv(B, R, g, par, st, e0(3, c), e1(3, c)));
     } else {
       // plain CG: update-only row pass, iteration count, z = r
       BHX_TRY(launch_rowfwd(B, R.precision, g.shape_r, 2, g.stream_t, g.r, g.lds_r, g.tw_r, par, st,
@@ -519,6 +578,8 @@ hipError_t launch_iterations(const Batch* B, int n_inst, const Resolved& R, cons
 #undef BHX_TRY
   return hipSuccess;
 }
+
+namespace {
 
 bool use_graphs() {
   const char* v = getenv("BHX_NO_GRAPH");
@@ -552,7 +613,9 @@ hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved&
         gr.lds_r == g.lds_r && gr.tw_r == g.tw_r && gr.lds_c == g.lds_c && gr.tw_c == g.tw_c &&
         gr.dim == g.dim && gr.gz == g.z && gr.lds_z == g.lds_z && gr.tw_z == g.tw_z &&
         gr.shape_r == g.shape_r && gr.shape_c == g.shape_c && gr.shape_z == g.shape_z &&
-        gr.stream_t == g.stream_t &&
+        gr.stream_t == g.stream_t && gr.fft == g.fft && gr.dense == g.dense &&
+        gr.rd == g.rd && gr.cd == g.cd && gr.lds_rd == g.lds_rd && gr.tab_rd == g.tab_rd &&
+        gr.lds_cd == g.lds_cd && gr.tab_cd == g.tab_cd &&
         gr.profile == R.profile && (gr.exec != nullptr) == graph) {
       *used = &gr;
       if (gr.exec) return hipGraphLaunch(gr.exec, st);
@@ -568,6 +631,8 @@ hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved&
   G.dim = g.dim; G.gz = g.z; G.lds_z = g.lds_z; G.tw_z = g.tw_z;
   G.shape_r = g.shape_r; G.shape_c = g.shape_c; G.shape_z = g.shape_z;
   G.stream_t = g.stream_t;
+  G.fft = g.fft; G.dense = g.dense; G.rd = g.rd; G.cd = g.cd;
+  G.lds_rd = g.lds_rd; G.tab_rd = g.tab_rd; G.lds_cd = g.lds_cd; G.tab_cd = g.tab_cd;
   hipError_t e;
   if (R.profile && (e = make_events(&G.ev, R.chunk)) != hipSuccess) {
     free_graph(G);
@@ -610,6 +675,8 @@ void set_last_error(const char* what, int line, hipError_t e) {
            hipGetErrorString(e));
 }
 
+void set_last_message(const char* what) { snprintf(g_last_error, sizeof(g_last_error), "%s", what); }
+
 const char* last_error() { return g_last_error; }
 
 #define BHX_CHECK(x)                                                      \
@@ -621,57 +688,75 @@ const char* last_error() { return g_last_error; }
     }                                                                     \
   } while (0)
 
-int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
-                  hipStream_t st, Grids* gout) {
-  BHX_CHECK(hipSetDevice(hd->device));
-  // earlier launches on st may still read the descriptors, tables and
-  // staging buffer replaced below
-  BHX_CHECK(hipStreamSynchronize(st));
-  // plans and layouts; a batch holds instances of one dimension
+bool dense_eligible(const AxisPlan& X, const AxisPlan& Y) {
+  return X.dense_P > 0 && Y.dense_P > 0;
+}
+
+// Built-in choice of the dense form for an eligible instance (transform 0):
+// none.  Measured on one MI355X (FP64, 64^2 to 512^2, single instances and
+// the 256-instance batch), the FFT family was faster at every size, also
+// where Bluestein doubles its length: the dense products cost 2 n flops per
+// node and transform against the FFT's O(log n), and run at about a fifth of
+// the FP64 matrix rate.  The autotuner still times the dense form.
+static bool dense_policy(const AxisPlan&, const AxisPlan&) { return false; }
+
+bool use_dense(const Resolved& R, const AxisPlan& X, const AxisPlan& Y) {
+  if (!R.precond || !dense_eligible(X, Y)) return false;
+  const int t = R.sched.transform >= 0 ? R.sched.transform : R.transform;
+  if (t == 2) return true;
+  if (t == 1) return false;
+  return dense_policy(X, Y);
+}
+
+int plan_layouts(PlanCache& plans, int n, const InstSpec* specs, const Resolved& R,
+                 BatchDesc* D) {
   const int dim = specs[0].dim;
-  std::vector<int> px(n), py(n), pz(n, 0);
-  std::vector<Layout> lay(n);
+  D->dim = dim;
+  D->px.assign(n, 0);
+  D->py.assign(n, 0);
+  D->pz.assign(n, 0);
+  D->lay.assign(n, Layout());
+  D->dense.assign(n, 0);
   for (int i = 0; i < n; ++i) {
     const InstSpec& S = specs[i];
     if (S.dim != dim) return BHX_ERR_ARG;
-    px[i] = hd->plans.get(S.nx, S.bcx);
-    py[i] = hd->plans.get(S.ny, S.bcy);
-    if (dim == 3) pz[i] = hd->plans.get(S.nz, S.bcz);
-    const int mz = dim == 3 ? hd->plans.plan(pz[i]).m : 0;
-    if (!make_layout(S.nx, S.ny, dim == 3 ? S.nz : 1, R.precision, hd->plans.plan(px[i]).m,
-                     hd->plans.plan(py[i]).m, mz, R.sched.rows_cap, &lay[i]))
+    D->px[i] = plans.get(S.nx, S.bcx);
+    D->py[i] = plans.get(S.ny, S.bcy);
+    if (dim == 3) D->pz[i] = plans.get(S.nz, S.bcz);
+    const int mz = dim == 3 ? plans.plan(D->pz[i]).m : 0;
+    D->dense[i] = dim == 2 && use_dense(R, plans.plan(D->px[i]), plans.plan(D->py[i]));
+    if (!make_layout(S.nx, S.ny, dim == 3 ? S.nz : 1, R.precision, plans.plan(D->px[i]).m,
+                     plans.plan(D->py[i]).m, mz, R.sched.rows_cap, &D->lay[i], D->dense[i]))
       return BHX_ERR_ARG;
   }
-  BHX_CHECK(hd->plans.sync_device(st));
-  const size_t ctl_bytes = align_up((size_t)n * sizeof(Ctl));
-  size_t total = ctl_bytes;
+  return BHX_OK;
+}
+
+size_t ctl_region_bytes(int n) { return align_up((size_t)n * sizeof(Ctl)); }
+
+void describe_batch(const PlanCache& plans, int n, const InstSpec* specs, const Resolved& R,
+                    char* ws, Ctl* ctl_d, BatchDesc* D) {
+  const int dim = D->dim;
+  D->inst.assign(n, Inst());
+  D->ctl.assign(n, Ctl());
+  for (int p = 0; p < kNumPass; ++p) D->items[p].clear();
+  // workspace: the control blocks, then one region per instance
+  size_t total = ctl_region_bytes(n);
   std::vector<size_t> base(n);
   for (int i = 0; i < n; ++i) {
     base[i] = total;
-    total += lay[i].bytes;
+    total += D->lay[i].bytes;
   }
-  if (total > hd->ws_cap) {
-    if (hd->ws) BHX_CHECK(hipFree(hd->ws));
-    hd->ws = nullptr;
-    hd->ws_cap = 0;
-    BHX_CHECK(hipMalloc(&hd->ws, total));
-    hd->ws_cap = total;
-  }
-  char* ws = (char*)hd->ws;
-  Ctl* ctl_d = (Ctl*)ws;
-  // host descriptors
-  std::vector<Inst> inst(n);
-  std::vector<int> items[kNumPass];
-  std::vector<Ctl> ctl(n);
+  D->ws_bytes = total;
   for (int i = 0; i < n; ++i) {
     const InstSpec& S = specs[i];
-    const Layout& L = lay[i];
-    Inst& I = inst[i];
+    const Layout& L = D->lay[i];
+    Inst& I = D->inst[i];
     std::memset(&I, 0, sizeof(I));
     const int nz = dim == 3 ? S.nz : 1;
     I.nx = S.nx; I.ny = S.ny; I.nz = nz; I.nrows = S.ny * nz;
     I.bcx = S.bcx; I.bcy = S.bcy; I.bcz = dim == 3 ? S.bcz : 0;
-    I.planx = px[i]; I.plany = py[i]; I.planz = pz[i];
+    I.planx = D->px[i]; I.plany = D->py[i]; I.planz = D->pz[i];
     I.G = L.G; I.Gc = L.Gc; I.Gz = L.Gz;
     I.tiles_x = L.tiles_x; I.tiles_y = L.tiles_y; I.tiles_z = L.tiles_z;
     for (int p = 0; p < kNumPass; ++p) I.n_items[p] = L.n_items[p];
@@ -679,29 +764,167 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
     I.flexible = R.flexible;
     I.warm = R.warm;
     I.reduce = L.n_items[kPassS] + 3 * L.n_items[kPassR] > kReduceMin;
+    I.dense = D->dense[i];
     I.phi = (decltype(I.phi))S.phi;
     I.F = (decltype(I.F))S.F;
     const size_t Np = vec_stride(S.nx, S.ny * nz);
-    char* b = ws + base[i];
-    I.mask = (decltype(I.mask))(b + L.off_mask);
-    double* v = (double*)(b + L.off_vec);
-    I.r = (decltype(I.r))v;
-    I.p[0] = (decltype(I.r))(v + Np);
-    I.p[1] = (decltype(I.r))(v + 2 * Np);
-    I.q = (decltype(I.r))(v + 3 * Np);
-    I.z = (decltype(I.r))(v + 4 * Np);
-    I.t = (decltype(I.t))(b + L.off_t);
-    I.part = (decltype(I.part))(b + L.off_part);
-    I.ctl = (decltype(I.ctl))(ctl_d + i);
+    char* b = ws ? ws + base[i] : nullptr;
+    if (b) {
+      I.mask = (decltype(I.mask))(b + L.off_mask);
+      double* v = (double*)(b + L.off_vec);
+      I.r = (decltype(I.r))v;
+      I.p[0] = (decltype(I.r))(v + Np);
+      I.p[1] = (decltype(I.r))(v + 2 * Np);
+      I.q = (decltype(I.r))(v + 3 * Np);
+      I.z = (decltype(I.r))(v + 4 * Np);
+      I.t = (decltype(I.t))(b + L.off_t);
+      I.part = (decltype(I.part))(b + L.off_part);
+      I.ctl = (decltype(I.ctl))(ctl_d + i);
+    }
     for (int p = 0; p < kNumPass; ++p)
-      for (int k = 0; k < L.n_items[p]; ++k) items[p].push_back((i << kItemShift) | k);
-    Ctl& C = ctl[i];
+      for (int k = 0; k < list_items(I, p); ++k) D->items[p].push_back((i << kItemShift) | k);
+    Ctl& C = D->ctl[i];
     std::memset(&C, 0, sizeof(C));
     C.tol2 = S.tol * S.tol;
     C.tol_inner2 = R.tol_inner * R.tol_inner;
     C.accurate = R.accurate;
     C.max_restarts = R.accurate ? 12 : 8;
   }
+}
+
+void fill_header(Batch* Bh, const BatchDesc& D, const Inst* inst_d, int* const items_d[kNumPass],
+                 const AxisPlan* plans_d, const void* const ctab[2], const void* const rtab[2]) {
+  std::memset(Bh, 0, sizeof(*Bh));
+  Bh->count = (int)D.inst.size();
+  for (int p = 0; p < kNumPass; ++p) {
+    Bh->n_items[p] = (int)D.items[p].size();
+    Bh->items[p] = (std::remove_reference_t<decltype(Bh->items[p])>)items_d[p];
+  }
+  Bh->inst = (decltype(Bh->inst))inst_d;
+  Bh->plans = (decltype(Bh->plans))plans_d;
+  for (int p = 0; p < 2; ++p) {
+    Bh->ctab[p] = (std::remove_reference_t<decltype(Bh->ctab[p])>)ctab[p];
+    Bh->rtab[p] = (std::remove_reference_t<decltype(Bh->rtab[p])>)rtab[p];
+  }
+}
+
+void dense_grids(int prec, int nx_max, int ny_max, int n_rd, int n_cd, int num_cu, int occ,
+                 Grids* g) {
+  g->rd = std::max(1, std::min(n_rd, num_cu * occ));
+  g->cd = std::max(1, std::min(n_cd, num_cu * occ));
+  g->lds_rd = dense_lds_bytes(kPassRD, prec, nx_max);
+  g->tab_rd = dense_tab_off(nx_max);
+  g->lds_cd = dense_lds_bytes(kPassCD, prec, ny_max);
+  g->tab_cd = dense_tab_off(ny_max);
+}
+
+int batch_grids(const PlanCache& plans, const BatchDesc& D, const Resolved& R, int num_cu,
+                Grids* gout) {
+  const int n = (int)D.inst.size();
+  const int dim = D.dim;
+  Grids g;
+  g.dim = dim;
+  g.count = n;
+  for (int i = 0; i < n; ++i) g.reduce |= D.inst[i].reduce;
+  const int ni[kNumPass] = {(int)D.items[kPassS].size(), (int)D.items[kPassR].size(),
+                            (int)D.items[kPassC].size(), (int)D.items[kPassZ].size()};
+  g.s = std::max(1, std::min(ni[kPassS], num_cu * R.sched.occ_s));
+  g.r = std::max(1, std::min(ni[kPassR], num_cu * R.sched.occ_r));
+  g.c = std::max(1, std::min(ni[kPassC], num_cu * R.sched.occ_c));
+  g.z = dim == 3 ? std::max(1, std::min(ni[kPassZ], num_cu * R.sched.occ_c)) : 0;
+  {
+    // dynamic LDS: packed rows followed by the staged plan tables
+    const int csize = R.precision == 0 ? 16 : 8;
+    int buf_r = 0, tab_r = 0, buf_c = 0, tab_c = 0, buf_z = 0, tab_z = 0;
+    for (int i = 0; i < n; ++i) {
+      if (D.dense[i]) continue;                 // no FFT pass works on it
+      const AxisPlan& PX = plans.plan(D.px[i]);
+      const AxisPlan& PY = plans.plan(D.py[i]);
+      buf_r = std::max(buf_r, (D.lay[i].G / 2) * row_slots(PX.m));
+      tab_r = std::max(tab_r, table_slots(PX.n, PX.m, PX.bc, false));
+      buf_c = std::max(buf_c, (D.lay[i].Gc / 2) * row_slots(PY.m));
+      tab_c = std::max(tab_c, table_slots(PY.n, PY.m, PY.bc, dim == 2));
+      if (dim == 3) {
+        const AxisPlan& PZ = plans.plan(D.pz[i]);
+        buf_z = std::max(buf_z, (D.lay[i].Gz / 2) * row_slots(PZ.m));
+        tab_z = std::max(tab_z, table_slots(PZ.n, PZ.m, PZ.bc, true));
+      }
+    }
+    g.tw_r = buf_r;
+    g.lds_r = (buf_r + tab_r) * csize;
+    g.tw_c = buf_c;
+    g.lds_c = (buf_c + tab_c) * csize;
+    g.tw_z = buf_z;
+    g.lds_z = (buf_z + tab_z) * csize;
+    if (g.lds_r > kLdsDynMax || g.lds_c > kLdsDynMax || g.lds_z > kLdsDynMax) return BHX_ERR_ARG;
+  }
+  int f0 = -1;                                  // first FFT-family instance
+  for (int i = 0; i < n && f0 < 0; ++i)
+    if (!D.dense[i]) f0 = i;
+  g.fft = f0 >= 0;
+  if (f0 >= 0) {
+    // compile-time-shape kernels when every FFT-family instance shares the
+    // axis plan and the line grouping of the first one
+    auto key = [&](int pass, const AxisPlan& P, int group) {
+      return shape_key(pass, R.precision, P.n, P.m, P.logm, P.bluestein, P.bc, group);
+    };
+    g.shape_r = key(kShapeRow, plans.plan(D.px[f0]), D.lay[f0].G);
+    g.shape_c = key(dim == 3 ? kShapeColY : kShapeCol2D, plans.plan(D.py[f0]), D.lay[f0].Gc);
+    g.shape_z = dim == 3 ? key(kShapeColZ, plans.plan(D.pz[f0]), D.lay[f0].Gz) : 0;
+    for (int i = f0 + 1; i < n; ++i) {
+      if (D.dense[i]) continue;
+      if (D.px[i] != D.px[f0] || D.lay[i].G != D.lay[f0].G) g.shape_r = 0;
+      if (D.pz[i] != D.pz[f0] || D.lay[i].Gz != D.lay[f0].Gz) g.shape_z = 0;
+      if (D.py[i] != D.py[f0] || D.lay[i].Gc != D.lay[f0].Gc) g.shape_c = 0;
+    }
+  }
+  {
+    int nxm = 0, nym = 0;
+    for (int i = 0; i < n; ++i)
+      if (D.dense[i]) {
+        nxm = std::max(nxm, plans.plan(D.px[i]).n);
+        nym = std::max(nym, plans.plan(D.py[i]).n);
+      }
+    g.dense = nxm > 0;
+    if (g.dense)
+      dense_grids(R.precision, nxm, nym, (int)D.items[kPassRD].size(),
+                  (int)D.items[kPassCD].size(), num_cu, R.sched.occ_d, &g);
+  }
+  {
+    // non-temporal stores of t in the row-forward pass while the launch's t
+    // arrays are small (1024^2 FP64: 12.5 -> 11.8 us per launch; 2048^2:
+    // 46 -> 91 us, so never for large t)
+    size_t tb = 0;
+    for (int i = 0; i < n; ++i) tb += D.lay[i].off_part - D.lay[i].off_t;
+    g.stream_t = tb <= kStreamTMax;
+  }
+  *gout = g;
+  return BHX_OK;
+}
+
+int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
+                  hipStream_t st, Grids* gout) {
+  BHX_CHECK(hipSetDevice(hd->device));
+  // earlier launches on st may still read the descriptors, tables and
+  // staging buffer replaced below
+  BHX_CHECK(hipStreamSynchronize(st));
+  BatchDesc D;
+  {
+    const int rc = plan_layouts(hd->plans, n, specs, R, &D);
+    if (rc != BHX_OK) return rc;
+  }
+  BHX_CHECK(hd->plans.sync_device(st));
+  describe_batch(hd->plans, n, specs, R, nullptr, nullptr, &D);   // sizes only
+  if (D.ws_bytes > hd->ws_cap) {
+    if (hd->ws) BHX_CHECK(hipFree(hd->ws));
+    hd->ws = nullptr;
+    hd->ws_cap = 0;
+    BHX_CHECK(hipMalloc(&hd->ws, D.ws_bytes));
+    hd->ws_cap = D.ws_bytes;
+  }
+  char* ws = (char*)hd->ws;
+  Ctl* ctl_d = (Ctl*)ws;
+  describe_batch(hd->plans, n, specs, R, ws, ctl_d, &D);
   // device descriptors
   if (n > hd->inst_cap) {
     if (hd->inst_d) BHX_CHECK(hipFree(hd->inst_d));
@@ -710,7 +933,7 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
     hd->inst_cap = std::max(n, 2 * hd->inst_cap);
   }
   for (int p = 0; p < kNumPass; ++p) {
-    const int need = std::max<int>(1, (int)items[p].size());
+    const int need = std::max<int>(1, (int)D.items[p].size());
     if (need > hd->items_cap[p]) {
       if (hd->items_d[p]) BHX_CHECK(hipFree(hd->items_d[p]));
       hd->items_d[p] = nullptr;
@@ -732,105 +955,32 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
     hd->ctl_h_cap = std::max(n, 2 * hd->ctl_h_cap);
   }
   Batch Bh;
-  std::memset(&Bh, 0, sizeof(Bh));
-  Bh.count = n;
+  const void* ctab[2] = {hd->plans.ctab(0), hd->plans.ctab(1)};
+  const void* rtab[2] = {hd->plans.rtab(0), hd->plans.rtab(1)};
+  fill_header(&Bh, D, hd->inst_d, hd->items_d, hd->plans.plans_d(), ctab, rtab);
   hd->batch_count = n;
-  for (int p = 0; p < kNumPass; ++p) {
-    Bh.n_items[p] = (int)items[p].size();
-    Bh.items[p] = (std::remove_reference_t<decltype(Bh.items[p])>)hd->items_d[p];
-  }
-  Bh.inst = (decltype(Bh.inst))hd->inst_d;
-  Bh.plans = (decltype(Bh.plans))hd->plans.plans_d();
-  for (int p = 0; p < 2; ++p) {
-    Bh.ctab[p] = (std::remove_reference_t<decltype(Bh.ctab[p])>)hd->plans.ctab(p);
-    Bh.rtab[p] = (std::remove_reference_t<decltype(Bh.rtab[p])>)hd->plans.rtab(p);
-  }
   // stream-ordered: the setup launches that follow on st read all of these
   {
-    Upload u[3 + kNumPass] = {{hd->inst_d, inst.data(), n * sizeof(Inst)},
-                              {ctl_d, ctl.data(), n * sizeof(Ctl)},
+    Upload u[3 + kNumPass] = {{hd->inst_d, D.inst.data(), n * sizeof(Inst)},
+                              {ctl_d, D.ctl.data(), n * sizeof(Ctl)},
                               {hd->batch_d, &Bh, sizeof(Batch)}};
     for (int p = 0; p < kNumPass; ++p)
-      u[3 + p] = {hd->items_d[p], items[p].data(), items[p].size() * sizeof(int)};
+      u[3 + p] = {hd->items_d[p], D.items[p].data(), D.items[p].size() * sizeof(int)};
     BHX_CHECK(upload_ordered(hd, st, u, 3 + kNumPass));
   }
-
-  Grids g;
-  g.dim = dim;
-  g.count = n;
-  for (int i = 0; i < n; ++i) g.reduce |= inst[i].reduce;
-  g.s = std::max(1, std::min(Bh.n_items[kPassS], hd->num_cu * R.sched.occ_s));
-  g.r = std::max(1, std::min(Bh.n_items[kPassR], hd->num_cu * R.sched.occ_r));
-  g.c = std::max(1, std::min(Bh.n_items[kPassC], hd->num_cu * R.sched.occ_c));
-  g.z = dim == 3 ? std::max(1, std::min(Bh.n_items[kPassZ], hd->num_cu * R.sched.occ_c)) : 0;
-  {
-    // dynamic LDS: packed rows followed by the staged plan tables
-    const int csize = R.precision == 0 ? 16 : 8;
-    int buf_r = 0, tab_r = 0, buf_c = 0, tab_c = 0, buf_z = 0, tab_z = 0;
-    for (int i = 0; i < n; ++i) {
-      const AxisPlan& PX = hd->plans.plan(px[i]);
-      const AxisPlan& PY = hd->plans.plan(py[i]);
-      buf_r = std::max(buf_r, (lay[i].G / 2) * row_slots(PX.m));
-      tab_r = std::max(tab_r, table_slots(PX.n, PX.m, PX.bc, false));
-      buf_c = std::max(buf_c, (lay[i].Gc / 2) * row_slots(PY.m));
-      tab_c = std::max(tab_c, table_slots(PY.n, PY.m, PY.bc, dim == 2));
-      if (dim == 3) {
-        const AxisPlan& PZ = hd->plans.plan(pz[i]);
-        buf_z = std::max(buf_z, (lay[i].Gz / 2) * row_slots(PZ.m));
-        tab_z = std::max(tab_z, table_slots(PZ.n, PZ.m, PZ.bc, true));
-      }
-    }
-    g.tw_r = buf_r;
-    g.lds_r = (buf_r + tab_r) * csize;
-    g.tw_c = buf_c;
-    g.lds_c = (buf_c + tab_c) * csize;
-    g.tw_z = buf_z;
-    g.lds_z = (buf_z + tab_z) * csize;
-    if (g.lds_r > kLdsDynMax || g.lds_c > kLdsDynMax || g.lds_z > kLdsDynMax) return BHX_ERR_ARG;
-  }
-  {
-    // compile-time-shape kernels when every instance shares the axis plan and
-    // the line grouping of instance 0
-    auto key = [&](int pass, const AxisPlan& P, int group) {
-      return shape_key(pass, R.precision, P.n, P.m, P.logm, P.bluestein, P.bc, group);
-    };
-    g.shape_r = key(kShapeRow, hd->plans.plan(px[0]), lay[0].G);
-    g.shape_c = key(dim == 3 ? kShapeColY : kShapeCol2D, hd->plans.plan(py[0]), lay[0].Gc);
-    g.shape_z = dim == 3 ? key(kShapeColZ, hd->plans.plan(pz[0]), lay[0].Gz) : 0;
-    for (int i = 1; i < n; ++i) {
-      if (px[i] != px[0] || lay[i].G != lay[0].G) g.shape_r = 0;
-      if (pz[i] != pz[0] || lay[i].Gz != lay[0].Gz) g.shape_z = 0;
-      if (py[i] != py[0] || lay[i].Gc != lay[0].Gc) g.shape_c = 0;
-    }
-  }
-  {
-    // non-temporal stores of t in the row-forward pass while the launch's t
-    // arrays are small (1024^2 FP64: 12.5 -> 11.8 us per launch; 2048^2:
-    // 46 -> 91 us, so never for large t)
-    size_t tb = 0;
-    for (int i = 0; i < n; ++i) tb += lay[i].off_part - lay[i].off_t;
-    g.stream_t = tb <= kStreamTMax;
-  }
-  *gout = g;
-  return BHX_OK;
+  return batch_grids(hd->plans, D, R, hd->num_cu, gout);
 }
 
-static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
-                            hipStream_t stream, bhx_stats* stats) {
-  const auto t0 = std::chrono::steady_clock::now();
-  hipStream_t st = stream ? stream : hd->own_stream;
-  Grids g;
-  {
-    const int s = prepare_batch(hd, n, specs, R, st, &g);
-    if (s != BHX_OK) return s;
-  }
-  Ctl* ctl_d = (Ctl*)hd->ws;
+int drive_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R, const Grids& g,
+                hipStream_t st, const DriveCtx& X, bhx_stats* stats,
+                std::chrono::steady_clock::time_point t0) {
+  Ctl* ctl_d = X.ctl_d;
   // setup: mask, right-hand side, counts
-  BHX_CHECK(launch_setup(hd->batch_d, g.dim, g.s, st));
-  BHX_CHECK(launch_setup_rows(hd->batch_d, g.r, st));
-  BHX_CHECK(launch_stencil(hd->batch_d, g.dim, kModeRhs, g.s, 0, st));
-  BHX_CHECK(launch_finalize(hd->batch_d, n, kFinSetupH, st));
-  Ctl* ch = hd->ctl_h;
+  BHX_CHECK(launch_setup(X.B, g.dim, g.s, st));
+  BHX_CHECK(launch_setup_rows(X.B, std::max(g.r, g.rd), st));
+  BHX_CHECK(launch_stencil(X.B, g.dim, kModeRhs, g.s, 0, st));
+  BHX_CHECK(launch_finalize(X.B, n, kFinSetupH, st));
+  Ctl* ch = X.ch;
   BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
   BHX_CHECK(hipStreamSynchronize(st));
   std::vector<int> status(n, BHX_OK), preset(n, 0), zero_flag(n, 0);
@@ -862,9 +1012,15 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
   if (active < n) {
     BHX_CHECK(hipMemcpyAsync(ctl_d, ch, n * sizeof(Ctl), hipMemcpyHostToDevice, st));
     if (any_zero) {
-      const Upload u{hd->flag_d, zero_flag.data(), n * sizeof(int)};
-      BHX_CHECK(upload_ordered(hd, st, &u, 1));
-      BHX_CHECK(launch_zero_unknown(hd->batch_d, g.dim, hd->flag_d, g.s, st));
+      if (X.graphs) {
+        const Upload u{X.flag_d, zero_flag.data(), n * sizeof(int)};
+        BHX_CHECK(upload_ordered(hd, st, &u, 1));
+      } else {
+        // from pageable memory; zero_flag outlives the synchronisation below
+        BHX_CHECK(hipMemcpyAsync(X.flag_d, zero_flag.data(), n * sizeof(int),
+                                 hipMemcpyHostToDevice, st));
+      }
+      BHX_CHECK(launch_zero_unknown(X.B, g.dim, X.flag_d, g.s, st));
     }
     BHX_CHECK(hipStreamSynchronize(st));
   }
@@ -873,8 +1029,8 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
   // here with F untouched
   std::vector<int> warm_done(n, 0);
   if (R.warm && active > 0) {
-    BHX_CHECK(launch_stencil(hd->batch_d, g.dim, kModeWarm, g.s, 0, st));
-    BHX_CHECK(launch_finalize(hd->batch_d, n, kFinWarmH, st));
+    BHX_CHECK(launch_stencil(X.B, g.dim, kModeWarm, g.s, 0, st));
+    BHX_CHECK(launch_finalize(X.B, n, kFinWarmH, st));
     BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
     BHX_CHECK(hipStreamSynchronize(st));
     int ended = 0;
@@ -898,11 +1054,12 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
   int pass_cnt[4] = {0, 0, 0, 0};
   std::vector<int> iter_before(n);
   if (active > 0) {
-    BHX_CHECK(launch_precond(hd->batch_d, R, g, st));
+    BHX_CHECK(launch_precond(X.B, R, g, st));
     for (;;) {
       for (int i = 0; i < n; ++i) iter_before[i] = ch[i].iter;
       Graph* used = nullptr;
-      BHX_CHECK(run_chunk(hd, hd->batch_d, n, R, g, st, &used));
+      if (X.graphs) BHX_CHECK(run_chunk(hd, X.B, n, R, g, st, &used));
+      else BHX_CHECK(launch_iterations(X.B, n, R, g, R.chunk, st, nullptr));
       BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
       BHX_CHECK(hipStreamSynchronize(st));
       if (R.profile && used && !used->ev.empty()) {
@@ -924,16 +1081,16 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
         if (ch[i].done == kRunning) all_done = false;
       if (!all_done) continue;
       // true residual of finished instances; restart those that miss the target
-      BHX_CHECK(launch_resid(hd->batch_d, g.dim, g.s, st));
-      BHX_CHECK(launch_finalize(hd->batch_d, n, kFinResidH, st));
-      BHX_CHECK(launch_restart(hd->batch_d, n, st));
+      BHX_CHECK(launch_resid(X.B, g.dim, g.s, st));
+      BHX_CHECK(launch_finalize(X.B, n, kFinResidH, st));
+      BHX_CHECK(launch_restart(X.B, n, st));
       BHX_CHECK(hipMemcpyAsync(ch, ctl_d, n * sizeof(Ctl), hipMemcpyDeviceToHost, st));
       BHX_CHECK(hipStreamSynchronize(st));
       bool restarted = false;
       for (int i = 0; i < n; ++i)
         if (ch[i].done == kRunning) restarted = true;
       if (!restarted) break;
-      BHX_CHECK(launch_precond(hd->batch_d, R, g, st));
+      BHX_CHECK(launch_precond(X.B, R, g, st));
     }
   }
   const double secs =
@@ -972,6 +1129,24 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
   return ret;
 }
 
+static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
+                            hipStream_t stream, bhx_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = stream ? stream : hd->own_stream;
+  Grids g;
+  {
+    const int s = prepare_batch(hd, n, specs, R, st, &g);
+    if (s != BHX_OK) return s;
+  }
+  DriveCtx X;
+  X.B = hd->batch_d;
+  X.ctl_d = (Ctl*)hd->ws;
+  X.ch = hd->ctl_h;
+  X.flag_d = hd->flag_d;
+  X.graphs = true;
+  return drive_batch(hd, n, specs, R, g, st, X, stats, t0);
+}
+
 int warm_start_outcome(const Ctl& c) {
   if (!std::isfinite(c.rr)) return 2;
   return c.rr <= c.accept ? 1 : 0;
@@ -981,8 +1156,10 @@ int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, dou
                 int ny, int nz, int bcx, int bcy, int bcz, int precision, hipStream_t stream) {
   bhx_opts o;
   bhx_default_opts(&o);
-  o.precision = precision;
+  o.precision = precision & 15;          // bits 4-7: the transform choice (bhx_opts.transform)
+  o.transform = (precision >> 4) & 15;
   const Resolved R = resolve_opts(&o);
+  if (R.transform > 2) return BHX_ERR_ARG;
   hipStream_t st = stream ? stream : hd->own_stream;
   InstSpec s{phi, out, nx, ny, bcx, bcy, 0.5};
   const bool d3 = nz > 1;
@@ -995,9 +1172,12 @@ int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, dou
   int rc = prepare_batch(hd, 1, &s, R, st, &g);
   if (rc != BHX_OK) return rc;
   Layout L;
-  make_layout(nx, ny, nz, precision, core_length(fft_length(nx, bcx)),
-              core_length(fft_length(ny, bcy)), d3 ? core_length(fft_length(nz, bcz)) : 0,
-              R.sched.rows_cap, &L);
+  {
+    const AxisPlan PX = hd->plans.plan(hd->plans.get(nx, bcx));
+    const AxisPlan PY = hd->plans.plan(hd->plans.get(ny, bcy));
+    make_layout(nx, ny, nz, R.precision, PX.m, PY.m, d3 ? core_length(fft_length(nz, bcz)) : 0,
+                R.sched.rows_cap, &L, !d3 && use_dense(R, PX, PY));
+  }
   const size_t N = (size_t)nx * ny * nz;
   const size_t Np = vec_stride(nx, ny * nz);
   double* v = (double*)((char*)hd->ws + align_up(sizeof(Ctl)) + L.off_vec);
@@ -1005,7 +1185,7 @@ int debug_apply(bhx_handle* hd, int op, const double* phi, const double* in, dou
   double* q = v + 3 * Np;
   double* z = v + 4 * Np;
   BHX_CHECK(launch_setup(hd->batch_d, g.dim, g.s, st));
-  BHX_CHECK(launch_setup_rows(hd->batch_d, g.r, st));
+  BHX_CHECK(launch_setup_rows(hd->batch_d, std::max(g.r, g.rd), st));
   if (op == 0) {
     BHX_CHECK(hipMemcpyAsync(z, in, N * sizeof(double), hipMemcpyDeviceToDevice, st));
     BHX_CHECK(launch_stencil(hd->batch_d, g.dim, kModeApply, g.s, 0, st));
@@ -1027,7 +1207,7 @@ static unsigned long long batch_signature(int n, const InstSpec* specs, const Re
     h *= 1099511628211ULL;
   };
   mix((unsigned long long)n);
-  mix((unsigned long long)(R.precision * 4 + R.precond * 2 + R.flexible));
+  mix((unsigned long long)(R.precision * 4 + R.precond * 2 + R.flexible + 16 * R.transform));
   for (int i = 0; i < n; ++i) {
     mix((unsigned long long)specs[i].nx);
     mix((unsigned long long)specs[i].ny);
@@ -1046,6 +1226,9 @@ static int autotune_schedule(bhx_handle* hd, int n, const InstSpec* specs, const
                              hipStream_t stream, Schedule* best) {
   const int trial_iters = 24;
   std::vector<Schedule> cands;
+  // the FFT family under every grouping and occupancy (the option's
+  // transform choice when it fixes one)
+  const int t_opt = R.transform;
   for (int rows : {1, 2, 4})
     for (int occ : {1, 2, 4}) {
       Schedule s;
@@ -1054,8 +1237,26 @@ static int autotune_schedule(bhx_handle* hd, int n, const InstSpec* specs, const
       s.occ_c = occ;
       s.occ_s = 8;
       s.chunk = trial_iters;
+      s.transform = t_opt == 0 ? 1 : t_opt;
       cands.push_back(s);
     }
+  // with the transform left to the library: the built-in choice and dense
+  // wherever the axes allow, at one or two dense blocks per CU
+  bool eligible = false;
+  for (int i = 0; i < n; ++i)
+    eligible |= specs[i].dim == 2 && specs[i].nx <= kDenseMax && specs[i].ny <= kDenseMax;
+  if (t_opt == 0 && eligible && R.precond)
+    for (int t : {0, 2})
+      for (int occ_d : {1, 2}) {
+        Schedule s;
+        s.rows_cap = 2;
+        s.occ_r = s.occ_c = 2;
+        s.occ_s = 8;
+        s.chunk = trial_iters;
+        s.transform = t;
+        s.occ_d = occ_d;
+        cands.push_back(s);
+      }
   double best_t = 1e30;
   std::vector<bhx_stats> st(n);
   for (const Schedule& s : cands) {

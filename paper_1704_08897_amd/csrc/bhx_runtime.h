@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <complex>
 #include <map>
 #include <mutex>
@@ -28,6 +29,11 @@ class PlanCache {
   const void* ctab(int p) const { return p == 0 ? (const void*)ctab_d_ : (const void*)ctab_f_; }
   const void* rtab(int p) const { return p == 0 ? (const void*)rtab_d_ : (const void*)rtab_f_; }
   void release();
+  // Host copies of every plan and table, rounded as the device copies are
+  // (for callers that place them in memory of their own).
+  const std::vector<AxisPlan>& plans_host() const { return plans_; }
+  void tables_host(std::vector<double2>* cd, std::vector<float2>* cf, std::vector<double>* rd,
+                   std::vector<float>* rf) const;
 
  private:
   std::vector<AxisPlan> plans_;
@@ -62,10 +68,13 @@ struct Layout {
 
 // Choose row-group sizes and item counts; false if the size is unsupported.
 // mz = 0: two dimensions (nz = 1); otherwise the z core length.
+// dense: the instance's preconditioner runs the dense-transform passes
+// (row and column groups of kDenseG lines).
 bool make_layout(int nx, int ny, int nz, int prec, int mx, int my, int mz, int rows_cap,
-                 Layout* L);
-inline bool make_layout(int nx, int ny, int prec, int mx, int my, int rows_cap, Layout* L) {
-  return make_layout(nx, ny, 1, prec, mx, my, 0, rows_cap, L);
+                 Layout* L, bool dense = false);
+inline bool make_layout(int nx, int ny, int prec, int mx, int my, int rows_cap, Layout* L,
+                        bool dense = false) {
+  return make_layout(nx, ny, 1, prec, mx, my, 0, rows_cap, L, dense);
 }
 // Core FFT length of a transform of length n (power of two, or Bluestein).
 int core_length(int n);
@@ -80,12 +89,15 @@ struct Schedule {
   int rows_cap = 0;
   int occ_s = 8, occ_r = 2, occ_c = 2;
   int chunk = 0;             // 0 = option's chunk
+  int transform = -1;        // -1: the option's; else 0 policy, 1 FFT, 2 dense where possible
+  int occ_d = 2;             // persistent blocks per CU of the dense-transform passes
 };
 
 struct Resolved {           // options after defaults
   int precision, maxit_user, precond, accurate, flexible, chunk, profile, autotune, warm;
   int solver;               // 0 PCG, 1 banded Cholesky (two dimensions)
   int rows_opt = 0, occ_opt = 0;
+  int transform = 0;        // 0 built-in choice, 1 FFT only, 2 dense where the axes allow
   double tol_inner;
   Schedule sched;
 };
@@ -101,6 +113,32 @@ struct Grids {
   int reduce = 0;          // 1: some instance has Inst::reduce (k_reduce launches)
   int shape_r = 0, shape_c = 0, shape_z = 0;   // compile-time shapes of the passes (shape_key)
   int stream_t = 0;        // 1: the row-forward pass stores t non-temporally
+  int fft = 1, dense = 0;  // launch the FFT-family / dense-transform passes
+  int rd = 0, cd = 0;      // persistent grids of the dense row and column passes
+  int lds_rd = 0, tab_rd = 0, lds_cd = 0, tab_cd = 0;   // their LDS and table offsets
+};
+
+// Host description of a batch: plans, layouts, descriptors, work lists,
+// control blocks and workspace size.
+struct BatchDesc {
+  int dim = 2;
+  std::vector<int> px, py, pz;
+  std::vector<Layout> lay;
+  std::vector<int> dense;   // per instance: dense-transform passes
+  std::vector<Inst> inst;
+  std::vector<int> items[kNumPass];
+  std::vector<Ctl> ctl;
+  size_t ws_bytes = 0;      // control blocks + instance regions
+};
+
+// Where the driver loop finds a prepared batch's device state.
+struct DriveCtx {
+  const Batch* B = nullptr;   // device batch header
+  Ctl* ctl_d = nullptr;       // device control blocks [n]
+  Ctl* ch = nullptr;          // host copy [n]
+  int* flag_d = nullptr;      // device flags [n]
+  bool graphs = true;         // captured chunks and pinned uploads; false: direct
+                              // launches and pageable copies (no allocation)
 };
 
 // Largest total of a launch's t arrays (bytes) whose row-forward stores go
@@ -116,6 +154,7 @@ struct Graph {
   int lds_r = 0, tw_r = 0, lds_c = 0, tw_c = 0;
   int dim = 2, gz = 0, lds_z = 0, tw_z = 0, reduce = 0, shape_r = 0, shape_c = 0, shape_z = 0;
   int stream_t = 0;
+  int fft = 1, dense = 0, rd = 0, cd = 0, lds_rd = 0, tab_rd = 0, lds_cd = 0, tab_cd = 0;
   std::vector<hipEvent_t> ev;   // [pass][iteration][start, end] when profiling
 };
 
@@ -164,6 +203,7 @@ size_t instance_bytes(int nx, int ny, int bcx, int bcy, int prec);
 size_t instance_bytes3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int prec);
 const char* last_error();
 void set_last_error(const char* what, int line, hipError_t e);
+void set_last_message(const char* what);
 int row_slots(int m);
 hipError_t launch_precond(const Batch* B, const Resolved& R, const Grids& g, hipStream_t st);
 hipError_t run_chunk(bhx_handle* hd, const Batch* B, int n_inst, const Resolved& R,
@@ -177,6 +217,37 @@ int init_handle(bhx_handle* hd, int device);
 int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
                   hipStream_t st, Grids* gout);
 int fft_length(int n, int bc);
+// Both axes have a dense form (at most kDenseMax nodes).
+bool dense_eligible(const AxisPlan& X, const AxisPlan& Y);
+// Whether an instance with these axes runs the dense-transform passes under
+// the options (transform choice, schedule) R.
+bool use_dense(const Resolved& R, const AxisPlan& X, const AxisPlan& Y);
+// Launch geometry of the dense-transform passes for axes of at most nx_max,
+// ny_max nodes, with `occ` blocks per CU (fills g.rd, g.cd, g.lds_*, g.tab_*).
+void dense_grids(int prec, int nx_max, int ny_max, int n_rd, int n_cd, int num_cu, int occ,
+                 Grids* g);
+// Plan indices and layouts of a batch (host only).
+int plan_layouts(PlanCache& plans, int n, const InstSpec* specs, const Resolved& R,
+                 BatchDesc* D);
+// Bytes of the control-block region at the start of a batch workspace.
+size_t ctl_region_bytes(int n);
+// Descriptors, work lists and control blocks of a batch whose workspace
+// starts at `ws` (control blocks at ctl_d); ws = nullptr computes sizes only.
+void describe_batch(const PlanCache& plans, int n, const InstSpec* specs, const Resolved& R,
+                    char* ws, Ctl* ctl_d, BatchDesc* D);
+// The batch header of a description, given the device copies' addresses.
+void fill_header(Batch* Bh, const BatchDesc& D, const Inst* inst_d, int* const items_d[kNumPass],
+                 const AxisPlan* plans_d, const void* const ctab[2], const void* const rtab[2]);
+// Launch geometry of a described batch.
+int batch_grids(const PlanCache& plans, const BatchDesc& D, const Resolved& R, int num_cu,
+                Grids* g);
+// The solve after a batch is prepared: setup, iterations, exit checks, stats.
+int drive_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R, const Grids& g,
+                hipStream_t st, const DriveCtx& X, bhx_stats* stats,
+                std::chrono::steady_clock::time_point t0);
+// `count` iterations launched directly (events of the profiled passes from ev).
+hipError_t launch_iterations(const Batch* B, int n_inst, const Resolved& R, const Grids& g,
+                             int count, hipStream_t st, const std::vector<hipEvent_t>* ev);
 // Banded Cholesky solve of fields sharing one phi (all specs: same phi, size
 // and rules; two dimensions, y axis not periodic).
 int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,

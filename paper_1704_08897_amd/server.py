@@ -94,9 +94,9 @@ class Server:
         self.close()
 
     def __del__(self):
-        if sys.is_finalizing():
-            return
         try:
+            if sys.is_finalizing():
+                return
             self.close()
         except Exception:
             pass

@@ -82,7 +82,8 @@ def test_null_pointers_and_handles():
 
 def test_bad_options_rejected():
     for kw in ({"precision": 2}, {"precond": 3}, {"maxit": -1}, {"flexible": 2},
-               {"tol_inner": 2.0}, {"accurate": 5}, {"warm_start": 2}, {"warm_start": -1}):
+               {"tol_inner": 2.0}, {"accurate": 5}, {"warm_start": 2}, {"warm_start": -1},
+               {"transform": 3}, {"transform": -1}):
         o = bhx.default_opts(**kw)
         s, _ = bhx.extend_ex(FAKE, FAKE, FAKE, 8, 8, 1.0, 0, 1e-8, opts=o)
         assert s == bhx.ERR_ARG, kw

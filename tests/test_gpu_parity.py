@@ -79,14 +79,17 @@ def test_masked_operator(handle, nx, ny, bx, by):
 
 @pytest.mark.parametrize("nx,ny,bx,by", CASES_OP)
 @pytest.mark.parametrize("prec", [0, 1])
-def test_preconditioner(handle, nx, ny, bx, by, prec):
+@pytest.mark.parametrize("transform", [1, 2])
+def test_preconditioner(handle, nx, ny, bx, by, prec, transform):
+    # transform 1: the FFT family; 2: dense products where the axes allow
     rng = np.random.default_rng(nx * 7 + ny)
     phi = random_phi(rng, nx, ny, 0.3)
     r = rng.normal(size=(ny, nx))
     known = O.known_mask(phi)
     ref = O.spectral_preconditioner(r, known, bx, by)
     out = dev(np.zeros((ny, nx)))
-    s = bhx.debug_apply(handle, 1, dev(phi), dev(r), out, bc=bhx.BC(bx, by), precision=prec)
+    s = bhx.debug_apply(handle, 1, dev(phi), dev(r), out, bc=bhx.BC(bx, by), precision=prec,
+                        transform=transform)
     assert s == bhx.OK
     got = host(out)
     assert np.array_equal(got[known], np.zeros(known.sum()))

@@ -10,7 +10,9 @@ Bounds: the preconditioner within relative L2 1e-11 of the oracle, as in the
 generic parity tests; the two kernel families perform the same operations in
 the same order (only constant folding and contraction differ), so their
 preconditioner outputs agree within 1e-13.  Solved fields at tol 1e-12 within
-1e-9 of the oracle (the star's conditioning, as in the full-size tests)."""
+1e-9 of the oracle (the star's conditioning, as in the full-size tests).
+Every call here asks for the FFT family (bhx_opts.transform = 1): the
+built-in choice would run some of these sizes as dense products."""
 import numpy as np
 import pytest
 
@@ -26,6 +28,7 @@ if not torch.cuda.is_available():
 from paper_1704_08897_amd import bhx  # noqa: E402
 
 DEV = "cuda:0"
+FFT = bhx.default_opts(transform=1)
 
 
 @pytest.fixture(scope="module")
@@ -46,7 +49,8 @@ def host(t):
 
 def apply_precond(handle, phi, r, bx, by):
     out = dev(np.zeros_like(r))
-    assert bhx.debug_apply(handle, 1, dev(phi), dev(r), out, bc=bhx.BC(bx, by)) == bhx.OK
+    assert bhx.debug_apply(handle, 1, dev(phi), dev(r), out, bc=bhx.BC(bx, by),
+                           transform=1) == bhx.OK
     return host(out)
 
 
@@ -87,7 +91,7 @@ def test_star1024_solve_shapes(handle, monkeypatch):
     for flag in ("1", "0"):
         monkeypatch.setenv("BHX_SHAPE_KERNELS", flag)
         G = dev(p.F)
-        s, st = bhx.extend_ex(handle, dev(p.phi), G, bc=p.bc, h=p.h, tol=p.tol)
+        s, st = bhx.extend_ex(handle, dev(p.phi), G, bc=p.bc, h=p.h, tol=p.tol, opts=FFT)
         assert s == bhx.OK, st.as_dict()
         got = host(G)
         assert np.array_equal(got[K], p.F[K])
@@ -108,7 +112,7 @@ def test_paper_masks_solve_shapes(handle, make):
     Fo, _ = O.extend_direct(p.phi, p.F, p.bcx, p.bcy)
     K = O.known_mask(p.phi)
     G = dev(p.F)
-    s, st = bhx.extend_ex(handle, dev(p.phi), G, bc=p.bc, h=p.h, tol=p.tol)
+    s, st = bhx.extend_ex(handle, dev(p.phi), G, bc=p.bc, h=p.h, tol=p.tol, opts=FFT)
     assert s == bhx.OK, st.as_dict()
     got = host(G)
     assert np.array_equal(got[K], p.F[K])
@@ -126,22 +130,22 @@ def test_fields_and_same_shape_batch(handle):
     X, Y = np.meshgrid(np.arange(nx) / nx, np.arange(ny) / ny)
     fields = [p.F, np.where(O.known_mask(p.phi), X**3 - Y, 0.0)]
     Fs = [dev(f) for f in fields]
-    s, sts = bhx.extend_fields(handle, dev(p.phi), Fs, h=p.h, bc=p.bc, tol=p.tol)
+    s, sts = bhx.extend_fields(handle, dev(p.phi), Fs, h=p.h, bc=p.bc, tol=p.tol, opts=FFT)
     assert s == bhx.OK
     for f, G in zip(fields, Fs):
         A = dev(f)
-        s1, _ = bhx.extend_ex(handle, dev(p.phi), A, bc=p.bc, h=p.h, tol=p.tol)
+        s1, _ = bhx.extend_ex(handle, dev(p.phi), A, bc=p.bc, h=p.h, tol=p.tol, opts=FFT)
         assert s1 == bhx.OK
         assert np.array_equal(host(G), host(A))
     q = W.annulus_problem(512, 1, 0, tol=1e-10)
     batch = [p, q]
     Bs = [dev(b.F) for b in batch]
     s, sts = bhx.extend_batched(handle, [dev(b.phi) for b in batch], Bs, [b.h for b in batch],
-                                [b.bc for b in batch], [b.tol for b in batch])
+                                [b.bc for b in batch], [b.tol for b in batch], opts=FFT)
     assert s == bhx.OK
     for b, G in zip(batch, Bs):
         A = dev(b.F)
-        s1, _ = bhx.extend_ex(handle, dev(b.phi), A, bc=b.bc, h=b.h, tol=b.tol)
+        s1, _ = bhx.extend_ex(handle, dev(b.phi), A, bc=b.bc, h=b.h, tol=b.tol, opts=FFT)
         assert s1 == bhx.OK
         got = host(G)
         assert np.array_equal(got, host(A))
@@ -159,11 +163,11 @@ def test_mixed_batch_runs_plan_table_family(handle):
     q = W.circle_problem(64, tol=1e-12)
     Bs = [dev(p.F), dev(q.F)]
     s, sts = bhx.extend_batched(handle, [dev(p.phi), dev(q.phi)], Bs, [p.h, q.h], [p.bc, q.bc],
-                                [p.tol, q.tol])
+                                [p.tol, q.tol], opts=FFT)
     assert s == bhx.OK
     got = host(Bs[0])
     A = dev(p.F)
-    s1, _ = bhx.extend_ex(handle, dev(p.phi), A, bc=p.bc, h=p.h, tol=p.tol)
+    s1, _ = bhx.extend_ex(handle, dev(p.phi), A, bc=p.bc, h=p.h, tol=p.tol, opts=FFT)
     assert s1 == bhx.OK
     solo = host(A)
     K = O.known_mask(p.phi)
@@ -188,7 +192,7 @@ def test_preconditioner_shapes_fp32(handle, monkeypatch, nx, ny, bx, by):
         monkeypatch.setenv("BHX_SHAPE_KERNELS", flag)
         out = dev(np.zeros_like(r))
         assert bhx.debug_apply(handle, 1, dev(phi), dev(r), out, bc=bhx.BC(bx, by),
-                               precision=1) == bhx.OK
+                               precision=1, transform=1) == bhx.OK
         outs.append(host(out))
     assert np.array_equal(outs[0][known], np.zeros(known.sum()))
     assert O.relative_l2(outs[0], ref) <= 2e-4
@@ -208,7 +212,7 @@ def test_star1024_fp32_solve_shapes(handle, monkeypatch):
         monkeypatch.setenv("BHX_SHAPE_KERNELS", flag)
         G = dev(p.F)
         s, st = bhx.extend_ex(handle, dev(p.phi), G, bc=p.bc, h=p.h, tol=p.tol,
-                              opts=bhx.default_opts(precision=1))
+                              opts=bhx.default_opts(precision=1, transform=1))
         assert s == bhx.OK, st.as_dict()
         got = host(G)
         assert np.array_equal(got[K], p.F[K])
@@ -230,7 +234,7 @@ def test_dirichlet_star1023_solve_shapes(handle, monkeypatch):
     for flag in ("1", "0"):
         monkeypatch.setenv("BHX_SHAPE_KERNELS", flag)
         G = dev(s0.F)
-        s, st = bhx.extend_ex(handle, dev(s0.phi), G, bc=bc, h=s0.h, tol=1e-12)
+        s, st = bhx.extend_ex(handle, dev(s0.phi), G, bc=bc, h=s0.h, tol=1e-12, opts=FFT)
         assert s == bhx.OK, st.as_dict()
         got = host(G)
         assert np.array_equal(got[K], s0.F[K])
