@@ -187,6 +187,34 @@ int bhx_extend(const double* phi, double* F, int nx, int ny, double h, int bc, d
 int bhx_extend_ex(bhx_handle* hd, const double* phi, double* F, int nx, int ny, double h,
                   int bc, double tol, const bhx_opts* o, void* stream, bhx_stats* out);
 
+/* Capacity of the static device array behind bhx_extend_noalloc, per device. */
+#define BHX_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* bhx_extend_ex for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * The call allocates no device or pinned memory: every buffer of the solve
+ * (descriptors, transform tables, control block, workspace vectors) lives in
+ * one static device array of the library of BHX_NOALLOC_SCRATCH_BYTES per
+ * device, whose address bhx_create looks up once per device.  The caller
+ * passes phi and F as for bhx_extend_ex (device pointers, caller-owned);
+ * arguments, options, statuses and stats are those of bhx_extend_ex, with
+ * these differences:
+ *   - a problem whose workspace, tables and descriptors exceed the array
+ *     (about 1.3 million nodes in FP64: 1024 x 1024 fits, 2048 x 2048 does
+ *     not) returns BHX_ERR_ARG, F untouched, bhx_last_error() saying the
+ *     bytes needed and the limit;
+ *   - opts.autotune, opts.profile and opts.solver = 1 return BHX_ERR_ARG;
+ *   - iteration chunks are launched directly (no captured graphs), so a
+ *     solve may take a little longer than with bhx_extend_ex; the kernels
+ *     and their order are the same, and so is the result, bit for bit.
+ * All calls on one device share that device's array, and each call leaves
+ * it holding its own state: calls are serialised by a lock per device in
+ * this process, and must not overlap with each other on one device in any
+ * other way (each process has its own copy).  Synchronises with the stream
+ * before returning. */
+int bhx_extend_noalloc(bhx_handle* hd, const double* phi, double* F, int nx, int ny, double h,
+                       int bc, double tol, const bhx_opts* o, void* stream, bhx_stats* out);
+
 /* `count` independent extensions of mixed sizes and boundary rules solved
  * together: each pass of every iteration is one launch over the tiles of all
  * unfinished instances; instances retire independently.  phi, F are host

@@ -82,6 +82,8 @@ _sig = {
     "bhx_extend": (_ci, [_vp, _vp, _ci, _ci, _cd, _ci, _cd]),
     "bhx_extend_ex": (_ci, [_vp, _vp, _vp, _ci, _ci, _cd, _ci, _cd, ctypes.POINTER(Opts), _vp,
                             ctypes.POINTER(Stats)]),
+    "bhx_extend_noalloc": (_ci, [_vp, _vp, _vp, _ci, _ci, _cd, _ci, _cd, ctypes.POINTER(Opts),
+                                 _vp, ctypes.POINTER(Stats)]),
     "bhx_extend_batched": (_ci, [_vp, _ci, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                  ctypes.POINTER(_ci), ctypes.POINTER(_ci), ctypes.POINTER(_cd),
                                  ctypes.POINTER(_ci), ctypes.POINTER(_cd), ctypes.POINTER(Opts),
@@ -287,6 +289,20 @@ def extend_ex(handle, phi, F, nx=None, ny=None, h=1.0, bc=0, tol=1e-8, opts=None
     s = _lib.bhx_extend_ex(hp, _ptr(phi), _ptr(F), nx, ny, float(h), int(bc), float(tol),
                            ctypes.byref(opts) if opts is not None else None, _stream(stream),
                            ctypes.byref(st))
+    return s, st
+
+
+def extend_noalloc(handle, phi, F, nx=None, ny=None, h=1.0, bc=0, tol=1e-8, opts=None,
+                   stream=None):
+    """``bhx_extend_noalloc`` (no device allocation: the library's static
+    scratch array); returns (status, Stats)."""
+    if nx is None:
+        nx, ny = _dims(phi)
+    hp = handle.ptr if isinstance(handle, Handle) else handle
+    st = Stats()
+    s = _lib.bhx_extend_noalloc(hp, _ptr(phi), _ptr(F), nx, ny, float(h), int(bc),
+                                float(tol), ctypes.byref(opts) if opts is not None else None,
+                                _stream(stream), ctypes.byref(st))
     return s, st
 
 

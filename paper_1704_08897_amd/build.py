@@ -6,8 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbhx.so")
-SOURCES = ["bhx_kernels.hip", "bhx_direct.hip", "bhx_runtime.cpp", "bhx_capi.cpp",
-           "bhx_engine.cpp"]
+SOURCES = ["bhx_kernels.hip", "bhx_direct.hip", "bhx_noalloc.hip", "bhx_runtime.cpp",
+           "bhx_capi.cpp", "bhx_engine.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -91,6 +91,17 @@ int bhx_extend_ex(bhx_handle* hd, const double* phi, double* F, int nx, int ny, 
   return bhx::solve_batch(hd, 1, &s, R, (hipStream_t)stream, out);
 }
 
+int bhx_extend_noalloc(bhx_handle* hd, const double* phi, double* F, int nx, int ny, double h,
+                       int bc, double tol, const bhx_opts* o, void* stream, bhx_stats* out) {
+  if (!hd) return BHX_ERR_ARG;
+  const Resolved R = bhx::resolve_opts(o);
+  int v = bhx::validate(phi, F, nx, ny, h, bc, tol, R);
+  if (v != BHX_OK) return v;
+  bhx::InstSpec s{phi, F, nx, ny, bc & 15, (bc >> 4) & 15, tol};
+  std::lock_guard<std::mutex> lk(hd->mu);
+  return bhx::solve_noalloc(hd, s, R, (hipStream_t)stream, out);
+}
+
 int bhx_extend_batched(bhx_handle* hd, int count, const double* const* phi, double* const* F,
                        const int* nx, const int* ny, const double* h, const int* bc,
                        const double* tol, const bhx_opts* o, void* stream, bhx_stats* out) {

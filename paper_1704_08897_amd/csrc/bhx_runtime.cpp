@@ -399,6 +399,14 @@ int init_handle(bhx_handle* hd, int device) {
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return BHX_ERR_HIP;
   hd->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   if (set_kernel_attributes() != hipSuccess) return BHX_ERR_HIP;
+  {
+    // the allocation-free entry point's scratch: its device address, looked
+    // up once per device with that device current (a failure here shows
+    // again, with its reason, on that entry point's first call)
+    void* p = nullptr;
+    size_t b = 0;
+    (void)noalloc_scratch(device, &p, &b);
+  }
   if (hipMalloc((void**)&hd->batch_d, sizeof(Batch)) != hipSuccess) return BHX_ERR_NOMEM;
   if (hipStreamCreate(&hd->own_stream) != hipSuccess) return BHX_ERR_HIP;
   return BHX_OK;

@@ -248,6 +248,13 @@ int drive_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
 // `count` iterations launched directly (events of the profiled passes from ev).
 hipError_t launch_iterations(const Batch* B, int n_inst, const Resolved& R, const Grids& g,
                              int count, hipStream_t st, const std::vector<hipEvent_t>* ev);
+// Allocation-free single solve: every device buffer in the library's static
+// scratch array (bhx_noalloc.hip).
+int solve_noalloc(bhx_handle* hd, const InstSpec& spec, const Resolved& R, hipStream_t stream,
+                  bhx_stats* stats);
+// Device address of the scratch array on `device` (looked up once per device
+// with that device current) and its size; BHX_OK or BHX_ERR_HIP.
+int noalloc_scratch(int device, void** ptr, size_t* bytes);
 // Banded Cholesky solve of fields sharing one phi (all specs: same phi, size
 // and rules; two dimensions, y axis not periodic).
 int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
