@@ -43,8 +43,10 @@
  *     Calls on one handle are serialised by a lock inside the handle.
  *   - Boundary rules: Neumann, periodic and Dirichlet axes, one rule per axis.
  *     A Dirichlet axis of n nodes is transformed through a DFT of length
- *     2(n+1) (its odd extension), which must fit LDS like any transform: in
- *     FP64 n <= 1023 or n = 2047, in FP32 n <= 2047; otherwise BHX_ERR_ARG.
+ *     2(n+1) (its odd extension) or, for 1024 <= n <= 2046, through a
+ *     chirp-z transform of n+1 points; either must fit LDS like any
+ *     transform: n <= 2047 in FP64 and FP32 (in three dimensions the y and z
+ *     axes take n <= 1023 or n = 2047); otherwise BHX_ERR_ARG.
  */
 #ifndef BHX_H
 #define BHX_H

@@ -20,7 +20,8 @@ import sys
 import weakref
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbhx.so")
+# BHX_LIB selects a debugging build of the library (build.py VARIANTS).
+LIB_PATH = os.environ.get("BHX_LIB") or os.path.join(_HERE, "libbhx.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "bhx.h")
 
 if not os.path.exists(LIB_PATH):

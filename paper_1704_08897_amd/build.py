@@ -34,12 +34,35 @@ def _run(cmd, verbose):
             print("\n".join(lines))
 
 
-def build(verbose=False, extra=()):
+# Debugging builds, each a library of its own beside libbhx.so (load one with
+# BHX_LIB=<path> in the environment of the process that imports the binding):
+#   lds_nan     every transform kernel fills its dynamic LDS with NaN before
+#               use, so reads of LDS no thread wrote poison the results;
+#   host_asan   host code (runtime, engine, C interface) under AddressSanitizer
+#               and UndefinedBehaviorSanitizer; device code unchanged.  The
+#               ASan runtime must be loaded first (LD_PRELOAD of the clang
+#               runtime), so this one is for host-only test runs on a CPU
+#               machine (tests/test_debug_builds.py).
+VARIANTS = {
+    "lds_nan": ["-DBHX_DEBUG_LDS_NAN=1"],
+    "host_asan": ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-omit-frame-pointer", "-shared-libsan"],
+}
+
+
+def variant_path(variant):
+    return os.path.join(HERE, f"libbhx_{variant}.so")
+
+
+def build(verbose=False, extra=(), variant=None):
     """Compile every source to an object (in parallel), then link
-    ``libbhx.so``; raises on failure."""
+    ``libbhx.so`` (or ``libbhx_<variant>.so`` for a debugging variant);
+    raises on failure."""
     from concurrent.futures import ThreadPoolExecutor
     inc = ["-I", os.path.join(HERE, "..", "include")]
-    objdir = os.path.join(HERE, "_build")
+    objdir = os.path.join(HERE, "_build", variant or "release")
+    if variant:
+        extra = list(extra) + VARIANTS[variant]
     os.makedirs(objdir, exist_ok=True)
     compile_flags = [f for f in FLAGS if f != "-shared"]
     jobs = []
@@ -50,11 +73,12 @@ def build(verbose=False, extra=()):
     workers = min(len(jobs), max(1, int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
     with ThreadPoolExecutor(max_workers=workers) as ex:
         list(ex.map(lambda j: _run(j[1], verbose), jobs))
-    tmp = LIB + ".tmp"
+    out = variant_path(variant) if variant else LIB
+    tmp = out + ".tmp"
     _run([HIPCC, *FLAGS, *extra, *[o for o, _ in jobs], "-o", tmp], verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, variant=sys.argv[1] if len(sys.argv) > 1 else None))

@@ -124,7 +124,11 @@ struct AxisPlan {
   int off_post;    // DCT: exp(-i pi k / (2n)), k < n; Dirichlet: unused
   int off_lam;     // eigenvalues lambda_k of T, k < n           (real table)
   int nf;          // length of the DFT computed: n (DCT-II via Makhoul, Hartley);
-                   // 2(n+1) for DST-I (odd extension 0, x, 0, -reversed x)
+                   // 2(n+1) for DST-I (odd extension 0, x, 0, -reversed x); n + 1
+                   // points for the chirp-z DST-I (cz)
+  int cz;          // 1: DST-I as a chirp-z transform: x at 1..n of a DFT of length
+                   // 2(n+1) (chirp exp(-i pi k^2 / (2 nf))), outputs 0..n, one real
+                   // line per complex row (Dirichlet axes of 1024-2046 nodes)
   // Dense form of the 1-D transform (n <= kDenseMax, else dense_P = 0): the
   // unnormalised basis T(k, i) = dtab[f(((k + ck) (di i + ci)) mod P)] with
   // (ck, di, ci, P) = (0, 2, 1, 4n) and dtab[a] = cos(pi a / 2n) (DCT-II),

@@ -32,6 +32,7 @@
 // to rounding).
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
+#include <hsa/hsa.h>
 #include <stdint.h>
 #include <cstdlib>
 
@@ -238,6 +239,30 @@ __device__ __forceinline__ int map_axis_sel(int g, int n, int bc, double& s) {
   return inside ? g : (valid ? ghost : 0);
 }
 
+// Debug build (BHX_DEBUG_LDS_NAN=1): every transform kernel starts by
+// filling its dynamic LDS with NaN, so a read of LDS that no thread of the
+// block wrote shows up as NaN in the results instead of as stale values.  The
+// dispatch packet gives the block's whole group segment; the dynamic part
+// starts at smem.  A no-op in the normal build.
+#ifndef BHX_DEBUG_LDS_NAN
+#define BHX_DEBUG_LDS_NAN 0
+#endif
+__device__ __forceinline__ void debug_fill_lds(unsigned char* dyn) {
+#if BHX_DEBUG_LDS_NAN
+  const hsa_kernel_dispatch_packet_t* pkt =
+      (const hsa_kernel_dispatch_packet_t*)__builtin_amdgcn_dispatch_ptr();
+  const unsigned total = pkt->group_segment_size;
+  const unsigned start =
+      (unsigned)(size_t)(__attribute__((address_space(3))) unsigned char*)dyn;
+  double* d = (double*)dyn;
+  for (unsigned i = threadIdx.x; start + 8 * (i + 1) <= total; i += blockDim.x)
+    d[i] = __builtin_nan("");
+  __syncthreads();
+#else
+  (void)dyn;
+#endif
+}
+
 // Work item `it` of pass `p`: (instance << kItemShift) | local item.  A
 // single-instance batch needs no table.
 __device__ __forceinline__ int item_code(const Batch& B, int p, int it) {
@@ -287,6 +312,8 @@ template <typename R, int SP = 0>
 struct XPlan {
   using C = typename V2<R>::T;
   int n, nf, m, logm, blue, bc, sh;
+  int cz;                     // chirp-z DST-I: one real line per FFT row, the two
+                              // lines of a pair in turn (plan-table family only)
   R s0, s1, g0, g1, hs;
   BHX_GLOBAL const C* twg;    // W_m^k, k < m/2, in device memory
   const C* tw;                // per-stage twiddle tables in LDS once staged
@@ -358,8 +385,10 @@ struct XPlan {
       n = sp_nodes(SP);
       blue = 0;
       bc = SP & 3;
+      cz = 0;
     } else {
       n = P.n; nf = P.nf; m = P.m; logm = P.logm; blue = P.bluestein; bc = P.bc;
+      cz = P.cz;
     }
     sh = rpos_shift(logm);
     s0 = (R)P.s0; s1 = (R)P.s1; g0 = (R)P.g0; g1 = (R)P.g1; hs = (R)P.hs;
@@ -429,13 +458,26 @@ struct XPlan {
       if (kk != k) row[pos(kk)] = b;
     }
   }
-  // DST-I: the odd extension is zero at 0 and n+1 (no other rule writes them)
+  // DST-I: the odd extension is zero at 0 and n+1 (no other rule writes them);
+  // the chirp-z form has input 0 at 0 (the points past n are zeroed by the
+  // Bluestein step)
   __device__ __forceinline__ void zero_ends(C* buf, int rows, int st) const {
     if (bc != kDirichlet) return;
     for (int r = threadIdx.x; r < rows; r += kThreads) {
       buf[r * st + pos(0)] = mk<C>(0, 0);
-      buf[r * st + pos(n + 1)] = mk<C>(0, 0);
+      if (!cz) buf[r * st + pos(n + 1)] = mk<C>(0, 0);
     }
+  }
+  // Chirp-z DST-I: sample i of the row's one real line at point i + 1.
+  __device__ __forceinline__ void put_cz(C* row, int i, R v) const {
+    row[pos(i + 1)] = mk<C>(v, (R)0);
+  }
+  // Chirp-z DST-I: orthonormal coefficient k of the row's line.  The row
+  // holds sum_{j=1..n} x_j W^(jk), W = exp(-2 pi i / (2(n+1))), whose
+  // imaginary part is -sum_j x_j sin(pi j k / (n+1)); hs is half of
+  // sqrt(2/(n+1)).
+  __device__ __forceinline__ R coef_cz(const C* row, int k) const {
+    return -out(row, k + 1).y * ((R)2 * hs);
   }
 };
 
@@ -1134,6 +1176,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
   const bool stream_t = (mode & 4) != 0;
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   extern __shared__ __align__(16) unsigned char smem[];
+  debug_fill_lds(smem);
   C* buf = (C*)smem;
   R* stg = (R*)smem;
   C* twl = buf + twoff;
@@ -1219,7 +1262,8 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
       }
       if (update != 2) {
         const int jr = e / nx, i = e - jr * nx;
-        X.put(buf + (jr >> 1) * st, i, jr & 1, (R)v);
+        if (!X.cz) X.put(buf + (jr >> 1) * st, i, jr & 1, (R)v);
+        else if (!(jr & 1)) X.put_cz(buf + (jr >> 1) * st, i, (R)v);   // first lines now
       }
     };
 #pragma unroll
@@ -1257,15 +1301,48 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
     // 3. real spectra of the pairs (k, n-k) into registers
     const int np = X.pairs();
     R va[kMaxPairs][4];
+    if (X.cz) {
+      // chirp-z DST-I: the first line of each pair is in its row now; then
+      // the second, whose updated r this block wrote to rb above
 #pragma unroll
-    for (int s = 0; s < kMaxPairs; ++s) {
-      const int pidx = threadIdx.x + s * kThreads;
-      if (pidx < rows * np) {
-        const int rr = pidx / np, k = pidx - rr * np;
-        const int kk = X.partner(k);
-        const C* row = buf + rr * st;
-        fwd_post_pair<R>(X, X.out(row, X.bin(k)), X.out(row, X.bin(kk)), k, kk, va[s][0],
-                         va[s][1], va[s][2], va[s][3]);
+      for (int s = 0; s < kMaxPairs; ++s) {
+        const int pidx = threadIdx.x + s * kThreads;
+        if (pidx < rows * np) {
+          const int rr = pidx / np, k = pidx - rr * np;
+          const C* row = buf + rr * st;
+          va[s][0] = X.coef_cz(row, k);
+          va[s][2] = X.coef_cz(row, X.partner(k));
+        }
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < G * nx; e += kThreads) {
+        const int jr = e / nx, i = e - jr * nx;
+        if (jr & 1) X.put_cz(buf + (jr >> 1) * st, i, (e < E && mk[e]) ? (R)rb[e] : (R)0);
+      }
+      X.zero_ends(buf, rows, st);
+      __syncthreads();
+      dft_core<R>(X, buf, rows);
+#pragma unroll
+      for (int s = 0; s < kMaxPairs; ++s) {
+        const int pidx = threadIdx.x + s * kThreads;
+        if (pidx < rows * np) {
+          const int rr = pidx / np, k = pidx - rr * np;
+          const C* row = buf + rr * st;
+          va[s][1] = X.coef_cz(row, k);
+          va[s][3] = X.coef_cz(row, X.partner(k));
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < kMaxPairs; ++s) {
+        const int pidx = threadIdx.x + s * kThreads;
+        if (pidx < rows * np) {
+          const int rr = pidx / np, k = pidx - rr * np;
+          const int kk = X.partner(k);
+          const C* row = buf + rr * st;
+          fwd_post_pair<R>(X, X.out(row, X.bin(k)), X.out(row, X.bin(kk)), k, kk, va[s][0],
+                           va[s][1], va[s][2], va[s][3]);
+        }
       }
     }
     __syncthreads();
@@ -1325,6 +1402,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
   constexpr bool kScale = KIND == kCol2D || KIND == kColZ;
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   extern __shared__ __align__(16) unsigned char smem[];
+  debug_fill_lds(smem);
   C* buf = (C*)smem;
   R* stg = (R*)smem;
   C* twl = buf + twoff;
@@ -1400,6 +1478,70 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
     const int rows = Gp >> 1;
     const int st = X.stride();
     const int np = X.pairs();
+    if constexpr (KIND == kCol2D && SP == 0) {
+      if (X.cz) {
+        // chirp-z DST-I along y: the first pencil of each pair, then the
+        // second, each through forward, scale and inverse (the DST-I is its
+        // own inverse) in the pair's row
+        if (threadIdx.x < kMaxGc) s_lam[threadIdx.x] = lam;
+        for (int h = 0; h < 2; ++h) {
+          for (int e = threadIdx.x; e < Et; e += kThreads) {
+            int cr, j;
+            split(e, cr, j);
+            if ((cr & 1) == h) X.put_cz(buf + (cr >> 1) * st, j, cr < cnt ? t[at(cr, j)] : (R)0);
+          }
+          X.zero_ends(buf, rows, st);
+          __syncthreads();
+          dft_core<R>(X, buf, rows);
+          R ys[kMaxPairs][2];
+#pragma unroll
+          for (int s = 0; s < kMaxPairs; ++s) {
+            const int pidx = threadIdx.x + s * kThreads;
+            if (pidx < rows * np) {
+              const int rr = pidx / np, k = pidx - rr * np;
+              const int kk = X.partner(k);
+              const C* row = buf + rr * st;
+              const R la = s_lam[2 * rr + h];
+              R lk, lkk;
+              X.lam_pair(k, kk, lk, lkk);
+              ys[s][0] = X.coef_cz(row, k) * inv_sq<R>(la + lk);
+              ys[s][1] = X.coef_cz(row, kk) * inv_sq<R>(la + lkk);
+            }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int s = 0; s < kMaxPairs; ++s) {
+            const int pidx = threadIdx.x + s * kThreads;
+            if (pidx < rows * np) {
+              const int rr = pidx / np, k = pidx - rr * np;
+              const int kk = X.partner(k);
+              X.put_cz(buf + rr * st, k, ys[s][0]);
+              if (kk != k) X.put_cz(buf + rr * st, kk, ys[s][1]);
+            }
+          }
+          X.zero_ends(buf, rows, st);
+          __syncthreads();
+          dft_core<R>(X, buf, rows);
+#pragma unroll
+          for (int s = 0; s < kMaxPairs; ++s) {
+            const int pidx = threadIdx.x + s * kThreads;
+            if (pidx < rows * np) {
+              const int rr = pidx / np, k = pidx - rr * np;
+              const int kk = X.partner(k);
+              const int cr = 2 * rr + h;
+              const C* row = buf + rr * st;
+              if (cr < cnt) {
+                t[at(cr, k)] = X.coef_cz(row, k);
+                if (kk != k) t[at(cr, kk)] = X.coef_cz(row, kk);
+              }
+            }
+          }
+          __syncthreads();
+        }
+        if (count_iter && c == 0 && threadIdx.x == 0) ctl->iter = ctl->iter + 1;
+        continue;
+      }
+    }
     C vin[kMaxPairs][2];
     if constexpr (KIND != kColYInv) {
       // 2. forward: place the pencils into the packed rows, FFT, spectra
@@ -1581,6 +1723,7 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
   using C = typename V2<R>::T;
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   extern __shared__ __align__(16) unsigned char smem[];
+  debug_fill_lds(smem);
   C* buf = (C*)smem;
   R* stg = (R*)smem;
   C* twl = buf + twoff;
@@ -1652,8 +1795,54 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
       stg[e] = jr < jn ? t[(size_t)k * ny + j0 + jr] : (R)0;
     }
     __syncthreads();
-    // 2. inverse inputs of the pairs, through registers
     const int np = X.pairs();
+    double acc = 0.0, acco = 0.0;
+    if (X.cz) {
+      // chirp-z DST-I (its own inverse): the first line of each pair, then
+      // the second, in the pair's row; outputs, z and dots per line.  The
+      // spectra share LDS with the rows: all of them into registers first.
+      R sv[kMaxPairs][4];
+#pragma unroll
+      for (int s = 0; s < kMaxPairs; ++s) {
+        const int pidx = threadIdx.x + s * kThreads;
+        if (pidx < rows * np) {
+          const int rr = pidx / np, k = pidx - rr * np;
+          const int kk = X.partner(k);
+          sv[s][0] = stg[k * G + 2 * rr];
+          sv[s][1] = stg[kk * G + 2 * rr];
+          sv[s][2] = stg[k * G + 2 * rr + 1];
+          sv[s][3] = stg[kk * G + 2 * rr + 1];
+        }
+      }
+      __syncthreads();
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int s = 0; s < kMaxPairs; ++s) {
+          const int pidx = threadIdx.x + s * kThreads;
+          if (pidx < rows * np) {
+            const int rr = pidx / np, k = pidx - rr * np;
+            const int kk = X.partner(k);
+            X.put_cz(buf + rr * st, k, sv[s][2 * h]);
+            if (kk != k) X.put_cz(buf + rr * st, kk, sv[s][2 * h + 1]);
+          }
+        }
+        X.zero_ends(buf, rows, st);
+        __syncthreads();
+        dft_core<R>(X, buf, rows);
+        for (int e = threadIdx.x; e < E; e += kThreads) {
+          const int jr = e / nx, i = e - jr * nx;
+          if ((jr & 1) != h || !mk[e]) continue;
+          const double zo = flex ? zb[e] : 0.0;
+          const double zv = (double)X.coef_cz(buf + (jr >> 1) * st, i);
+          const double rv = rb[e];
+          zb[e] = zv;
+          acc += rv * zv;
+          acco += rv * zo;
+        }
+        __syncthreads();
+      }
+    } else {
+    // 2. inverse inputs of the pairs, through registers
     C vin[kMaxPairs][2];
 #pragma unroll
     for (int s = 0; s < kMaxPairs; ++s) {
@@ -1678,7 +1867,6 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
     __syncthreads();
     dft_core<R>(X, buf, rows);
     // 3. outputs: restrict, store z, dots
-    double acc = 0.0, acco = 0.0;
     auto emit = [&](int e, int m, double rv, double zo) {
       if (!m) return;
       const int jr = e / nx, i = e - jr * nx;
@@ -1719,6 +1907,7 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) emit(e0 + u * kThreads, m[u], rv[u], zo[u]);
+    }
     }
     acc = block_sum(acc, red);
     if (flex) acco = block_sum(acco, red);
@@ -1903,6 +2092,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd_dense(const Batch* __restri
   const int update = mode & 3;
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   extern __shared__ __align__(16) unsigned char smem[];
+  debug_fill_lds(smem);
   R* dat = (R*)smem;
   R* tabl = dat + tab_off;
   __shared__ double red[8];
@@ -2020,6 +2210,7 @@ __global__ void __launch_bounds__(kThreads) k_col_dense(const Batch* __restrict_
   using M = Mfma<R>;
   const Batch B = *(BHX_CONST const Batch*)Bp;
   extern __shared__ __align__(16) unsigned char smem[];
+  debug_fill_lds(smem);
   R* dat = (R*)smem;
   R* tabl = dat + tab_off;
   R* laml = tabl + 2 * kDenseMax + 2;       // after the longest table (DST-I: 2(n+1))
@@ -2090,6 +2281,7 @@ __global__ void __launch_bounds__(kThreads) k_rowinv_dense(const Batch* __restri
   using M = Mfma<R>;
   const Batch B = *(BHX_CONST const Batch*)Bp;
   extern __shared__ __align__(16) unsigned char smem[];
+  debug_fill_lds(smem);
   R* dat = (R*)smem;
   R* tabl = dat + tab_off;
   __shared__ double red[4];

@@ -89,7 +89,15 @@ int row_slots(int m) { return m + (m >> 3) + (m >> rpos_shift(ilog2(m))); }
 
 
 // Length of the DFT behind the 1-D transform of an axis of n nodes.
-int fft_length(int n, int bc) { return bc == kDirichlet ? 2 * (n + 1) : n; }
+// A Dirichlet axis of 1024 to 2046 nodes, whose odd extension of 2(n + 1)
+// points would need an 8192-point Bluestein core (no room in LDS in FP64),
+// takes its DST-I as a chirp-z transform of n + 1 points instead: the DFT of
+// length 2(n + 1) of x placed at 1..n, evaluated at 0..n (dst_chirp).
+bool dst_chirp(int n, int bc) { return bc == kDirichlet && n >= 1024 && n <= 2046; }
+int fft_length(int n, int bc) {
+  if (bc != kDirichlet) return n;
+  return dst_chirp(n, bc) ? n + 1 : 2 * (n + 1);
+}
 
 bool length_supported(int n, int bc, int prec) {
   if (n < 4) return false;
@@ -164,6 +172,8 @@ size_t instance_bytes3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int pr
   if (!length_supported(nx, bcx, prec) || !length_supported(ny, bcy, prec) ||
       !length_supported(nz, bcz, prec))
     return 0;
+  // the three-dimensional column passes have no chirp-z DST-I
+  if (dst_chirp(ny, bcy) || dst_chirp(nz, bcz)) return 0;
   if (!make_layout(nx, ny, nz, prec, core_length(fft_length(nx, bcx)),
                    core_length(fft_length(ny, bcy)), core_length(fft_length(nz, bcz)), 0, &L))
     return 0;
@@ -224,9 +234,12 @@ int PlanCache::get(int n, int bc) {
   P.bc = bc;
   P.nf = fft_length(n, bc);
   const int nf = P.nf;
+  P.cz = dst_chirp(n, bc);
   P.m = core_length(nf);
   P.logm = ilog2(P.m);
   P.bluestein = P.m != nf;
+  // the chirp's period: the DFT length (2 nf for the chirp-z DST-I)
+  const long long L = P.cz ? 2LL * nf : nf;
   using cl = std::complex<long double>;
   auto expi = [](long double a) { return cl(cosl(a), sinl(a)); };
   P.off_tw = (int)ctab_.size();
@@ -236,8 +249,8 @@ int PlanCache::get(int n, int bc) {
   if (P.bluestein) {
     std::vector<cl> w(nf);
     for (int k = 0; k < nf; ++k) {
-      const long long kk = ((long long)k * k) % (2LL * nf);  // exact argument reduction
-      w[k] = expi(-kPi * (long double)kk / nf);
+      const long long kk = ((long long)k * k) % (2LL * L);   // exact argument reduction
+      w[k] = expi(-kPi * (long double)kk / L);
     }
     for (int k = 0; k < nf; ++k) ctab_.push_back(w[k]);
     std::vector<cl> b(P.m, cl(0, 0));
@@ -376,6 +389,8 @@ int validate3(const double* phi, const double* F, int nx, int ny, int nz, double
   const int v = validate(phi, F, nx, ny, h, bc & 0xff, tol, R);
   if (v != BHX_OK) return v;
   if (!length_supported(nz, bz, R.precision)) return BHX_ERR_ARG;
+  // the three-dimensional column passes (along y and z) have no chirp-z DST-I
+  if (dst_chirp(ny, (bc >> 4) & 15) || dst_chirp(nz, bz)) return BHX_ERR_ARG;
   if ((long long)nx * ny * nz >= (1LL << 31)) return BHX_ERR_ARG;
   return BHX_OK;
 }

@@ -217,6 +217,9 @@ int init_handle(bhx_handle* hd, int device);
 int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
                   hipStream_t st, Grids* gout);
 int fft_length(int n, int bc);
+// A Dirichlet axis whose DST-I runs as a chirp-z transform of n + 1 points
+// (1024 to 2046 nodes; AxisPlan::cz).
+bool dst_chirp(int n, int bc);
 // Both axes have a dense form (at most kDenseMax nodes).
 bool dense_eligible(const AxisPlan& X, const AxisPlan& Y);
 // Whether an instance with these axes runs the dense-transform passes under

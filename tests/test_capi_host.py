@@ -103,8 +103,12 @@ def test_workspace_bytes():
     assert bhx.workspace_bytes(64, 64, bhx.BC(2, 0)) > 0
     assert bhx.workspace_bytes(1023, 1023, bhx.BC(2, 2)) > 0          # core length 2048
     assert bhx.workspace_bytes(1000, 64, bhx.BC(2, 0)) > 0            # Bluestein core 4096
-    assert bhx.workspace_bytes(1100, 64, bhx.BC(2, 0)) == 0           # core 8192: too long
-    assert bhx.workspace_bytes(1100, 64, bhx.BC(2, 0), bhx.default_opts(precision=1)) > 0
+    # 1024-2046 nodes: a chirp-z DST-I of n + 1 points, Bluestein core 4096
+    for n in (1024, 1100, 1500, 2046):
+        assert bhx.workspace_bytes(n, n, bhx.BC(2, 2)) > 0
+        assert bhx.workspace_bytes(n, 64, bhx.BC(0, 2), bhx.default_opts(precision=1)) > 0
+    assert bhx.workspace_bytes(2047, 64, bhx.BC(2, 0)) > 0            # odd extension, core 4096
+    assert bhx.workspace_bytes(2048, 64, bhx.BC(2, 0)) == 0           # core 8192: too long
     assert bhx.workspace_bytes(64, 64, bhx.BC(3, 0)) == 0             # no such rule
 
 
@@ -125,7 +129,8 @@ def test_three_dimensional_arguments():
     assert bhx.workspace_bytes3d(64, 64, 64, 0x1000) == 0            # bits beyond z
     assert bhx.workspace_bytes3d(1024, 1024, 2048, 0) == 0           # 2^31 nodes
     assert bhx.workspace_bytes3d(100, 75, 33, bhx.BC3(2, 1, 0)) > 0  # Bluestein, Dirichlet
-    assert bhx.workspace_bytes3d(64, 64, 1100, bhx.BC3(0, 0, 2)) == 0   # z core too long
+    assert bhx.workspace_bytes3d(64, 64, 1100, bhx.BC3(0, 0, 2)) == 0   # no chirp-z along z
+    assert bhx.workspace_bytes3d(64, 1100, 64, bhx.BC3(0, 2, 0)) == 0   # nor along y
     s, _ = bhx.extend3d(None, FAKE, FAKE, 8, 8, 8)
     assert s == bhx.ERR_ARG
     for args in [(8, 8, 3, 0), (8, 8, 8, 0x300), (3, 8, 8, 0), (8, 8, 8, -1)]:

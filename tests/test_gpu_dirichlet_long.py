@@ -1,0 +1,101 @@
+"""Dirichlet axes of 1024 to 2046 nodes on the GPU (the rest of the sine
+transform rule): their DST-I runs as a chirp-z transform of n + 1 points
+(one real line per complex row, through a 4096-point Bluestein core),
+because the 2(n + 1)-point odd extension of the shorter axes would need an
+8192-point core.
+
+Bounds as in the generic parity tests: the preconditioner within relative L2
+1e-11 of the oracle's scipy DST-I (FP64) and 2e-4 (FP32); solved fields at
+tol 1e-12 within 1e-9 of the sparse direct oracle; the paper's 1024 x 1024
+rows of Tables 1 and 4 (Dirichlet, mixed, and Neumann beside them) as soft
+pins: iterations at tol 1e-6 within 8 %, errors near the interface within
+15 % (tests/golden/paper_tables_1024.txt)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1704_08897_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1704_08897_amd import bhx  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def handle():
+    h = bhx.Handle(0)
+    yield h
+    h.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# one long Dirichlet axis (both ends of the range, and between) with a short
+# axis of each rule, and both axes long
+CASES = [(1024, 40, 2, 0), (37, 1100, 1, 2), (1500, 21, 2, 2), (2046, 16, 2, 1),
+         (1024, 1024, 2, 2), (1300, 1031, 0, 2)]
+
+
+@pytest.mark.parametrize("nx,ny,bx,by", CASES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_long_dirichlet_preconditioner(handle, nx, ny, bx, by, prec):
+    rng = np.random.default_rng(nx + 7 * ny + bx + by)
+    phi = -(rng.random((ny, nx)) - 0.3)
+    r = rng.normal(size=(ny, nx))
+    known = O.known_mask(phi)
+    ref = O.spectral_preconditioner(r, known, bx, by)
+    out = dev(np.zeros((ny, nx)))
+    s = bhx.debug_apply(handle, 1, dev(phi), dev(r), out, bc=bhx.BC(bx, by), precision=prec)
+    assert s == bhx.OK
+    got = host(out)
+    assert np.array_equal(got[known], np.zeros(known.sum()))
+    assert O.relative_l2(got, ref) <= (1e-11 if prec == 0 else 2e-4)
+
+
+@pytest.mark.parametrize("nx,ny,bx,by", [(1100, 96, 2, 0), (80, 1300, 0, 2), (1024, 130, 2, 2)])
+def test_long_dirichlet_solve_matches_oracle(handle, nx, ny, bx, by):
+    h = 2.0 / min(nx, ny)
+    X, Y = np.meshgrid(W.axis_nodes(nx, -nx * h / 2, nx * h / 2, bx),
+                       W.axis_nodes(ny, -ny * h / 2, ny * h / 2, by))
+    phi = np.hypot(X, Y) - 0.6 * min(nx, ny) * h / 2
+    F = np.sin(X) + Y * Y
+    p = W.Problem(phi, F, bx, by, h, 1e-12)
+    G = dev(p.F)
+    s, st = bhx.extend_ex(handle, dev(p.phi), G, bc=p.bc, h=p.h, tol=p.tol)
+    assert s == bhx.OK, st.as_dict()
+    got = host(G)
+    K = O.known_mask(p.phi)
+    assert np.array_equal(got[K], p.F[K])
+    ref, _ = O.extend_direct(p.phi, p.F, p.bcx, p.bcy)
+    assert O.relative_l2(got, ref) <= 1e-9
+
+
+def test_paper_1024_rows(handle, golden_dir):
+    """Examples 1 and 3 at 1024 x 1024 with the paper's boundary rules: PCG
+    iterations at tol 1e-6 and errors near the interface against Tables 1
+    and 4."""
+    from test_oracle_pins import _BCL, _example, _near_error, _tables
+    done = {}
+    for name, n, bx, by, iters, kind, err in _tables(golden_dir, "paper_tables_1024.txt"):
+        key = (name, n, bx, by)
+        if key not in done:
+            p = _example(name, n, _BCL[bx], _BCL[by])
+            G = dev(p.F)
+            s, st = bhx.extend_ex(handle, dev(p.phi), G, bc=p.bc, h=p.h, tol=1e-6)
+            assert s == bhx.OK, key
+            done[key] = (p, host(G), st.iterations)
+        p, got, it = done[key]
+        assert abs(it - iters) <= 0.08 * iters, (key, it, iters)
+        e = _near_error(p, got, kind)
+        assert abs(e - err) <= 0.15 * err, (key, kind, e, err)

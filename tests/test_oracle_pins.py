@@ -417,9 +417,9 @@ def test_refinement_reaches_cubic_to_rounding():
 
 # -- P9: the paper's tables, soft --------------------------------------------------
 
-def _tables(golden_dir):
+def _tables(golden_dir, name="paper_tables.txt"):
     out = []
-    for l in open(os.path.join(golden_dir, "paper_tables.txt")):
+    for l in open(os.path.join(golden_dir, name)):
         if l.strip() and not l.startswith("#"):
             s = l.split()
             out.append((s[0], int(s[1]), s[2], s[3], int(s[4]), s[5], float(s[6])))
