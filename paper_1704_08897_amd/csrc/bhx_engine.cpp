@@ -209,12 +209,18 @@ Grids engine_grids(bhx_engine* E, const std::vector<Req*>& reqs) {
   g.c = cu * 2;
   const int csize = E->R.precision == 0 ? 16 : 8;
   int buf_r = 0, tab_r = 0, buf_c = 0, tab_c = 0;
+  int any_dense = 0;
   g.count = (int)reqs.size();
   for (Req* q : reqs) {
     g.reduce |= q->inst.reduce;
-    if (q->inst.dense) continue;                 // no FFT pass works on it
+    if (q->inst.dense) {                         // no FFT pass works on it
+      any_dense = 1;
+      continue;
+    }
     const AxisPlan& PX = E->hd->plans.plan(q->inst.planx);
     const AxisPlan& PY = E->hd->plans.plan(q->inst.plany);
+    plan_family(PX, q->inst.G / 2, &g.shape_r);  // plan-table kernel families
+    plan_family(PY, q->inst.Gc / 2, &g.shape_c);
     buf_r = std::max(buf_r, (q->inst.G / 2) * row_slots(PX.m));
     tab_r = std::max(tab_r, table_slots(PX.n, PX.m, PX.bc, false));
     buf_c = std::max(buf_c, (q->inst.Gc / 2) * row_slots(PY.m));
@@ -226,12 +232,13 @@ Grids engine_grids(bhx_engine* E, const std::vector<Req*>& reqs) {
   g.lds_r = std::min(kLdsDynMax, up((buf_r + tab_r) * csize));
   g.tw_c = buf_c;
   g.lds_c = std::min(kLdsDynMax, up((buf_c + tab_c) * csize));
-  // both transform families launch every iteration (a family without
-  // requests returns at once), with the dense passes sized for the longest
-  // dense axis, so the captured graphs do not depend on the active set
+  // the FFT family launches every iteration (with no request on it it
+  // returns at once); the dense passes, sized for the longest dense axis,
+  // only while a dense request is active.  The captured graphs depend on the
+  // active set through these few fields alone.
   g.fft = 1;
-  g.dense = 1;
-  dense_grids(E->R.precision, kDenseMax, kDenseMax, cu * 2, cu * 2, cu, 2, &g);
+  g.dense = any_dense;
+  if (any_dense) dense_grids(E->R.precision, kDenseMax, kDenseMax, cu * 2, cu * 2, cu, 2, &g);
   return g;
 }
 

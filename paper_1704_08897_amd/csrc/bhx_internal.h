@@ -43,7 +43,7 @@ enum Bc { kNeumann = 0, kPeriodic = 1, kDirichlet = 2 };
 
 // Shift of the second pad term of an FFT row in LDS (see rpos in the kernels):
 // rows of length 2^logm >= 256 get one extra slot every 2^(logm-4) elements.
-__host__ __device__ inline int rpos_shift(int logm) { return logm >= 8 ? logm - 4 : 31; }
+__host__ __device__ constexpr int rpos_shift(int logm) { return logm >= 8 ? logm - 4 : 31; }
 // Complex slots of the per-stage twiddle tables of a length-2^logm FFT: h
 // for each radix-4 stage of span h (h = 1, 4, 16, ... or 2, 8, 32, ...).
 __host__ __device__ inline int stage_twiddles(int logm) {
@@ -264,6 +264,17 @@ hipError_t launch_resid(const Batch* B, int dim, int grid, hipStream_t st);
 // pass family `pass` (ShapePass), or 0 when that shape is not instantiated; a
 // batch uses it when every instance has that axis plan and grouping.
 enum ShapePass { kShapeRow = 0, kShapeCol2D = 1, kShapeColY = 2, kShapeColZ = 3 };
+// Plan-table kernel families (`shape` values below 2^8, which no compile-time
+// shape takes): kShapeNarrowKey (0) has only the one-stage FFT passes, which
+// keeps its register use low; kShapeWideKey also has the 16-point passes,
+// for launches with a work item of at least kFftWideLaunch points
+// (rows x FFT length); kShapeCzKey in addition the chirp-z Dirichlet path,
+// for launches with such an axis.  All three give bit-identical results.
+constexpr int kShapeNarrowKey = 0;
+constexpr int kShapeCzKey = 1;
+constexpr int kShapeWideKey = 2;
+enum PlanFamily { kFamNarrow = 0, kFamWide = 1, kFamCz = 2 };
+constexpr int kFftWideLaunch = 4096;
 int shape_key(int pass, int prec, int n, int m, int logm, int bluestein, int bc, int group);
 // `stream_t` != 0: the row-forward pass writes t with non-temporal stores.
 // Its transposed store writes G-element pieces of many lines.  While the

@@ -481,130 +481,216 @@ struct XPlan {
   }
 };
 
-// In-place radix-4/2 DIT FFT of `rows` rows (stride `st`) of length m held in
-// LDS in bit-reversed order (positions rpos(., sh)); natural-order output;
-// sign -1.  `tw`: the per-stage twiddle tables of XPlan::stage().
-template <typename R>
-__device__ void fft_dit(typename V2<R>::T* buf, int rows, int st, int m, int logm, int sh,
-                        const typename V2<R>::T* __restrict__ tw) {
+// ---------------------------------------------------------------------------
+// LDS FFT in register passes
+//
+// The complex DFT of length m = 2^L is the in-place radix-4 decimation-in-time
+// FFT on bit-reversed input (with one radix-2 stage first when L is odd).  Its
+// stages are grouped into passes of one or two radix-4 stages (4 or 16
+// points; the radix-2 stage joins the first radix-4 one as an 8-point pass):
+// each thread loads the RAD points a pass combines into registers, runs the
+// pass's stages there and stores them back, so a row goes through LDS once
+// per pass instead of once per stage.  A pass of smallest span h combines
+// the points base + j h, j < RAD, with base = g RAD h + k and k < h; that set
+// is closed under each of its stages.  The inverse transform used inside
+// Bluestein's method is decimation in frequency over the same passes in the
+// reverse order, so the last forward pass and the first inverse pass combine
+// the same points: the pointwise product with the kernel spectrum between the
+// two convolution transforms happens in registers, as does the chirp on the
+// inputs in the first pass's loads.
+// ---------------------------------------------------------------------------
+
+// Passes of a length-2^L FFT in forward order: count, radix, log2 of the
+// span.  Wide schedule: 16-point passes (two radix-4 stages each), for blocks
+// whose rows hold enough points that every thread gets a 16-point group
+// (rows 2^L >= kFftWideMin); narrow schedule otherwise: one radix-4 stage per
+// pass, so that more threads share the short rows.
+constexpr int kFftWideMin = 2048;
+__host__ __device__ constexpr int fft_npass(int L, bool wide) {
+  return !wide ? (L & 1) ? 1 + (L - 3) / 2 : L / 2
+       : L <= 4 ? 1 : (L & 1) ? 1 + ((L - 3) / 2 + 1) / 2 : (L / 2 + 1) / 2;
+}
+__host__ __device__ constexpr int fft_pass_rad(int L, int p, bool wide) {
+  return !wide ? ((L & 1) && p == 0 ? 8 : 4)
+       : L <= 4 ? (1 << L)
+       : (L & 1) ? (p == 0 ? 8 : ((((L - 3) / 2) & 1) && p == 1) ? 4 : 16)
+                 : (((L / 2) & 1) && p == 0) ? 4 : 16;
+}
+__host__ __device__ constexpr int fft_pass_lspan(int L, int p, bool wide) {
+  // narrow: the 8-point pass (odd L) then radix-4 passes of span 8, 32, ...
+  // or (even L) of span 1, 4, ...; wide, odd L: the 8-point pass, an
+  // optional radix-4 pass of span 8, then 16-point passes from span 8 or 32;
+  // wide, even L: an optional radix-4 pass of span 1, then 16-point passes
+  // from span 1 or 4
+  return !wide ? ((L & 1) ? (p == 0 ? 0 : 3 + 2 * (p - 1)) : 2 * p)
+       : L <= 4 ? 0
+       : (L & 1) ? (p == 0 ? 0
+                    : (((L - 3) / 2) & 1) ? (p == 1 ? 3 : 5 + 4 * (p - 2)) : 3 + 4 * (p - 1))
+                 : (((L / 2) & 1) ? (p == 0 ? 0 : 2 + 4 * (p - 1)) : 4 * p);
+}
+
+// Radix-4 butterflies of one stage with twiddle w2 = W_4h^k (forward, the
+// stage's W_2h^k = w2^2) and its inverse with conj(w2).
+template <typename C>
+__device__ __forceinline__ void dit4(C& a0, C& a1, C& a2, C& a3, C w2) {
+  const C w1 = cmul(w2, w2);
+  C t = cmul(w1, a1);
+  const C t0 = cadd(a0, t), tt1 = csub(a0, t);
+  t = cmul(w1, a3);
+  const C tt2 = cadd(a2, t), tt3 = csub(a2, t);
+  t = cmul(w2, tt2);
+  a0 = cadd(t0, t);
+  a2 = csub(t0, t);
+  t = cmul_mi(cmul(w2, tt3));           // W_4h^(k+h) = W_4h^k (-i)
+  a1 = cadd(tt1, t);
+  a3 = csub(tt1, t);
+}
+template <typename C>
+__device__ __forceinline__ void dif4(C& a0, C& a1, C& a2, C& a3, C tw) {
+  const C w2 = cconj(tw);
+  const C w1 = cmul(w2, w2);
+  const C t0 = cadd(a0, a2), t2v = cmul(csub(a0, a2), w2);
+  const C t1v = cadd(a1, a3), t3 = cmul_pi(cmul(csub(a1, a3), w2));
+  a0 = cadd(t0, t1v);
+  a1 = cmul(csub(t0, t1v), w1);
+  a2 = cadd(t2v, t3);
+  a3 = cmul(csub(t2v, t3), w1);
+}
+template <typename C> __device__ __forceinline__ void bfly2(C& a0, C& a1) {
+  const C u = a0, v = a1;
+  a0 = cadd(u, v);
+  a1 = csub(u, v);
+}
+
+enum { kFftChirp = 1, kFftDit = 2, kFftBhat = 4, kFftDif = 8 };
+
+// One pass of RAD points (4, 8 or 16) and span 2^lh over `rows` rows of
+// length 2^logm (stride st, pad shift sh).  `fl` selects, in this order: the
+// chirp on the inputs (Bluestein; inputs at logical index >= nf are zero),
+// the forward stages, the product with the kernel spectrum bhat, the inverse
+// stages.  Stage twiddles: the table of span h starts at (h - h0) / 3.
+template <typename R, int RAD>
+__device__ __forceinline__ void fft_pass(typename V2<R>::T* buf, int rows, int st, int logm,
+                                         int sh, int lh, int fl,
+                                         const typename V2<R>::T* __restrict__ tw,
+                                         BHX_GLOBAL const typename V2<R>::T* chirp, int nf,
+                                         BHX_GLOBAL const typename V2<R>::T* bhat) {
   using C = typename V2<R>::T;
-  const int tid = threadIdx.x;
-  int h = 1;
-  if (logm & 1) {
-    const int half = m >> 1;
-    for (int idx = tid; idx < rows * half; idx += kThreads) {
-      const int r = idx >> (logm - 1), b = (idx & (half - 1)) << 1;
-      C* a = buf + r * st;
-      const int i0 = rpos(b, sh), i1 = rpos(b + 1, sh);
-      C u = a[i0], v = a[i1];
-      a[i0] = cadd(u, v);
-      a[i1] = csub(u, v);
+  constexpr int LR = RAD == 4 ? 2 : RAD == 8 ? 3 : 4;
+  const int h = 1 << lh;
+  const int h0 = (logm & 1) ? 2 : 1;
+  const int lnb = logm - LR;                  // log2 of the point groups per row
+  const C* __restrict__ ta = tw + ((h - h0) / 3);            // span h (RAD 4, 16)
+  const C* __restrict__ tb = tw + ((4 * h - h0) / 3);        // span 4h (RAD 16)
+  for (int u = threadIdx.x; u < (rows << lnb); u += kThreads) {
+    const int r = u >> lnb, rem = u & ((1 << lnb) - 1);
+    const int k = rem & (h - 1);
+    const int base = ((rem >> lh) << (LR + lh)) + k;
+    C* a = buf + r * st;
+    C v[RAD];
+#pragma unroll
+    for (int j = 0; j < RAD; ++j) v[j] = a[rpos(base + (j << lh), sh)];
+    if (fl & kFftChirp) {
+#pragma unroll
+      for (int j = 0; j < RAD; ++j) {
+        const int q = bitrev(base + (j << lh), logm);
+        const C c = chirp[min(q, nf - 1)];
+        v[j] = q < nf ? cmul(v[j], c) : mk<C>(0, 0);
+      }
     }
-    __syncthreads();
-    h = 2;
-  }
-  const int lq = logm - 2;
-  for (int toff = 0; h < m; toff += h, h <<= 2) {
-    const int quarter = m >> 2;
-    const C* __restrict__ t2 = tw + toff;      // W_4h^k
-    for (int idx = tid; idx < rows * quarter; idx += kThreads) {
-      const int r = idx >> lq, rem = idx & (quarter - 1);
-      const int k = rem & (h - 1);
-      const int b = (rem - k) << 2;
-      C* a = buf + r * st;
-      const int i0 = rpos(b + k, sh), i1 = rpos(b + k + h, sh), i2 = rpos(b + k + 2 * h, sh),
-                i3 = rpos(b + k + 3 * h, sh);
-      const C w2 = t2[k];
-      const C w1 = cmul(w2, w2);           // W_2h^k
-      C a0 = a[i0], a1 = a[i1], a2 = a[i2], a3 = a[i3];
-      C t = cmul(w1, a1);
-      C t0 = cadd(a0, t), tt1 = csub(a0, t);
-      t = cmul(w1, a3);
-      C tt2 = cadd(a2, t), tt3 = csub(a2, t);
-      t = cmul(w2, tt2);
-      a[i0] = cadd(t0, t);
-      a[i2] = csub(t0, t);
-      t = cmul_mi(cmul(w2, tt3));          // W_4h^(k+h) = W_4h^k * (-i)
-      a[i1] = cadd(tt1, t);
-      a[i3] = csub(tt1, t);
+    if (fl & kFftDit) {
+      if constexpr (RAD == 4) {
+        dit4(v[0], v[1], v[2], v[3], ta[k]);
+      } else if constexpr (RAD == 8) {
+        // radix-2 (span 1), then radix-4 of span 2 (its table starts at 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bfly2(v[2 * q], v[2 * q + 1]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) dit4(v[q], v[q + 2], v[q + 4], v[q + 6], tw[q]);
+      } else {
+        const C wa = ta[k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dit4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3], wa);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dit4(v[q], v[q + 4], v[q + 8], v[q + 12], tb[k + q * h]);
+      }
     }
-    __syncthreads();
+    if (fl & kFftBhat) {
+#pragma unroll
+      for (int j = 0; j < RAD; ++j) v[j] = cmul(v[j], bhat[base + (j << lh)]);
+    }
+    if (fl & kFftDif) {
+      if constexpr (RAD == 4) {
+        dif4(v[0], v[1], v[2], v[3], ta[k]);
+      } else if constexpr (RAD == 8) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) dif4(v[q], v[q + 2], v[q + 4], v[q + 6], tw[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bfly2(v[2 * q], v[2 * q + 1]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dif4(v[q], v[q + 4], v[q + 8], v[q + 12], tb[k + q * h]);
+        const C wa = ta[k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dif4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3], wa);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < RAD; ++j) a[rpos(base + (j << lh), sh)] = v[j];
   }
 }
 
-// In-place radix-4/2 DIF FFT, natural-order input, bit-reversed output,
-// sign +1, unnormalised (inverse of fft_dit up to the factor m).
-template <typename R>
-__device__ void fft_dif_inv(typename V2<R>::T* buf, int rows, int st, int m, int logm, int sh,
-                            const typename V2<R>::T* __restrict__ tw) {
-  using C = typename V2<R>::T;
-  const int tid = threadIdx.x;
-  const int lq = logm - 2;
-  // the stages run from the largest span down: start at the last table
-  int toff = stage_twiddles(logm) - (m >> 2);
-  for (int h = m >> 2; h >= 1; h >>= 2) {
-    const int quarter = m >> 2;
-    const C* __restrict__ t2 = tw + toff;
-    for (int idx = tid; idx < rows * quarter; idx += kThreads) {
-      const int r = idx >> lq, rem = idx & (quarter - 1);
-      const int k = rem & (h - 1);
-      const int b = (rem - k) << 2;
-      C* a = buf + r * st;
-      const int i0 = rpos(b + k, sh), i1 = rpos(b + k + h, sh), i2 = rpos(b + k + 2 * h, sh),
-                i3 = rpos(b + k + 3 * h, sh);
-      const C w2 = cconj(t2[k]);
-      const C w1 = cmul(w2, w2);
-      C a0 = a[i0], a1 = a[i1], a2 = a[i2], a3 = a[i3];
-      C t0 = cadd(a0, a2), t2v = cmul(csub(a0, a2), w2);
-      C t1v = cadd(a1, a3), t3 = cmul_pi(cmul(csub(a1, a3), w2));   // conj(W_4h^(k+h))
-      a[i0] = cadd(t0, t1v);
-      a[i1] = cmul(csub(t0, t1v), w1);
-      a[i2] = cadd(t2v, t3);
-      a[i3] = cmul(csub(t2v, t3), w1);
-    }
+// The forward passes of a length-2^L FFT known at compile time.
+template <typename R, int L, bool W, int P>
+__device__ __forceinline__ void fft_fixed(typename V2<R>::T* buf, int rows, int st,
+                                          const typename V2<R>::T* __restrict__ tw) {
+  if constexpr (P < fft_npass(L, W)) {
+    fft_pass<R, fft_pass_rad(L, P, W)>(buf, rows, st, L, rpos_shift(L),
+                                       fft_pass_lspan(L, P, W), kFftDit, tw, nullptr, 0,
+                                       nullptr);
     __syncthreads();
-    if (h == 1 || h == 2) break;
-    toff -= h >> 2;
-  }
-  if (logm & 1) {
-    const int half = m >> 1;
-    for (int idx = tid; idx < rows * half; idx += kThreads) {
-      const int r = idx >> (logm - 1), b = (idx & (half - 1)) << 1;
-      C* a = buf + r * st;
-      const int i0 = rpos(b, sh), i1 = rpos(b + 1, sh);
-      C u = a[i0], v = a[i1];
-      a[i0] = cadd(u, v);
-      a[i1] = csub(u, v);
-    }
-    __syncthreads();
+    fft_fixed<R, L, W, P + 1>(buf, rows, st, tw);
   }
 }
 
-// After inputs are placed at pos(k) (k < n): Bluestein multiplies by the
-// chirp and zero-fills k in [n, m); then the core forward DFT of length n.
-template <typename R, int SP>
+// After inputs are placed at pos(k) (k < nf): the forward DFT of length nf of
+// every row.  Power-of-two nf: the FFT passes, natural-order output.
+// Otherwise Bluestein: chirp (zero past nf), FFT, product with the kernel
+// spectrum, inverse FFT (bit-reversed output; out() applies the final chirp).
+template <bool W, typename R, int SP>
 __device__ void dft_core(const XPlan<R, SP>& X, typename V2<R>::T* buf, int rows) {
-  using C = typename V2<R>::T;
-  const int st = X.stride();
-  if (X.blue) {
-    for (int idx = threadIdx.x; idx < rows * X.m; idx += kThreads) {
-      const int r = idx >> X.logm, k = idx & (X.m - 1);
-      C* row = buf + r * st;
-      const int p = X.pos(k);
-      const C c = X.chirp[min(k, X.nf - 1)];
-      row[p] = k < X.nf ? cmul(row[p], c) : mk<C>(0, 0);
+  if constexpr (SP != 0) {
+    constexpr int L = (SP >> 2) & 63;
+    // rows is a constant of the instance here
+    if ((rows << L) >= kFftWideMin)
+      fft_fixed<R, L, true, 0>(buf, rows, X.stride(), X.tw);
+    else
+      fft_fixed<R, L, false, 0>(buf, rows, X.stride(), X.tw);
+  } else {
+    const int st = X.stride();
+    const int logm = X.logm;
+    // W = false: instances compiled without the 16-point pass body (lower
+    // register use); every row takes the narrow schedule, same arithmetic
+    const bool wide = W && (rows << logm) >= kFftWideMin;
+    const int np = fft_npass(logm, wide);
+    const bool blue = X.blue;
+    // steps 0..np-1: forward passes; then (Bluestein) passes np-2..0 inverse
+    const int nstep = blue ? 2 * np - 1 : np;
+#pragma unroll 1
+    for (int s = 0; s < nstep; ++s) {
+      const int p = s < np ? s : 2 * np - 2 - s;
+      int fl = s < np ? kFftDit : kFftDif;
+      if (blue && s == 0) fl |= kFftChirp;
+      if (blue && s == np - 1) fl |= kFftBhat | kFftDif;
+      const int rad = fft_pass_rad(logm, p, wide), lh = fft_pass_lspan(logm, p, wide);
+      if (W && rad == 16)
+        fft_pass<R, W ? 16 : 4>(buf, rows, st, logm, X.sh, lh, fl, X.tw, X.chirp, X.nf, X.bhat);
+      else if (rad == 8)
+        fft_pass<R, 8>(buf, rows, st, logm, X.sh, lh, fl, X.tw, X.chirp, X.nf, X.bhat);
+      else
+        fft_pass<R, 4>(buf, rows, st, logm, X.sh, lh, fl, X.tw, X.chirp, X.nf, X.bhat);
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  fft_dit<R>(buf, rows, st, X.m, X.logm, X.sh, X.tw);
-  if (X.blue) {
-    for (int idx = threadIdx.x; idx < rows * X.m; idx += kThreads) {
-      const int r = idx >> X.logm, k = idx & (X.m - 1);
-      const int p = r * st + rpos(k, X.sh);
-      buf[p] = cmul(buf[p], X.bhat[k]);
-    }
-    __syncthreads();
-    fft_dif_inv<R>(buf, rows, st, X.m, X.logm, X.sh, X.tw);
   }
 }
 
@@ -1168,10 +1254,12 @@ __global__ void __launch_bounds__(kThreads) k_resid(const Batch* __restrict__ Bp
 // buffer parity of the iteration (as in k_stencil): p_new = p[lpar ^ 1],
 // current r.z partials rz(lpar).  SP: compile-time shape of the x axis and
 // row group (see XPlan), 0 for any shape.
-template <typename R, int SP>
+template <typename R, int SP, int FAM = 0>
 __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ Bp, int mode,
                                                      int twoff, int lpar) {
   using C = typename V2<R>::T;
+  constexpr bool CZ = FAM == kFamCz;
+  constexpr bool kWide = FAM != kFamNarrow;
   const int update = mode & 3;
   const bool stream_t = (mode & 4) != 0;
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
@@ -1239,6 +1327,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
       xv0[u] = update ? Fb[ea] : 0.0;
     }
     XPlan<R, SP> X(B, I.planx);
+    if constexpr (!CZ) X.cz = 0;   // chirp-z axes run on the CZ instances only
     if (update != 2) X.stage(twl, I.planx, staged, false);
     double alpha = 0.0;
     if (update) {
@@ -1297,7 +1386,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
       if (update == 2) continue;       // plain CG: update only
     }
     // 2. FFT
-    dft_core<R>(X, buf, rows);
+    dft_core<kWide>(X, buf, rows);
     // 3. real spectra of the pairs (k, n-k) into registers
     const int np = X.pairs();
     R va[kMaxPairs][4];
@@ -1321,7 +1410,7 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
       }
       X.zero_ends(buf, rows, st);
       __syncthreads();
-      dft_core<R>(X, buf, rows);
+      dft_core<kWide>(X, buf, rows);
 #pragma unroll
       for (int s = 0; s < kMaxPairs; ++s) {
         const int pidx = threadIdx.x + s * kThreads;
@@ -1393,10 +1482,12 @@ __global__ void __launch_bounds__(kThreads) k_rowfwd(const Batch* __restrict__ B
 // group (see XPlan), 0 for any shape.
 // ---------------------------------------------------------------------------
 
-template <typename R, int KIND, int SP>
+template <typename R, int KIND, int SP, int FAM = 0>
 __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, int count_iter,
                                                   int twoff) {
   using C = typename V2<R>::T;
+  constexpr bool CZ = FAM == kFamCz;
+  constexpr bool kWide = FAM != kFamNarrow;
   constexpr int kPass = KIND == kColZ ? kPassZ : kPassC;
   constexpr bool kStrided = KIND == kColZ;       // z pencils: stride ny
   constexpr bool kScale = KIND == kCol2D || KIND == kColZ;
@@ -1474,6 +1565,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
     }
     if (ctl->done) continue;
     XPlan<R, SP> X(B, plan);
+    if constexpr (!CZ) X.cz = 0;   // chirp-z axes run on the CZ instances only
     X.stage(twl, plan, staged, kScale);
     const int rows = Gp >> 1;
     const int st = X.stride();
@@ -1484,6 +1576,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
         // second, each through forward, scale and inverse (the DST-I is its
         // own inverse) in the pair's row
         if (threadIdx.x < kMaxGc) s_lam[threadIdx.x] = lam;
+#pragma unroll 1
         for (int h = 0; h < 2; ++h) {
           for (int e = threadIdx.x; e < Et; e += kThreads) {
             int cr, j;
@@ -1492,7 +1585,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
           }
           X.zero_ends(buf, rows, st);
           __syncthreads();
-          dft_core<R>(X, buf, rows);
+          dft_core<kWide>(X, buf, rows);
           R ys[kMaxPairs][2];
 #pragma unroll
           for (int s = 0; s < kMaxPairs; ++s) {
@@ -1521,7 +1614,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
           }
           X.zero_ends(buf, rows, st);
           __syncthreads();
-          dft_core<R>(X, buf, rows);
+          dft_core<kWide>(X, buf, rows);
 #pragma unroll
           for (int s = 0; s < kMaxPairs; ++s) {
             const int pidx = threadIdx.x + s * kThreads;
@@ -1561,7 +1654,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
       if (kScale && threadIdx.x < kMaxGc) s_lam[threadIdx.x] = lam;
       X.zero_ends(buf, rows, st);
       __syncthreads();
-      dft_core<R>(X, buf, rows);
+      dft_core<kWide>(X, buf, rows);
 #pragma unroll
       for (int s = 0; s < kMaxPairs; ++s) {
         const int pidx = threadIdx.x + s * kThreads;
@@ -1635,7 +1728,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
     }
     X.zero_ends(buf, rows, st);
     __syncthreads();
-    dft_core<R>(X, buf, rows);
+    dft_core<kWide>(X, buf, rows);
     // 4. inverse outputs back into t
     if (X.bc == kNeumann) {
       for (int e = threadIdx.x; e < Et; e += kThreads) {
@@ -1717,10 +1810,12 @@ __global__ void __launch_bounds__(kThreads) k_col(const Batch* __restrict__ Bp, 
 // `lpar`: buffer parity of the iteration; the r.z partials written here are
 // the next iteration's current ones, rz(lpar ^ 1) (and rzo(lpar ^ 1)).  SP as
 // in k_rowfwd.
-template <typename R, int SP>
-__global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ Bp, int twoff,
-                                                     int lpar) {
+template <typename R, int SP, int FAM = 0>
+__global__ void __launch_bounds__(kThreads, FAM == kFamCz ? 1 : 2)
+    k_rowinv(const Batch* __restrict__ Bp, int twoff, int lpar) {
   using C = typename V2<R>::T;
+  constexpr bool CZ = FAM == kFamCz;
+  constexpr bool kWide = FAM != kFamNarrow;
   const Batch B = *(BHX_CONST const Batch*)Bp;   // scalar loads, kept in registers
   extern __shared__ __align__(16) unsigned char smem[];
   debug_fill_lds(smem);
@@ -1758,9 +1853,13 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
     BHX_GLOBAL const double* __restrict__ rb = I.r + base;
     BHX_GLOBAL double* __restrict__ zb = I.z + base;
     const bool flex = I.flexible != 0;
-    int m0[kPre];
+    // outputs prefetched across the transform (compile-time shapes only, and
+    // fewer for rows of 2048 points or more: the registers go to the
+    // transform passes)
+    constexpr int kPreO = SP == 0 ? 0 : ((SP >> 2) & 63) >= 11 ? kPre / 2 : kPre;
+    int m0[kPreO + 1];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
+    for (int u = 0; u < kPreO; ++u) {
       const int e = threadIdx.x + u * kThreads;
       m0[u] = mk[min(e, E - 1)] && e < E;
     }
@@ -1774,14 +1873,15 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
       }
       continue;
     }
-    double rv0[kPre], zo0[kPre];
+    double rv0[kPreO + 1], zo0[kPreO + 1];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
+    for (int u = 0; u < kPreO; ++u) {
       const int ea = m0[u] ? threadIdx.x + u * kThreads : 0;
       rv0[u] = rb[ea];
       zo0[u] = flex ? zb[ea] : 0.0;
     }
     XPlan<R, SP> X(B, I.planx);
+    if constexpr (!CZ) X.cz = 0;   // chirp-z axes run on the CZ instances only
     X.stage(twl, I.planx, staged, false);
     const int rows = G >> 1;
     const int st = X.stride();
@@ -1800,35 +1900,42 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
     if (X.cz) {
       // chirp-z DST-I (its own inverse): the first line of each pair, then
       // the second, in the pair's row; outputs, z and dots per line.  The
-      // spectra share LDS with the rows: all of them into registers first.
-      R sv[kMaxPairs][4];
-#pragma unroll
-      for (int s = 0; s < kMaxPairs; ++s) {
-        const int pidx = threadIdx.x + s * kThreads;
-        if (pidx < rows * np) {
-          const int rr = pidx / np, k = pidx - rr * np;
-          const int kk = X.partner(k);
-          sv[s][0] = stg[k * G + 2 * rr];
-          sv[s][1] = stg[kk * G + 2 * rr];
-          sv[s][2] = stg[k * G + 2 * rr + 1];
-          sv[s][3] = stg[kk * G + 2 * rr + 1];
-        }
-      }
-      __syncthreads();
+      // spectra share LDS with the rows: the first lines' ones go through
+      // registers before the rows are written, the second lines' are read
+      // again from t.
+#pragma unroll 1
       for (int h = 0; h < 2; ++h) {
+        R sv[kMaxPairs][2];
 #pragma unroll
         for (int s = 0; s < kMaxPairs; ++s) {
           const int pidx = threadIdx.x + s * kThreads;
           if (pidx < rows * np) {
             const int rr = pidx / np, k = pidx - rr * np;
             const int kk = X.partner(k);
-            X.put_cz(buf + rr * st, k, sv[s][2 * h]);
-            if (kk != k) X.put_cz(buf + rr * st, kk, sv[s][2 * h + 1]);
+            const int jr = 2 * rr + h;
+            if (h == 0) {
+              sv[s][0] = stg[k * G + jr];
+              sv[s][1] = stg[kk * G + jr];
+            } else {
+              sv[s][0] = jr < jn ? t[(size_t)k * ny + j0 + jr] : (R)0;
+              sv[s][1] = jr < jn ? t[(size_t)kk * ny + j0 + jr] : (R)0;
+            }
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < kMaxPairs; ++s) {
+          const int pidx = threadIdx.x + s * kThreads;
+          if (pidx < rows * np) {
+            const int rr = pidx / np, k = pidx - rr * np;
+            const int kk = X.partner(k);
+            X.put_cz(buf + rr * st, k, sv[s][0]);
+            if (kk != k) X.put_cz(buf + rr * st, kk, sv[s][1]);
           }
         }
         X.zero_ends(buf, rows, st);
         __syncthreads();
-        dft_core<R>(X, buf, rows);
+        dft_core<kWide>(X, buf, rows);
         for (int e = threadIdx.x; e < E; e += kThreads) {
           const int jr = e / nx, i = e - jr * nx;
           if ((jr & 1) != h || !mk[e]) continue;
@@ -1865,7 +1972,7 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
     }
     X.zero_ends(buf, rows, st);
     __syncthreads();
-    dft_core<R>(X, buf, rows);
+    dft_core<kWide>(X, buf, rows);
     // 3. outputs: restrict, store z, dots
     auto emit = [&](int e, int m, double rv, double zo) {
       if (!m) return;
@@ -1890,8 +1997,8 @@ __global__ void __launch_bounds__(kThreads) k_rowinv(const Batch* __restrict__ B
       acco += rv * zo;
     };
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) emit(threadIdx.x + u * kThreads, m0[u], rv0[u], zo0[u]);
-    for (int e0 = threadIdx.x + kPre * kThreads; e0 < E; e0 += kUnroll * kThreads) {
+    for (int u = 0; u < kPreO; ++u) emit(threadIdx.x + u * kThreads, m0[u], rv0[u], zo0[u]);
+    for (int e0 = threadIdx.x + kPreO * kThreads; e0 < E; e0 += kUnroll * kThreads) {
       int m[kUnroll];
       double rv[kUnroll], zo[kUnroll];
 #pragma unroll
@@ -2585,6 +2692,12 @@ hipError_t launch_rowfwd(const Batch* B, int prec, int shape, int update, int st
       BHX_COL2D_SHAPES(BHX_CASE)
 #undef BHX_CASE
       case 0: BHX_LAUNCH((k_rowfwd<float, 0>), grid, lds, st, e0, e1, B, update, twoff, lpar); break;
+      case kShapeWideKey:
+        BHX_LAUNCH((k_rowfwd<float, 0, kFamWide>), grid, lds, st, e0, e1, B, update, twoff, lpar);
+        break;
+      case kShapeCzKey:
+        BHX_LAUNCH((k_rowfwd<float, 0, kFamCz>), grid, lds, st, e0, e1, B, update, twoff, lpar);
+        break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2598,24 +2711,49 @@ hipError_t launch_rowfwd(const Batch* B, int prec, int shape, int update, int st
     BHX_ROW_SHAPES(BHX_CASE)
 #undef BHX_CASE
     case 0: BHX_LAUNCH((k_rowfwd<double, 0>), grid, lds, st, e0, e1, B, update, twoff, lpar); break;
+    case kShapeWideKey:
+      BHX_LAUNCH((k_rowfwd<double, 0, kFamWide>), grid, lds, st, e0, e1, B, update, twoff, lpar);
+      break;
+    case kShapeCzKey:
+      BHX_LAUNCH((k_rowfwd<double, 0, kFamCz>), grid, lds, st, e0, e1, B, update, twoff, lpar);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template <typename R, int FAM>
+static hipError_t launch_col_fam(const Batch* B, int kind, int count_iter, int grid, int lds,
+                                 int twoff, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  switch (kind) {
+    case kCol2D: BHX_LAUNCH((k_col<R, kCol2D, 0, FAM>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
+    case kColYFwd: BHX_LAUNCH((k_col<R, kColYFwd, 0, FAM>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
+    case kColZ: BHX_LAUNCH((k_col<R, kColZ, 0, FAM>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
+    case kColYInv: BHX_LAUNCH((k_col<R, kColYInv, 0, FAM>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 template <typename R>
-static hipError_t launch_col_prec(const Batch* B, int kind, int count_iter, int grid, int lds,
-                                  int twoff, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  switch (kind) {
-    case kCol2D: BHX_LAUNCH((k_col<R, kCol2D, 0>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
-    case kColYFwd: BHX_LAUNCH((k_col<R, kColYFwd, 0>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
-    case kColZ: BHX_LAUNCH((k_col<R, kColZ, 0>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
-    case kColYInv: BHX_LAUNCH((k_col<R, kColYInv, 0>), grid, lds, st, e0, e1, B, count_iter, twoff); break;
-    default: return hipErrorInvalidValue;
+static hipError_t launch_col_prec(const Batch* B, int kind, int shape, int count_iter, int grid,
+                                  int lds, int twoff, hipStream_t st, hipEvent_t e0,
+                                  hipEvent_t e1) {
+  if (shape == kShapeCzKey) {
+    // chirp-z Dirichlet axes exist in two dimensions only
+    if (kind != kCol2D) return hipErrorInvalidValue;
+    BHX_LAUNCH((k_col<R, kCol2D, 0, kFamCz>), grid, lds, st, e0, e1, B, count_iter, twoff);
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  return shape == kShapeWideKey
+             ? launch_col_fam<R, kFamWide>(B, kind, count_iter, grid, lds, twoff, st, e0, e1)
+             : launch_col_fam<R, kFamNarrow>(B, kind, count_iter, grid, lds, twoff, st, e0, e1);
 }
 hipError_t launch_col(const Batch* B, int prec, int shape, int kind, int count_iter, int grid,
                       int lds, int twoff, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (shape == kShapeCzKey || shape == kShapeWideKey) {
+    return prec == 0
+               ? launch_col_prec<double>(B, kind, shape, count_iter, grid, lds, twoff, st, e0, e1)
+               : launch_col_prec<float>(B, kind, shape, count_iter, grid, lds, twoff, st, e0, e1);
+  }
   if (shape != 0 && prec != 0) {
     if (kind != kCol2D) return hipErrorInvalidValue;
     switch (shape) {
@@ -2662,8 +2800,9 @@ hipError_t launch_col(const Batch* B, int prec, int shape, int kind, int count_i
 #undef BHX_CASE_K
     return hipGetLastError();
   }
-  return prec == 0 ? launch_col_prec<double>(B, kind, count_iter, grid, lds, twoff, st, e0, e1)
-                   : launch_col_prec<float>(B, kind, count_iter, grid, lds, twoff, st, e0, e1);
+  return prec == 0
+             ? launch_col_prec<double>(B, kind, 0, count_iter, grid, lds, twoff, st, e0, e1)
+             : launch_col_prec<float>(B, kind, 0, count_iter, grid, lds, twoff, st, e0, e1);
 }
 hipError_t launch_rowinv(const Batch* B, int prec, int shape, int grid, int lds, int twoff,
                          int lpar, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
@@ -2676,6 +2815,12 @@ hipError_t launch_rowinv(const Batch* B, int prec, int shape, int grid, int lds,
       BHX_COL2D_SHAPES(BHX_CASE)
 #undef BHX_CASE
       case 0: BHX_LAUNCH((k_rowinv<float, 0>), grid, lds, st, e0, e1, B, twoff, lpar); break;
+      case kShapeWideKey:
+        BHX_LAUNCH((k_rowinv<float, 0, kFamWide>), grid, lds, st, e0, e1, B, twoff, lpar);
+        break;
+      case kShapeCzKey:
+        BHX_LAUNCH((k_rowinv<float, 0, kFamCz>), grid, lds, st, e0, e1, B, twoff, lpar);
+        break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2688,6 +2833,12 @@ hipError_t launch_rowinv(const Batch* B, int prec, int shape, int grid, int lds,
     BHX_ROW_SHAPES(BHX_CASE)
 #undef BHX_CASE
     case 0: BHX_LAUNCH((k_rowinv<double, 0>), grid, lds, st, e0, e1, B, twoff, lpar); break;
+    case kShapeWideKey:
+      BHX_LAUNCH((k_rowinv<double, 0, kFamWide>), grid, lds, st, e0, e1, B, twoff, lpar);
+      break;
+    case kShapeCzKey:
+      BHX_LAUNCH((k_rowinv<double, 0, kFamCz>), grid, lds, st, e0, e1, B, twoff, lpar);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -2777,6 +2928,24 @@ hipError_t set_kernel_attributes() {
   set((const void*)k_col<float, kColYInv, 0>);
   set((const void*)k_rowinv<double, 0>);
   set((const void*)k_rowinv<float, 0>);
+  set((const void*)k_rowfwd<double, 0, kFamCz>);
+  set((const void*)k_rowfwd<float, 0, kFamCz>);
+  set((const void*)k_col<double, kCol2D, 0, kFamCz>);
+  set((const void*)k_col<float, kCol2D, 0, kFamCz>);
+  set((const void*)k_rowinv<double, 0, kFamCz>);
+  set((const void*)k_rowinv<float, 0, kFamCz>);
+  set((const void*)k_rowfwd<double, 0, kFamWide>);
+  set((const void*)k_rowfwd<float, 0, kFamWide>);
+  set((const void*)k_col<double, kCol2D, 0, kFamWide>);
+  set((const void*)k_col<float, kCol2D, 0, kFamWide>);
+  set((const void*)k_col<double, kColYFwd, 0, kFamWide>);
+  set((const void*)k_col<float, kColYFwd, 0, kFamWide>);
+  set((const void*)k_col<double, kColZ, 0, kFamWide>);
+  set((const void*)k_col<float, kColZ, 0, kFamWide>);
+  set((const void*)k_col<double, kColYInv, 0, kFamWide>);
+  set((const void*)k_col<float, kColYInv, 0, kFamWide>);
+  set((const void*)k_rowinv<double, 0, kFamWide>);
+  set((const void*)k_rowinv<float, 0, kFamWide>);
   set((const void*)k_rowfwd_dense<double>);
   set((const void*)k_rowfwd_dense<float>);
   set((const void*)k_col_dense<double>);

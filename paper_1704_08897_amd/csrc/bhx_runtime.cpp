@@ -900,6 +900,9 @@ int batch_grids(const PlanCache& plans, const BatchDesc& D, const Resolved& R, i
       if (D.pz[i] != D.pz[f0] || D.lay[i].Gz != D.lay[f0].Gz) g.shape_z = 0;
       if (D.py[i] != D.py[f0] || D.lay[i].Gc != D.lay[f0].Gc) g.shape_c = 0;
     }
+    // plan-table launches: the kernel family from the longest work item
+    // and the chirp-z axes
+    plan_families(plans, D, &g);
   }
   {
     int nxm = 0, nym = 0;
@@ -923,6 +926,24 @@ int batch_grids(const PlanCache& plans, const BatchDesc& D, const Resolved& R, i
   }
   *gout = g;
   return BHX_OK;
+}
+
+void plan_family(const AxisPlan& P, int rows, int* shape) {
+  if (*shape != kShapeNarrowKey && *shape != kShapeWideKey) return;   // compile-time shape or cz
+  if (P.cz)
+    *shape = kShapeCzKey;
+  else if ((long)rows * P.m >= kFftWideLaunch)
+    *shape = kShapeWideKey;
+}
+
+void plan_families(const PlanCache& plans, const BatchDesc& D, Grids* g) {
+  const bool sr = g->shape_r == 0, sc = g->shape_c == 0, sz = g->shape_z == 0;
+  for (size_t i = 0; i < D.inst.size(); ++i) {
+    if (D.dense[i]) continue;
+    if (sr) plan_family(plans.plan(D.px[i]), D.lay[i].G / 2, &g->shape_r);
+    if (sc) plan_family(plans.plan(D.py[i]), D.lay[i].Gc / 2, &g->shape_c);
+    if (sz && D.dim == 3) plan_family(plans.plan(D.pz[i]), D.lay[i].Gz / 2, &g->shape_z);
+  }
 }
 
 int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,

@@ -131,6 +131,13 @@ struct BatchDesc {
   size_t ws_bytes = 0;      // control blocks + instance regions
 };
 
+// Plan-table kernel family of a pass (shape kShapeNarrowKey, kShapeWideKey or
+// kShapeCzKey): raised to what an axis plan with `rows` packed rows per work
+// item needs; compile-time shapes are left alone.
+void plan_family(const AxisPlan& P, int rows, int* shape);
+// The same over every FFT-family instance of a batch, for the three passes.
+void plan_families(const PlanCache& plans, const BatchDesc& D, Grids* g);
+
 // Where the driver loop finds a prepared batch's device state.
 struct DriveCtx {
   const Batch* B = nullptr;   // device batch header
