@@ -208,7 +208,7 @@ Grids engine_grids(bhx_engine* E, const std::vector<Req*>& reqs) {
   g.r = cu * 2;
   g.c = cu * 2;
   const int csize = E->R.precision == 0 ? 16 : 8;
-  int buf_r = 0, tab_r = 0, buf_c = 0, tab_c = 0;
+  int buf_r = 0, buf_c = 0;
   int any_dense = 0;
   g.count = (int)reqs.size();
   for (Req* q : reqs) {
@@ -222,16 +222,17 @@ Grids engine_grids(bhx_engine* E, const std::vector<Req*>& reqs) {
     plan_family(PX, q->inst.G / 2, &g.shape_r);  // plan-table kernel families
     plan_family(PY, q->inst.Gc / 2, &g.shape_c);
     buf_r = std::max(buf_r, (q->inst.G / 2) * row_slots(PX.m));
-    tab_r = std::max(tab_r, table_slots(PX.n, PX.m, PX.bc, false));
     buf_c = std::max(buf_c, (q->inst.Gc / 2) * row_slots(PY.m));
-    tab_c = std::max(tab_c, table_slots(PY.n, PY.m, PY.bc, true));
   }
-  // round the LDS up to 16 KiB steps so graphs are reused across batches
-  auto up = [](int b) { return (b + 16383) / 16384 * 16384; };
+  // the engine runs the plan-table kernels, which read their tables from
+  // global memory: LDS for the packed rows alone, rounded up to 4 KiB steps
+  // so graphs are reused across batches (two 4096-point FP64 rows' blocks
+  // still fit one CU)
+  auto up = [](int b) { return (b + 4095) / 4096 * 4096; };
   g.tw_r = buf_r;
-  g.lds_r = std::min(kLdsDynMax, up((buf_r + tab_r) * csize));
+  g.lds_r = std::min(kLdsDynMax, up(buf_r * csize));
   g.tw_c = buf_c;
-  g.lds_c = std::min(kLdsDynMax, up((buf_c + tab_c) * csize));
+  g.lds_c = std::min(kLdsDynMax, up(buf_c * csize));
   // the FFT family launches every iteration (with no request on it it
   // returns at once); the dense passes, sized for the longest dense axis,
   // only while a dense request is active.  The captured graphs depend on the

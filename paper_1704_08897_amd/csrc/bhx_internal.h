@@ -275,6 +275,9 @@ constexpr int kShapeCzKey = 1;
 constexpr int kShapeWideKey = 2;
 enum PlanFamily { kFamNarrow = 0, kFamWide = 1, kFamCz = 2 };
 constexpr int kFftWideLaunch = 4096;
+// Plan-table families take the shape values below 2^8; compile-time shapes
+// have G >= 2 in bits 8 and up.
+inline bool plan_table_shape(int shape) { return shape < 256; }
 int shape_key(int pass, int prec, int n, int m, int logm, int bluestein, int bc, int group);
 // `stream_t` != 0: the row-forward pass writes t with non-temporal stores.
 // Its transposed store writes G-element pieces of many lines.  While the

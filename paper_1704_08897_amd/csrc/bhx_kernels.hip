@@ -334,6 +334,12 @@ struct XPlan {
   // a round issued before its LDS writes: one or two memory round trips per
   // launch instead of one per table.
   __device__ void stage(C* lds, int idx, int& staged, bool with_lam) {
+    if constexpr (SP == 0) {
+      // plan-table instances read every table from global memory (L2): the
+      // LDS holds the packed rows alone, so two work items fit on a CU even
+      // for 4096-point FP64 rows
+      return;
+    }
     const int np = pairs();
     const int ntw = stage_twiddles(logm);
     C* tw_l = lds;
@@ -418,13 +424,19 @@ struct XPlan {
   // DCT-II post-twiddles of the pair: t[k] = exp(-i pi k / 2n) staged, and
   // t[n-k] = -i conj(t[k])
   __device__ __forceinline__ void post_pair(int k, int kk, C& tk, C& tkk) const {
-    tk = postl[k];
+    if constexpr (SP == 0)
+      tk = post[k];
+    else
+      tk = postl[k];
     tkk = kk == k ? tk : mk<C>(-tk.y, -tk.x);
   }
   // eigenvalues of the pair: lambda[partner] = lambda[k] for the periodic
   // axis, 4 - lambda[k] for the DCT and DST-I ones (4 sin^2 -> 4 cos^2)
   __device__ __forceinline__ void lam_pair(int k, int kk, R& lk, R& lkk) const {
-    lk = laml[k];
+    if constexpr (SP == 0)
+      lk = lam[k];
+    else
+      lk = laml[k];
     lkk = kk == k ? lk : (bc == kPeriodic ? lk : (R)4 - lk);
   }
   __device__ __forceinline__ int partner(int k) const {
@@ -569,10 +581,11 @@ enum { kFftChirp = 1, kFftDit = 2, kFftBhat = 4, kFftDif = 8 };
 // chirp on the inputs (Bluestein; inputs at logical index >= nf are zero),
 // the forward stages, the product with the kernel spectrum bhat, the inverse
 // stages.  Stage twiddles: the table of span h starts at (h - h0) / 3.
-template <typename R, int RAD>
+template <typename R, int RAD, bool TG>
 __device__ __forceinline__ void fft_pass(typename V2<R>::T* buf, int rows, int st, int logm,
                                          int sh, int lh, int fl,
                                          const typename V2<R>::T* __restrict__ tw,
+                                         BHX_GLOBAL const typename V2<R>::T* twg,
                                          BHX_GLOBAL const typename V2<R>::T* chirp, int nf,
                                          BHX_GLOBAL const typename V2<R>::T* bhat) {
   using C = typename V2<R>::T;
@@ -580,8 +593,13 @@ __device__ __forceinline__ void fft_pass(typename V2<R>::T* buf, int rows, int s
   const int h = 1 << lh;
   const int h0 = (logm & 1) ? 2 : 1;
   const int lnb = logm - LR;                  // log2 of the point groups per row
+  // stage twiddles W_4h^k: from the LDS tables (TG = false) or the global
+  // table W_m^j (TG), the same values
   const C* __restrict__ ta = tw + ((h - h0) / 3);            // span h (RAD 4, 16)
   const C* __restrict__ tb = tw + ((4 * h - h0) / 3);        // span 4h (RAD 16)
+  auto wa = [&](int k) { return TG ? twg[k << (logm - 2 - lh)] : ta[k]; };
+  auto wb = [&](int k) { return TG ? twg[k << (logm - 4 - lh)] : tb[k]; };
+  auto w8 = [&](int q) { return TG ? twg[q << (logm - 3)] : tw[q]; };
   for (int u = threadIdx.x; u < (rows << lnb); u += kThreads) {
     const int r = u >> lnb, rem = u & ((1 << lnb) - 1);
     const int k = rem & (h - 1);
@@ -600,19 +618,19 @@ __device__ __forceinline__ void fft_pass(typename V2<R>::T* buf, int rows, int s
     }
     if (fl & kFftDit) {
       if constexpr (RAD == 4) {
-        dit4(v[0], v[1], v[2], v[3], ta[k]);
+        dit4(v[0], v[1], v[2], v[3], wa(k));
       } else if constexpr (RAD == 8) {
         // radix-2 (span 1), then radix-4 of span 2 (its table starts at 0)
 #pragma unroll
         for (int q = 0; q < 4; ++q) bfly2(v[2 * q], v[2 * q + 1]);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) dit4(v[q], v[q + 2], v[q + 4], v[q + 6], tw[q]);
+        for (int q = 0; q < 2; ++q) dit4(v[q], v[q + 2], v[q + 4], v[q + 6], w8(q));
       } else {
-        const C wa = ta[k];
+        const C w = wa(k);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dit4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3], wa);
+        for (int q = 0; q < 4; ++q) dit4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3], w);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dit4(v[q], v[q + 4], v[q + 8], v[q + 12], tb[k + q * h]);
+        for (int q = 0; q < 4; ++q) dit4(v[q], v[q + 4], v[q + 8], v[q + 12], wb(k + q * h));
       }
     }
     if (fl & kFftBhat) {
@@ -621,18 +639,18 @@ __device__ __forceinline__ void fft_pass(typename V2<R>::T* buf, int rows, int s
     }
     if (fl & kFftDif) {
       if constexpr (RAD == 4) {
-        dif4(v[0], v[1], v[2], v[3], ta[k]);
+        dif4(v[0], v[1], v[2], v[3], wa(k));
       } else if constexpr (RAD == 8) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) dif4(v[q], v[q + 2], v[q + 4], v[q + 6], tw[q]);
+        for (int q = 0; q < 2; ++q) dif4(v[q], v[q + 2], v[q + 4], v[q + 6], w8(q));
 #pragma unroll
         for (int q = 0; q < 4; ++q) bfly2(v[2 * q], v[2 * q + 1]);
       } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dif4(v[q], v[q + 4], v[q + 8], v[q + 12], tb[k + q * h]);
-        const C wa = ta[k];
+        for (int q = 0; q < 4; ++q) dif4(v[q], v[q + 4], v[q + 8], v[q + 12], wb(k + q * h));
+        const C w = wa(k);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dif4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3], wa);
+        for (int q = 0; q < 4; ++q) dif4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3], w);
       }
     }
 #pragma unroll
@@ -645,9 +663,9 @@ template <typename R, int L, bool W, int P>
 __device__ __forceinline__ void fft_fixed(typename V2<R>::T* buf, int rows, int st,
                                           const typename V2<R>::T* __restrict__ tw) {
   if constexpr (P < fft_npass(L, W)) {
-    fft_pass<R, fft_pass_rad(L, P, W)>(buf, rows, st, L, rpos_shift(L),
-                                       fft_pass_lspan(L, P, W), kFftDit, tw, nullptr, 0,
-                                       nullptr);
+    fft_pass<R, fft_pass_rad(L, P, W), false>(buf, rows, st, L, rpos_shift(L),
+                                              fft_pass_lspan(L, P, W), kFftDit, tw, nullptr,
+                                              nullptr, 0, nullptr);
     __syncthreads();
     fft_fixed<R, L, W, P + 1>(buf, rows, st, tw);
   }
@@ -683,12 +701,16 @@ __device__ void dft_core(const XPlan<R, SP>& X, typename V2<R>::T* buf, int rows
       if (blue && s == 0) fl |= kFftChirp;
       if (blue && s == np - 1) fl |= kFftBhat | kFftDif;
       const int rad = fft_pass_rad(logm, p, wide), lh = fft_pass_lspan(logm, p, wide);
+      // twiddles from the global table (no LDS tables in these instances)
       if (W && rad == 16)
-        fft_pass<R, W ? 16 : 4>(buf, rows, st, logm, X.sh, lh, fl, X.tw, X.chirp, X.nf, X.bhat);
+        fft_pass<R, W ? 16 : 4, true>(buf, rows, st, logm, X.sh, lh, fl, nullptr, X.twg,
+                                      X.chirp, X.nf, X.bhat);
       else if (rad == 8)
-        fft_pass<R, 8>(buf, rows, st, logm, X.sh, lh, fl, X.tw, X.chirp, X.nf, X.bhat);
+        fft_pass<R, 8, true>(buf, rows, st, logm, X.sh, lh, fl, nullptr, X.twg, X.chirp, X.nf,
+                             X.bhat);
       else
-        fft_pass<R, 4>(buf, rows, st, logm, X.sh, lh, fl, X.tw, X.chirp, X.nf, X.bhat);
+        fft_pass<R, 4, true>(buf, rows, st, logm, X.sh, lh, fl, nullptr, X.twg, X.chirp, X.nf,
+                             X.bhat);
       __syncthreads();
     }
   }

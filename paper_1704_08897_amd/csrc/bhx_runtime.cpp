@@ -905,6 +905,14 @@ int batch_grids(const PlanCache& plans, const BatchDesc& D, const Resolved& R, i
     plan_families(plans, D, &g);
   }
   {
+    // plan-table launches read their tables from global memory: their LDS
+    // is the packed rows alone
+    const int csize = R.precision == 0 ? 16 : 8;
+    if (plan_table_shape(g.shape_r)) g.lds_r = g.tw_r * csize;
+    if (plan_table_shape(g.shape_c)) g.lds_c = g.tw_c * csize;
+    if (dim == 3 && plan_table_shape(g.shape_z)) g.lds_z = g.tw_z * csize;
+  }
+  {
     int nxm = 0, nym = 0;
     for (int i = 0; i < n; ++i)
       if (D.dense[i]) {
