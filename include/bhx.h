@@ -109,7 +109,10 @@ typedef struct {
   int chunk;        /* iterations per captured graph between convergence checks;
                          0 -> 32; an odd value is rounded up to even                 */
   int rows;         /* packed complex rows (two grid rows each) per transform work
-                         item; 0 = automatic (autotuner or built-in policy)           */
+                         item; 0 = automatic (autotuner or built-in policy: as many as
+                         fit, fewer while the instance alone supplies under two items
+                         per CU); -1 = as many as fit (the engine's default, whose
+                         launches are shared by many requests)                        */
   int occupancy;    /* persistent blocks per CU of the transform passes; 0 = auto   */
   int autotune;     /* 1 = choose the launch schedule (packed rows per transform work
                          item, persistent-grid occupancy per pass, iterations per

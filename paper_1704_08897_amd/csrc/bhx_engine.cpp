@@ -198,6 +198,14 @@ int upload_batch(bhx_engine* E, DevBatch& db, const std::vector<Req*>& reqs, hip
   return BHX_OK;
 }
 
+// Packed rows per transform work item of the engine's requests: the
+// caller's bhx_opts.rows, else the fullest items (-1): every launch is
+// shared with other requests, so none has to fill the GPU alone.  A request
+// equals its solo solve with the same bhx_opts.rows bit for bit.
+int engine_rows(const bhx_engine* E) {
+  return E->R.sched.rows_cap != 0 ? E->R.sched.rows_cap : -1;
+}
+
 // Launch geometry for a set of requests: persistent grids of fixed size (so
 // captured graphs survive changes of the active set) and LDS from the
 // largest transform among the requests.
@@ -263,8 +271,8 @@ int setup_new(bhx_engine* E, std::vector<Req*>& news, hipStream_t st) {
     const int px = hd->plans.get(S.nx, S.bcx), py = hd->plans.get(S.ny, S.bcy);
     Layout L;
     const bool dense = use_dense(E->R, hd->plans.plan(px), hd->plans.plan(py));
-    make_layout(S.nx, S.ny, E->R.precision, hd->plans.plan(px).m, hd->plans.plan(py).m, 0, &L,
-                dense);
+    make_layout(S.nx, S.ny, E->R.precision, hd->plans.plan(px).m, hd->plans.plan(py).m,
+                engine_rows(E), &L, dense);
     Inst& I = q->inst;
     std::memset(&I, 0, sizeof(I));
     I.nx = S.nx; I.ny = S.ny; I.nz = 1; I.nrows = S.ny;
@@ -563,7 +571,8 @@ int bhx_engine_submit(bhx_engine* E, const double* phi, double* F, int nx, int n
   if (!E || !id) return BHX_ERR_ARG;
   int v = bhx::validate(phi, F, nx, ny, h, bc, tol, E->R);
   if (v != BHX_OK) return v;
-  const size_t bytes = bhx::instance_bytes(nx, ny, bc & 15, (bc >> 4) & 15, E->R.precision);
+  const size_t bytes =
+      bhx::instance_bytes(nx, ny, bc & 15, (bc >> 4) & 15, E->R.precision, bhx::engine_rows(E));
   if (bytes == 0 || bytes > E->budget) return BHX_ERR_ARG;      // can never fit
   bhx::Req* q = new (std::nothrow) bhx::Req();
   if (!q) return BHX_ERR_NOMEM;

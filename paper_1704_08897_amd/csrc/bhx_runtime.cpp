@@ -114,12 +114,15 @@ bool make_layout(int nx, int ny, int nz, int prec, int mx, int my, int mz, int r
   const bool d3 = mz > 0;
   const int csize = prec == 0 ? 16 : 8;
   const int rows_cap = prec == 0 ? 4 : 8;
-  // packed rows per item: the most that fit LDS and the register pair pass,
-  // reduced until the instance supplies kTargetItems items (two per CU)
+  // packed rows per item: the most that fit LDS and the register pair pass
+  // (rows_user < 0: the fullest items, for launches shared with other
+  // instances), reduced until the instance supplies kTargetItems items (two
+  // per CU) when it is to fill the GPU alone (rows_user = 0)
   auto rows_for = [&](int n, int m, long lines, int cap) {
     int r = std::min(cap, kLdsBytes / (row_slots(m) * csize));
     r = std::min(r, (kThreads * kMaxPairs) / (n / 2 + 1));
     if (rows_user > 0) return std::min(r, rows_user);
+    if (rows_user < 0) return r;
     while (r > 1 && (lines + 2 * r - 1) / (2 * r) < kTargetItems) --r;
     return r;
   };
@@ -158,11 +161,11 @@ bool make_layout(int nx, int ny, int nz, int prec, int mx, int my, int mz, int r
   return true;
 }
 
-size_t instance_bytes(int nx, int ny, int bcx, int bcy, int prec) {
+size_t instance_bytes(int nx, int ny, int bcx, int bcy, int prec, int rows_user) {
   Layout L;
   if (!length_supported(nx, bcx, prec) || !length_supported(ny, bcy, prec)) return 0;
   if (!make_layout(nx, ny, prec, core_length(fft_length(nx, bcx)),
-                   core_length(fft_length(ny, bcy)), 0, &L))
+                   core_length(fft_length(ny, bcy)), rows_user, &L))
     return 0;
   return L.bytes;
 }
@@ -202,7 +205,7 @@ Resolved resolve_opts(const bhx_opts* o) {
   R.rows_opt = o->rows;
   R.occ_opt = o->occupancy;
   R.transform = o->transform;
-  if (o->rows > 0) R.sched.rows_cap = o->rows;
+  if (o->rows != 0) R.sched.rows_cap = o->rows;   // -1: fullest work items
   if (o->occupancy > 0) R.sched.occ_r = R.sched.occ_c = o->occupancy;
   return R;
 }
@@ -373,7 +376,7 @@ int validate(const double* phi, const double* F, int nx, int ny, double h, int b
   if (R.warm != 0 && R.warm != 1) return BHX_ERR_ARG;
   if (R.solver != 0 && R.solver != 1) return BHX_ERR_ARG;
   if (R.solver == 1 && (R.precision != BHX_PREC_FP64 || by == BHX_PERIODIC)) return BHX_ERR_ARG;
-  if (R.rows_opt < 0 || R.rows_opt > 8 || R.occ_opt < 0 || R.occ_opt > 8) return BHX_ERR_ARG;
+  if (R.rows_opt < -1 || R.rows_opt > 8 || R.occ_opt < 0 || R.occ_opt > 8) return BHX_ERR_ARG;
   if (R.transform < 0 || R.transform > 2) return BHX_ERR_ARG;
   if (!length_supported(nx, bx, R.precision) || !length_supported(ny, by, R.precision))
     return BHX_ERR_ARG;

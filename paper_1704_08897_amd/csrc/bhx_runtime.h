@@ -70,6 +70,9 @@ struct Layout {
 // mz = 0: two dimensions (nz = 1); otherwise the z core length.
 // dense: the instance's preconditioner runs the dense-transform passes
 // (row and column groups of kDenseG lines).
+// rows_cap: packed rows per transform work item; 0 = the built-in policy
+// (as many as fit, reduced until the instance alone supplies kTargetItems
+// items), -1 = as many as fit.
 bool make_layout(int nx, int ny, int nz, int prec, int mx, int my, int mz, int rows_cap,
                  Layout* L, bool dense = false);
 inline bool make_layout(int nx, int ny, int prec, int mx, int my, int rows_cap, Layout* L,
@@ -206,7 +209,7 @@ int validate3(const double* phi, const double* F, int nx, int ny, int nz, double
 // With R.warm the values of F at the unknown nodes are the first iterate.
 int solve_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
                 hipStream_t stream, bhx_stats* stats);
-size_t instance_bytes(int nx, int ny, int bcx, int bcy, int prec);
+size_t instance_bytes(int nx, int ny, int bcx, int bcy, int prec, int rows_cap = 0);
 size_t instance_bytes3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int prec);
 const char* last_error();
 void set_last_error(const char* what, int line, hipError_t e);

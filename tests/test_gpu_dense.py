@@ -182,7 +182,8 @@ def test_engine_with_dense_requests(handle):
     try:
         for p, q in zip(probs, reqs):
             A = dev(p.F)
-            s, st = bhx.extend_ex(handle, dev(p.phi), A, bc=p.bc, h=p.h, tol=p.tol, opts=DENSE)
+            s, st = bhx.extend_ex(handle, dev(p.phi), A, bc=p.bc, h=p.h, tol=p.tol,
+                                  opts=bhx.default_opts(transform=2, rows=-1))
             assert s == bhx.OK
             assert torch.equal(q.F, A)
             ref, _ = O.extend_direct(p.phi, p.F, p.bcx, p.bcy)

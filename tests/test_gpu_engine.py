@@ -43,12 +43,14 @@ def handle():
 def alone(handle, p):
     """The request solved alone with bhx_extend_ex on the plan-table kernels,
     the family the engine runs (a single solve of a compile-time shape would
-    otherwise take the shape instances, which agree only to rounding)."""
+    otherwise take the shape instances, which agree only to rounding), with
+    the engine's work-item policy (rows = -1: the fullest items)."""
     old = os.environ.get("BHX_SHAPE_KERNELS")
     os.environ["BHX_SHAPE_KERNELS"] = "0"
     try:
         F = dev(p.F)
-        s, st = bhx.extend_ex(handle, dev(p.phi), F, bc=p.bc, h=p.h, tol=p.tol)
+        s, st = bhx.extend_ex(handle, dev(p.phi), F, bc=p.bc, h=p.h, tol=p.tol,
+                              opts=bhx.default_opts(rows=-1))
         torch.cuda.synchronize()
     finally:
         if old is None:
