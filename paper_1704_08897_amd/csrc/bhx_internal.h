@@ -41,9 +41,23 @@ constexpr int kReduceMin = 4096;
 
 enum Bc { kNeumann = 0, kPeriodic = 1, kDirichlet = 2 };
 
-// Shift of the second pad term of an FFT row in LDS (see rpos in the kernels):
-// rows of length 2^logm >= 256 get one extra slot every 2^(logm-4) elements.
-__host__ __device__ constexpr int rpos_shift(int logm) { return logm >= 8 ? logm - 4 : 31; }
+// Pad code of an FFT row of 2^logm complex points in LDS: one pad slot after
+// every 2^a elements and one more after every 2^b (b = 31: none), packed as
+// (a << 8) | b (see rpos in the kernels).  Chosen per length so that the
+// register passes the length runs, the bit-reversed scatter of the inputs and
+// natural-order reads spread over the LDS banks (16-byte elements, eight lanes
+// per bank cycle): 4096 points (the wide schedule only) pad every 16 and every
+// 512, 512 points every 8 and every 64, other lengths every 8 and (from 256
+// points) every 2^(logm-4).
+__host__ __device__ constexpr int rpos_shift(int logm) {
+  return logm == 12 ? (4 << 8) | 9
+       : logm == 9  ? (3 << 8) | 6
+                    : (3 << 8) | (logm >= 8 ? logm - 4 : 31);
+}
+// Position of element i of a row with pad code `code`.
+__host__ __device__ constexpr int rpos_code(int i, int code) {
+  return i + (i >> (code >> 8)) + (i >> (code & 255));
+}
 // Complex slots of the per-stage twiddle tables of a length-2^logm FFT: h
 // for each radix-4 stage of span h (h = 1, 4, 16, ... or 2, 8, 32, ...).
 __host__ __device__ inline int stage_twiddles(int logm) {

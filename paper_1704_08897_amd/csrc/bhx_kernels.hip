@@ -79,12 +79,12 @@ template <typename R> __device__ __forceinline__ R inv_sq(R s) {
   return s > (R)0 ? recip(s * s) : (R)0;
 }
 
-// LDS position of element i of a packed FFT row: one pad slot after every 8
-// elements, and for rows of length m >= 256 one more after every m/16
-// (sh = log2(m) - 4; sh = 31 adds nothing).  The first spreads the
-// small-stride butterfly stages over the banks, the second the bit-reversed
-// scatter of the inputs, whose consecutive indices differ in the top bits.
-__device__ __forceinline__ int rpos(int i, int sh) { return i + (i >> 3) + (i >> sh); }
+// LDS position of element i of a packed FFT row: a pad slot after every 2^a
+// elements and another after every 2^b, sh = rpos_shift(logm) = (a << 8) | b.
+// The first spreads the small-stride pass loads over the banks, the second
+// the bit-reversed scatter of the inputs, whose consecutive indices differ in
+// the top bits.
+__device__ __forceinline__ int rpos(int i, int sh) { return rpos_code(i, sh); }
 
 
 __device__ __forceinline__ int bitrev(int k, int logm) {

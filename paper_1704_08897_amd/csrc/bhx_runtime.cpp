@@ -85,7 +85,7 @@ int core_length(int n) {
 
 // Complex slots of one packed FFT row in LDS, pad slots included (the
 // kernels' rpos(m, shift)).
-int row_slots(int m) { return m + (m >> 3) + (m >> rpos_shift(ilog2(m))); }
+int row_slots(int m) { return rpos_code(m, rpos_shift(ilog2(m))); }
 
 
 // Length of the DFT behind the 1-D transform of an axis of n nodes.
