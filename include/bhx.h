@@ -132,13 +132,15 @@ typedef struct {
                          0 = x0 = 0 (Algorithm 1), input values at U are ignored    */
   int solver;       /* 0 = preconditioned conjugate gradients (Algorithm 1);
                          1 = sparse direct (Sec. 2.2): banded Cholesky of A_UU on the
-                         GPU with the unknowns numbered row by row, then refinement
+                         GPU with the unknowns numbered line by line, then refinement
                          with the compensated residual until ||b - A u|| <= tol ||b||
                          (bhx_stats.iterations = refinement solves).  Two dimensions,
-                         FP64, y axis Neumann or Dirichlet (a periodic y axis couples
-                         the first and last rows: BHX_ERR_ARG); band storage is about
-                         8 (64 + w) bytes per unknown, w the band width (about twice
-                         the unknowns per grid row).  Fields sharing phi in one
+                         FP64, at most one periodic axis (both periodic: BHX_ERR_ARG).
+                         The lines run along y (grid columns) when y is periodic or
+                         when x is the longer non-periodic axis, else along x, so a
+                         periodic axis never couples the first and last lines; band
+                         storage is about 8 (64 + w) bytes per unknown, w the band
+                         width (about twice the unknowns per line).  Fields sharing phi in one
                          bhx_extend_fields call share one factorisation.  Not for
                          the serving engine or three dimensions (BHX_ERR_ARG).       */
   int transform;    /* form of the preconditioner's 1-D transforms (two dimensions):

@@ -1,12 +1,16 @@
 // Direct solve of the masked biharmonic system on the GPU (two dimensions):
 // banded Cholesky factorisation of A_UU, the direct route of Sec. 2.2.
 //
-// The unknowns are numbered row by row (x fastest), so a 13-point row of
-// A_UU reaches back at most about two grid rows of unknowns: the lower band
-// width w is the largest distance, in that numbering, from an unknown to the
-// first unknown its stencil couples to (computed exactly from the stencil and
-// the ghost rules).  A periodic y axis couples the first and last grid rows
-// and would make the band span the whole grid; it is rejected.
+// The unknowns are numbered line by line, along grid rows (x fastest) or
+// along grid columns (y fastest), so a 13-point row of A_UU reaches back at
+// most about two lines of unknowns: the lower band width w is the largest
+// distance, in that numbering, from an unknown to the first unknown its
+// stencil couples to (computed exactly from the stencil and the ghost rules).
+// A periodic axis across the lines would couple the first and last lines and
+// make the band span the whole grid, so a periodic y axis takes the column
+// numbering, and otherwise the lines run along the shorter axis (the band, and
+// the factorisation's work, shrink with the line length).  Both axes periodic
+// is rejected.
 //
 // Storage: panels of kNb columns.  Panel k holds columns [k*kNb, (k+1)*kNb)
 // of the lower band, rows [k*kNb, k*kNb + H) with H = kNb + W (W = w rounded
@@ -68,31 +72,36 @@ __device__ double block_sum_d(double v, double* red) {
   return t;
 }
 
-// Unknown nodes per grid row (one block per row).
-__global__ void __launch_bounds__(kThreads) k_dir_rowcount(const uint8_t* __restrict__ mask,
-                                                           int nx, int* __restrict__ cnt) {
+// Unknown nodes per line (one block per line): line l holds the nodes
+// l * sl + j * sj, j < len.
+__global__ void __launch_bounds__(kThreads) k_dir_linecount(const uint8_t* __restrict__ mask,
+                                                            int len, int sl, int sj,
+                                                            int* __restrict__ cnt) {
   __shared__ double red[4];
-  const int y = blockIdx.x;
+  const int l = blockIdx.x;
   double c = 0;
-  for (int x = threadIdx.x; x < nx; x += kThreads) c += mask[(size_t)y * nx + x];
+  for (int j = threadIdx.x; j < len; j += kThreads) c += mask[(size_t)l * sl + (size_t)j * sj];
   c = block_sum_d(c, red);
-  if (threadIdx.x == 0) cnt[y] = (int)c;
+  if (threadIdx.x == 0) cnt[l] = (int)c;
 }
 
-// Position of each unknown in the row-by-row numbering (-1 at known nodes):
-// row offset plus the exclusive prefix count within the row (block scan).
-__global__ void __launch_bounds__(kThreads) k_dir_index(const uint8_t* __restrict__ mask, int nx,
-                                                        const int* __restrict__ row_off,
+// Position of each unknown in the line-by-line numbering (-1 at known
+// nodes): line offset plus the exclusive prefix count within the line (block
+// scan).
+__global__ void __launch_bounds__(kThreads) k_dir_index(const uint8_t* __restrict__ mask, int len,
+                                                        int sl, int sj,
+                                                        const int* __restrict__ line_off,
                                                         int* __restrict__ uidx) {
   __shared__ int wsum[4];
   __shared__ int carry;
-  const int y = blockIdx.x;
+  const int l = blockIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (threadIdx.x == 0) carry = row_off[y];
+  if (threadIdx.x == 0) carry = line_off[l];
   __syncthreads();
-  for (int x0 = 0; x0 < nx; x0 += kThreads) {
-    const int x = x0 + threadIdx.x;
-    const int u = x < nx ? mask[(size_t)y * nx + x] : 0;
+  for (int j0 = 0; j0 < len; j0 += kThreads) {
+    const int j = j0 + threadIdx.x;
+    const size_t node = (size_t)l * sl + (size_t)j * sj;
+    const int u = j < len ? mask[node] : 0;
     // inclusive scan within the wave
     int v = u;
 #pragma unroll
@@ -104,7 +113,7 @@ __global__ void __launch_bounds__(kThreads) k_dir_index(const uint8_t* __restric
     __syncthreads();
     int before = carry;
     for (int i = 0; i < w; ++i) before += wsum[i];
-    if (x < nx) uidx[(size_t)y * nx + x] = u ? before + v - 1 : -1;
+    if (j < len) uidx[node] = u ? before + v - 1 : -1;
     __syncthreads();
     if (threadIdx.x == kThreads - 1) carry = before + v;
     __syncthreads();
@@ -606,7 +615,7 @@ InstPtrs instance0(bhx_handle* hd, const InstSpec& S, const Resolved& R) {
 
 }  // namespace
 
-bool direct_supported(int bcy) { return bcy != kPeriodic; }
+bool direct_supported(int bcx, int bcy) { return !(bcx == kPeriodic && bcy == kPeriodic); }
 
 // Banded Cholesky solve of a group of fields sharing phi (specs[0..n) have
 // the same phi, sizes and rules): factor once, then per field: right-hand
@@ -622,7 +631,7 @@ int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R
   R.sched.transform = -1;
   const InstSpec& S0 = specs[0];
   const int nx = S0.nx, ny = S0.ny, N = nx * ny;
-  if (S0.dim != 2 || !direct_supported(S0.bcy)) return BHX_ERR_ARG;
+  if (S0.dim != 2 || !direct_supported(S0.bcx, S0.bcy)) return BHX_ERR_ARG;
   int ret = BHX_OK;
   bool factored = false;
   Band B{};
@@ -653,9 +662,13 @@ int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R
       preset = false;
     }
     if (!preset && !factored) {
-      // ordering, band width, storage
-      std::vector<int> cnt(ny), off(ny + 1, 0);
-      const size_t need = align256((size_t)N * sizeof(int)) + align256((ny + 2) * sizeof(int));
+      // ordering, band width, storage: lines along y (columns) when y is
+      // periodic or x the longer non-periodic axis, else along x (rows)
+      const bool cols = S.bcy == kPeriodic || (S.bcx != kPeriodic && nx > ny);
+      const int nl = cols ? nx : ny, len = cols ? ny : nx;
+      const int sl = cols ? 1 : nx, sj = cols ? nx : 1;
+      std::vector<int> cnt(nl), off(nl + 1, 0);
+      const size_t need = align256((size_t)N * sizeof(int)) + align256((nl + 2) * sizeof(int));
       if (need > hd->dws_cap) {
         if (hd->dws) DIR_CHECK(hipFree(hd->dws));
         hd->dws = nullptr;
@@ -665,19 +678,21 @@ int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R
       }
       uidx = (int*)hd->dws;
       int* cnt_d = (int*)((char*)hd->dws + align256((size_t)N * sizeof(int)));
-      hipLaunchKernelGGL(k_dir_rowcount, dim3(ny), dim3(kThreads), 0, st, P.mask, nx, cnt_d);
+      hipLaunchKernelGGL(k_dir_linecount, dim3(nl), dim3(kThreads), 0, st, P.mask, len, sl, sj,
+                         cnt_d);
       DIR_CHECK(hipGetLastError());
-      DIR_CHECK(hipMemcpyAsync(cnt.data(), cnt_d, ny * sizeof(int), hipMemcpyDeviceToHost, st));
+      DIR_CHECK(hipMemcpyAsync(cnt.data(), cnt_d, nl * sizeof(int), hipMemcpyDeviceToHost, st));
       DIR_CHECK(hipStreamSynchronize(st));
-      for (int j = 0; j < ny; ++j) off[j + 1] = off[j] + cnt[j];
-      const int nu = off[ny];
+      for (int j = 0; j < nl; ++j) off[j + 1] = off[j] + cnt[j];
+      const int nu = off[nl];
       {
-        const Upload u{cnt_d, off.data(), (ny + 1) * sizeof(int)};
+        const Upload u{cnt_d, off.data(), (nl + 1) * sizeof(int)};
         DIR_CHECK(upload_ordered(hd, st, &u, 1));
       }
-      hipLaunchKernelGGL(k_dir_index, dim3(ny), dim3(kThreads), 0, st, P.mask, nx, cnt_d, uidx);
+      hipLaunchKernelGGL(k_dir_index, dim3(nl), dim3(kThreads), 0, st, P.mask, len, sl, sj, cnt_d,
+                         uidx);
       DIR_CHECK(hipGetLastError());
-      int* w_d = cnt_d + ny + 1;
+      int* w_d = cnt_d + nl + 1;
       DIR_CHECK(hipMemsetAsync(w_d, 0, sizeof(int), st));
       hipLaunchKernelGGL(k_dir_width, dim3((N + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
                          P.mask, uidx, nx, ny, S.bcx, S.bcy, w_d);

@@ -375,7 +375,7 @@ int validate(const double* phi, const double* F, int nx, int ny, double h, int b
   if (R.autotune != 0 && R.autotune != 1) return BHX_ERR_ARG;
   if (R.warm != 0 && R.warm != 1) return BHX_ERR_ARG;
   if (R.solver != 0 && R.solver != 1) return BHX_ERR_ARG;
-  if (R.solver == 1 && (R.precision != BHX_PREC_FP64 || by == BHX_PERIODIC)) return BHX_ERR_ARG;
+  if (R.solver == 1 && (R.precision != BHX_PREC_FP64 || !direct_supported(bx, by))) return BHX_ERR_ARG;
   if (R.rows_opt < -1 || R.rows_opt > 8 || R.occ_opt < 0 || R.occ_opt > 8) return BHX_ERR_ARG;
   if (R.transform < 0 || R.transform > 2) return BHX_ERR_ARG;
   if (!length_supported(nx, bx, R.precision) || !length_supported(ny, by, R.precision))

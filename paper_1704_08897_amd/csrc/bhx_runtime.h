@@ -269,10 +269,10 @@ int solve_noalloc(bhx_handle* hd, const InstSpec& spec, const Resolved& R, hipSt
 // with that device current) and its size; BHX_OK or BHX_ERR_HIP.
 int noalloc_scratch(int device, void** ptr, size_t* bytes);
 // Banded Cholesky solve of fields sharing one phi (all specs: same phi, size
-// and rules; two dimensions, y axis not periodic).
+// and rules; two dimensions, at most one periodic axis).
 int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
                  hipStream_t stream, bhx_stats* stats);
-bool direct_supported(int bcy);
+bool direct_supported(int bcx, int bcy);
 // One host array to copy to device memory.
 struct Upload {
   void* dst;

@@ -323,6 +323,29 @@ def annulus_problem(n: int, bcx: int, bcy: int, tol: float = 1e-6) -> Problem:
     return Problem(phi, F, bcx, bcy, 4.0 / n, tol, f"annulus{n}")
 
 
+def channel_problem(ny: int, terms: int = 10, seed: int = 8, bcy: int = PERIODIC,
+                    tol: float = 1e-6) -> Problem:
+    """Example 4 (Sec. 3.4): D = [0, 3] x [0, 1] on a 3 ny x ny grid, Neumann
+    sides, periodic (or, for the channel geometry, Neumann) top and bottom.
+    The interface is x = 1.5 + sum_k a_k sin(2 pi k y + w_k), k = 1..terms,
+    with seeded a_k ~ U[-0.05, 0.05] and w_k ~ U[0, 2 pi); f is known to the
+    left of it: x + cos(2 pi (y - 1/4)) / 5 with periodic top and bottom,
+    x + cos(pi y) / 5 with Neumann ones."""
+    nx = 3 * ny
+    X, Y = _mesh(nx, ny, ((0.0, 3.0), (0.0, 1.0)), NEUMANN, bcy)
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-0.05, 0.05, size=terms)
+    w = rng.uniform(0.0, 2 * np.pi, size=terms)
+    front = 1.5 + sum(a[k] * np.sin(2 * np.pi * (k + 1) * Y + w[k]) for k in range(terms))
+    phi = X - front
+    if bcy == PERIODIC:
+        F = X + np.cos(2 * np.pi * (Y - 0.25)) / 5
+    else:
+        F = X + np.cos(np.pi * Y) / 5
+    return Problem(phi, F, NEUMANN, bcy, 1.0 / ny, tol, f"channel{nx}x{ny}",
+                   {"amplitudes": a, "phases": w})
+
+
 # ----------------------------------------------------------------------------
 # Three dimensions (Sec. 3.2, Example 2)
 # ----------------------------------------------------------------------------

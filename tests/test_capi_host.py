@@ -144,10 +144,10 @@ def test_three_dimensional_arguments():
 
 
 def test_direct_solver_option_checks():
-    """solver = 1 (banded Cholesky): FP64, y axis not periodic, two
+    """solver = 1 (banded Cholesky): FP64, at most one periodic axis, two
     dimensions, not the engine; anything else is rejected on the host."""
     assert bhx.default_opts().solver == 0
-    for kw, bc in (({"solver": 2}, 0), ({"solver": 1}, bhx.BC(0, 1)),
+    for kw, bc in (({"solver": 2}, 0), ({"solver": 1}, bhx.BC(1, 1)),
                    ({"solver": 1, "precision": 1}, 0)):
         s, _ = bhx.extend_ex(FAKE, FAKE, FAKE, 8, 8, 1.0, bc, 1e-8, opts=bhx.default_opts(**kw))
         assert s == bhx.ERR_ARG, kw

@@ -75,3 +75,23 @@ def test_generators_are_deterministic():
     c = W.star_cubic_batch(3, seed=4)
     d = W.star_cubic_batch(3, seed=4)
     assert all(np.array_equal(x.phi, y.phi) for x, y in zip(c, d))
+
+
+@pytest.mark.parametrize("bcy", [W.PERIODIC, W.NEUMANN])
+def test_channel_problem(bcy):
+    """Example 4's channel: 3 ny x ny, known to the left of a front near
+    x = 1.5 whose terms stay within the stated amplitudes, seeded."""
+    p = W.channel_problem(64, terms=10, seed=8, bcy=bcy)
+    assert p.phi.shape == (64, 192) and p.bcx == W.NEUMANN and p.bcy == bcy
+    assert p.h == 1.0 / 64
+    known = p.phi < 0
+    # every grid row is known on a prefix only (one front crossing per row)
+    assert np.all(np.diff(known.astype(int), axis=1) <= 0)
+    width = known.sum(axis=1) * p.h
+    assert np.all(np.abs(width - 1.5) <= 10 * 0.05 + p.h)
+    assert 0.4 <= known.mean() <= 0.6
+    a = p.meta["amplitudes"]
+    assert len(a) == 10 and np.all(np.abs(a) <= 0.05)
+    q = W.channel_problem(64, terms=10, seed=8, bcy=bcy)
+    assert np.array_equal(p.phi, q.phi) and np.array_equal(p.F, q.F)
+    assert not np.array_equal(p.phi, W.channel_problem(64, terms=10, seed=9, bcy=bcy).phi)
