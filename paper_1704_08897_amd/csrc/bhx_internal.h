@@ -37,7 +37,7 @@ constexpr int kMaxGc = 16;             // columns per column-pass item (2 x rows
 constexpr int kTargetItems = 512;      // row/column items one instance should supply
 // Partial-sum arrays longer than this (tiles + 3 x row groups) are reduced
 // once per pass by a one-block launch instead of in every consumer block.
-constexpr int kReduceMin = 4096;
+constexpr int kReduceMin = 8192;
 
 enum Bc { kNeumann = 0, kPeriodic = 1, kDirichlet = 2 };
 

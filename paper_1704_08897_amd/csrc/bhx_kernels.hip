@@ -111,6 +111,39 @@ __device__ double block_sum_array(BHX_GLOBAL const double* __restrict__ a, int n
   return t;
 }
 
+// Sum of a long array a[0..n) by one block (the scalars of instances with
+// tens of thousands of partials): 16 loads in flight per thread, thread t
+// accumulating entries t + kThreads (16 r + u) in acc[u]; the accumulators,
+// lanes and waves are then combined in a fixed order.  n is uniform over the
+// block.
+__device__ double block_sum_long(BHX_GLOBAL const double* __restrict__ a, int n, double* red) {
+  constexpr int kU = 16;
+  if (n <= 0) return 0.0;
+  double acc[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) acc[u] = 0.0;
+  for (int i0 = 0; i0 < n; i0 += kU * kThreads) {
+    double v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = a[min(i0 + u * kThreads + (int)threadIdx.x, n - 1)];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      acc[u] += (i0 + u * kThreads + (int)threadIdx.x < n) ? v[u] : 0.0;
+  }
+#pragma unroll
+  for (int h = kU / 2; h > 0; h >>= 1)
+#pragma unroll
+    for (int u = 0; u < h; ++u) acc[u] += acc[u + h];
+  const double s = wave_sum(acc[0]);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = s;
+  __syncthreads();
+  const double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
 // Sums of K partial arrays a[k][0..n[k]) in one pass (all loads in flight
 // together); the order of every sum is fixed, so each block of a launch
 // obtains bit-identical values.  red must hold 4*K doubles.
@@ -2553,15 +2586,15 @@ __global__ void __launch_bounds__(kThreads) k_reduce(const Batch* __restrict__ B
   if (ctl->done) return;             // no writer of `done` runs during this launch
   const PartLayout PL(I.n_items[kPassS], I.n_items[kPassR]);
   if (which == kRedPQ) {
-    const double v = block_sum_array(I.part + PL.pq(), PL.nS, red);
+    const double v = block_sum_long(I.part + PL.pq(), PL.nS, red);
     if (threadIdx.x == 0) ctl->red_pq = v;
   } else if (which == kRedRR) {
-    const double v = block_sum_array(I.part + PL.rr(), PL.nR, red);
+    const double v = block_sum_long(I.part + PL.rr(), PL.nR, red);
     if (threadIdx.x == 0) ctl->red_rr = v;
   } else {
     const int par = lpar ^ 1;        // the parity the row-inverse pass wrote
-    const double v = block_sum_array(I.part + PL.rz(par), PL.nR, red);
-    const double w = I.flexible ? block_sum_array(I.part + PL.rzo(par), PL.nR, red) : 0.0;
+    const double v = block_sum_long(I.part + PL.rz(par), PL.nR, red);
+    const double w = I.flexible ? block_sum_long(I.part + PL.rzo(par), PL.nR, red) : 0.0;
     if (threadIdx.x == 0) {
       ctl->red_rz[par] = v;
       ctl->red_rzo[par] = w;

@@ -230,17 +230,20 @@ def test_3d_deterministic(handle):
 
 
 def test_reduced_scalars_mode(handle):
-    """96^3 (6 x 12 x 24 tiles, 1152 row groups): long enough partial-sum
-    arrays that the scalars are summed once per pass by k_reduce.  Standard
-    FP64 PCG follows the oracle's iteration count; the flexible FP32 form
-    (which also reduces r.z_old) and plain CG (identity preconditioner)
-    meet the tolerance by the CPU long-double residual."""
-    p = W.ball_problem3(96, 96, 96, 0, 1, 2, seed=7, tol=1e-6)
+    """128 x 128 x 112 (8 x 16 x 28 tiles, 1792 row groups: 3584 + 3 * 1792
+    = 8960 partials, above the 8192 from which the scalars are summed once
+    per pass by k_reduce).  Standard FP64 PCG follows the oracle's iteration
+    count; the flexible FP32 form (which also reduces r.z_old) and plain CG
+    (identity preconditioner) meet the tolerance by the CPU long-double
+    residual."""
+    p = W.ball_problem3(128, 128, 112, 0, 1, 2, seed=7, tol=1e-6)
     K = O.known_mask(p.phi)
     _, it_o, _ = O.pcg_3d(K, p.F, p.bcx, p.bcy, p.bcz, 1e-6, 3000)
     s, st, got = solve3(handle, p)
     assert s == bhx.OK
-    assert abs(st.iterations - it_o) <= 2, (st.iterations, it_o)
+    # sums in tile / row-group order against NumPy's: the exit iteration
+    # moves by a few percent at this size
+    assert abs(st.iterations - it_o) <= max(3, 0.05 * it_o), (st.iterations, it_o)
     assert O.true_relative_residual_3d(K, p.F, got, p.bcx, p.bcy, p.bcz) <= 1e-6 * 1.001
     for opts in ({"precision": 1, "flexible": 1}, {"precond": 0, "maxit": 200000}):
         s, st2, got2 = solve3(handle, p, **opts)
