@@ -465,6 +465,45 @@ __global__ void __launch_bounds__(kThreads) k_dir_update(Band B, int k) {
       }
 }
 
+// Column `lane` of L_kk (zeros below the diagonal of L^T), from the
+// row-major copy: col[j] = L[j][lane].
+__device__ __forceinline__ void load_diag_col(const Band& B, int k, int lane, double (&col)[kNb]) {
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) col[j] = B.d[diag_row(k, j, lane)];
+}
+
+// One wave solves L_kk u = v (lane t: v_t in, u_t out; a = row t of L_kk);
+// 1 / L_tt is formed once, so the serial chain multiplies.
+__device__ __forceinline__ double tri_lower(const double (&a)[kNb], double v, int lane) {
+  double dg = 1.0;
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) dg = lane == j ? a[j] : dg;
+  const double rd = 1.0 / dg;
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) {
+    const double yj = lane_value(v, j) * lane_value(rd, j);
+    if (lane == j) v = yj;
+    else if (lane > j) v -= a[j] * yj;
+  }
+  return v;
+}
+
+// One wave solves L_kk^T u = v (lane t: v_t in, u_t out; col = column t of
+// L_kk).
+__device__ __forceinline__ double tri_upper(const double (&col)[kNb], double v, int lane) {
+  double dg = 1.0;
+#pragma unroll
+  for (int j = 0; j < kNb; ++j) dg = lane == j ? col[j] : dg;
+  const double rd = 1.0 / dg;
+#pragma unroll
+  for (int j = kNb - 1; j >= 0; --j) {
+    const double xj = lane_value(v, j) * lane_value(rd, j);
+    if (lane == j) v = xj;
+    else if (lane < j) v -= col[j] * xj;
+  }
+  return v;
+}
+
 // Forward substitution step k: wave 0 of every block solves L_kk z_k = y_k
 // (lane t: y_t and row t of L_kk in registers, and 1 / L_tt, so that the
 // serial chain multiplies instead of dividing); block 0 stores z_k, block
@@ -487,18 +526,7 @@ __global__ void __launch_bounds__(kThreads) k_dir_fwd(Band B, int k, double* __r
     const int lane = threadIdx.x;
     double a[kNb];
     load_diag_row(B, k, lane, a);
-    double v = y[k * kNb + lane];
-    double dg = 1.0;
-#pragma unroll
-    for (int j = 0; j < kNb; ++j) dg = lane == j ? a[j] : dg;
-    const double rd = 1.0 / dg;
-#pragma unroll
-    for (int j = 0; j < kNb; ++j) {
-      const double yj = lane_value(v, j) * lane_value(rd, j);
-      if (lane == j) v = yj;
-      else if (lane > j) v -= a[j] * yj;
-    }
-    yk[lane] = v;
+    yk[lane] = tri_lower(a, y[k * kNb + lane], lane);
   }
   __syncthreads();
   if (b == 0) {
@@ -537,20 +565,8 @@ __global__ void __launch_bounds__(kThreads) k_dir_bwd(Band B, int k, double* __r
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     double col[kNb];                     // col[j] = L[j][lane]
-#pragma unroll
-    for (int j = 0; j < kNb; ++j) col[j] = B.d[diag_row(k, j, lane)];
-    double v = z[k * kNb + lane];
-    double dg = 1.0;
-#pragma unroll
-    for (int j = 0; j < kNb; ++j) dg = lane == j ? col[j] : dg;
-    const double rd = 1.0 / dg;
-#pragma unroll
-    for (int j = kNb - 1; j >= 0; --j) {
-      const double xj = lane_value(v, j) * lane_value(rd, j);
-      if (lane == j) v = xj;
-      else if (lane < j) v -= col[j] * xj;
-    }
-    xk[lane] = v;
+    load_diag_col(B, k, lane, col);
+    xk[lane] = tri_upper(col, z[k * kNb + lane], lane);
   }
   __syncthreads();
   if (b == 0) {
@@ -566,6 +582,158 @@ __global__ void __launch_bounds__(kThreads) k_dir_bwd(Band B, int k, double* __r
   if (threadIdx.x < kNb)
     z[kb * kNb + threadIdx.x] -=
         (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
+}
+
+// Two forward steps in one launch, k and k + 1 (k + 1 < nblk): wave 0
+// solves z_k, every thread then takes its part of L_(k+1,k) z_k, wave 1
+// solves z_(k+1) from y_(k+1) less that product, and block b >= 1 updates
+// y_(k+1+b) by both steps' terms in the order two single steps would apply
+// them (so the results equal the one-step kernel's bit for bit).  Block 0
+// stores z_k and z_(k+1).
+__global__ void __launch_bounds__(kThreads) k_dir_fwd2(Band B, int k, double* __restrict__ y,
+                                                       double* __restrict__ z) {
+  __shared__ double yk[2][kNb];
+  __shared__ double part[2][4][kNb];
+  const int b = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int r = tid & 63, cs = tid >> 6;
+  const bool mid = B.Q >= 1;                 // L_(k+1,k) is inside the band
+  const bool has0 = b > 0 && b + 1 <= B.Q;   // L_(k+1+b,k)
+  const bool has1 = b > 0;                   // L_(k+1+b,k+1)
+  double lm[16], l0[16], l1[16];
+  if (mid) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) lm[u] = B.p[band_at(B, k, kNb + r, cs * 16 + u)];
+  }
+  if (has0) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) l0[u] = B.p[band_at(B, k, (b + 1) * kNb + r, cs * 16 + u)];
+  }
+  if (has1) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) l1[u] = B.p[band_at(B, k + 1, b * kNb + r, cs * 16 + u)];
+  }
+  double a[kNb];
+  double v1 = 0.0;
+  if (w == 0) load_diag_row(B, k, lane, a);
+  else if (w == 1) {
+    load_diag_row(B, k + 1, lane, a);
+    v1 = y[(k + 1) * kNb + lane];
+  }
+  if (w == 0) yk[0][lane] = tri_lower(a, y[k * kNb + lane], lane);
+  __syncthreads();
+  if (mid) {
+    double sm = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sm += lm[u] * yk[0][cs * 16 + u];
+    part[0][cs][r] = sm;
+  }
+  __syncthreads();
+  if (w == 1) {
+    if (mid)
+      v1 -= (part[0][0][lane] + part[0][1][lane]) + (part[0][2][lane] + part[0][3][lane]);
+    yk[1][lane] = tri_lower(a, v1, lane);
+  }
+  __syncthreads();
+  if (b == 0) {
+    if (tid < kNb) {
+      z[k * kNb + tid] = yk[0][tid];
+      z[(k + 1) * kNb + tid] = yk[1][tid];
+    }
+    return;
+  }
+  double s0 = 0.0, s1 = 0.0;
+  if (has0) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s0 += l0[u] * yk[0][cs * 16 + u];
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) s1 += l1[u] * yk[1][cs * 16 + u];
+  part[0][cs][r] = s0;
+  part[1][cs][r] = s1;
+  __syncthreads();
+  if (tid < kNb) {
+    double v = y[(k + 1 + b) * kNb + tid];
+    if (has0)
+      v -= (part[0][0][tid] + part[0][1][tid]) + (part[0][2][tid] + part[0][3][tid]);
+    v -= (part[1][0][tid] + part[1][1][tid]) + (part[1][2][tid] + part[1][3][tid]);
+    y[(k + 1 + b) * kNb + tid] = v;
+  }
+}
+
+// Two backward steps in one launch, k and k - 1 (k >= 1), as k_dir_fwd2
+// for L^T: wave 0 solves x_k, every thread takes its part of
+// L_(k,k-1)^T x_k, wave 1 solves x_(k-1), block b >= 1 updates
+// z_(k-1-b) by both steps' terms in single-step order; block 0 stores
+// x_k and x_(k-1).
+__global__ void __launch_bounds__(kThreads) k_dir_bwd2(Band B, int k, double* __restrict__ z,
+                                                       double* __restrict__ x) {
+  __shared__ double xk[2][kNb];
+  __shared__ double part[2][4][kNb];
+  const int b = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int c = tid & 63, rs = tid >> 6;
+  const int kb = k - 1 - b;                  // row block this block updates (b >= 1)
+  const bool mid = B.Q >= 1;                 // L_(k,k-1): panel k-1, rows kNb..
+  const bool has0 = b > 0 && b + 1 <= B.Q;   // L_(k,kb): panel kb, rows (b+1) kNb..
+  const bool has1 = b > 0;                   // L_(k-1,kb): panel kb, rows b kNb..
+  double lm[16], l0[16], l1[16];
+  if (mid) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) lm[u] = B.p[band_at(B, k - 1, kNb + rs * 16 + u, c)];
+  }
+  if (has0) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) l0[u] = B.p[band_at(B, kb, (b + 1) * kNb + rs * 16 + u, c)];
+  }
+  if (has1) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) l1[u] = B.p[band_at(B, kb, b * kNb + rs * 16 + u, c)];
+  }
+  double col[kNb];
+  double v1 = 0.0;
+  if (w == 0) load_diag_col(B, k, lane, col);
+  else if (w == 1) {
+    load_diag_col(B, k - 1, lane, col);
+    v1 = z[(k - 1) * kNb + lane];
+  }
+  if (w == 0) xk[0][lane] = tri_upper(col, z[k * kNb + lane], lane);
+  __syncthreads();
+  if (mid) {
+    double sm = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sm += lm[u] * xk[0][rs * 16 + u];
+    part[0][rs][c] = sm;
+  }
+  __syncthreads();
+  if (w == 1) {
+    if (mid)
+      v1 -= (part[0][0][lane] + part[0][1][lane]) + (part[0][2][lane] + part[0][3][lane]);
+    xk[1][lane] = tri_upper(col, v1, lane);
+  }
+  __syncthreads();
+  if (b == 0) {
+    if (tid < kNb) {
+      x[k * kNb + tid] = xk[0][tid];
+      x[(k - 1) * kNb + tid] = xk[1][tid];
+    }
+    return;
+  }
+  double s0 = 0.0, s1 = 0.0;
+  if (has0) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s0 += l0[u] * xk[0][rs * 16 + u];
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) s1 += l1[u] * xk[1][rs * 16 + u];
+  part[0][rs][c] = s0;
+  part[1][rs][c] = s1;
+  __syncthreads();
+  if (tid < kNb) {
+    double v = z[kb * kNb + tid];
+    if (has0)
+      v -= (part[0][0][tid] + part[0][1][tid]) + (part[0][2][tid] + part[0][3][tid]);
+    v -= (part[1][0][tid] + part[1][1][tid]) + (part[1][2][tid] + part[1][3][tid]);
+    z[kb * kNb + tid] = v;
+  }
 }
 
 // y[uidx] = r at unknown nodes; the pad is zeroed.
@@ -746,12 +914,23 @@ int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R
         // y = residual at U (the right-hand side on the first pass)
         hipLaunchKernelGGL(k_dir_gather, dim3(grid), dim3(256), 0, st, P.mask, uidx, P.r, N, B.n,
                            B.npad, y);
-        for (int k = 0; k < B.nblk; ++k)
-          hipLaunchKernelGGL(k_dir_fwd, dim3(1 + std::min(B.Q, B.nblk - 1 - k)), dim3(kThreads),
-                             0, st, B, k, y, z);
-        for (int k = B.nblk - 1; k >= 0; --k)
-          hipLaunchKernelGGL(k_dir_bwd, dim3(1 + std::min(B.Q, k)), dim3(kThreads), 0, st, B, k,
-                             z, y);
+        // two panels per launch, one for an odd last panel
+        for (int k = 0; k < B.nblk; k += 2) {
+          if (k + 1 < B.nblk)
+            hipLaunchKernelGGL(k_dir_fwd2, dim3(1 + std::min(B.Q, B.nblk - 2 - k)),
+                               dim3(kThreads), 0, st, B, k, y, z);
+          else
+            hipLaunchKernelGGL(k_dir_fwd, dim3(1 + std::min(B.Q, B.nblk - 1 - k)),
+                               dim3(kThreads), 0, st, B, k, y, z);
+        }
+        for (int k = B.nblk - 1; k >= 0; k -= 2) {
+          if (k >= 1)
+            hipLaunchKernelGGL(k_dir_bwd2, dim3(1 + std::min(B.Q, k - 1)), dim3(kThreads), 0,
+                               st, B, k, z, y);
+          else
+            hipLaunchKernelGGL(k_dir_bwd, dim3(1 + std::min(B.Q, k)), dim3(kThreads), 0, st, B,
+                               k, z, y);
+        }
         hipLaunchKernelGGL(k_dir_scatter, dim3((N + 255) / 256), dim3(256), 0, st, P.mask, uidx,
                            y, N, it > 0 ? 1 : 0, S.F);
         DIR_CHECK(hipGetLastError());
