@@ -17,11 +17,12 @@ Beside it (unless --no-extra): the same stream served with the FP32
 preconditioner; the 1024^2 star (one solve per step, FP64 at tol 1e-8 and in
 accurate mode at tol 1e-13); the 256-instance batch (FP64 and FP32 batched
 against one call per instance); the 2048^2 periodic multi-circle case with
-the FP32 and FP64 preconditioners; and the CPU oracle timed on a bounded
-sample of the stream.
+the FP32 and FP64 preconditioners; Example 2 (256^3) and Example 4 (1536 x
+512, direct and PCG); and the CPU oracle timed on a bounded sample of the
+stream.
 
 Other workloads (--workload): star_inward_1024, circle_64,
-periodic_circles_2048(_fp64), batch256, example2_256.
+periodic_circles_2048(_fp64), batch256, example2_256, example4_channel.
 
 Prints ONE JSON line (last line of stdout).  Progress goes to stderr.
 """
@@ -519,8 +520,8 @@ def bench_direct(p, phi, F, handle, stream, bhx, reps=3):
     log(f"direct: {sec * 1e3:.1f} ms per solve; 3 fields {tf * 1e3:.1f} ms")
     return {"ms_per_solve": round(1e3 * sec, 3), "refinement_solves": st.iterations,
             "true_rel_residual": st.true_rel_residual, "three_fields_ms": round(1e3 * tf, 3),
-            "method": "banded Cholesky of A_UU (unknowns row by row), FP64, refined with the "
-                      "compensated residual"}
+            "method": "banded Cholesky of A_UU (unknowns numbered line by line, here row by row), "
+                      "FP64, refined with the compensated residual"}
 
 
 def bench_time_step(p, phi, F, handle, stream, bhx, reps=3):
@@ -606,6 +607,38 @@ def bench_example2(handle, bhx, n=256, reps=3):
             "seconds": round(sec, 4), "true_rel_residual": st.true_rel_residual}
 
 
+def bench_channel(handle, bhx, ny=512, reps=3):
+    """Example 4 of the paper at its largest grid (3 ny x ny = 1536 x 512,
+    Neumann sides, periodic top and bottom, ten-term front, tol 1e-6): the
+    sparse direct path (unknowns numbered along columns) and PCG."""
+    import torch
+    from paper_1704_08897_amd import workloads as W
+    p = W.channel_problem(ny, terms=10, bcy=W.PERIODIC, tol=1e-6)
+    dev = torch.device("cuda:0")
+    phi = torch.from_numpy(p.phi).to(dev)
+    out = {"grid": f"{3 * ny}x{ny}", "bc": "neumann x periodic", "tol": p.tol,
+           "n_unknown": int((p.phi >= 0).sum())}
+    for name, solver in (("direct", 1), ("pcg", 0)):
+        times = []
+        for _ in range(reps + 1):
+            F = torch.from_numpy(p.F.copy()).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s, st = bhx.extend_ex(handle, phi, F, bc=p.bc, h=p.h, tol=p.tol,
+                                  opts=bhx.default_opts(solver=solver))
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            if s != bhx.OK:
+                raise SystemExit(f"channel solve failed: {bhx.status_string(s)} {st.as_dict()}")
+        out[name] = {"ms_per_solve": round(1e3 * statistics.median(times[1:]), 3),
+                     "iterations": st.iterations, "true_rel_residual": st.true_rel_residual}
+        log(f"example 4 {3 * ny}x{ny} {name}: {out[name]['ms_per_solve']:.1f} ms, "
+            f"{st.iterations} iterations")
+    del phi
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -659,6 +692,7 @@ def main():
                 out["batch256"] = bench_batch(args, handle, steps=2)
                 out["periodic_circles_2048"] = bench_periodic(handle)
                 out["example2_3d"] = bench_example2(handle, bhx)
+                out["example4_channel"] = bench_channel(handle, bhx)
             if not args.no_cpu_baseline:
                 import oracle as O
                 out["cpu_baseline"] = cpu_baseline_serve(sets, args.cpu_seconds)
@@ -679,6 +713,8 @@ def main():
                         "higher_is_better": True, "scaling": "weak", "vs_baseline": None})
         elif args.workload == "example2_256":
             out = {"workload": "example2_256", **bench_example2(handle, bhx)}
+        elif args.workload == "example4_channel":
+            out = {"workload": "example4_channel", **bench_channel(handle, bhx)}
         else:
             p, prec = workload(args.workload)
             res = bench_single(p, prec, args, handle, args.workload, extra=not args.no_extra)
