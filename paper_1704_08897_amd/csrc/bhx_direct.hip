@@ -201,9 +201,9 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // column-major, M[c][r] = A[r][c], lower part), right-looking in four steps of
 // 16 columns: wave 0 factors the 16 x 16 diagonal in its registers (one row
 // per lane, pivots exchanged by readlane), threads solve the rows below it,
-// and all threads update the trailing block.  Block 0 then stores L; wave w
-// of block b solves tile t = 4 b + w >= 1 of the panel (rows 64 t..) against
-// L on the matrix cores, with L read from LDS.
+// and all threads update the trailing block.  Block 0 then stores L; block
+// t >= 1 solves tile t of the panel (rows 64 t..) against L on the matrix
+// cores, with L read from LDS, 16 rows per wave.
 __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int tiles) {
   __shared__ __align__(16) double M[kNb][kNb + 2];
   __shared__ double rinv[kNb];                 // 1 / L[j][j]
@@ -339,24 +339,23 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
       B.d[diag_row(k, r2, c2)] = r2 >= c2 ? M[c2][r2] : 0.0;
     }
   }
-  const int t = blockIdx.x * 4 + w;
+  const int t = blockIdx.x;
   if (t == 0 || t >= tiles) return;      // no barrier below
   // Tile t solves X L^T = T (rows 64 t.. of the panel), as L Z = T^T with
   // Z = X^T, by 16-row blocks on the matrix cores:
   //   Z_d = L_dd^-1 (W_d - sum_{a<d} L_da Z_a),  W = T^T.
-  // Z is held as 4 x 4 tiles of 16 x 16 in the v_mfma_f64_16x16x4 output
-  // layout (lane l, element v: row 4 v + l / 16, column l % 16 of the tile),
-  // in which element s of a tile is exactly the B operand of k-step s, so the
-  // products chain without leaving registers.
-  const int r0 = t * kNb;
-  v4d Z[4][4];
+  // Wave w takes the tile's rows 16 w.. (one 16-column strip of Z, which no
+  // other strip's products touch).  Z_d is held as a 16 x 16 tile in the
+  // v_mfma_f64_16x16x4 output layout (lane l, element v: row 4 v + l / 16,
+  // column l % 16), in which element s is exactly the B operand of k-step s,
+  // so the products chain without leaving registers.
+  const int r0 = t * kNb + kStep * w;
+  v4d Z[4];
 #pragma unroll
   for (int d = 0; d < 4; ++d)
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        Z[d][jt][v] = B.p[band_at(B, k, r0 + kStep * jt + li, kStep * d + 4 * v + lk)];
+    for (int v = 0; v < 4; ++v)
+      Z[d][v] = B.p[band_at(B, k, r0 + li, kStep * d + 4 * v + lk)];
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
 #pragma unroll
@@ -365,30 +364,21 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
       for (int s4 = 0; s4 < 4; ++s4) {
         // A operand -L[16 d + i][16 a2 + 4 s4 + kk], i = l % 16, kk = l / 16
         const double aop = -M[kStep * a2 + 4 * s4 + lk][kStep * d + li];
-#pragma unroll
-        for (int jt = 0; jt < 4; ++jt)
-          Z[d][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, Z[a2][jt][s4], Z[d][jt], 0, 0, 0);
+        Z[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, Z[a2][s4], Z[d], 0, 0, 0);
       }
-    v4d T[4];
-#pragma unroll
-    for (int jt = 0; jt < 4; ++jt) T[jt] = (v4d){0.0, 0.0, 0.0, 0.0};
+    v4d T = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
       const double aop = Li[d][li][4 * s4 + lk];
-#pragma unroll
-      for (int jt = 0; jt < 4; ++jt)
-        T[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, Z[d][jt][s4], T[jt], 0, 0, 0);
+      T = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, Z[d][s4], T, 0, 0, 0);
     }
-#pragma unroll
-    for (int jt = 0; jt < 4; ++jt) Z[d][jt] = T[jt];
+    Z[d] = T;
   }
 #pragma unroll
   for (int d = 0; d < 4; ++d)
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        B.p[band_at(B, k, r0 + kStep * jt + li, kStep * d + 4 * v + lk)] = Z[d][jt][v];
+    for (int v = 0; v < 4; ++v)
+      B.p[band_at(B, k, r0 + li, kStep * d + 4 * v + lk)] = Z[d][v];
 }
 
 // Step k, part 2: trailing update of the band by panel k.  Tile (q, rt):
@@ -900,7 +890,7 @@ int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R
       }
       for (int k = 0; k < B.nblk; ++k) {
         const int below = std::min(B.Q, B.nblk - 1 - k);
-        hipLaunchKernelGGL(k_dir_potrf_trsm, dim3((1 + below + 3) / 4), dim3(kThreads), 0, st, B,
+        hipLaunchKernelGGL(k_dir_potrf_trsm, dim3(1 + below), dim3(kThreads), 0, st, B,
                            k, 1 + below);
         if (below > 0)
           hipLaunchKernelGGL(k_dir_update, dim3(below * (B.Q + 1)), dim3(kThreads), 0, st, B, k);
