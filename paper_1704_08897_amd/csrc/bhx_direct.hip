@@ -384,11 +384,12 @@ __global__ void __launch_bounds__(kThreads) k_dir_potrf_trsm(Band B, int k, int 
 // Step k, part 2: trailing update of the band by panel k.  Tile (q, rt):
 // rows rt*kNb.. of panel k+q -= (panel k rows (rt+q)*kNb..) (panel k rows
 // q*kNb..)^T, a 64 x 64 x 64 FP64 product on the matrix cores: the operands
-// are staged in LDS, wave w computes the 32 x 32 quadrant (w >> 1, w & 1) as
-// 2 x 2 tiles of v_mfma_f64_16x16x4 over k in steps of 4.  Lane layout of that
-// instruction: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
-// receives D[4 v + l / 16][l % 16] in accumulator element v.
-__global__ void __launch_bounds__(kThreads) k_dir_update(Band B, int k) {
+// are staged in LDS and each of the block's 16 waves computes one 16 x 16
+// output tile with v_mfma_f64_16x16x4 over k in steps of 4.  Lane layout of
+// that instruction: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// and receives D[4 v + l / 16][l % 16] in accumulator element v.
+constexpr int kUpdThreads = 1024;
+__global__ void __launch_bounds__(kUpdThreads) k_dir_update(Band B, int k) {
   __shared__ double sA[kNb][kNb];   // [t][r]
   __shared__ double sB[kNb][kNb];   // [t][c]
   const int q = 1 + blockIdx.x / (B.Q + 1), rt = blockIdx.x % (B.Q + 1);
@@ -396,63 +397,41 @@ __global__ void __launch_bounds__(kThreads) k_dir_update(Band B, int k) {
   if (rt > B.Q - q || j + rt >= B.nblk) return;       // no such tile, or past the pad
   const int ra = (rt + q) * kNb, rb = q * kNb;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int qr = (w >> 1) * 32, qc = (w & 1) * 32;      // the wave's quadrant
+  const int tr = (w >> 2) * 16, tc = (w & 3) * 16;      // the wave's output tile
   const int li = lane & 15, lk = lane >> 4;
   // every load of the block is issued before the first wait: the thread's
   // part of the output tile (which only this block reads or writes), then
   // the two operand tiles
-  double cv[2][2][4];
+  double cv[4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        cv[a][b][v] = B.p[band_at(B, j, rt * kNb + qr + 16 * a + 4 * v + lk, qc + 16 * b + li)];
+  for (int v = 0; v < 4; ++v) cv[v] = B.p[band_at(B, j, rt * kNb + tr + 4 * v + lk, tc + li)];
   {
-    constexpr int kPer = kNb * kNb / kThreads;
+    constexpr int kPer = kNb * kNb / kUpdThreads;
     double va[kPer], vb[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-      const int e = threadIdx.x + u * kThreads, t = e / kNb, r = e - t * kNb;
+      const int e = threadIdx.x + u * kUpdThreads, t = e / kNb, r = e - t * kNb;
       va[u] = B.p[band_at(B, k, ra + r, t)];
       vb[u] = B.p[band_at(B, k, rb + r, t)];
     }
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-      const int e = threadIdx.x + u * kThreads, t = e / kNb, r = e - t * kNb;
+      const int e = threadIdx.x + u * kUpdThreads, t = e / kNb, r = e - t * kNb;
       sA[t][r] = va[u];
       sB[t][r] = vb[u];
     }
   }
   __syncthreads();
-  v4d acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  v4d acc = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-  for (int t0 = 0; t0 < kNb; t0 += 4) {
-    double av[2], bv[2];
+  for (int t0 = 0; t0 < kNb; t0 += 4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[t0 + lk][tr + li], sB[t0 + lk][tc + li], acc,
+                                               0, 0, 0);
 #pragma unroll
-    for (int a = 0; a < 2; ++a) av[a] = sA[t0 + lk][qr + 16 * a + li];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) bv[b] = sB[t0 + lk][qc + 16 * b + li];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+  for (int v = 0; v < 4; ++v) {
+    const int r = tr + 4 * v + lk, c = tc + li;
+    B.p[band_at(B, j, rt * kNb + r, c)] = cv[v] - acc[v];
   }
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = qr + 16 * a + 4 * v + lk, c = qc + 16 * b + li;
-        B.p[band_at(B, j, rt * kNb + r, c)] = cv[a][b][v] - acc[a][b][v];
-      }
 }
 
 // Column `lane` of L_kk (zeros below the diagonal of L^T), from the
@@ -893,7 +872,8 @@ int solve_direct(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R
         hipLaunchKernelGGL(k_dir_potrf_trsm, dim3(1 + below), dim3(kThreads), 0, st, B,
                            k, 1 + below);
         if (below > 0)
-          hipLaunchKernelGGL(k_dir_update, dim3(below * (B.Q + 1)), dim3(kThreads), 0, st, B, k);
+          hipLaunchKernelGGL(k_dir_update, dim3(below * (B.Q + 1)), dim3(kUpdThreads), 0, st, B,
+                             k);
       }
       DIR_CHECK(hipGetLastError());
       factored = true;
