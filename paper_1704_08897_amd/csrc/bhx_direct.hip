@@ -22,8 +22,8 @@
 // registers, pivots exchanged by readlane), the panel below it solved against
 // it (TRSM, L read from LDS), and the trailing band updated by tile products
 // of the panel with itself.
-// Solves: forward and backward substitution, one step per panel, each step
-// updating the right-hand side blocks it reaches (no cross-block sums).
+// Solves: forward and backward substitution, two panels per launch, each
+// block updating the right-hand side block it owns (no cross-block sums).
 // Every sum runs in a fixed order, so results are deterministic.
 #include <algorithm>
 #include <chrono>
