@@ -106,6 +106,26 @@ def test_channel_example(handle, ny, terms, by):
     assert O.relative_l2(host(G), Fo) <= 1e-9, O.relative_l2(host(G), Fo)
 
 
+@pytest.mark.parametrize("gap", [3, 2])
+def test_isolated_unknowns(handle, gap):
+    """Unknown nodes on a lattice of spacing 3 couple to no other unknown
+    (the 13-point stencil reaches two nodes): the band has width 0, every
+    panel is its diagonal block alone and the two-panel substitutions take
+    their uncoupled branches.  Spacing 2 couples each unknown to the next
+    in its row and column, a band of one panel.  Both against the oracle."""
+    n = 200
+    rng = np.random.default_rng(gap)
+    phi = -np.ones((n, n))
+    phi[::gap, ::gap] = 1.0
+    F = rng.normal(size=(n, n))
+    known = O.known_mask(phi)
+    Fo, _ = O.extend_direct(phi, F, 0, 0)
+    s, st, got = direct(handle, phi, F, 0, 1e-12)
+    assert s == bhx.OK, st.as_dict()
+    assert np.array_equal(got[known], F[known])
+    assert O.relative_l2(got, Fo) <= 1e-9
+
+
 def test_star1024_direct(handle):
     """The 1024 x 1024 star of the benchmark, tol 1e-8 and 1e-12."""
     p = W.star_inward_problem(1024, tol=1e-8)
