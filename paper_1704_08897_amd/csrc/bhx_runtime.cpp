@@ -1023,7 +1023,42 @@ int prepare_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& 
       u[3 + p] = {hd->items_d[p], D.items[p].data(), D.items[p].size() * sizeof(int)};
     BHX_CHECK(upload_ordered(hd, st, u, 3 + kNumPass));
   }
+  hd->batch_h = Bh;
+  for (int p = 0; p < kNumPass; ++p) hd->items_h[p] = D.items[p];
   return batch_grids(hd->plans, D, R, hd->num_cu, gout);
+}
+
+// Upload the work lists of the handle's current batch with only the items of
+// instances still running (all = false), or in full (all = true), together
+// with the header that carries their lengths.  The kernels read both at run
+// time, so captured chunks stay valid; an item's work does not depend on
+// which block takes it, so results are unchanged.  The stream must be idle
+// (the staging buffer is reused).
+static hipError_t upload_work_lists(bhx_handle* hd, hipStream_t st, const Ctl* ch, bool all) {
+  std::vector<int> lists[kNumPass];
+  Batch Bh = hd->batch_h;
+  Upload u[1 + kNumPass];
+  int nu = 0;
+  for (int p = 0; p < kNumPass; ++p) {
+    const std::vector<int>& full = hd->items_h[p];
+    if (all) {
+      lists[p] = full;
+    } else {
+      lists[p].reserve(full.size());
+      for (int c : full)
+        if (ch[c >> kItemShift].done == kRunning) lists[p].push_back(c);
+    }
+    Bh.n_items[p] = (int)lists[p].size();
+    if (!lists[p].empty())
+      u[nu++] = {hd->items_d[p], lists[p].data(), lists[p].size() * sizeof(int)};
+  }
+  u[nu++] = {hd->batch_d, &Bh, sizeof(Batch)};
+  return upload_ordered(hd, st, u, nu);
+}
+
+static bool compaction_enabled() {
+  const char* v = getenv("BHX_COMPACT");
+  return !(v && v[0] == '0');
 }
 
 int drive_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R, const Grids& g,
@@ -1108,6 +1143,7 @@ int drive_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
   double pass_ms[4] = {0, 0, 0, 0};
   int pass_cnt[4] = {0, 0, 0, 0};
   std::vector<int> iter_before(n);
+  int listed = n;                     // instances whose items the work lists hold
   if (active > 0) {
     BHX_CHECK(launch_precond(X.B, R, g, st));
     for (;;) {
@@ -1131,10 +1167,24 @@ int drive_batch(bhx_handle* hd, int n, const InstSpec* specs, const Resolved& R,
           }
         }
       }
-      bool all_done = true;
-      for (int i = 0; i < n; ++i)
-        if (ch[i].done == kRunning) all_done = false;
-      if (!all_done) continue;
+      int running = 0;
+      for (int i = 0; i < n; ++i) running += ch[i].done == kRunning;
+      if (running > 0) {
+        // once a quarter of the listed instances have finished, list only the
+        // running ones: a finished instance's items would still cost each
+        // block that meets one a round trip of loads before it is skipped
+        if (X.compact && 4 * running <= 3 * listed) {
+          BHX_CHECK(upload_work_lists(hd, st, ch, false));
+          listed = running;
+        }
+        continue;
+      }
+      // the residual, finalisation, restart and preconditioner launches below
+      // go over every instance: full lists again
+      if (listed < n) {
+        BHX_CHECK(upload_work_lists(hd, st, ch, true));
+        listed = n;
+      }
       // true residual of finished instances; restart those that miss the target
       BHX_CHECK(launch_resid(X.B, g.dim, g.s, st));
       BHX_CHECK(launch_finalize(X.B, n, kFinResidH, st));
@@ -1199,6 +1249,8 @@ static int solve_batch_once(bhx_handle* hd, int n, const InstSpec* specs, const 
   X.ch = hd->ctl_h;
   X.flag_d = hd->flag_d;
   X.graphs = true;
+  // one instance runs without work lists (its item index is its item)
+  X.compact = n > 1 && compaction_enabled();
   return drive_batch(hd, n, specs, R, g, st, X, stats, t0);
 }
 

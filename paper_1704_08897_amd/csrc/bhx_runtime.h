@@ -149,6 +149,8 @@ struct DriveCtx {
   int* flag_d = nullptr;      // device flags [n]
   bool graphs = true;         // captured chunks and pinned uploads; false: direct
                               // launches and pageable copies (no allocation)
+  bool compact = false;       // between chunks, drop finished instances' items from
+                              // the work lists (needs the handle's host copies)
 };
 
 // Largest total of a launch's t arrays (bytes) whose row-forward stores go
@@ -182,6 +184,10 @@ struct bhx_handle {
   int* items_d[bhx::kNumPass] = {nullptr, nullptr, nullptr};
   int items_cap[bhx::kNumPass] = {0, 0, 0};
   int batch_count = 0;         // instances of the current batch
+  // host copies of the current batch's full work lists and of its header, for
+  // compacting the lists while instances finish (drive_batch)
+  std::vector<int> items_h[bhx::kNumPass];
+  bhx::Batch batch_h{};
   int* flag_d = nullptr;
   int flag_cap = 0;
   bhx::Ctl* ctl_h = nullptr;   // pinned copy of the control blocks

@@ -265,6 +265,48 @@ def test_batched_equals_alone(handle, monkeypatch):
         check_against_oracle(p, got, bound=1e-9)
 
 
+def compaction_batch():
+    return (W.star_cubic_batch(5, seed=41, nmin=40, nmax=96, tol=1e-12) +
+            W.star_cubic_batch(2, seed=42, nmin=200, nmax=260, tol=1e-12))
+
+
+@pytest.fixture(scope="module")
+def compaction_refs():
+    return [O.extend_direct(p.phi, p.F, p.bcx, p.bcy)[0] for p in compaction_batch()]
+
+
+@pytest.mark.parametrize("kw", [{}, {"accurate": 1, "tol_inner": 1e-9}, {"precision": 1}])
+def test_batch_work_list_compaction(handle, monkeypatch, compaction_refs, kw):
+    """Between iteration chunks a batch drops finished instances' items from
+    its work lists, and puts them back for the true-residual check and any
+    restart.  Short chunks (many compaction points), instances whose
+    iteration counts differ several-fold, accurate mode (restarts) and the
+    FP32 preconditioner: the results and statistics equal those of the same
+    batch with compaction off, bit for bit, and meet the oracle bar."""
+    monkeypatch.setenv("BHX_SHAPE_KERNELS", "0")
+    batch = compaction_batch()
+    out = {}
+    for compact in ("1", "0"):
+        monkeypatch.setenv("BHX_COMPACT", compact)
+        Fs = [dev(p.F) for p in batch]
+        s, sts = bhx.extend_batched(handle, [dev(p.phi) for p in batch], Fs,
+                                    [p.h for p in batch], [p.bc for p in batch],
+                                    [p.tol for p in batch],
+                                    opts=bhx.default_opts(chunk=2, **kw))
+        assert s == bhx.OK, [st.as_dict() for st in sts]
+        out[compact] = ([host(F) for F in Fs], [(st.iterations, st.restarts) for st in sts])
+    its = [i for i, _ in out["1"][1]]
+    assert max(its) >= 2 * min(its), its
+    assert out["1"][1] == out["0"][1]
+    for a, b in zip(out["1"][0], out["0"][0]):
+        assert np.array_equal(a, b)
+    bound = 1e-8 if kw.get("precision") else 1e-9
+    for p, got, ref in zip(batch, out["1"][0], compaction_refs):
+        known = O.known_mask(p.phi)
+        assert np.array_equal(got[known], p.F[known])
+        assert O.relative_l2(got, ref) <= bound
+
+
 def test_batched_autotuned_fp32(handle):
     """FP32 preconditioner (flexible PCG) in one batched call with the
     autotuned schedule: every instance meets the tolerance and the mixed
