@@ -80,6 +80,28 @@ def test_mix_equals_alone(handle):
         assert O.relative_l2(got, ref) <= 1e-9
 
 
+def test_large_requests_mix_equals_alone(handle):
+    """Requests large enough that the engine's transform lists hold more
+    items than its persistent grids have blocks (each block takes several
+    items of different requests): each result still equals the request
+    solved alone bit for bit."""
+    probs = mixed_requests(5, seed=13, nmin=380, nmax=700, tol=1e-10)
+    srv = Server(0, hbm_budget=4 << 30, max_slots=8)
+    try:
+        reqs = [Request(dev(p.phi), dev(p.F), p.bc, p.h, p.tol, arrival=0.0) for p in probs]
+        res = serve_stream(srv, reqs)
+    finally:
+        srv.close()
+    assert len(res) == len(probs)
+    for r in res:
+        assert r.stats["status"] == bhx.OK, r.stats
+    torch.cuda.synchronize()
+    for p, q in zip(probs, reqs):
+        s, st, ref_alone = alone(handle, p)
+        assert s == bhx.OK
+        assert np.array_equal(q.F.cpu().numpy(), ref_alone)
+
+
 def test_requests_join_running_batch(handle):
     """Later arrivals are admitted while earlier requests iterate; every
     result still equals the request solved alone."""
