@@ -40,6 +40,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "extension solves/sec + p50/p99 latency at 1e-8 rel. residual; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 PASS_NAMES = ["stencil", "row_forward", "column", "row_inverse"]
 PASS_KERNELS = ["k_stencil", "k_rowfwd", "k_col", "k_rowinv"]
 
@@ -77,6 +78,20 @@ def pass_coeffs(p, prec):
     if p == 3:      # t read, r read, z written, mask
         return 16, 1 + tb
     raise ValueError(p)
+
+
+def column_pass_flops(n):
+    """Algorithmic FP64 flops of one 2-D column-pass launch over an n x n grid
+    with a Neumann or periodic y axis, by the usual count of 5 m log2(m) per
+    complex FFT of m points: the n columns go two to a complex row; each row
+    runs a forward and an inverse transform, each one m-point FFT (m = n, a
+    power of two) or two through the chirp-z core (m = the power of two at
+    least 2n - 1)."""
+    import math
+    pow2 = n & (n - 1) == 0
+    m = n if pow2 else 1 << (2 * n - 2).bit_length()
+    ffts = 2 if pow2 else 4
+    return (n + 1) // 2 * ffts * 5 * m * math.log2(m)
 
 
 def pass_bytes(p, n_unknown, N, prec):
@@ -181,7 +196,8 @@ def bench_serve(args):
         ns = n_sat or len(sets["sat"])
         nt = n_timed or len(sets["timed"])
         try:
-            run(srv, sets["warm"], fields["warm"], [0.0] * len(sets["warm"]), "warm-up")
+            res_warm, _, _ = run(srv, sets["warm"], fields["warm"], [0.0] * len(sets["warm"]),
+                                 "warm-up")
             res, ok, span = run(srv, sets["sat"][:ns], fields["sat"][:ns], [0.0] * ns,
                                 f"saturated fp{64 if precision == 0 else 32}")
             sat = len(ok) / span
@@ -192,6 +208,9 @@ def bench_serve(args):
             log(f"saturated (prec {precision}): {sat:.3f} solves/s over {len(res)} requests")
             if profile:
                 out["profile"] = bhx.engine_profile(srv.engine)
+                # the engine's profile covers the warm-up requests too
+                out["served"] = [(r.request.tag.n, r.stats["iterations"])
+                                 for r in res_warm + res]
                 return out
             if timed:
                 rate = 0.8 * sat
@@ -227,7 +246,8 @@ def bench_serve(args):
     # roofline: the first requests of the saturated phase again, with
     # dispatch events on every pass
     n_prof = min(8, len(sets["sat"]))
-    prof = serve(0, profile=15, timed=False, n_sat=n_prof)["profile"]
+    prof_out = serve(0, profile=15, timed=False, n_sat=n_prof)
+    prof = prof_out["profile"]
     tot = [prof["ms"][p] for p in range(4)]
     dom = int(np.argmax(tot))
     cu, cn = pass_coeffs(dom, 0)
@@ -245,10 +265,28 @@ def bench_serve(args):
                                                             max(1, prof["launches"][p]), 5)
                                        for p in range(4)},
                 "timed_with": "dispatch start/stop events (hipExtLaunchKernelGGL) on every "
-                              "launch of the engine's chunks while it serves the first "
-                              f"{n_prof} requests of the saturated phase again; bytes per "
-                              "launch summed over the requests each launch worked on"}
+                              "launch of the engine's chunks while a fresh engine serves the "
+                              f"warm-up requests and the first {n_prof} requests of the "
+                              "saturated phase again; bytes per launch summed over the "
+                              "requests each launch worked on"}
     log(f"roofline: {PASS_KERNELS[dom]} {achieved:.1f} GB/s ({achieved / HBM_PEAK_GBS:.3f})")
+    # the column pass seen from the arithmetic side: chirp-z cores give it more
+    # flops per byte than the FP64 vector ridge (peak flops / peak bandwidth)
+    col_ms = prof["ms"][2]
+    col_flops = sum(it * column_pass_flops(n) for n, it in prof_out["served"])
+    col_bytes = 2 * 8 * prof["nodes"][2]
+    if col_ms > 0 and col_bytes > 0:
+        tflops = col_flops / (col_ms * 1e-3) / 1e12
+        roofline["column_pass_compute_view"] = {
+            "bound": "alu", "achieved": round(tflops, 2), "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4),
+            "intensity_flop_per_byte": round(col_flops / col_bytes, 1),
+            "ridge_flop_per_byte": round(FP64_VECTOR_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9), 1),
+            "count": "5 m log2(m) flops per complex m-point FFT; per pair of columns a forward "
+                     "and an inverse transform, two FFTs each through a chirp-z core (m the "
+                     "power of two >= 2n - 1), one each for a power-of-two side (m = n); "
+                     "summed over the profiled requests' iterations"}
+        log(f"column pass: {tflops:.2f} TFLOP/s FP64, {col_flops / col_bytes:.1f} flop/B")
     out = {
         "metric": METRIC, "value": fp64["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
         "steps": fp64["requests"], "warmup": len(sets["warm"]),
