@@ -24,7 +24,12 @@ stream.
 Other workloads (--workload): star_inward_1024, circle_64,
 periodic_circles_2048(_fp64), batch256, example2_256, example4_channel.
 
-Prints ONE JSON line (last line of stdout).  Progress goes to stderr.
+Prints ONE JSON line (last line of stdout).  Progress goes to stderr.  Its
+`roofline` is the HBM view of the dominant pass (algorithmic bytes per launch
+over the launch's time); for the serving stream,
+`roofline.column_pass_compute_view` gives the same launches' FP64 flop rate
+against the vector peak, since chirp-z cores put the column pass above the
+FP64 ridge.
 """
 import argparse
 import hashlib
